@@ -1,0 +1,85 @@
+"""Sparse-sign single-pass sketch of f(L'R') (Section 3.1, Alg. 3, Eq. 4, Alg. 4).
+
+Readings:
+* Alg. 3 puts z nonzeros in each column of the n x h test matrix, at z
+  distinct uniformly random rows, with independent fair signs.  Entries are
+  scaled to +-1/sqrt(z); the SVD of Alg. 4 does not depend on this scale
+  (orth(Y) is unchanged and the two pseudo-inverses cancel the scale of O in W).
+* Alg. 4 line 4 multiplies an n x v matrix by S; it is read as S(p, :), the
+  v nonzero rows of S.  Lines 6-7 reuse the name p for the unique rows of O;
+  read as p_O and O(p_O, :).
+* The realizations (rows, signs) are inputs (drawn by ``synth.sparse_sign``).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from .netmf import trunc_log
+
+
+def sparse_sign_matrix(n: int, rows: np.ndarray, signs: np.ndarray) -> sp.csr_matrix:
+    """The n x cols test matrix of Alg. 3 (sparse), entries +-1/sqrt(z)."""
+    cols, z = rows.shape
+    c_idx = np.repeat(np.arange(cols), z)
+    vals = signs.ravel().astype(np.float64) / np.sqrt(z)
+    return sp.csr_matrix((vals, (rows.ravel().astype(np.int64), c_idx)), shape=(n, cols))
+
+
+def sparse_sign_dense(n: int, rows: np.ndarray, signs: np.ndarray) -> np.ndarray:
+    """The n x cols test matrix of Alg. 3 as a dense array (small n only)."""
+    return sparse_sign_matrix(n, rows, signs).toarray()
+
+
+def unique_rows(rows: np.ndarray) -> np.ndarray:
+    """Alg. 3 last step: the sorted unique row coordinates p."""
+    return np.unique(rows.ravel())
+
+
+def sketch_dense(Lp, Rp, S, O):
+    """Plain definition: X = L'R' formed densely, Y = f(X) S, Z = O^T f(X) O."""
+    F = trunc_log(Lp @ Rp)
+    return F @ S, O.T @ F @ O
+
+
+def sketch_y_sampled(Lp, Rp, rows, signs, row_subset=None):
+    """Eq. (4): Y = f(L' R'(:, p)) S(p, :), only v = |p| columns of f(L'R') formed.
+
+    ``row_subset`` restricts the output to some rows of Y (rows of Y are
+    independent: row i only needs row i of L')."""
+    n = Rp.shape[1]
+    p = unique_rows(rows)
+    S = sparse_sign_matrix(n, rows, signs)[p, :].toarray()
+    L = Lp if row_subset is None else Lp[row_subset]
+    return trunc_log(L @ Rp[:, p]) @ S
+
+
+def sketch_z_sampled(Lp, Rp, rows, signs):
+    """Alg. 4 line 7: Z = O(p,:)^T f(L'(p,:) R'(:,p)) O(p,:)."""
+    n = Rp.shape[1]
+    p = unique_rows(rows)
+    O = sparse_sign_matrix(n, rows, signs)[p, :].toarray()
+    return O.T @ trunc_log(Lp[p, :] @ Rp[:, p]) @ O
+
+
+def single_pass_svd(Y, Z, O, d: int):
+    """Alg. 4 lines 5 and 8-10 given the sketches.
+
+    Q = orth(Y); solve (O^T Q) T = Z, then (O^T Q) W^T = T^T (two least
+    squares problems, Section 3.1); [U^, Sigma, V^] = svd(W);
+    U_d = Q U^(:, 1:d), Sigma_d, V_d = Q V^(:, 1:d)."""
+    Q, _ = np.linalg.qr(Y, mode="reduced")
+    B = np.asarray(O.T @ Q)
+    Tm = np.linalg.lstsq(B, Z, rcond=None)[0]
+    W = np.linalg.lstsq(B, Tm.T, rcond=None)[0].T
+    Uh, sig, Vh = np.linalg.svd(W)
+    return Q @ Uh[:, :d], sig[:d], Q @ Vh.T[:, :d], W, Q
+
+
+def reduced_matrix_from_sampled_O(Q, Z, rows, signs):
+    """W of Alg. 4 line 8 with O given by coordinates (only its nonzero rows used)."""
+    n = Q.shape[0]
+    O = sparse_sign_matrix(n, rows, signs)
+    B = np.asarray(O.T @ Q)
+    Tm = np.linalg.lstsq(B, Z, rcond=None)[0]
+    return np.linalg.lstsq(B, Tm.T, rcond=None)[0].T
