@@ -1,0 +1,208 @@
+/*
+ * sketchne.h -- C ABI of the MI355X (gfx950) SketchNE hot path.
+ *
+ * The method (SketchNE, TKDE 2023, arXiv 2110.12782) embeds a graph by
+ *   1. a randomized eigendecomposition of D^-a A D^-a     (Alg. 5, Alg. 6 line 1)
+ *   2. the low-rank factors L', R' of Eq. (11)            (Alg. 6 lines 2-3)
+ *   3. the sparse-sign single-pass sketch of f(L'R')      (Alg. 3, Eq. 4, Alg. 4 lines 2-4, 6-7)
+ *   4. the reduced matrix W, its SVD and E = U_d S_d^1/2  (Alg. 4 lines 5, 8-10, Alg. 6 line 5)
+ * where f = trunc_log (Eq. 1).  The n x n matrix f(L'R') is never formed.
+ *
+ * Conventions for every entry point
+ *   - Array arguments are DEVICE pointers unless marked "host".  Dense
+ *     matrices are row-major with the stated leading dimension.
+ *   - The caller owns every buffer, including the workspace.  The library
+ *     allocates no device memory and keeps no pointer after a call returns,
+ *     except for the work it enqueued on the context's stream; keep buffers
+ *     alive until sketchne_sync() (or a sync of that stream).
+ *   - Arguments are validated before anything is enqueued.  On SKETCHNE_E_ARG
+ *     or SKETCHNE_E_WORKSPACE nothing was enqueued and outputs are untouched.
+ *   - Numerical breakdown detected on the device (a Cholesky pivot that is
+ *     not positive, an eigensolver that did not converge, a non-finite Ritz
+ *     value) sets a device flag; sketchne_sync() reports it as
+ *     SKETCHNE_E_NUMERIC.  Output contents are then unspecified.
+ *   - No C++ exception crosses this boundary.
+ *   - Workspace pointers must be 256-byte aligned.
+ *   - Graphs are undirected and unweighted: the CSR pattern is symmetric,
+ *     rows are sorted, there are no self loops and no duplicate entries
+ *     (A_ij in {0,1}); vol(G) = nnz (Section 2).  An isolated vertex has all
+ *     its degree powers taken as 0, so its rows of U, Y and E are 0.
+ */
+#ifndef SKETCHNE_H
+#define SKETCHNE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SKETCHNE_OK = 0,
+  SKETCHNE_E_ARG = 1,         /* invalid argument; nothing enqueued            */
+  SKETCHNE_E_WORKSPACE = 2,   /* workspace null, too small or misaligned       */
+  SKETCHNE_E_DEVICE = 3,      /* HIP runtime / launch failure                  */
+  SKETCHNE_E_NUMERIC = 4,     /* device-side numerical breakdown (at sync)     */
+  SKETCHNE_E_UNSUPPORTED = 5  /* size or option outside what this build runs   */
+} sketchne_status;
+
+/* Input type of the fused sketch GEMM (accumulation is FP32 in every case). */
+typedef enum { SKETCHNE_FP32 = 0, SKETCHNE_BF16 = 1, SKETCHNE_FP16 = 2 } sketchne_precision;
+
+/* Numeric flag bits returned by sketchne_sync(). */
+#define SKETCHNE_FLAG_CHOL_SHIFT   0x1u  /* a Cholesky needed a diagonal shift        */
+#define SKETCHNE_FLAG_CHOL_FAIL    0x2u  /* a Cholesky failed even after the shift    */
+#define SKETCHNE_FLAG_EIG_NOCONV   0x4u  /* Jacobi reached its sweep limit            */
+#define SKETCHNE_FLAG_NONFINITE    0x8u  /* non-finite eigenvalue / singular value    */
+#define SKETCHNE_FLAG_BAD_INDEX    0x10u /* a test-matrix row outside [0, n) was read  */
+
+/* Workspace query operations (bitmask: the size covers every op named). */
+#define SKETCHNE_OP_EIG    0x1
+#define SKETCHNE_OP_SKETCH 0x2
+#define SKETCHNE_OP_EMBED  0x4
+#define SKETCHNE_OP_SPMM   0x8
+
+typedef struct sketchne_ctx sketchne_ctx;
+
+/* An undirected graph G = (V, E, A) in CSR, n vertices, nnz = 2m stored entries. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int64_t* rowptr; /* device, n+1 */
+  const int32_t* colidx; /* device, nnz */
+} sketchne_graph;
+
+/* Hyper-parameters (Table 1 notation; Alg. 4, 5, 6). */
+typedef struct {
+  double alpha;      /* a in D^-a A D^-a, 0 < a <= 0.5 (Section 3.2)                 */
+  int32_t T;         /* context window size, >= 1 (Eq. 1)                             */
+  double b;          /* number of negative samples, > 0 (Eq. 1)                       */
+  int32_t k;         /* eigen rank (Alg. 5)                                           */
+  int32_t s_eig;     /* oversampling of Alg. 5; K = k + s_eig start columns           */
+  int32_t q;         /* power iterations of Alg. 5, >= 0                              */
+  int32_t d;         /* embedding dimension                                          */
+  int32_t h;         /* columns of the test matrix S, d <= h (Alg. 4: h = d + s1)     */
+  int32_t l;         /* columns of the test matrix O, h <= l (Alg. 4: l = d + s2)     */
+  int32_t z;         /* nonzeros per test-matrix column, 1 <= z <= n (Alg. 3)         */
+  uint64_t seed;     /* seed of the device generators (Omega, S, O)                   */
+  int32_t precision; /* sketchne_precision of the fused sketch GEMM                   */
+  int32_t split_r;   /* BF16/FP16: leading components carried as hi+lo pairs (0..k)  */
+} sketchne_params;
+
+/* A sparse-sign test matrix (Alg. 3) of size n x cols with z nonzeros per
+ * column.  Column c owns rows[c*z .. c*z+z-1] (distinct, in [0, n)) with signs
+ * signs[c*z .. c*z+z-1] in {-1, +1}; the entry value is sign / sqrt(z). */
+typedef struct {
+  int32_t cols;
+  int32_t z;
+  int32_t* rows;   /* device, cols*z */
+  int8_t* signs;   /* device, cols*z */
+} sketchne_sparse_sign;
+
+const char* sketchne_status_str(sketchne_status s);
+
+/* Context bound to a device and a caller-owned HIP stream (NULL = default
+ * stream).  One context per host thread.  The context owns a few bytes of
+ * device flags and pinned host memory, released by sketchne_destroy. */
+sketchne_status sketchne_create(sketchne_ctx** ctx, int device, void* hip_stream);
+sketchne_status sketchne_destroy(sketchne_ctx* ctx);
+sketchne_status sketchne_set_stream(sketchne_ctx* ctx, void* hip_stream);
+
+/* Bytes of workspace needed by the operations in op_mask for a graph of n
+ * vertices and nnz entries (*bytes is host memory). */
+sketchne_status sketchne_workspace_size(const sketchne_params* p, int64_t n, int64_t nnz,
+                                        int op_mask, size_t* bytes);
+
+/* Alg. 5 on X = D^-a A D^-a (Alg. 6 line 1): Y = X Omega, Q = orth(Y),
+ * q times Q = orth(X(XQ)), Rayleigh-Ritz on Q^T X Q, eigenpairs sorted by
+ * |lambda| descending (ties: lambda descending, then index).
+ *   omega0: n x (k+s_eig) row-major start block, or NULL to draw a standard
+ *           Gaussian block on the device from p->seed.
+ *   U:      n x k row-major FP32 output (orthonormal columns).
+ *   lambda: k FP64 output.
+ * Orthonormalisation is Cholesky-QR with FP64 Gram/Cholesky (twice). */
+sketchne_status sketchne_eig(sketchne_ctx* ctx, const sketchne_graph* A, const sketchne_params* p,
+                             const float* omega0, float* U, double* lambda,
+                             void* ws, size_t ws_bytes);
+
+/* Alg. 6 lines 2-3 and Alg. 4 lines 3-4, 6-7: forms L' and R' of Eq. (11)
+ * from U, lambda and the degrees, then
+ *   Y  = f(L'R') S           (n x h, written TRANSPOSED: Yt[c*n + i] = Y[i][c])
+ *   Z  = O^T f(L'R') O       (l x l row-major)
+ * visiting only the rows/columns of f(L'R') that S and O touch (Eq. 4).
+ * If generate != 0, S and O are drawn on the device from p->seed and written
+ * into S->rows/signs and O->rows/signs; otherwise they are read from there.
+ * S->cols must equal h, O->cols must equal l, and both z must equal p->z. */
+sketchne_status sketchne_sketch(sketchne_ctx* ctx, const sketchne_graph* A, const sketchne_params* p,
+                                const float* U, const double* lambda,
+                                sketchne_sparse_sign* S, sketchne_sparse_sign* O, int generate,
+                                float* Yt, float* Z, void* ws, size_t ws_bytes);
+
+/* Alg. 4 lines 5, 8-10 and Alg. 6 line 5: Q = orth(Y); W = (O^T Q)^+ Z (Q^T O)^+
+ * by two least-squares solves (QR of O^T Q, FP64); SVD of W (W is symmetric
+ * because Z is, so its SVD is taken from a symmetric eigendecomposition with
+ * singular values |eigenvalue|); E = Q U^(:, 1:d) diag(sigma)^1/2.
+ *   Yt: h x n (as written by sketchne_sketch); Z: l x l; O: the test matrix of Z.
+ *   E:  n x d row-major FP32 output; sigma: d FP64 output, descending. */
+sketchne_status sketchne_embed(sketchne_ctx* ctx, const sketchne_params* p, int64_t n,
+                               const float* Yt, const float* Z, const sketchne_sparse_sign* O,
+                               float* E, double* sigma, void* ws, size_t ws_bytes);
+
+/* Wait for the context's stream; *flags (host, nullable) receives the OR of
+ * the numeric flag bits raised since the previous sync.  Returns
+ * SKETCHNE_E_NUMERIC if CHOL_FAIL, EIG_NOCONV or NONFINITE was raised, and
+ * SKETCHNE_E_ARG if BAD_INDEX was raised (such a row contributes zero). */
+sketchne_status sketchne_sync(sketchne_ctx* ctx, uint32_t* flags);
+
+/* ---- Steps of the path, exposed for composition and testing ------------ */
+
+/* C = D^-a A D^-a B (the SpMM of Alg. 5 lines 4, 6, 9; Section 3.4).
+ * B: n x cols (ld ldb), C: n x cols (ld ldc), FP32; cols % 4 == 0, cols <= 512;
+ * ldb, ldc multiples of 4.  B and C must not overlap. */
+sketchne_status sketchne_spmm(sketchne_ctx* ctx, const sketchne_graph* A, double alpha,
+                              const float* B, int64_t ldb, int32_t cols,
+                              float* C, int64_t ldc, void* ws, size_t ws_bytes);
+
+/* In-place orthonormalisation of the columns of B (n x cols, ld ldb, FP32):
+ * Cholesky-QR twice with FP64 Gram and Cholesky (the orth of Alg. 5).
+ * cols <= 1024.  Workspace: sketchne_orth_workspace_size(). */
+sketchne_status sketchne_orth_workspace_size(int64_t n, int32_t cols, size_t* bytes);
+sketchne_status sketchne_orth(sketchne_ctx* ctx, int64_t n, int32_t cols, float* B, int64_t ldb,
+                              void* ws, size_t ws_bytes);
+
+/* Symmetric eigendecomposition of the m x m FP64 matrix A (only its upper
+ * triangle is read) by parallel cyclic Jacobi: A = V diag(w) V^T, pairs
+ * sorted by |w| descending (ties: w descending, then index).  V: m x m
+ * row-major, column j = eigenvector j.  m <= 1024. */
+sketchne_status sketchne_symeig_workspace_size(int32_t m, size_t* bytes);
+sketchne_status sketchne_symeig(sketchne_ctx* ctx, int32_t m, const double* A, double* V, double* w,
+                                void* ws, size_t ws_bytes);
+
+/* Device generators (counter-based SplitMix64, Steele, Lea & Flood 2014).
+ * gauss: n x cols standard normal block (Box-Muller in FP64, stored FP32).
+ * sparse_sign: fills out->rows/signs for an n-row test matrix (Alg. 3). */
+sketchne_status sketchne_gen_gauss(sketchne_ctx* ctx, int64_t n, int32_t cols, uint64_t seed,
+                                   float* out);
+sketchne_status sketchne_gen_sparse_sign(sketchne_ctx* ctx, int64_t n, uint64_t seed,
+                                         sketchne_sparse_sign* out);
+
+/* ---- Per-kernel-class timing (measurement support) --------------------- */
+/* When enabled, every launch of a kernel class is bracketed by HIP events on
+ * the context's stream.  sketchne_profile_read() synchronizes and returns,
+ * per class, the summed milliseconds and the launch count since the last
+ * reset (host arrays of length SKETCHNE_PROF_CLASSES). */
+#define SKETCHNE_PROF_SPMM      0
+#define SKETCHNE_PROF_SKETCH_Y  1
+#define SKETCHNE_PROF_SKETCH_Z  2
+#define SKETCHNE_PROF_GEMM64    3
+#define SKETCHNE_PROF_SMALL     4
+#define SKETCHNE_PROF_PREP      5
+#define SKETCHNE_PROF_CLASSES   6
+sketchne_status sketchne_profile_enable(sketchne_ctx* ctx, int on);
+sketchne_status sketchne_profile_read(sketchne_ctx* ctx, double* ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SKETCHNE_H */

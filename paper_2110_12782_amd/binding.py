@@ -1,0 +1,295 @@
+"""ctypes binding of libsketchne (argument marshalling only).
+
+PyTorch provides device memory and the stream; every step of the method runs
+in the library's HIP kernels.  There is no fallback: if the library or a GPU
+is missing, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsketchne.so")
+
+OK, E_ARG, E_WORKSPACE, E_DEVICE, E_NUMERIC, E_UNSUPPORTED = range(6)
+FP32, BF16, FP16 = 0, 1, 2
+OP_EIG, OP_SKETCH, OP_EMBED, OP_SPMM = 1, 2, 4, 8
+PROF_NAMES = ["spmm", "sketch_y", "sketch_z", "gemm64", "small", "prep"]
+
+EXPORTED = [
+    "sketchne_status_str", "sketchne_create", "sketchne_destroy", "sketchne_set_stream",
+    "sketchne_workspace_size", "sketchne_eig", "sketchne_sketch", "sketchne_embed", "sketchne_sync",
+    "sketchne_spmm", "sketchne_orth_workspace_size", "sketchne_orth", "sketchne_symeig_workspace_size",
+    "sketchne_symeig", "sketchne_gen_gauss", "sketchne_gen_sparse_sign", "sketchne_profile_enable",
+    "sketchne_profile_read",
+]
+
+
+class SketchneError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {msg} (status {status})")
+        self.status = status
+
+
+class Graph(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p), ("colidx", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("alpha", C.c_double), ("T", C.c_int32), ("b", C.c_double),
+        ("k", C.c_int32), ("s_eig", C.c_int32), ("q", C.c_int32),
+        ("d", C.c_int32), ("h", C.c_int32), ("l", C.c_int32), ("z", C.c_int32),
+        ("seed", C.c_uint64), ("precision", C.c_int32), ("split_r", C.c_int32),
+    ]
+
+
+class SparseSign(C.Structure):
+    _fields_ = [("cols", C.c_int32), ("z", C.c_int32), ("rows", C.c_void_p), ("signs", C.c_void_p)]
+
+
+@dataclass
+class SketchParams:
+    """Hyper-parameters (Table 1 notation)."""
+    alpha: float = 0.5
+    T: int = 10
+    b: float = 1.0
+    k: int = 256
+    s_eig: int = 32
+    q: int = 2
+    d: int = 128
+    h: int = 272
+    l: int = 1128
+    z: int = 8
+    seed: int = 1
+    precision: int = FP32
+    split_r: int = 0
+
+    def c(self) -> Params:
+        return Params(self.alpha, self.T, self.b, self.k, self.s_eig, self.q, self.d, self.h, self.l,
+                      self.z, self.seed, self.precision, self.split_r)
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else t.data_ptr()
+
+
+class Library:
+    _inst = None
+
+    @classmethod
+    def get(cls) -> "Library":
+        if cls._inst is None:
+            cls._inst = Library()
+        return cls._inst
+
+    def __init__(self, path: str = LIB_PATH, need_gpu: bool = True):
+        import torch  # noqa: F401  (load torch's HIP runtime first so both share it)
+        if not os.path.exists(path):
+            raise RuntimeError(f"libsketchne not built: {path} is missing (run __graft_entry__.build())")
+        self.lib = C.CDLL(path)
+        L = self.lib
+        L.sketchne_status_str.restype = C.c_char_p
+        L.sketchne_status_str.argtypes = [C.c_int]
+        for name in EXPORTED[1:]:
+            getattr(L, name).restype = C.c_int
+        L.sketchne_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]
+        L.sketchne_destroy.argtypes = [C.c_void_p]
+        L.sketchne_set_stream.argtypes = [C.c_void_p, C.c_void_p]
+        L.sketchne_workspace_size.argtypes = [C.POINTER(Params), C.c_int64, C.c_int64, C.c_int, C.POINTER(C.c_size_t)]
+        L.sketchne_eig.argtypes = [C.c_void_p, C.POINTER(Graph), C.POINTER(Params), C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_size_t]
+        L.sketchne_sketch.argtypes = [C.c_void_p, C.POINTER(Graph), C.POINTER(Params), C.c_void_p, C.c_void_p,
+                                      C.POINTER(SparseSign), C.POINTER(SparseSign), C.c_int, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_size_t]
+        L.sketchne_embed.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p,
+                                     C.POINTER(SparseSign), C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]
+        L.sketchne_sync.argtypes = [C.c_void_p, C.POINTER(C.c_uint32)]
+        L.sketchne_spmm.argtypes = [C.c_void_p, C.POINTER(Graph), C.c_double, C.c_void_p, C.c_int64, C.c_int32,
+                                    C.c_void_p, C.c_int64, C.c_void_p, C.c_size_t]
+        L.sketchne_orth_workspace_size.argtypes = [C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
+        L.sketchne_orth.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
+                                    C.c_size_t]
+        L.sketchne_symeig_workspace_size.argtypes = [C.c_int32, C.POINTER(C.c_size_t)]
+        L.sketchne_symeig.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_size_t]
+        L.sketchne_gen_gauss.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_uint64, C.c_void_p]
+        L.sketchne_gen_sparse_sign.argtypes = [C.c_void_p, C.c_int64, C.c_uint64, C.POINTER(SparseSign)]
+        L.sketchne_profile_enable.argtypes = [C.c_void_p, C.c_int]
+        L.sketchne_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        self._ctx = None
+
+    # ---------------------------------------------------------------- helpers
+    def check(self, st: int, where: str):
+        if st != OK:
+            raise SketchneError(st, where, self.lib.sketchne_status_str(st).decode())
+
+    def workspace_size(self, p: SketchParams, n: int, nnz: int, ops: int) -> int:
+        out = C.c_size_t(0)
+        pc = p.c()
+        self.check(self.lib.sketchne_workspace_size(C.byref(pc), n, nnz, ops, C.byref(out)), "workspace_size")
+        return out.value
+
+    def ctx(self):
+        """The library context bound to cuda:0 and torch's current stream."""
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("sketchne needs a GPU: torch.cuda.is_available() is False")
+        if self._ctx is None:
+            h = C.c_void_p()
+            self.check(self.lib.sketchne_create(C.byref(h), 0, C.c_void_p(torch.cuda.current_stream().cuda_stream)),
+                       "create")
+            self._ctx = h
+        self.lib.sketchne_set_stream(self._ctx, C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        return self._ctx
+
+    @staticmethod
+    def workspace(nbytes: int):
+        import torch
+        return torch.empty(max(nbytes, 256) + 256, dtype=torch.uint8, device="cuda")
+
+    @staticmethod
+    def _aligned(buf):
+        p = buf.data_ptr()
+        return p + ((-p) % 256)
+
+    def sync(self) -> int:
+        f = C.c_uint32(0)
+        st = self.lib.sketchne_sync(self.ctx(), C.byref(f))
+        self.check(st, "sync")
+        return f.value
+
+    # ---------------------------------------------------------------- the path
+    def eig(self, g: "DeviceGraph", p: SketchParams, omega0=None, ws=None):
+        """Alg. 5 on D^-a A D^-a; returns U (n x k float32), lambda (k float64)."""
+        import torch
+        K = p.k + p.s_eig
+        U = torch.empty((g.n, p.k), dtype=torch.float32, device="cuda")
+        lam = torch.empty(p.k, dtype=torch.float64, device="cuda")
+        if omega0 is not None:
+            assert omega0.dtype == torch.float32 and omega0.is_contiguous() and tuple(omega0.shape) == (g.n, K)
+        nb = self.workspace_size(p, g.n, g.nnz, OP_EIG)
+        ws = ws if ws is not None else self.workspace(nb)
+        pc = p.c()
+        gs = g.c()
+        self.check(self.lib.sketchne_eig(self.ctx(), C.byref(gs), C.byref(pc), C.c_void_p(_ptr(omega0)),
+                                         C.c_void_p(U.data_ptr()), C.c_void_p(lam.data_ptr()),
+                                         C.c_void_p(self._aligned(ws)), nb), "eig")
+        return U, lam
+
+    def sketch(self, g: "DeviceGraph", p: SketchParams, U, lam, S=None, O=None, ws=None):
+        """Y (returned transposed, h x n) and Z (l x l).  S, O: (rows, signs)
+        int32/int8 device tensors of shape (cols, z), or None to draw on the
+        device (then they are returned)."""
+        import torch
+        generate = S is None or O is None
+        if generate:
+            S = (torch.empty((p.h, p.z), dtype=torch.int32, device="cuda"),
+                 torch.empty((p.h, p.z), dtype=torch.int8, device="cuda"))
+            O = (torch.empty((p.l, p.z), dtype=torch.int32, device="cuda"),
+                 torch.empty((p.l, p.z), dtype=torch.int8, device="cuda"))
+        Ss = SparseSign(p.h, p.z, S[0].data_ptr(), S[1].data_ptr())
+        Os = SparseSign(p.l, p.z, O[0].data_ptr(), O[1].data_ptr())
+        Yt = torch.empty((p.h, g.n), dtype=torch.float32, device="cuda")
+        Z = torch.empty((p.l, p.l), dtype=torch.float32, device="cuda")
+        nb = self.workspace_size(p, g.n, g.nnz, OP_SKETCH)
+        ws = ws if ws is not None else self.workspace(nb)
+        pc = p.c()
+        gs = g.c()
+        self.check(self.lib.sketchne_sketch(self.ctx(), C.byref(gs), C.byref(pc), C.c_void_p(U.data_ptr()),
+                                            C.c_void_p(lam.data_ptr()), C.byref(Ss), C.byref(Os), int(generate),
+                                            C.c_void_p(Yt.data_ptr()), C.c_void_p(Z.data_ptr()),
+                                            C.c_void_p(self._aligned(ws)), nb), "sketch")
+        return Yt, Z, S, O
+
+    def embed(self, n: int, p: SketchParams, Yt, Z, O, ws=None):
+        """E (n x d float32) and sigma (d float64)."""
+        import torch
+        E = torch.empty((n, p.d), dtype=torch.float32, device="cuda")
+        sig = torch.empty(p.d, dtype=torch.float64, device="cuda")
+        Os = SparseSign(p.l, p.z, O[0].data_ptr(), O[1].data_ptr())
+        nb = self.workspace_size(p, n, 0, OP_EMBED)
+        ws = ws if ws is not None else self.workspace(nb)
+        pc = p.c()
+        self.check(self.lib.sketchne_embed(self.ctx(), C.byref(pc), n, C.c_void_p(Yt.data_ptr()),
+                                           C.c_void_p(Z.data_ptr()), C.byref(Os), C.c_void_p(E.data_ptr()),
+                                           C.c_void_p(sig.data_ptr()), C.c_void_p(self._aligned(ws)), nb), "embed")
+        return E, sig
+
+    # ---------------------------------------------------------------- steps
+    def spmm(self, g: "DeviceGraph", alpha: float, B, out=None):
+        import torch
+        n, cols = B.shape
+        out = out if out is not None else torch.empty_like(B)
+        pp = SketchParams(k=1, s_eig=0, d=1, h=1, l=1, z=1)
+        nb = self.workspace_size(pp, g.n, g.nnz, OP_SPMM)
+        ws = self.workspace(nb)
+        gs = g.c()
+        self.check(self.lib.sketchne_spmm(self.ctx(), C.byref(gs), alpha, C.c_void_p(B.data_ptr()), B.stride(0),
+                                          cols, C.c_void_p(out.data_ptr()), out.stride(0),
+                                          C.c_void_p(self._aligned(ws)), nb), "spmm")
+        return out
+
+    def orth(self, B):
+        n, cols = B.shape
+        nb = C.c_size_t(0)
+        self.check(self.lib.sketchne_orth_workspace_size(n, cols, C.byref(nb)), "orth_workspace_size")
+        ws = self.workspace(nb.value)
+        self.check(self.lib.sketchne_orth(self.ctx(), n, cols, C.c_void_p(B.data_ptr()), B.stride(0),
+                                          C.c_void_p(self._aligned(ws)), nb.value), "orth")
+        return B
+
+    def symeig(self, A):
+        import torch
+        m = A.shape[0]
+        V = torch.empty((m, m), dtype=torch.float64, device="cuda")
+        w = torch.empty(m, dtype=torch.float64, device="cuda")
+        nb = C.c_size_t(0)
+        self.check(self.lib.sketchne_symeig_workspace_size(m, C.byref(nb)), "symeig_workspace_size")
+        ws = self.workspace(nb.value)
+        self.check(self.lib.sketchne_symeig(self.ctx(), m, C.c_void_p(A.data_ptr()), C.c_void_p(V.data_ptr()),
+                                            C.c_void_p(w.data_ptr()), C.c_void_p(self._aligned(ws)), nb.value),
+                   "symeig")
+        return V, w
+
+    def gen_gauss(self, n: int, cols: int, seed: int):
+        import torch
+        out = torch.empty((n, cols), dtype=torch.float32, device="cuda")
+        self.check(self.lib.sketchne_gen_gauss(self.ctx(), n, cols, seed, C.c_void_p(out.data_ptr())), "gen_gauss")
+        return out
+
+    def gen_sparse_sign(self, n: int, cols: int, z: int, seed: int):
+        import torch
+        rows = torch.empty((cols, z), dtype=torch.int32, device="cuda")
+        signs = torch.empty((cols, z), dtype=torch.int8, device="cuda")
+        s = SparseSign(cols, z, rows.data_ptr(), signs.data_ptr())
+        self.check(self.lib.sketchne_gen_sparse_sign(self.ctx(), n, seed, C.byref(s)), "gen_sparse_sign")
+        return rows, signs
+
+    def profile_enable(self, on: bool):
+        self.check(self.lib.sketchne_profile_enable(self.ctx(), int(on)), "profile_enable")
+
+    def profile_read(self) -> dict:
+        ms = (C.c_double * 6)()
+        n = (C.c_int64 * 6)()
+        self.check(self.lib.sketchne_profile_read(self.ctx(), ms, n), "profile_read")
+        return {PROF_NAMES[i]: (ms[i], n[i]) for i in range(6)}
+
+
+class DeviceGraph:
+    """CSR arrays resident on cuda:0 (rowptr int64, colidx int32)."""
+
+    def __init__(self, rowptr: np.ndarray, colidx: np.ndarray):
+        import torch
+        self.n = len(rowptr) - 1
+        self.nnz = int(rowptr[-1])
+        self.rowptr = torch.from_numpy(np.ascontiguousarray(rowptr, dtype=np.int64)).cuda()
+        cols = np.ascontiguousarray(colidx, dtype=np.int32)
+        self.colidx = torch.from_numpy(cols if len(cols) else np.zeros(1, np.int32)).cuda()
+
+    def c(self) -> Graph:
+        return Graph(self.n, self.nnz, self.rowptr.data_ptr(), self.colidx.data_ptr())

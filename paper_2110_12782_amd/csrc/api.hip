@@ -1,0 +1,703 @@
+// Host side of the C ABI: argument validation, workspace carving and the
+// orchestration of the three calls of the path (Alg. 6 lines 1-5).
+#include <math.h>
+#include <initializer_list>
+#include <new>
+#include <string.h>
+
+#include "internal.h"
+#include "sketch.h"
+
+using namespace skne;
+
+namespace {
+
+#define SK_TRY(expr)                                   \
+  do {                                                 \
+    sketchne_status _st = (expr);                      \
+    if (_st != SKETCHNE_OK) return _st;                \
+  } while (0)
+
+__global__ void k_symmetrize(int m, const double* __restrict__ A, double* __restrict__ S) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * m) return;
+  int i = idx / m, j = idx % m;
+  S[idx] = 0.5 * (A[idx] + A[j * m + i]);
+}
+
+// Map[i][j] = V[i][j] * sqrt(|w_j|) (j < d), sigma[j] = |w_j|
+__global__ void k_embed_map(int h, int d, const double* __restrict__ V, const double* __restrict__ w,
+                            double* __restrict__ Map, double* __restrict__ sigma) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < d) sigma[idx] = fabs(w[idx]);
+  if (idx >= h * d) return;
+  int i = idx / d, j = idx % d;
+  Map[idx] = V[i * h + j] * sqrt(fabs(w[j]));
+}
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & (kAlign - 1)) == 0; }
+
+// ------------------------------------------------------------- orthonormalise
+// Cholesky-QR twice with FP64 Gram and Cholesky.  The tall matrix is either
+// row-major n x m (element (i,j) at X[i*ld + j]) or "transposed" m x n
+// (element (i,j) at Xt[j*ld + i]); src -> tmp -> dst, src may equal dst.
+struct OrthWs {
+  double* partial;
+  size_t partial_cap;
+  double* G;
+  double* RinvT;
+  double* cwork;
+};
+
+GemmDesc gram_desc(int64_t n, int m, const float* X, int64_t ld, bool transposed, double* G) {
+  GemmDesc g;
+  g.M = m; g.N = m; g.K = n;
+  g.A = X; g.ta = Ty::F32;
+  g.B = X; g.tb = Ty::F32;
+  if (!transposed) { g.sai = 1; g.sak = ld; g.sbk = ld; g.sbj = 1; }
+  else { g.sai = ld; g.sak = 1; g.sbk = 1; g.sbj = ld; }
+  g.C = G; g.tc = Ty::F64; g.sci = m; g.scj = 1;
+  g.upper_only = true;
+  return g;
+}
+
+GemmDesc apply_desc(int64_t n, int m, const float* X, int64_t ld, bool transposed, const double* RinvT, float* out) {
+  GemmDesc g;
+  if (!transposed) {  // out (n x m) = X (n x m) * R^-1 ;  R^-1 (k, j) = RinvT[j][k]
+    g.M = n; g.N = m; g.K = m;
+    g.A = X; g.ta = Ty::F32; g.sai = ld; g.sak = 1;
+    g.B = RinvT; g.tb = Ty::F64; g.sbk = 1; g.sbj = m;
+    g.C = out; g.tc = Ty::F32; g.sci = ld; g.scj = 1;
+  } else {            // out^T (m x n) = R^-T (m x m) * X^T (m x n)
+    g.M = m; g.N = n; g.K = m;
+    g.A = RinvT; g.ta = Ty::F64; g.sai = m; g.sak = 1;
+    g.B = X; g.tb = Ty::F32; g.sbk = ld; g.sbj = 1;
+    g.C = out; g.tc = Ty::F32; g.sci = ld; g.scj = 1;
+  }
+  return g;
+}
+
+size_t max_bytes(std::initializer_list<size_t> v) {
+  size_t m = 0;
+  for (size_t x : v) m = x > m ? x : m;
+  return m;
+}
+
+size_t orth_partial_bytes(int64_t n, int m, bool transposed) {
+  GemmDesc g = gram_desc(n, m, nullptr, transposed ? n : m, transposed, nullptr);
+  GemmDesc a = apply_desc(n, m, nullptr, transposed ? n : m, transposed, nullptr, nullptr);
+  return max_bytes({gemm64_partial_bytes(g.M, g.N, g.K, g.upper_only),
+                    gemm64_partial_bytes(a.M, a.N, a.K, a.upper_only)});
+}
+
+OrthWs carve_orth(Arena& ar, int64_t n, int m, bool transposed) {
+  OrthWs w;
+  w.partial_cap = orth_partial_bytes(n, m, transposed);
+  w.partial = ar.take<double>(w.partial_cap / sizeof(double) + 1);
+  w.G = ar.take<double>((size_t)m * m);
+  w.RinvT = ar.take<double>((size_t)m * m);
+  w.cwork = ar.take<double>(chol_ws_bytes(m) / sizeof(double) + 1);
+  return w;
+}
+
+sketchne_status orth_pass(sketchne_ctx* c, int64_t n, int m, const float* src, float* dst, int64_t ld,
+                          bool transposed, const OrthWs& w) {
+  GemmDesc g = gram_desc(n, m, src, ld, transposed, w.G);
+  SK_TRY(gemm64(c, g, w.partial, w.partial_cap));
+  SK_TRY(chol_inv(c, m, w.G, w.RinvT, w.cwork));
+  GemmDesc a = apply_desc(n, m, src, ld, transposed, w.RinvT, dst);
+  return gemm64(c, a, w.partial, w.partial_cap);
+}
+
+sketchne_status orth2(sketchne_ctx* c, int64_t n, int m, const float* src, float* tmp, float* dst, int64_t ld,
+                      bool transposed, const OrthWs& w) {
+  SK_TRY(orth_pass(c, n, m, src, tmp, ld, transposed, w));
+  return orth_pass(c, n, m, tmp, dst, ld, transposed, w);
+}
+
+// ------------------------------------------------------------- validation
+sketchne_status check_params(const sketchne_params* p, int64_t n) {
+  if (!p) return SKETCHNE_E_ARG;
+  if (!(p->alpha > 0.0 && p->alpha <= 0.5)) return SKETCHNE_E_ARG;
+  if (p->T < 1 || !(p->b > 0.0)) return SKETCHNE_E_ARG;
+  if (p->k < 1 || p->s_eig < 0 || p->q < 0) return SKETCHNE_E_ARG;
+  int64_t K = (int64_t)p->k + p->s_eig;
+  if (K > n) return SKETCHNE_E_ARG;
+  if (p->d < 1 || p->h < p->d || p->l < p->h) return SKETCHNE_E_ARG;
+  if (p->z < 1 || p->z > n) return SKETCHNE_E_ARG;
+  if (p->precision < 0 || p->precision > 2) return SKETCHNE_E_ARG;
+  if (p->split_r < 0 || p->split_r > p->k) return SKETCHNE_E_ARG;
+  return SKETCHNE_OK;
+}
+
+sketchne_status check_graph(const sketchne_graph* A) {
+  if (!A || A->n < 1 || A->nnz < 0 || !A->rowptr || (A->nnz > 0 && !A->colidx)) return SKETCHNE_E_ARG;
+  if (A->n >= (int64_t)1 << 31) return SKETCHNE_E_UNSUPPORTED;
+  return SKETCHNE_OK;
+}
+
+// ------------------------------------------------------------- eig
+struct EigWs {
+  float* dscale;
+  float* Q;
+  float* P1;
+  float* P2;
+  float* spmm_part;
+  OrthWs ow;
+  double* Hfull;
+  double* H;
+  double* Vh;
+  double* wv;
+  double* rr_partial;
+  size_t rr_cap;
+  void* symws;
+};
+
+EigWs carve_eig(Arena& ar, const sketchne_params* p, int64_t n, int64_t nnz) {
+  const int K = p->k + p->s_eig;
+  EigWs w;
+  w.dscale = ar.take<float>(n);
+  w.Q = ar.take<float>((size_t)n * K);
+  w.P1 = ar.take<float>((size_t)n * K);
+  w.P2 = ar.take<float>((size_t)n * K);
+  w.spmm_part = ar.take<float>(spmm_ws_bytes(nnz, K) / sizeof(float) + 1);
+  w.ow = carve_orth(ar, n, K, false);
+  w.Hfull = ar.take<double>((size_t)K * K);
+  w.H = ar.take<double>((size_t)K * K);
+  w.Vh = ar.take<double>((size_t)K * K);
+  w.wv = ar.take<double>(K);
+  w.rr_cap = max_bytes({gemm64_partial_bytes(K, K, n, false), gemm64_partial_bytes(n, p->k, K, false)});
+  w.rr_partial = ar.take<double>(w.rr_cap / sizeof(double) + 1);
+  w.symws = ar.take<char>(symeig_ws_bytes(K));
+  return w;
+}
+
+// ------------------------------------------------------------- sketch
+struct SketchGeo {
+  int prec, r, KS, ntS, ntO, FB;
+  int64_t nvt_pad, nvtO_pad, zl;
+};
+
+SketchGeo sketch_geo(const sketchne_params* p, int64_t n) {
+  SketchGeo g;
+  g.prec = p->precision;
+  g.r = g.prec == SKETCHNE_FP32 ? 0 : p->split_r;
+  const int kstep = sketch_kstep(g.prec);
+  g.KS = sketch_ks_supported(g.prec, (p->k + 2 * g.r + kstep - 1) / kstep);
+  g.FB = sketch_frag_bytes(g.prec);
+  g.ntS = (p->h + 3) / 4;
+  g.ntO = (p->l + 3) / 4;
+  const int wg_tiles = 4 * sketch_vt(g.prec);
+  int64_t nvt = (n + 31) / 32;
+  g.nvt_pad = (nvt + wg_tiles - 1) / wg_tiles * wg_tiles;
+  g.zl = (int64_t)p->z * p->l;
+  int64_t nvtO = (g.zl + 31) / 32;
+  g.nvtO_pad = (nvtO + wg_tiles - 1) / wg_tiles * wg_tiles;
+  return g;
+}
+
+struct SketchWs {
+  double* d1;
+  double* d2;
+  double* Kmat;
+  double* Sa;
+  double* Sb;
+  double* Cc;
+  double* k_partial;
+  size_t k_cap;
+  double* Gsel;
+  double* RtT;
+  void* ApS;
+  void* ApO;
+  float* sgnS;
+  float* sgnO;
+  void* Bp;
+  float* T1t;
+};
+
+SketchWs carve_sketch(Arena& ar, const sketchne_params* p, int64_t n) {
+  SketchGeo g = sketch_geo(p, n);
+  const int k = p->k;
+  SketchWs w;
+  w.d1 = ar.take<double>(n);
+  w.d2 = ar.take<double>(n);
+  w.Kmat = ar.take<double>((size_t)k * k);
+  w.Sa = ar.take<double>((size_t)k * k);
+  w.Sb = ar.take<double>((size_t)k * k);
+  w.Cc = ar.take<double>((size_t)k * k);
+  int ntmax = g.ntS > g.ntO ? g.ntS : g.ntO;
+  w.k_cap = max_bytes({gemm64_partial_bytes(k, k, n, false), gemm64_partial_bytes(k, k, k, false),
+                       gemm64_partial_bytes((int64_t)g.ntS * 32, k, k, false),
+                       gemm64_partial_bytes((int64_t)g.ntO * 32, k, k, false)});
+  w.k_partial = ar.take<double>(w.k_cap / sizeof(double) + 1);
+  w.Gsel = ar.take<double>((size_t)ntmax * 32 * k);
+  w.RtT = ar.take<double>((size_t)ntmax * 32 * k);
+  w.ApS = ar.take<char>((size_t)g.ntS * g.KS * 64 * g.FB);
+  w.ApO = ar.take<char>((size_t)g.ntO * g.KS * 64 * g.FB);
+  w.sgnS = ar.take<float>((size_t)g.ntS * 32);
+  w.sgnO = ar.take<float>((size_t)g.ntO * 32);
+  int64_t nvtmax = g.nvt_pad > g.nvtO_pad ? g.nvt_pad : g.nvtO_pad;
+  w.Bp = ar.take<char>((size_t)nvtmax * g.KS * 64 * g.FB);
+  w.T1t = ar.take<float>((size_t)p->l * g.zl);
+  return w;
+}
+
+// ------------------------------------------------------------- embed
+struct EmbedWs {
+  float* Q1;
+  float* Q2;
+  OrthWs ow;
+  double* Bm;
+  double* Bq1;
+  double* Bq;
+  double* Gb;
+  double* Rb1;
+  double* Rb2;
+  double* cwork;
+  double* Rinv;
+  double* M1;
+  double* M2;
+  double* M3;
+  double* W;
+  double* Vw;
+  double* ww;
+  double* Map;
+  double* s_partial;
+  size_t s_cap;
+  void* symws;
+};
+
+EmbedWs carve_embed(Arena& ar, const sketchne_params* p, int64_t n) {
+  const int h = p->h, l = p->l, d = p->d;
+  EmbedWs w;
+  w.Q1 = ar.take<float>((size_t)h * n);
+  w.Q2 = ar.take<float>((size_t)h * n);
+  w.ow = carve_orth(ar, n, h, true);
+  w.Bm = ar.take<double>((size_t)l * h);
+  w.Bq1 = ar.take<double>((size_t)l * h);
+  w.Bq = ar.take<double>((size_t)l * h);
+  w.Gb = ar.take<double>((size_t)h * h);
+  w.Rb1 = ar.take<double>((size_t)h * h);
+  w.Rb2 = ar.take<double>((size_t)h * h);
+  w.cwork = ar.take<double>(chol_ws_bytes(h) / sizeof(double) + 1);
+  w.Rinv = ar.take<double>((size_t)h * h);
+  w.M1 = ar.take<double>((size_t)h * l);
+  w.M2 = ar.take<double>((size_t)h * h);
+  w.M3 = ar.take<double>((size_t)h * h);
+  w.W = ar.take<double>((size_t)h * h);
+  w.Vw = ar.take<double>((size_t)h * h);
+  w.ww = ar.take<double>(h);
+  w.Map = ar.take<double>((size_t)h * d);
+  // the largest split-K partial of the small products and of E = Q Map
+  w.s_cap = max_bytes({gemm64_partial_bytes(h, h, l, true), gemm64_partial_bytes(l, h, h, false),
+                       gemm64_partial_bytes(h, h, h, false), gemm64_partial_bytes(h, l, l, false),
+                       gemm64_partial_bytes(h, h, l, false), gemm64_partial_bytes(n, d, h, false)});
+  w.s_partial = ar.take<double>(w.s_cap / sizeof(double) + 1);
+  w.symws = ar.take<char>(symeig_ws_bytes(h));
+  return w;
+}
+
+size_t op_bytes(const sketchne_params* p, int64_t n, int64_t nnz, int mask) {
+  size_t best = 0;
+  if (mask & SKETCHNE_OP_EIG) { Arena a(nullptr, 0); carve_eig(a, p, n, nnz); best = a.off > best ? a.off : best; }
+  if (mask & SKETCHNE_OP_SKETCH) { Arena a(nullptr, 0); carve_sketch(a, p, n); best = a.off > best ? a.off : best; }
+  if (mask & SKETCHNE_OP_EMBED) { Arena a(nullptr, 0); carve_embed(a, p, n); best = a.off > best ? a.off : best; }
+  if (mask & SKETCHNE_OP_SPMM) {
+    size_t s = align_up(sizeof(float) * n) + spmm_ws_bytes(nnz, 512);
+    best = s > best ? s : best;
+  }
+  return best;
+}
+
+sketchne_status check_ws(void* ws, size_t ws_bytes, size_t need) {
+  if (need == 0) return SKETCHNE_OK;
+  if (!ws || ws_bytes < need || !aligned(ws)) return SKETCHNE_E_WORKSPACE;
+  return SKETCHNE_OK;
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+
+extern "C" {
+
+const char* sketchne_status_str(sketchne_status s) {
+  switch (s) {
+    case SKETCHNE_OK: return "ok";
+    case SKETCHNE_E_ARG: return "invalid argument";
+    case SKETCHNE_E_WORKSPACE: return "workspace missing, too small or misaligned";
+    case SKETCHNE_E_DEVICE: return "HIP device or launch error";
+    case SKETCHNE_E_NUMERIC: return "numerical breakdown on the device";
+    case SKETCHNE_E_UNSUPPORTED: return "unsupported size or option";
+  }
+  return "unknown status";
+}
+
+sketchne_status sketchne_create(sketchne_ctx** out, int device, void* stream) {
+  if (!out) return SKETCHNE_E_ARG;
+  *out = nullptr;
+  sketchne_ctx* c = new (std::nothrow) sketchne_ctx();
+  if (!c) return SKETCHNE_E_DEVICE;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(device) != hipSuccess) { delete c; return SKETCHNE_E_DEVICE; }
+  if (hipMalloc(&c->d_flags, sizeof(uint32_t)) != hipSuccess) { delete c; return SKETCHNE_E_DEVICE; }
+  if (hipHostMalloc(&c->h_flags, sizeof(uint32_t) + sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
+    hipFree(c->d_flags);
+    delete c;
+    return SKETCHNE_E_DEVICE;
+  }
+  c->h_counter = reinterpret_cast<int*>(c->h_flags + 1);
+  hipMemset(c->d_flags, 0, sizeof(uint32_t));
+  for (int i = 0; i < sketchne_ctx::kMaxEvents; ++i) hipEventCreate(&c->ev[i]);
+  *out = c;
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_destroy(sketchne_ctx* c) {
+  if (!c) return SKETCHNE_E_ARG;
+  hipStreamSynchronize(c->stream);
+  for (int i = 0; i < sketchne_ctx::kMaxEvents; ++i) hipEventDestroy(c->ev[i]);
+  hipFree(c->d_flags);
+  hipHostFree(c->h_flags);
+  delete c;
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_set_stream(sketchne_ctx* c, void* stream) {
+  if (!c) return SKETCHNE_E_ARG;
+  c->stream = static_cast<hipStream_t>(stream);
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_workspace_size(const sketchne_params* p, int64_t n, int64_t nnz, int op_mask,
+                                        size_t* bytes) {
+  if (!bytes || n < 1 || nnz < 0) return SKETCHNE_E_ARG;
+  SK_TRY(check_params(p, n));
+  *bytes = op_bytes(p, n, nnz, op_mask);
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_eig(sketchne_ctx* c, const sketchne_graph* A, const sketchne_params* p,
+                             const float* omega0, float* U, double* lambda, void* ws, size_t ws_bytes) {
+  if (!c || !U || !lambda) return SKETCHNE_E_ARG;
+  SK_TRY(check_graph(A));
+  SK_TRY(check_params(p, A->n));
+  const int K = p->k + p->s_eig;
+  if (K > 512) return SKETCHNE_E_UNSUPPORTED;
+  if (K % 4) return SKETCHNE_E_UNSUPPORTED;  // row length of the SpMM float4 path
+  SK_TRY(check_ws(ws, ws_bytes, op_bytes(p, A->n, A->nnz, SKETCHNE_OP_EIG)));
+  const int64_t n = A->n;
+  Arena ar(ws, ws_bytes);
+  EigWs w = carve_eig(ar, p, n, A->nnz);
+  if (ar.overflow) return SKETCHNE_E_WORKSPACE;
+
+  SK_TRY(degree_scale(c, n, A->rowptr, p->alpha, w.dscale));
+  const float* start = omega0;
+  if (!start) {
+    SK_TRY(gen_gauss(c, n, K, K, p->seed, w.Q));
+    start = w.Q;
+  }
+  // line 4-5: Y = X Omega, Q = orth(Y)
+  SK_TRY(spmm(c, n, A->nnz, A->rowptr, A->colidx, w.dscale, start, K, K, w.P1, K, w.spmm_part));
+  SK_TRY(orth2(c, n, K, w.P1, w.P2, w.Q, K, false, w.ow));
+  // lines 6-8: q times Q = orth(X (X Q))
+  for (int it = 0; it < p->q; ++it) {
+    SK_TRY(spmm(c, n, A->nnz, A->rowptr, A->colidx, w.dscale, w.Q, K, K, w.P1, K, w.spmm_part));
+    SK_TRY(spmm(c, n, A->nnz, A->rowptr, A->colidx, w.dscale, w.P1, K, K, w.P2, K, w.spmm_part));
+    SK_TRY(orth2(c, n, K, w.P2, w.P1, w.Q, K, false, w.ow));
+  }
+  // line 9: H = Q^T X Q
+  SK_TRY(spmm(c, n, A->nnz, A->rowptr, A->colidx, w.dscale, w.Q, K, K, w.P1, K, w.spmm_part));
+  {
+    GemmDesc g;
+    g.M = K; g.N = K; g.K = n;
+    g.A = w.Q; g.ta = Ty::F32; g.sai = 1; g.sak = K;
+    g.B = w.P1; g.tb = Ty::F32; g.sbk = K; g.sbj = 1;
+    g.C = w.Hfull; g.tc = Ty::F64; g.sci = K; g.scj = 1;
+    SK_TRY(gemm64(c, g, w.rr_partial, w.rr_cap));
+    hipLaunchKernelGGL(k_symmetrize, dim3((K * K + 255) / 256), dim3(256), 0, c->stream, K, w.Hfull, w.H);
+    SK_TRY(launch_status());
+  }
+  // line 10: eigendecomposition, sorted by |lambda|
+  SK_TRY(symeig(c, K, w.H, w.Vh, w.wv, w.symws));
+  // line 11: U = Q U^(:, 1:k)
+  {
+    GemmDesc g;
+    g.M = n; g.N = p->k; g.K = K;
+    g.A = w.Q; g.ta = Ty::F32; g.sai = K; g.sak = 1;
+    g.B = w.Vh; g.tb = Ty::F64; g.sbk = K; g.sbj = 1;
+    g.C = U; g.tc = Ty::F32; g.sci = p->k; g.scj = 1;
+    SK_TRY(gemm64(c, g, w.rr_partial, w.rr_cap));
+  }
+  if (hipMemcpyAsync(lambda, w.wv, sizeof(double) * p->k, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return SKETCHNE_E_DEVICE;
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_sketch(sketchne_ctx* c, const sketchne_graph* A, const sketchne_params* p,
+                                const float* U, const double* lambda, sketchne_sparse_sign* S,
+                                sketchne_sparse_sign* O, int generate, float* Yt, float* Z, void* ws,
+                                size_t ws_bytes) {
+  if (!c || !U || !lambda || !S || !O || !Yt || !Z) return SKETCHNE_E_ARG;
+  SK_TRY(check_graph(A));
+  SK_TRY(check_params(p, A->n));
+  if (S->cols != p->h || O->cols != p->l || S->z != p->z || O->z != p->z) return SKETCHNE_E_ARG;
+  if (!S->rows || !S->signs || !O->rows || !O->signs) return SKETCHNE_E_ARG;
+  if (p->z > 8) return SKETCHNE_E_UNSUPPORTED;  // group of one lane's accumulators
+  SketchGeo g = sketch_geo(p, A->n);
+  if (g.KS == 0) return SKETCHNE_E_UNSUPPORTED;
+  if (g.zl >= ((int64_t)1 << 31)) return SKETCHNE_E_UNSUPPORTED;
+  SK_TRY(check_ws(ws, ws_bytes, op_bytes(p, A->n, A->nnz, SKETCHNE_OP_SKETCH)));
+  const int64_t n = A->n;
+  const int k = p->k;
+  Arena ar(ws, ws_bytes);
+  SketchWs w = carve_sketch(ar, p, n);
+  if (ar.overflow) return SKETCHNE_E_WORKSPACE;
+
+  if (generate) {
+    SK_TRY(gen_sparse_sign(c, n, p->h, p->z, p->seed ^ 0x5555555555555555ULL, S->rows, S->signs));
+    SK_TRY(gen_sparse_sign(c, n, p->l, p->z, p->seed ^ 0xaaaaaaaaaaaaaaaaULL, O->rows, O->signs));
+  }
+  SK_TRY(degree_powers(c, n, A->rowptr, p->alpha, w.d1, w.d2));
+  // Alg. 6 line 2: K = U^T D^(-1+2a) U Lambda
+  {
+    GemmDesc gd;
+    gd.M = k; gd.N = k; gd.K = n;
+    gd.A = U; gd.ta = Ty::F32; gd.sai = 1; gd.sak = k;
+    gd.B = U; gd.tb = Ty::F32; gd.sbk = k; gd.sbj = 1;
+    gd.C = w.Kmat; gd.tc = Ty::F64; gd.sci = k; gd.scj = 1;
+    gd.kw = w.d2;
+    SK_TRY(gemm64(c, gd, w.k_partial, w.k_cap));
+    SK_TRY(scale_cols(c, k, k, w.Kmat, lambda));
+  }
+  // Alg. 6 line 3: sum_{r=1..T} K^(r-1) by Horner, C = Lambda * sum
+  SK_TRY(identity(c, k, w.Sa));
+  double* cur = w.Sa;
+  double* nxt = w.Sb;
+  for (int r = 1; r < p->T; ++r) {
+    GemmDesc gd;
+    gd.M = k; gd.N = k; gd.K = k;
+    gd.A = w.Kmat; gd.ta = Ty::F64; gd.sai = k; gd.sak = 1;
+    gd.B = cur; gd.tb = Ty::F64; gd.sbk = k; gd.sbj = 1;
+    gd.C = nxt; gd.tc = Ty::F64; gd.sci = k; gd.scj = 1;
+    gd.diag_add = 1.0;
+    SK_TRY(gemm64(c, gd, w.k_partial, w.k_cap));
+    double* t = cur; cur = nxt; nxt = t;
+  }
+  SK_TRY(scale_rows(c, k, k, cur, lambda, w.Cc));
+
+  const double vol = (double)A->nnz;
+  const double scale = vol / (p->b * p->T);
+  const float ln2 = 0.69314718055994530942f;
+  const float inv_sqrt_z = (float)(1.0 / sqrt((double)p->z));
+
+  // expanded columns R~^T = scale * D1(p) U(p,:) C^T  for one test matrix
+  auto build_A = [&](const sketchne_sparse_sign* T, int ntiles, int groups, void* Ap, float* sgn) -> sketchne_status {
+    SK_TRY(gather_expanded(c, n, ntiles, groups, p->z, T->rows, U, k, k, w.d1, scale, w.Gsel));
+    GemmDesc gd;
+    gd.M = (int64_t)ntiles * 32; gd.N = k; gd.K = k;
+    gd.A = w.Gsel; gd.ta = Ty::F64; gd.sai = k; gd.sak = 1;
+    gd.B = w.Cc; gd.tb = Ty::F64; gd.sbk = 1; gd.sbj = k;
+    gd.C = w.RtT; gd.tc = Ty::F64; gd.sci = k; gd.scj = 1;
+    SK_TRY(gemm64(c, gd, w.k_partial, w.k_cap));
+    SK_TRY(pack_A(c, g.prec, ntiles, g.KS, k, g.r, w.RtT, Ap));
+    return pack_signs(c, ntiles, groups, p->z, T->signs, sgn);
+  };
+
+  // Alg. 4 line 4: Y = f(L' R'(:, p)) S(p, :)
+  SK_TRY(build_A(S, g.ntS, p->h, w.ApS, w.sgnS));
+  SK_TRY(pack_B(c, g.prec, n, n, g.nvt_pad, g.KS, k, g.r, nullptr, U, k, w.d1, w.Bp));
+  SK_TRY(fused_sketch(c, SKETCHNE_PROF_SKETCH_Y, g.prec, n, p->h, g.ntS, g.KS, w.Bp, w.ApS, w.sgnS, Yt, n,
+                      ln2 * inv_sqrt_z));
+  // Alg. 4 line 7: Z = O(p,:)^T f(L'(p,:) R'(:, p)) O(p,:)
+  SK_TRY(build_A(O, g.ntO, p->l, w.ApO, w.sgnO));
+  SK_TRY(pack_B(c, g.prec, n, g.zl, g.nvtO_pad, g.KS, k, g.r, O->rows, U, k, w.d1, w.Bp));
+  SK_TRY(fused_sketch(c, SKETCHNE_PROF_SKETCH_Z, g.prec, g.zl, p->l, g.ntO, g.KS, w.Bp, w.ApO, w.sgnO, w.T1t, g.zl,
+                      ln2 * inv_sqrt_z));
+  SK_TRY(z_reduce(c, p->l, p->z, O->signs, w.T1t, g.zl, inv_sqrt_z, Z));
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_embed(sketchne_ctx* c, const sketchne_params* p, int64_t n, const float* Yt,
+                               const float* Z, const sketchne_sparse_sign* O, float* E, double* sigma, void* ws,
+                               size_t ws_bytes) {
+  if (!c || !Yt || !Z || !O || !E || !sigma || n < 1) return SKETCHNE_E_ARG;
+  SK_TRY(check_params(p, n));
+  if (O->cols != p->l || O->z != p->z || !O->rows || !O->signs) return SKETCHNE_E_ARG;
+  if (p->h > 512) return SKETCHNE_E_UNSUPPORTED;
+  if (p->h > n) return SKETCHNE_E_ARG;
+  SK_TRY(check_ws(ws, ws_bytes, op_bytes(p, n, 0, SKETCHNE_OP_EMBED)));
+  const int h = p->h, l = p->l, d = p->d;
+  Arena ar(ws, ws_bytes);
+  EmbedWs w = carve_embed(ar, p, n);
+  if (ar.overflow) return SKETCHNE_E_WORKSPACE;
+
+  // Alg. 4 line 5: Q = orth(Y), Y held transposed (h x n)
+  SK_TRY(orth2(c, n, h, Yt, w.Q1, w.Q2, n, true, w.ow));
+  const float* Qt = w.Q2;
+  // B = O^T Q (l x h)
+  SK_TRY(ot_q(c, l, p->z, h, O->rows, O->signs, Qt, n, 1.0 / sqrt((double)p->z), w.Bm));
+  // QR of B by Cholesky-QR twice in FP64: B = Bq R, R^-1 = R1^-1 R2^-1
+  auto small = [&](int64_t M, int64_t N, int64_t K, const void* Ap, Ty ta, int64_t sai, int64_t sak, const void* Bp,
+                   Ty tb, int64_t sbk, int64_t sbj, double* C, bool upper) -> sketchne_status {
+    GemmDesc gd;
+    gd.M = M; gd.N = N; gd.K = K;
+    gd.A = Ap; gd.ta = ta; gd.sai = sai; gd.sak = sak;
+    gd.B = Bp; gd.tb = tb; gd.sbk = sbk; gd.sbj = sbj;
+    gd.C = C; gd.tc = Ty::F64; gd.sci = N; gd.scj = 1;
+    gd.upper_only = upper;
+    return gemm64(c, gd, w.s_partial, w.s_cap);
+  };
+  SK_TRY(small(h, h, l, w.Bm, Ty::F64, 1, h, w.Bm, Ty::F64, h, 1, w.Gb, true));
+  SK_TRY(chol_inv(c, h, w.Gb, w.Rb1, w.cwork));
+  SK_TRY(small(l, h, h, w.Bm, Ty::F64, h, 1, w.Rb1, Ty::F64, 1, h, w.Bq1, false));
+  SK_TRY(small(h, h, l, w.Bq1, Ty::F64, 1, h, w.Bq1, Ty::F64, h, 1, w.Gb, true));
+  SK_TRY(chol_inv(c, h, w.Gb, w.Rb2, w.cwork));
+  SK_TRY(small(l, h, h, w.Bq1, Ty::F64, h, 1, w.Rb2, Ty::F64, 1, h, w.Bq, false));
+  // Rinv = R1^-1 R2^-1, with R^-1(i, j) = RinvT[j][i]
+  SK_TRY(small(h, h, h, w.Rb1, Ty::F64, 1, h, w.Rb2, Ty::F64, 1, h, w.Rinv, false));
+  // W = Rinv (Bq^T Z Bq) Rinv^T  (Alg. 4 line 8, two least-squares solves)
+  SK_TRY(small(h, l, l, w.Bq, Ty::F64, 1, h, Z, Ty::F32, l, 1, w.M1, false));
+  SK_TRY(small(h, h, l, w.M1, Ty::F64, l, 1, w.Bq, Ty::F64, h, 1, w.M2, false));
+  SK_TRY(small(h, h, h, w.Rinv, Ty::F64, h, 1, w.M2, Ty::F64, h, 1, w.M3, false));
+  SK_TRY(small(h, h, h, w.M3, Ty::F64, h, 1, w.Rinv, Ty::F64, 1, h, w.W, false));
+  hipLaunchKernelGGL(k_symmetrize, dim3((h * h + 255) / 256), dim3(256), 0, c->stream, h, w.W, w.M2);
+  SK_TRY(launch_status());
+  // Alg. 4 line 9: SVD of the symmetric W from its eigendecomposition
+  SK_TRY(symeig(c, h, w.M2, w.Vw, w.ww, w.symws));
+  hipLaunchKernelGGL(k_embed_map, dim3((h * d + 255) / 256), dim3(256), 0, c->stream, h, d, w.Vw, w.ww, w.Map,
+                     sigma);
+  SK_TRY(launch_status());
+  // Alg. 4 line 10 and Alg. 6 line 5: E = Q U^(:, 1:d) Sigma^(1/2)
+  {
+    GemmDesc gd;
+    gd.M = n; gd.N = d; gd.K = h;
+    gd.A = Qt; gd.ta = Ty::F32; gd.sai = 1; gd.sak = n;
+    gd.B = w.Map; gd.tb = Ty::F64; gd.sbk = d; gd.sbj = 1;
+    gd.C = E; gd.tc = Ty::F32; gd.sci = d; gd.scj = 1;
+    SK_TRY(gemm64(c, gd, w.s_partial, w.s_cap));
+  }
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_sync(sketchne_ctx* c, uint32_t* flags) {
+  if (!c) return SKETCHNE_E_ARG;
+  if (hipMemcpyAsync(c->h_flags, c->d_flags, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return SKETCHNE_E_DEVICE;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return SKETCHNE_E_DEVICE;
+  uint32_t f = *c->h_flags;
+  if (f) hipMemsetAsync(c->d_flags, 0, sizeof(uint32_t), c->stream);
+  if (flags) *flags = f;
+  if (f & SKETCHNE_FLAG_BAD_INDEX) return SKETCHNE_E_ARG;
+  if (f & (SKETCHNE_FLAG_CHOL_FAIL | SKETCHNE_FLAG_EIG_NOCONV | SKETCHNE_FLAG_NONFINITE)) return SKETCHNE_E_NUMERIC;
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_spmm(sketchne_ctx* c, const sketchne_graph* A, double alpha, const float* B, int64_t ldb,
+                              int32_t cols, float* C, int64_t ldc, void* ws, size_t ws_bytes) {
+  if (!c || !B || !C) return SKETCHNE_E_ARG;
+  SK_TRY(check_graph(A));
+  if (!(alpha > 0.0 && alpha <= 0.5)) return SKETCHNE_E_ARG;
+  if (cols < 0 || cols % 4 || cols > 512 || ldb < cols || ldc < cols || ldb % 4 || ldc % 4) return SKETCHNE_E_ARG;
+  size_t need = align_up(sizeof(float) * A->n) + spmm_ws_bytes(A->nnz, cols);
+  SK_TRY(check_ws(ws, ws_bytes, need));
+  Arena ar(ws, ws_bytes);
+  float* dscale = ar.take<float>(A->n);
+  float* part = ar.take<float>(spmm_ws_bytes(A->nnz, cols) / sizeof(float));
+  if (ar.overflow) return SKETCHNE_E_WORKSPACE;
+  SK_TRY(degree_scale(c, A->n, A->rowptr, alpha, dscale));
+  return spmm(c, A->n, A->nnz, A->rowptr, A->colidx, dscale, B, ldb, cols, C, ldc, part);
+}
+
+sketchne_status sketchne_orth_workspace_size(int64_t n, int32_t cols, size_t* bytes) {
+  if (!bytes || n < 1 || cols < 1 || cols > n) return SKETCHNE_E_ARG;
+  Arena a(nullptr, 0);
+  a.take<float>((size_t)n * cols);
+  carve_orth(a, n, cols, false);
+  *bytes = a.off;
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_orth(sketchne_ctx* c, int64_t n, int32_t cols, float* B, int64_t ldb, void* ws,
+                              size_t ws_bytes) {
+  if (!c || !B || n < 1 || cols < 1 || cols > n || ldb < cols) return SKETCHNE_E_ARG;
+  if (cols > 512) return SKETCHNE_E_UNSUPPORTED;
+  size_t need = 0;
+  SK_TRY(sketchne_orth_workspace_size(n, cols, &need));
+  SK_TRY(check_ws(ws, ws_bytes, need));
+  Arena ar(ws, ws_bytes);
+  float* tmp = ar.take<float>((size_t)n * cols);
+  OrthWs ow = carve_orth(ar, n, cols, false);
+  if (ar.overflow) return SKETCHNE_E_WORKSPACE;
+  // tmp has leading dimension cols; B has ldb
+  GemmDesc g = gram_desc(n, cols, B, ldb, false, ow.G);
+  SK_TRY(gemm64(c, g, ow.partial, ow.partial_cap));
+  SK_TRY(chol_inv(c, cols, ow.G, ow.RinvT, ow.cwork));
+  GemmDesc a = apply_desc(n, cols, B, ldb, false, ow.RinvT, tmp);
+  a.sci = cols;
+  SK_TRY(gemm64(c, a, ow.partial, ow.partial_cap));
+  GemmDesc g2 = gram_desc(n, cols, tmp, cols, false, ow.G);
+  SK_TRY(gemm64(c, g2, ow.partial, ow.partial_cap));
+  SK_TRY(chol_inv(c, cols, ow.G, ow.RinvT, ow.cwork));
+  GemmDesc a2 = apply_desc(n, cols, tmp, cols, false, ow.RinvT, B);
+  a2.sci = ldb;
+  return gemm64(c, a2, ow.partial, ow.partial_cap);
+}
+
+sketchne_status sketchne_symeig_workspace_size(int32_t m, size_t* bytes) {
+  if (!bytes || m < 1) return SKETCHNE_E_ARG;
+  *bytes = symeig_ws_bytes(m);
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_symeig(sketchne_ctx* c, int32_t m, const double* A, double* V, double* w, void* ws,
+                                size_t ws_bytes) {
+  if (!c || !A || !V || !w || m < 1) return SKETCHNE_E_ARG;
+  if (m > 1024) return SKETCHNE_E_UNSUPPORTED;
+  SK_TRY(check_ws(ws, ws_bytes, symeig_ws_bytes(m)));
+  return symeig(c, m, A, V, w, ws);
+}
+
+sketchne_status sketchne_gen_gauss(sketchne_ctx* c, int64_t n, int32_t cols, uint64_t seed, float* out) {
+  if (!c || !out || n < 0 || cols < 0) return SKETCHNE_E_ARG;
+  return gen_gauss(c, n, cols, cols, seed, out);
+}
+
+sketchne_status sketchne_gen_sparse_sign(sketchne_ctx* c, int64_t n, uint64_t seed, sketchne_sparse_sign* out) {
+  if (!c || !out || !out->rows || !out->signs || n < 1 || out->cols < 0 || out->z < 1 || out->z > n)
+    return SKETCHNE_E_ARG;
+  if (n >= ((int64_t)1 << 31)) return SKETCHNE_E_UNSUPPORTED;
+  return gen_sparse_sign(c, n, out->cols, out->z, seed, out->rows, out->signs);
+}
+
+sketchne_status sketchne_profile_enable(sketchne_ctx* c, int on) {
+  if (!c) return SKETCHNE_E_ARG;
+  c->profiling = on != 0;
+  c->n_ev = 0;
+  for (int i = 0; i < SKETCHNE_PROF_CLASSES; ++i) { c->prof_ms[i] = 0; c->prof_n[i] = 0; }
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_profile_read(sketchne_ctx* c, double* ms, int64_t* launches) {
+  if (!c || !ms || !launches) return SKETCHNE_E_ARG;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return SKETCHNE_E_DEVICE;
+  for (int e = 0; e + 1 < c->n_ev; e += 2) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, c->ev[e], c->ev[e + 1]) == hipSuccess) {
+      int cls = c->ev_class[e / 2];
+      c->prof_ms[cls] += t;
+      c->prof_n[cls] += 1;
+    }
+  }
+  c->n_ev = 0;
+  for (int i = 0; i < SKETCHNE_PROF_CLASSES; ++i) {
+    ms[i] = c->prof_ms[i];
+    launches[i] = c->prof_n[i];
+    c->prof_ms[i] = 0;
+    c->prof_n[i] = 0;
+  }
+  return SKETCHNE_OK;
+}
+
+}  // extern "C"

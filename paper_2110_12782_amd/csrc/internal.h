@@ -1,0 +1,119 @@
+// Internal declarations shared by the translation units of libsketchne.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/sketchne.h"
+
+struct sketchne_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint32_t* d_flags = nullptr;      // numeric flag word (device)
+  uint32_t* h_flags = nullptr;      // pinned host copy
+  int* h_counter = nullptr;         // pinned host scratch for convergence checks
+  bool profiling = false;
+  // per-class event pairs (recorded on the stream when profiling)
+  static constexpr int kMaxEvents = 4096;
+  hipEvent_t ev[kMaxEvents];
+  int ev_class[kMaxEvents / 2];
+  int n_ev = 0;
+  double prof_ms[SKETCHNE_PROF_CLASSES] = {0};
+  int64_t prof_n[SKETCHNE_PROF_CLASSES] = {0};
+};
+
+namespace skne {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+
+// Bump allocator over a caller-provided workspace.  In "measure" mode (base
+// == nullptr) it only accumulates the size.
+struct Arena {
+  char* base;
+  size_t cap;
+  size_t off = 0;
+  bool overflow = false;
+  Arena(void* b, size_t c) : base(static_cast<char*>(b)), cap(c) {}
+  template <class T>
+  T* take(size_t count) {
+    size_t bytes = align_up(count * sizeof(T));
+    size_t at = off;
+    off += bytes;
+    if (base == nullptr) return nullptr;
+    if (off > cap) { overflow = true; return nullptr; }
+    return reinterpret_cast<T*>(base + at);
+  }
+};
+
+// Profiling bracket: records an event pair around a launch when enabled.
+struct ProfScope {
+  sketchne_ctx* c;
+  int cls;
+  int slot = -1;
+  ProfScope(sketchne_ctx* ctx, int klass) : c(ctx), cls(klass) {
+    if (c && c->profiling && c->n_ev + 2 <= sketchne_ctx::kMaxEvents) {
+      slot = c->n_ev;
+      c->n_ev += 2;
+      c->ev_class[slot / 2] = cls;
+      hipEventRecord(c->ev[slot], c->stream);
+    }
+  }
+  ~ProfScope() {
+    if (slot >= 0) hipEventRecord(c->ev[slot + 1], c->stream);
+  }
+};
+
+inline sketchne_status launch_status() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SKETCHNE_OK : SKETCHNE_E_DEVICE;
+}
+
+// ---- launchers implemented in the kernel translation units -------------
+
+// rng.hip
+sketchne_status gen_gauss(sketchne_ctx* c, int64_t n, int cols, int64_t ld, uint64_t seed, float* out);
+sketchne_status gen_sparse_sign(sketchne_ctx* c, int64_t n, int cols, int z, uint64_t seed,
+                                int32_t* rows, int8_t* signs);
+
+// spmm.hip
+size_t spmm_ws_bytes(int64_t nnz, int cols);
+sketchne_status degree_scale(sketchne_ctx* c, int64_t n, const int64_t* rowptr, double alpha,
+                             float* dscale);
+sketchne_status spmm(sketchne_ctx* c, int64_t n, int64_t nnz, const int64_t* rowptr,
+                     const int32_t* colidx, const float* dscale, const float* B, int64_t ldb,
+                     int cols, float* C, int64_t ldc, float* partial);
+
+// gemm64.hip : C(i,j) = alpha * sum_k A(i,k) * w(k) * B(k,j)  [+ diag_add * (i==j)]
+// A(i,k) = A[i*sai + k*sak], B(k,j) = B[k*sbk + j*sbj], C(i,j) = C[i*sci + j*scj].
+enum class Ty { F32 = 0, F64 = 1 };
+struct GemmDesc {
+  int64_t M = 0, N = 0, K = 0;
+  const void* A = nullptr; Ty ta = Ty::F64; int64_t sai = 0, sak = 0;
+  const void* B = nullptr; Ty tb = Ty::F64; int64_t sbk = 0, sbj = 0;
+  void* C = nullptr; Ty tc = Ty::F64; int64_t sci = 0, scj = 0;
+  const double* kw = nullptr;   // optional weights on the summation index
+  double alpha = 1.0;
+  double diag_add = 0.0;        // added to C(i,i)
+  bool upper_only = false;      // compute tiles with i-tile <= j-tile and mirror
+};
+// Split-K partial sums need splits*M*N doubles of scratch; gemm64 lowers the
+// split count to what `partial_cap` bytes hold (down to 1, which needs none).
+size_t gemm64_ws_bytes(const GemmDesc& g, int splits);
+int gemm64_pick_splits(const GemmDesc& g);
+size_t gemm64_partial_bytes(int64_t M, int64_t N, int64_t K, bool upper);
+sketchne_status gemm64(sketchne_ctx* c, const GemmDesc& g, double* partial, size_t partial_cap);
+
+// dense_small.hip
+// Cholesky G = R^T R of an SPD m x m FP64 matrix (row-major, ld = m) and the
+// inverse factor; writes RinvT (= R^-T, lower triangular, row-major m x m).
+size_t chol_ws_bytes(int m);
+sketchne_status chol_inv(sketchne_ctx* c, int m, const double* G, double* RinvT, double* work);
+size_t symeig_ws_bytes(int m);
+sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* V, double* w, void* ws);
+
+// sketch.hip
+struct SketchPlan;
+}  // namespace skne

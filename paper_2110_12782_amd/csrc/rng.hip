@@ -1,0 +1,95 @@
+// Counter-based random draws on the device.
+//
+// Each value is SplitMix64's output function (Steele, Lea & Flood,
+// "Fast splittable pseudorandom number generators", OOPSLA 2014) applied to
+// the state seed + gamma * (counter + 1): the counter-th output of a SplitMix64
+// generator, computable independently per thread.  Independent streams use
+// seeds derived by mixing the user seed with a stream constant.
+#include "internal.h"
+
+namespace skne {
+namespace {
+
+constexpr uint64_t kGamma = 0x9e3779b97f4a7c15ULL;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t draw(uint64_t seed, uint64_t ctr) {
+  return mix64(seed + kGamma * (ctr + 1));
+}
+
+__device__ __forceinline__ double unit_open(uint64_t r) {
+  // (0, 1]: 53 random bits, shifted away from 0 so the logarithm is finite
+  return (double)((r >> 11) + 1) * (1.0 / 9007199254740992.0);
+}
+
+__global__ void k_gauss(int64_t n, int cols, int64_t ld, uint64_t seed, float* __restrict__ out) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t total = n * cols;
+  if (idx >= total) return;
+  int64_t i = idx / cols;
+  int j = (int)(idx - i * cols);
+  uint64_t s = mix64(seed ^ 0x6a09e667f3bcc909ULL);
+  double u1 = unit_open(draw(s, 2 * (uint64_t)idx));
+  double u2 = unit_open(draw(s, 2 * (uint64_t)idx + 1));
+  // Box-Muller
+  double g = sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925 * u2);
+  out[i * ld + j] = (float)g;
+}
+
+// One thread per column: z distinct rows uniformly from [0, n), independent
+// fair signs.  A duplicate is redrawn with a fresh counter; after a bounded
+// number of redraws the next free row (cyclically) is taken, which keeps the
+// loop finite for z close to n.
+__global__ void k_sparse_sign(int64_t n, int cols, int z, uint64_t seed,
+                              int32_t* __restrict__ rows, int8_t* __restrict__ signs) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  uint64_t s = mix64(seed ^ 0xbb67ae8584caa73bULL);
+  uint64_t base = (uint64_t)c * (uint64_t)z * 64u;
+  int32_t* rc = rows + (int64_t)c * z;
+  for (int t = 0; t < z; ++t) {
+    int64_t r = 0;
+    bool ok = false;
+    for (int a = 0; a < 32 && !ok; ++a) {
+      uint64_t x = draw(s, base + (uint64_t)t * 32u + a);
+      r = (int64_t)__umul64hi(x, (uint64_t)n);
+      ok = true;
+      for (int u = 0; u < t; ++u) ok = ok && (rc[u] != r);
+    }
+    while (!ok) {  // deterministic fallback: next unused row
+      r = (r + 1) % n;
+      ok = true;
+      for (int u = 0; u < t; ++u) ok = ok && (rc[u] != r);
+    }
+    rc[t] = (int32_t)r;
+    uint64_t y = draw(s ^ 0x3c6ef372fe94f82bULL, (uint64_t)c * z + t);
+    signs[(int64_t)c * z + t] = (y >> 63) ? (int8_t)1 : (int8_t)-1;
+  }
+}
+
+}  // namespace
+
+sketchne_status gen_gauss(sketchne_ctx* c, int64_t n, int cols, int64_t ld, uint64_t seed, float* out) {
+  int64_t total = n * cols;
+  if (total == 0) return SKETCHNE_OK;
+  ProfScope ps(c, SKETCHNE_PROF_PREP);
+  int64_t blocks = (total + 255) / 256;
+  hipLaunchKernelGGL(k_gauss, dim3((unsigned)blocks), dim3(256), 0, c->stream, n, cols, ld, seed, out);
+  return launch_status();
+}
+
+sketchne_status gen_sparse_sign(sketchne_ctx* c, int64_t n, int cols, int z, uint64_t seed,
+                                int32_t* rows, int8_t* signs) {
+  if (cols == 0) return SKETCHNE_OK;
+  ProfScope ps(c, SKETCHNE_PROF_PREP);
+  hipLaunchKernelGGL(k_sparse_sign, dim3((cols + 127) / 128), dim3(128), 0, c->stream, n, cols, z,
+                     seed, rows, signs);
+  return launch_status();
+}
+
+}  // namespace skne

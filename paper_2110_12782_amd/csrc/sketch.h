@@ -1,0 +1,31 @@
+// Launchers of the sketch translation unit (internal).
+#pragma once
+#include "internal.h"
+
+namespace skne {
+
+int sketch_kstep(int prec);
+int sketch_frag_bytes(int prec);
+int sketch_vt(int prec);
+int sketch_ks_supported(int prec, int ks_needed);
+
+sketchne_status degree_powers(sketchne_ctx* c, int64_t n, const int64_t* rowptr, double alpha, double* d1,
+                              double* d2);
+sketchne_status scale_cols(sketchne_ctx* c, int rows, int cols, double* M, const double* s);
+sketchne_status scale_rows(sketchne_ctx* c, int rows, int cols, const double* M, const double* s, double* out);
+sketchne_status identity(sketchne_ctx* c, int m, double* M);
+sketchne_status gather_expanded(sketchne_ctx* c, int64_t n, int ntiles, int groups, int z, const int32_t* rows,
+                                const float* U, int64_t ldu, int k, const double* d1, double scale, double* Gsel);
+sketchne_status pack_A(sketchne_ctx* c, int prec, int ntiles, int KS, int k, int r, const double* RtT, void* out);
+sketchne_status pack_B(sketchne_ctx* c, int prec, int64_t n, int64_t nrows, int64_t nvt, int KS, int k, int r,
+                       const int32_t* gather, const float* U, int64_t ldu, const double* d1, void* out);
+sketchne_status pack_signs(sketchne_ctx* c, int ntiles, int groups, int z, const int8_t* signs, float* sgn);
+sketchne_status fused_sketch(sketchne_ctx* c, int cls, int prec, int64_t nrows, int groups, int ntiles, int KS,
+                             const void* Bpack, const void* Apack, const float* sgn, float* out, int64_t ld_out,
+                             float out_scale);
+sketchne_status z_reduce(sketchne_ctx* c, int l, int z, const int8_t* signs, const float* T1t, int64_t ld_t1,
+                         float inv_sqrt_z, float* Z);
+sketchne_status ot_q(sketchne_ctx* c, int l, int z, int hcols, const int32_t* rows, const int8_t* signs,
+                     const float* Qt, int64_t n, double inv_sqrt_z, double* Bm);
+
+}  // namespace skne

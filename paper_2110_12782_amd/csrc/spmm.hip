@@ -1,0 +1,190 @@
+// CSR SpMM with the modified Laplacian: C = D^-a A D^-a B.
+//
+// The paper's CPU version walks vertices in parallel and, for each neighbour
+// v of u, adds D(u,u)^-a D(v,v)^-a times row v of the row-major dense matrix
+// to row u of the output (Section 3.4).  Here the work unit is a fixed slice
+// of P stored entries per wavefront instead of a vertex, so a hub with
+// thousands of neighbours is spread over many wavefronts and no wavefront
+// waits on one long row.  Inside a wavefront the 64 lanes cover one dense
+// row in float4 chunks, so every neighbour gather is a contiguous, coalesced
+// read of cols*4 bytes.  A row that crosses a slice boundary is written as
+// partial sums (one "head" and one "tail" slot per wavefront) and a fixup
+// kernel adds the partials of each such row in slice order, so the result is
+// deterministic (no floating-point atomics).
+#include "internal.h"
+
+namespace skne {
+namespace {
+
+constexpr int kP = 256;  // stored entries per wavefront slice
+
+__global__ void k_degree_scale(int64_t n, const int64_t* __restrict__ rowptr, double alpha,
+                               float* __restrict__ dscale) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t deg = rowptr[i + 1] - rowptr[i];
+  dscale[i] = deg > 0 ? (float)pow((double)deg, -alpha) : 0.0f;
+}
+
+__device__ __forceinline__ int64_t row_of(const int64_t* __restrict__ rowptr, int64_t n, int64_t e) {
+  // largest r with rowptr[r] <= e  (rowptr[0] = 0 <= e < rowptr[n])
+  int64_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) >> 1;
+    if (rowptr[mid] <= e) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <int NIT>
+__global__ __launch_bounds__(256) void k_spmm(int64_t n, int64_t nnz, const int64_t* __restrict__ rowptr,
+                                              const int32_t* __restrict__ colidx,
+                                              const float* __restrict__ dscale,
+                                              const float* __restrict__ B, int64_t ldb, int cols,
+                                              float* __restrict__ C, int64_t ldc,
+                                              float* __restrict__ partial, int64_t nwaves) {
+  const int lane = threadIdx.x & 63;
+  int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  w = __builtin_amdgcn_readfirstlane((int)w);
+  if (w >= nwaves) return;
+  const int nc4 = cols >> 2;
+  const int64_t e0 = w * kP;
+  const int64_t e1 = min(e0 + (int64_t)kP, nnz);
+  int64_t r = row_of(rowptr, n, e0);
+  while (true) {
+    const int64_t rs = rowptr[r], re = rowptr[r + 1];
+    const int64_t a = max(rs, e0), bnd = min(re, e1);
+    float4 acc[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) acc[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+    int64_t e = a;
+    for (; e + 4 <= bnd; e += 4) {
+      int j[4];
+      float s[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) j[u] = colidx[e + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s[u] = dscale[j[u]];
+      float4 v[4][NIT];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+          int c4 = lane + 64 * it;
+          v[u][it] = c4 < nc4 ? *reinterpret_cast<const float4*>(B + (int64_t)j[u] * ldb + 4 * c4)
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+          acc[it].x = fmaf(s[u], v[u][it].x, acc[it].x);
+          acc[it].y = fmaf(s[u], v[u][it].y, acc[it].y);
+          acc[it].z = fmaf(s[u], v[u][it].z, acc[it].z);
+          acc[it].w = fmaf(s[u], v[u][it].w, acc[it].w);
+        }
+    }
+    for (; e < bnd; ++e) {
+      int jj = colidx[e];
+      float ss = dscale[jj];
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        int c4 = lane + 64 * it;
+        if (c4 < nc4) {
+          float4 vv = *reinterpret_cast<const float4*>(B + (int64_t)jj * ldb + 4 * c4);
+          acc[it].x = fmaf(ss, vv.x, acc[it].x);
+          acc[it].y = fmaf(ss, vv.y, acc[it].y);
+          acc[it].z = fmaf(ss, vv.z, acc[it].z);
+          acc[it].w = fmaf(ss, vv.w, acc[it].w);
+        }
+      }
+    }
+    const float sr = dscale[r];
+    const bool whole = (rs >= e0) && (re <= e1);
+    float* dst = whole ? (C + r * ldc) : (partial + (2 * w + (rs < e0 ? 0 : 1)) * (int64_t)cols);
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      int c4 = lane + 64 * it;
+      if (c4 < nc4) {
+        float4 o = make_float4(sr * acc[it].x, sr * acc[it].y, sr * acc[it].z, sr * acc[it].w);
+        *reinterpret_cast<float4*>(dst + 4 * c4) = o;
+      }
+    }
+    if (re >= e1) break;
+    ++r;
+    while (rowptr[r + 1] == rowptr[r]) ++r;  // skip empty rows (written by k_zero_empty)
+  }
+}
+
+// For each slice boundary b*P: the row containing entry b*P, if it began in an
+// earlier slice and b is the first boundary it crosses, is finished here.
+__global__ __launch_bounds__(256) void k_spmm_fixup(int64_t n, int64_t nnz, const int64_t* __restrict__ rowptr,
+                                                    int cols, float* __restrict__ C, int64_t ldc,
+                                                    const float* __restrict__ partial, int64_t nwaves) {
+  const int lane = threadIdx.x & 63;
+  int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6) + 1;
+  if (b >= nwaves) return;
+  const int64_t e = b * kP;
+  const int64_t r = row_of(rowptr, n, e);
+  const int64_t rs = rowptr[r], re = rowptr[r + 1];
+  if (rs >= e) return;                 // row starts at this boundary: not split here
+  const int64_t ws = rs / kP;
+  if (ws + 1 != b) return;             // an earlier boundary owns this row
+  const int64_t we = (re - 1) / kP;
+  const int nc4 = cols >> 2;
+  for (int c4 = lane; c4 < nc4; c4 += 64) {
+    float4 acc = *reinterpret_cast<const float4*>(partial + (2 * ws + 1) * (int64_t)cols + 4 * c4);
+    for (int64_t wv = ws + 1; wv <= we; ++wv) {
+      float4 p = *reinterpret_cast<const float4*>(partial + (2 * wv) * (int64_t)cols + 4 * c4);
+      acc.x += p.x; acc.y += p.y; acc.z += p.z; acc.w += p.w;
+    }
+    *reinterpret_cast<float4*>(C + r * ldc + 4 * c4) = acc;
+  }
+}
+
+__global__ void k_zero_empty(int64_t n, const int64_t* __restrict__ rowptr, int cols,
+                             float* __restrict__ C, int64_t ldc) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (rowptr[i + 1] != rowptr[i]) return;
+  for (int c = 0; c < cols; ++c) C[i * ldc + c] = 0.0f;
+}
+
+}  // namespace
+
+size_t spmm_ws_bytes(int64_t nnz, int cols) {
+  int64_t nwaves = (nnz + kP - 1) / kP;
+  return align_up(sizeof(float) * (size_t)(2 * nwaves + 2) * (size_t)cols);
+}
+
+sketchne_status degree_scale(sketchne_ctx* c, int64_t n, const int64_t* rowptr, double alpha, float* dscale) {
+  if (n == 0) return SKETCHNE_OK;
+  ProfScope ps(c, SKETCHNE_PROF_PREP);
+  hipLaunchKernelGGL(k_degree_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, rowptr,
+                     alpha, dscale);
+  return launch_status();
+}
+
+sketchne_status spmm(sketchne_ctx* c, int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colidx,
+                     const float* dscale, const float* B, int64_t ldb, int cols, float* C, int64_t ldc,
+                     float* partial) {
+  if (n == 0 || cols == 0) return SKETCHNE_OK;
+  ProfScope ps(c, SKETCHNE_PROF_SPMM);
+  hipLaunchKernelGGL(k_zero_empty, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, rowptr, cols,
+                     C, ldc);
+  if (nnz == 0) return launch_status();
+  int64_t nwaves = (nnz + kP - 1) / kP;
+  unsigned blocks = (unsigned)((nwaves + 3) / 4);
+  if (cols <= 256)
+    hipLaunchKernelGGL(k_spmm<1>, dim3(blocks), dim3(256), 0, c->stream, n, nnz, rowptr, colidx, dscale, B, ldb,
+                       cols, C, ldc, partial, nwaves);
+  else
+    hipLaunchKernelGGL(k_spmm<2>, dim3(blocks), dim3(256), 0, c->stream, n, nnz, rowptr, colidx, dscale, B, ldb,
+                       cols, C, ldc, partial, nwaves);
+  if (nwaves > 1)
+    hipLaunchKernelGGL(k_spmm_fixup, dim3((unsigned)((nwaves - 1 + 3) / 4)), dim3(256), 0, c->stream, n, nnz,
+                       rowptr, cols, C, ldc, partial, nwaves);
+  return launch_status();
+}
+
+}  // namespace skne

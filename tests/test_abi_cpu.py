@@ -1,0 +1,86 @@
+"""The C-ABI library loads and exports every symbol the header declares; the
+host-only parts of the ABI (workspace sizing, argument validation that runs
+before anything is enqueued) behave as documented.  No GPU is used."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2110_12782_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sketchne.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sketchne_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail("libsketchne.so is not built (run __graft_entry__.build())")
+    return B.Library(need_gpu=False)
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib.lib, name), f"{name} declared in sketchne.h but not exported"
+    assert set(names) == set(B.EXPORTED)
+
+
+def test_status_strings(lib):
+    for st in range(6):
+        assert lib.lib.sketchne_status_str(st)
+    assert b"invalid" in lib.lib.sketchne_status_str(B.E_ARG)
+
+
+def test_workspace_sizes_scale(lib):
+    p = B.SketchParams(k=256, s_eig=32, d=128, h=272, l=1128, z=8)
+    small = lib.workspace_size(p, 65536, 1 << 20, B.OP_EIG | B.OP_SKETCH | B.OP_EMBED)
+    big = lib.workspace_size(p, 1 << 20, 21 << 20, B.OP_EIG | B.OP_SKETCH | B.OP_EMBED)
+    assert 0 < small < big
+    # eig holds three n x K FP32 blocks at least
+    assert lib.workspace_size(p, 1 << 20, 21 << 20, B.OP_EIG) >= 3 * (1 << 20) * 288 * 4
+    bf = B.SketchParams(k=256, s_eig=32, d=128, h=272, l=1128, z=8, precision=B.BF16, split_r=32)
+    assert lib.workspace_size(bf, 1 << 20, 0, B.OP_SKETCH) > 0
+
+
+@pytest.mark.parametrize("field,value", [
+    ("alpha", 0.0), ("alpha", 0.6), ("T", 0), ("b", 0.0), ("k", 0), ("q", -1),
+    ("d", 0), ("h", 100), ("l", 200), ("z", 0), ("precision", 3), ("split_r", -1),
+])
+def test_invalid_params_rejected(lib, field, value):
+    p = B.SketchParams(k=128, s_eig=32, d=128, h=272, l=1128, z=8)
+    setattr(p, field, value)
+    pc = p.c()
+    out = C.c_size_t(0)
+    st = lib.lib.sketchne_workspace_size(C.byref(pc), 65536, 1 << 20, B.OP_SKETCH, C.byref(out))
+    assert st == B.E_ARG
+
+
+def test_k_larger_than_n_rejected(lib):
+    p = B.SketchParams(k=256, s_eig=32, d=8, h=16, l=32, z=8)
+    pc = p.c()
+    out = C.c_size_t(0)
+    assert lib.lib.sketchne_workspace_size(C.byref(pc), 200, 1000, B.OP_EIG, C.byref(out)) == B.E_ARG
+
+
+def test_null_context_and_pointers_rejected_before_any_work(lib):
+    p = B.SketchParams(k=8, s_eig=8, d=4, h=8, l=16, z=4).c()
+    g = B.Graph(100, 0, None, None)
+    L = lib.lib
+    assert L.sketchne_eig(None, C.byref(g), C.byref(p), None, None, None, None, 0) == B.E_ARG
+    assert L.sketchne_sketch(None, C.byref(g), C.byref(p), None, None, None, None, 0, None, None, None, 0) == B.E_ARG
+    assert L.sketchne_embed(None, C.byref(p), 100, None, None, None, None, None, None, 0) == B.E_ARG
+    assert L.sketchne_sync(None, None) == B.E_ARG
+    assert L.sketchne_destroy(None) == B.E_ARG
+    out = C.c_size_t(0)
+    assert L.sketchne_orth_workspace_size(0, 4, C.byref(out)) == B.E_ARG
+    assert L.sketchne_symeig_workspace_size(0, C.byref(out)) == B.E_ARG
+    assert L.sketchne_symeig_workspace_size(300, C.byref(out)) == B.OK and out.value >= 3 * 300 * 300 * 8

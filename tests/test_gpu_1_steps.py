@@ -1,0 +1,127 @@
+"""GPU parity of the individual steps, through the C ABI: device generators,
+SpMM with the modified Laplacian, Cholesky-QR orthonormalisation and the
+Jacobi symmetric eigensolver, each against a plain FP64 reference."""
+import numpy as np
+import pytest
+
+from tests.util import say, c1_graph, netmf, synth, metrics
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def test_gen_sparse_sign(lib, torch):
+    say("gen_sparse_sign n=1000 cols=300 z=8; n=8 z=8")
+    rows, signs = lib.gen_sparse_sign(1000, 300, 8, 7)
+    r = rows.cpu().numpy()
+    s = signs.cpu().numpy()
+    assert r.min() >= 0 and r.max() < 1000
+    assert all(len(np.unique(x)) == 8 for x in r)
+    assert set(np.unique(s)) == {-1, 1}
+    assert abs((s == 1).mean() - 0.5) < 0.05
+    r2, s2 = lib.gen_sparse_sign(1000, 300, 8, 7)
+    assert np.array_equal(r, r2.cpu().numpy()) and np.array_equal(s, s2.cpu().numpy())
+    r3, _ = lib.gen_sparse_sign(8, 50, 8, 3)  # z == n: every column is a permutation
+    assert all(sorted(x) == list(range(8)) for x in r3.cpu().numpy())
+    # uniform coverage of rows (chi-square, 100 bins)
+    rb, _ = lib.gen_sparse_sign(100000, 4000, 8, 11)
+    counts = np.bincount(rb.cpu().numpy().ravel() // 1000, minlength=100)
+    exp = 4000 * 8 / 100
+    chi2 = ((counts - exp) ** 2 / exp).sum()
+    assert chi2 < 180  # 99 dof
+
+
+def test_gen_gauss(lib, torch):
+    say("gen_gauss 200000 x 8")
+    g = lib.gen_gauss(200000, 8, 5).cpu().numpy().astype(np.float64)
+    assert abs(g.mean()) < 0.01 and abs(g.std() - 1) < 0.01
+    assert abs((np.abs(g) < 1).mean() - 0.6827) < 0.005
+    assert np.array_equal(g, lib.gen_gauss(200000, 8, 5).cpu().numpy())
+
+
+def _spmm_case(lib, torch, rowptr, colidx, cols, alpha, seed):
+    from paper_2110_12782_amd.binding import DeviceGraph
+    A = netmf.adjacency(rowptr, colidx)
+    X = netmf.modified_laplacian(A, alpha)
+    B = np.random.default_rng(seed).standard_normal((A.shape[0], cols)).astype(np.float32)
+    ref = X @ B.astype(np.float64)
+    g = DeviceGraph(rowptr, colidx)
+    out = lib.spmm(g, alpha, torch.from_numpy(B).cuda()).cpu().numpy()
+    err = metrics.rel_fro(out, ref)
+    rows = np.linalg.norm(ref, axis=1) + 1e-30
+    rowerr = (np.linalg.norm(out - ref, axis=1) / rows).max()
+    return err, rowerr
+
+
+@pytest.mark.parametrize("cols", [4, 64, 288])
+def test_spmm_sbm(lib, torch, cols):
+    say(f"spmm SBM n=4096 cols={cols}")
+    rowptr, colidx = c1_graph()
+    err, rowerr = _spmm_case(lib, torch, rowptr, colidx, cols, 0.5, cols)
+    assert err < 1e-6 and rowerr < 1e-5
+
+
+def test_spmm_hubs_and_isolated(lib, torch):
+    # Chung-Lu with hubs (rows far longer than one wavefront slice) plus
+    # isolated vertices and an empty trailing row
+    say("spmm Chung-Lu n=20000 + isolated, cols=288, alpha=0.4")
+    rowptr, colidx = synth.chung_lu(20000, 2.1, 16, 2, 5)
+    rowptr = np.concatenate([rowptr[:1], rowptr[1:5001], np.full(3, rowptr[5000]), rowptr[5001:],
+                             np.full(2, rowptr[-1])])
+    colidx = np.where(colidx >= 5000, colidx + 3, colidx).astype(np.int32)
+    err, rowerr = _spmm_case(lib, torch, rowptr, colidx, 288, 0.4, 1)
+    assert err < 1e-6 and rowerr < 1e-5
+
+
+def test_orth(lib, torch):
+    for n, K in [(20000, 64), (50000, 288), (4100, 160)]:
+        say(f"orth n={n} K={K}")
+        rng = np.random.default_rng(K)
+        B = (rng.standard_normal((n, K)) @ np.diag(np.logspace(0, 3, K))).astype(np.float32)
+        Qd = torch.from_numpy(B.copy()).cuda()
+        Q = lib.orth(Qd).cpu().numpy().astype(np.float64)
+        assert np.abs(Q.T @ Q - np.eye(K)).max() < 5e-6
+        s = metrics.sin_principal_angles(Q, B.astype(np.float64))
+        assert s.max() < 1e-5
+
+
+@pytest.mark.parametrize("m", [2, 7, 64, 288])
+def test_symeig_random(lib, torch, m):
+    say(f"symeig random m={m}")
+    rng = np.random.default_rng(m)
+    M = rng.standard_normal((m, m))
+    A = (M + M.T) / 2
+    V, w = lib.symeig(torch.from_numpy(A.copy()).cuda())
+    V = V.cpu().numpy()
+    w = w.cpu().numpy()
+    ref = np.linalg.eigvalsh(A)
+    ref = ref[np.lexsort((-ref, -np.abs(ref)))]
+    scale = np.abs(ref).max()
+    assert np.abs(w - ref).max() < 1e-12 * scale * max(1, m / 16)
+    assert np.abs(V.T @ V - np.eye(m)).max() < 1e-12 * max(1, m / 16)
+    assert np.abs(V @ np.diag(w) @ V.T - A).max() < 1e-12 * scale * max(1, m / 16)
+
+
+def test_symeig_degenerate(lib, torch):
+    say("symeig degenerate spectra")
+    m = 40
+    rng = np.random.default_rng(1)
+    Qm = np.linalg.qr(rng.standard_normal((m, m)))[0]
+    lam = np.repeat([3.0, -3.0, 1.0, 0.5, 0.0], 8)
+    A = Qm @ np.diag(lam) @ Qm.T
+    A = (A + A.T) / 2
+    V, w = lib.symeig(torch.from_numpy(A).cuda())
+    V = V.cpu().numpy()
+    w = w.cpu().numpy()
+    # +3 and -3 tie in |w|, so only the multiset and the |w| order are fixed
+    assert np.allclose(np.sort(w), np.sort(lam), atol=1e-12)
+    assert np.all(np.diff(np.abs(w)) <= 1e-12)
+    assert np.abs(V @ np.diag(w) @ V.T - A).max() < 1e-12
+    D, Vd = lib.symeig(torch.eye(6, dtype=torch.float64, device="cuda") * 2)
+    assert np.allclose(Vd.cpu().numpy(), 2.0) and np.allclose(np.abs(D.cpu().numpy()), np.eye(6))

@@ -1,0 +1,157 @@
+"""GPU parity of the eigendecomposition (Alg. 5), the embedding step (Alg. 4
+lines 5, 8-10) and the whole path (Alg. 6 lines 1-5) against the FP64 oracle
+on identical random realizations."""
+import numpy as np
+import pytest
+
+from tests.util import say, c1_graph, rel, sk, netmf, synth, fr, metrics
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_eig_c1(lib):
+    from paper_2110_12782_amd.binding import DeviceGraph, SketchParams
+    say("eig C1 SBM n=4096 k=128 K=160 q=2 alpha=0.5, given Omega")
+    rowptr, colidx = c1_graph()
+    A = netmf.adjacency(rowptr, colidx)
+    n, k, K = A.shape[0], 128, 160
+    Om = synth.gaussian_block(n, K, 2001)
+    X = netmf.modified_laplacian(A, 0.5)
+    Uo, lo, Qo = fr.freigs(X, Om.astype(np.float64), k, 2, return_basis=True)
+    p = SketchParams(alpha=0.5, k=k, s_eig=K - k, q=2, d=32, h=80, l=1032)
+    U, lam = lib.eig(DeviceGraph(rowptr, colidx), p, omega0=dev(Om))
+    assert lib.sync() == 0
+    U = U.cpu().numpy().astype(np.float64)
+    lam = lam.cpu().numpy()
+    el = np.abs(lam - lo).max() / np.abs(lo).max()
+    UL = (U * lam) @ U.T
+    ULo = (Uo * lo) @ Uo.T
+    eu = rel(UL, ULo)
+    orth = np.abs(U.T @ U - np.eye(k)).max()
+    top = [abs(U[:, j] @ Uo[:, j]) for j in range(8)]
+    say(f"  lambda err {el:.3e}  U L U^T rel {eu:.3e}  orth {orth:.2e}  top8 |cos| min {min(top):.8f}")
+    assert el <= 1e-5
+    assert eu <= 1e-4
+    assert orth <= 1e-5
+    assert min(top) >= 1 - 1e-6
+    # Ritz values never exceed the largest eigenvalue, which is 1 (q = 2 at
+    # alpha = 1/2 leaves the top Ritz value below it: method error, shared with
+    # the oracle and checked above)
+    assert lam[0] <= 1 + 1e-6
+
+
+def test_embed_exact_low_rank(lib):
+    # Y = X S, Z = O^T X O for a symmetric X of exact rank r <= h: Q W Q^T = X,
+    # so sigma are the |eigenvalues| of X and E E^T = U_d |Mu_d| U_d^T exactly.
+    import torch
+    from paper_2110_12782_amd.binding import SketchParams
+    say("embed exact low rank n=3000 r=12 h=24 l=80 d=8")
+    rng = np.random.default_rng(3)
+    n, r, h, l, d, z = 3000, 12, 24, 80, 8, 8
+    V = np.linalg.qr(rng.standard_normal((n, r)))[0]
+    mu = np.concatenate([np.linspace(5, 1, r // 2), -np.linspace(4.5, 0.5, r // 2)])
+    X = V @ np.diag(mu) @ V.T
+    rS, sS = synth.sparse_sign(n, h, z, 1)
+    rO, sO = synth.sparse_sign(n, l, z, 2)
+    S = sk.sparse_sign_dense(n, rS, sS)
+    O = sk.sparse_sign_dense(n, rO, sO)
+    Y = X @ S
+    Z = O.T @ X @ O
+    p = SketchParams(k=8, s_eig=0, d=d, h=h, l=l, z=z)
+    E, sig = lib.embed(n, p, dev(Y.T.astype(np.float32)), dev(Z.astype(np.float32)), (dev(rO), dev(sO)))
+    # Y = X S has rank r < h, so the Gram of Y is singular: the first
+    # Cholesky-QR pass takes the documented diagonal shift (informational
+    # flag bit 0), nothing fails
+    assert lib.sync() & ~1 == 0
+    E = E.cpu().numpy().astype(np.float64)
+    sig = sig.cpu().numpy()
+    expect = np.sort(np.abs(mu))[::-1][:d]
+    say(f"  sigma rel err {np.abs(sig - expect).max() / expect.max():.3e}")
+    assert np.allclose(sig, expect, rtol=2e-5)
+    order = np.argsort(-np.abs(mu))[:d]
+    EEt = (V[:, order] * np.abs(mu[order])) @ V[:, order].T
+    assert rel(E @ E.T, EEt) < 1e-4
+
+
+def test_embed_parity_from_oracle_sketches(lib):
+    # Alg. 4 lines 5, 8-10 on the oracle's Y and Z of an SBM graph
+    from paper_2110_12782_amd.binding import SketchParams
+    say("embed parity C1 sketches (oracle Y, Z) d=32 h=80 l=1032")
+    rowptr, colidx = c1_graph()
+    A = netmf.adjacency(rowptr, colidx)
+    n = A.shape[0]
+    X = netmf.modified_laplacian(A, 0.5)
+    U, lam = fr.freigs(X, synth.gaussian_block(n, 160, 2001).astype(np.float64), 128, 2)
+    Lp, Rp, _ = netmf.eq11_factors(U, lam, netmf.degrees(A), netmf.volume(A), 0.5, 10, 1.0)
+    rS, sS = synth.sparse_sign(n, 80, 8, 3001)
+    rO, sO = synth.sparse_sign(n, 1032, 8, 4001)
+    Y = sk.sketch_y_sampled(Lp, Rp, rS, sS)
+    Z = sk.sketch_z_sampled(Lp, Rp, rO, sO)
+    Y32, Z32 = Y.astype(np.float32), Z.astype(np.float32)
+    O = sk.sparse_sign_matrix(n, rO, sO)
+    Ud, sig_o, _, _, _ = sk.single_pass_svd(Y32.astype(np.float64), Z32.astype(np.float64), O, 32)
+    Eo = Ud * np.sqrt(sig_o)
+    p = SketchParams(k=128, s_eig=32, d=32, h=80, l=1032, z=8)
+    E, sig = lib.embed(n, p, dev(Y32.T), dev(Z32), (dev(rO), dev(sO)))
+    assert lib.sync() == 0
+    E = E.cpu().numpy().astype(np.float64)
+    sig = sig.cpu().numpy()
+    es = np.abs(sig - sig_o).max() / sig_o.max()
+    et = metrics.sin_theta_fro(E, Eo)
+    ee = rel(E @ E.T, Eo @ Eo.T)
+    say(f"  sigma {es:.3e}  sin theta {et:.3e}  EE^T {ee:.3e}")
+    assert es <= 1e-4 and et <= 1e-3 and ee <= 1e-3
+
+
+def test_pipeline_c1(lib):
+    # Alg. 6 lines 1-5 on the GPU vs the oracle, same Omega, S, O
+    from paper_2110_12782_amd.binding import DeviceGraph, SketchParams
+    from oracle import pipeline
+    say("pipeline C1 SBM n=4096, all three calls")
+    rowptr, colidx = c1_graph()
+    A = netmf.adjacency(rowptr, colidx)
+    n = A.shape[0]
+    pp = pipeline.Params(alpha=0.5, T=10, b=1.0, k=128, s_eig=32, q=2, d=32, h=80, l=1032, z=8)
+    Om = synth.gaussian_block(n, 160, 2001)
+    rS, sS = synth.sparse_sign(n, 80, 8, 3001)
+    rO, sO = synth.sparse_sign(n, 1032, 8, 4001)
+    ref = pipeline.sketchne(A, pp, Om.astype(np.float64), rS, sS, rO, sO)
+    p = SketchParams(alpha=0.5, T=10, b=1.0, k=128, s_eig=32, q=2, d=32, h=80, l=1032, z=8)
+    g = DeviceGraph(rowptr, colidx)
+    U, lam = lib.eig(g, p, omega0=dev(Om))
+    Yt, Z, S, O = lib.sketch(g, p, U, lam, S=(dev(rS), dev(sS)), O=(dev(rO), dev(sO)))
+    E, sig = lib.embed(n, p, Yt, Z, O)
+    assert lib.sync() == 0
+    E = E.cpu().numpy().astype(np.float64)
+    ey = rel(Yt.cpu().numpy().T, ref["Y"])
+    ez = rel(Z.cpu().numpy(), ref["Z"])
+    et = metrics.sin_theta_fro(E, ref["E"])
+    ee = rel(E @ E.T, ref["E"] @ ref["E"].T)
+    say(f"  Y {ey:.3e}  Z {ez:.3e}  sin theta {et:.3e}  EE^T {ee:.3e}")
+    assert ey <= 1e-3 and ez <= 1e-3
+    assert et <= 1e-2 and ee <= 1e-2
+
+
+def test_pipeline_device_draws(lib):
+    # The production path: Omega, S and O drawn on the device.  Checked by
+    # properties that hold for any realization: finite outputs, descending
+    # sigma, E E^T symmetric PSD, Y rows of isolated vertices zero.
+    import torch
+    from paper_2110_12782_amd.binding import DeviceGraph, SketchParams
+    say("pipeline device draws Chung-Lu n=30000 k=64 d=16")
+    rowptr, colidx = synth.chung_lu(30000, 2.1, 12, 2, 77)
+    p = SketchParams(alpha=0.45, T=5, k=64, s_eig=16, q=1, d=16, h=48, l=256, z=8, seed=99)
+    g = DeviceGraph(rowptr, colidx)
+    U, lam = lib.eig(g, p)
+    Yt, Z, S, O = lib.sketch(g, p, U, lam)
+    E, sig = lib.embed(g.n, p, Yt, Z, O)
+    assert lib.sync() == 0
+    sig = sig.cpu().numpy()
+    assert np.all(np.isfinite(E.cpu().numpy())) and np.all(np.diff(sig) <= 1e-12 * sig[0])
+    r = S[0].cpu().numpy()
+    assert all(len(set(x)) == 8 for x in r) and r.max() < 30000
