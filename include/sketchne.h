@@ -121,7 +121,10 @@ sketchne_status sketchne_workspace_size(const sketchne_params* p, int64_t n, int
  *           Gaussian block on the device from p->seed.
  *   U:      n x k row-major FP32 output (orthonormal columns).
  *   lambda: k FP64 output.
- * Orthonormalisation is Cholesky-QR with FP64 Gram/Cholesky (twice). */
+ * Requires k + s_eig <= 288 (order of the Rayleigh-Ritz eigensolver).
+ * Orthonormalisation is Cholesky-QR with FP64 Gram and Cholesky; a second
+ * pass runs only when the first factor's 1-norm condition number exceeds
+ * 1e5 or its Cholesky needed a diagonal shift. */
 sketchne_status sketchne_eig(sketchne_ctx* ctx, const sketchne_graph* A, const sketchne_params* p,
                              const float* omega0, float* U, double* lambda,
                              void* ws, size_t ws_bytes);
@@ -144,7 +147,8 @@ sketchne_status sketchne_sketch(sketchne_ctx* ctx, const sketchne_graph* A, cons
  * because Z is, so its SVD is taken from a symmetric eigendecomposition with
  * singular values |eigenvalue|); E = Q U^(:, 1:d) diag(sigma)^1/2.
  *   Yt: h x n (as written by sketchne_sketch); Z: l x l; O: the test matrix of Z.
- *   E:  n x d row-major FP32 output; sigma: d FP64 output, descending. */
+ *   E:  n x d row-major FP32 output; sigma: d FP64 output, descending.
+ * Requires h <= 288 (order of the eigensolver for W). */
 sketchne_status sketchne_embed(sketchne_ctx* ctx, const sketchne_params* p, int64_t n,
                                const float* Yt, const float* Z, const sketchne_sparse_sign* O,
                                float* E, double* sigma, void* ws, size_t ws_bytes);
@@ -164,17 +168,18 @@ sketchne_status sketchne_spmm(sketchne_ctx* ctx, const sketchne_graph* A, double
                               const float* B, int64_t ldb, int32_t cols,
                               float* C, int64_t ldc, void* ws, size_t ws_bytes);
 
-/* In-place orthonormalisation of the columns of B (n x cols, ld ldb, FP32):
- * Cholesky-QR twice with FP64 Gram and Cholesky (the orth of Alg. 5).
- * cols <= 1024.  Workspace: sketchne_orth_workspace_size(). */
+/* In-place orthonormalisation of the columns of B (n x cols, FP32, packed:
+ * ldb == cols): Cholesky-QR with FP64 Gram and Cholesky, repeated once when
+ * the first factor is ill-conditioned (the orth of Alg. 5).  cols <= 512.
+ * Workspace: sketchne_orth_workspace_size(). */
 sketchne_status sketchne_orth_workspace_size(int64_t n, int32_t cols, size_t* bytes);
 sketchne_status sketchne_orth(sketchne_ctx* ctx, int64_t n, int32_t cols, float* B, int64_t ldb,
                               void* ws, size_t ws_bytes);
 
 /* Symmetric eigendecomposition of the m x m FP64 matrix A (only its upper
- * triangle is read) by parallel cyclic Jacobi: A = V diag(w) V^T, pairs
- * sorted by |w| descending (ties: w descending, then index).  V: m x m
- * row-major, column j = eigenvector j.  m <= 1024. */
+ * triangle is read) by one-sided block Jacobi on A + ||A||_F I:
+ * A = V diag(w) V^T, pairs sorted by |w| descending (ties: w descending,
+ * then index).  V: m x m row-major, column j = eigenvector j.  m <= 288. */
 sketchne_status sketchne_symeig_workspace_size(int32_t m, size_t* bytes);
 sketchne_status sketchne_symeig(sketchne_ctx* ctx, int32_t m, const double* A, double* V, double* w,
                                 void* ws, size_t ws_bytes);

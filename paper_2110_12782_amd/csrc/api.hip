@@ -47,6 +47,7 @@ struct OrthWs {
   double* G;
   double* RinvT;
   double* cwork;
+  int* need2;
 };
 
 GemmDesc gram_desc(int64_t n, int m, const float* X, int64_t ld, bool transposed, double* G) {
@@ -97,22 +98,33 @@ OrthWs carve_orth(Arena& ar, int64_t n, int m, bool transposed) {
   w.G = ar.take<double>((size_t)m * m);
   w.RinvT = ar.take<double>((size_t)m * m);
   w.cwork = ar.take<double>(chol_ws_bytes(m) / sizeof(double) + 1);
+  w.need2 = ar.take<int>(1);
   return w;
 }
 
+// One Cholesky-QR pass src -> dst.  need_more: set by the Cholesky when a
+// second pass is needed; run_if: the pass runs only when it points to 1.
 sketchne_status orth_pass(sketchne_ctx* c, int64_t n, int m, const float* src, float* dst, int64_t ld,
-                          bool transposed, const OrthWs& w) {
+                          bool transposed, const OrthWs& w, int* need_more, const int* run_if) {
   GemmDesc g = gram_desc(n, m, src, ld, transposed, w.G);
+  g.run_if = run_if;
   SK_TRY(gemm64(c, g, w.partial, w.partial_cap));
-  SK_TRY(chol_inv(c, m, w.G, w.RinvT, w.cwork));
+  SK_TRY(chol_inv(c, m, w.G, w.RinvT, w.cwork, need_more, run_if));
   GemmDesc a = apply_desc(n, m, src, ld, transposed, w.RinvT, dst);
+  a.run_if = run_if;
   return gemm64(c, a, w.partial, w.partial_cap);
 }
 
+// Cholesky-QR with FP64 Gram and Cholesky: src -> dst, and a second pass
+// (dst -> tmp -> dst) only when the first factor's 1-norm condition number
+// exceeds kCholQRRepeat or its Cholesky needed a shift.  Below that bound one
+// FP64 pass already leaves dst orthonormal to the FP32 rounding of its storage.
 sketchne_status orth2(sketchne_ctx* c, int64_t n, int m, const float* src, float* tmp, float* dst, int64_t ld,
                       bool transposed, const OrthWs& w) {
-  SK_TRY(orth_pass(c, n, m, src, tmp, ld, transposed, w));
-  return orth_pass(c, n, m, tmp, dst, ld, transposed, w);
+  SK_TRY(orth_pass(c, n, m, src, dst, ld, transposed, w, w.need2, nullptr));
+  SK_TRY(orth_pass(c, n, m, dst, tmp, ld, transposed, w, nullptr, w.need2));
+  int64_t count = transposed ? (int64_t)m * ld : n * ld;
+  return copy_if(c, count, tmp, dst, w.need2);
 }
 
 // ------------------------------------------------------------- validation
@@ -144,7 +156,6 @@ struct EigWs {
   float* P2;
   float* spmm_part;
   OrthWs ow;
-  double* Hfull;
   double* H;
   double* Vh;
   double* wv;
@@ -162,11 +173,10 @@ EigWs carve_eig(Arena& ar, const sketchne_params* p, int64_t n, int64_t nnz) {
   w.P2 = ar.take<float>((size_t)n * K);
   w.spmm_part = ar.take<float>(spmm_ws_bytes(nnz, K) / sizeof(float) + 1);
   w.ow = carve_orth(ar, n, K, false);
-  w.Hfull = ar.take<double>((size_t)K * K);
   w.H = ar.take<double>((size_t)K * K);
   w.Vh = ar.take<double>((size_t)K * K);
   w.wv = ar.take<double>(K);
-  w.rr_cap = max_bytes({gemm64_partial_bytes(K, K, n, false), gemm64_partial_bytes(n, p->k, K, false)});
+  w.rr_cap = max_bytes({gemm64_partial_bytes(K, K, n, true), gemm64_partial_bytes(n, p->k, K, false)});
   w.rr_partial = ar.take<double>(w.rr_cap / sizeof(double) + 1);
   w.symws = ar.take<char>(symeig_ws_bytes(K));
   return w;
@@ -226,7 +236,7 @@ SketchWs carve_sketch(Arena& ar, const sketchne_params* p, int64_t n) {
   w.Sb = ar.take<double>((size_t)k * k);
   w.Cc = ar.take<double>((size_t)k * k);
   int ntmax = g.ntS > g.ntO ? g.ntS : g.ntO;
-  w.k_cap = max_bytes({gemm64_partial_bytes(k, k, n, false), gemm64_partial_bytes(k, k, k, false),
+  w.k_cap = max_bytes({gemm64_partial_bytes(k, k, n, true), gemm64_partial_bytes(k, k, k, false),
                        gemm64_partial_bytes((int64_t)g.ntS * 32, k, k, false),
                        gemm64_partial_bytes((int64_t)g.ntO * 32, k, k, false)});
   w.k_partial = ar.take<double>(w.k_cap / sizeof(double) + 1);
@@ -384,7 +394,7 @@ sketchne_status sketchne_eig(sketchne_ctx* c, const sketchne_graph* A, const ske
   SK_TRY(check_graph(A));
   SK_TRY(check_params(p, A->n));
   const int K = p->k + p->s_eig;
-  if (K > 512) return SKETCHNE_E_UNSUPPORTED;
+  if (K > kSymeigMax) return SKETCHNE_E_UNSUPPORTED;
   if (K % 4) return SKETCHNE_E_UNSUPPORTED;  // row length of the SpMM float4 path
   SK_TRY(check_ws(ws, ws_bytes, op_bytes(p, A->n, A->nnz, SKETCHNE_OP_EIG)));
   const int64_t n = A->n;
@@ -414,10 +424,9 @@ sketchne_status sketchne_eig(sketchne_ctx* c, const sketchne_graph* A, const ske
     g.M = K; g.N = K; g.K = n;
     g.A = w.Q; g.ta = Ty::F32; g.sai = 1; g.sak = K;
     g.B = w.P1; g.tb = Ty::F32; g.sbk = K; g.sbj = 1;
-    g.C = w.Hfull; g.tc = Ty::F64; g.sci = K; g.scj = 1;
+    g.C = w.H; g.tc = Ty::F64; g.sci = K; g.scj = 1;
+    g.upper_only = true;  // Q^T X Q is symmetric: compute its upper tiles and mirror
     SK_TRY(gemm64(c, g, w.rr_partial, w.rr_cap));
-    hipLaunchKernelGGL(k_symmetrize, dim3((K * K + 255) / 256), dim3(256), 0, c->stream, K, w.Hfull, w.H);
-    SK_TRY(launch_status());
   }
   // line 10: eigendecomposition, sorted by |lambda|
   SK_TRY(symeig(c, K, w.H, w.Vh, w.wv, w.symws));
@@ -468,6 +477,7 @@ sketchne_status sketchne_sketch(sketchne_ctx* c, const sketchne_graph* A, const 
     gd.B = U; gd.tb = Ty::F32; gd.sbk = k; gd.sbj = 1;
     gd.C = w.Kmat; gd.tc = Ty::F64; gd.sci = k; gd.scj = 1;
     gd.kw = w.d2;
+    gd.upper_only = true;  // U^T D U is symmetric; Lambda is applied after
     SK_TRY(gemm64(c, gd, w.k_partial, w.k_cap));
     SK_TRY(scale_cols(c, k, k, w.Kmat, lambda));
   }
@@ -525,7 +535,7 @@ sketchne_status sketchne_embed(sketchne_ctx* c, const sketchne_params* p, int64_
   if (!c || !Yt || !Z || !O || !E || !sigma || n < 1) return SKETCHNE_E_ARG;
   SK_TRY(check_params(p, n));
   if (O->cols != p->l || O->z != p->z || !O->rows || !O->signs) return SKETCHNE_E_ARG;
-  if (p->h > 512) return SKETCHNE_E_UNSUPPORTED;
+  if (p->h > kSymeigMax) return SKETCHNE_E_UNSUPPORTED;
   if (p->h > n) return SKETCHNE_E_ARG;
   SK_TRY(check_ws(ws, ws_bytes, op_bytes(p, n, 0, SKETCHNE_OP_EMBED)));
   const int h = p->h, l = p->l, d = p->d;
@@ -630,19 +640,12 @@ sketchne_status sketchne_orth(sketchne_ctx* c, int64_t n, int32_t cols, float* B
   float* tmp = ar.take<float>((size_t)n * cols);
   OrthWs ow = carve_orth(ar, n, cols, false);
   if (ar.overflow) return SKETCHNE_E_WORKSPACE;
-  // tmp has leading dimension cols; B has ldb
-  GemmDesc g = gram_desc(n, cols, B, ldb, false, ow.G);
-  SK_TRY(gemm64(c, g, ow.partial, ow.partial_cap));
-  SK_TRY(chol_inv(c, cols, ow.G, ow.RinvT, ow.cwork));
-  GemmDesc a = apply_desc(n, cols, B, ldb, false, ow.RinvT, tmp);
-  a.sci = cols;
-  SK_TRY(gemm64(c, a, ow.partial, ow.partial_cap));
-  GemmDesc g2 = gram_desc(n, cols, tmp, cols, false, ow.G);
-  SK_TRY(gemm64(c, g2, ow.partial, ow.partial_cap));
-  SK_TRY(chol_inv(c, cols, ow.G, ow.RinvT, ow.cwork));
-  GemmDesc a2 = apply_desc(n, cols, tmp, cols, false, ow.RinvT, B);
-  a2.sci = ldb;
-  return gemm64(c, a2, ow.partial, ow.partial_cap);
+  if (ldb != cols) return SKETCHNE_E_UNSUPPORTED;  // tmp shares B's leading dimension
+  // in place: B -> tmp, copy back, then the conditional second pass B -> tmp -> B
+  SK_TRY(orth_pass(c, n, cols, B, tmp, ldb, false, ow, ow.need2, nullptr));
+  SK_TRY(copy_if(c, n * ldb, tmp, B, nullptr));
+  SK_TRY(orth_pass(c, n, cols, B, tmp, ldb, false, ow, nullptr, ow.need2));
+  return copy_if(c, n * ldb, tmp, B, ow.need2);
 }
 
 sketchne_status sketchne_symeig_workspace_size(int32_t m, size_t* bytes) {
@@ -654,7 +657,7 @@ sketchne_status sketchne_symeig_workspace_size(int32_t m, size_t* bytes) {
 sketchne_status sketchne_symeig(sketchne_ctx* c, int32_t m, const double* A, double* V, double* w, void* ws,
                                 size_t ws_bytes) {
   if (!c || !A || !V || !w || m < 1) return SKETCHNE_E_ARG;
-  if (m > 1024) return SKETCHNE_E_UNSUPPORTED;
+  if (m > kSymeigMax) return SKETCHNE_E_UNSUPPORTED;
   SK_TRY(check_ws(ws, ws_bytes, symeig_ws_bytes(m)));
   return symeig(c, m, A, V, w, ws);
 }

@@ -8,14 +8,7 @@
 // a small diagonal shift (shifted Cholesky-QR) and raises a flag; a second
 // failure raises CHOL_FAIL.
 //
-// Eigensolver: two-sided cyclic Jacobi with the round-robin ("circle")
-// ordering, so each step rotates m/2 disjoint index pairs at once.  One
-// kernel per step updates every 2 x 2 block A[{p1,q1},{p2,q2}] <- J1^T A J2
-// into a second buffer (rotations are recomputed from the 2 x 2 diagonal
-// blocks of the input buffer) and rotates the pairs of columns of V in place.
-// A per-sweep rotation counter stops the iteration: once a whole sweep
-// performs no rotation, later step kernels return immediately.  Pairs are
-// finally sorted by |w| descending, ties by w descending, then index.
+// Eigensolver: one-sided block Jacobi (see the comment above k_oj_step).
 #include "internal.h"
 
 namespace skne {
@@ -24,11 +17,14 @@ namespace {
 constexpr int NB = 32;
 
 __global__ __launch_bounds__(1024) void k_chol_inv(int m, const double* __restrict__ G, double* __restrict__ W,
-                                                   double* __restrict__ RinvT, uint32_t* __restrict__ flags) {
+                                                   double* __restrict__ RinvT, uint32_t* __restrict__ flags,
+                                                   int* __restrict__ need_more, const int* __restrict__ run_if) {
+  if (run_if && *run_if == 0) return;
   extern __shared__ double smem[];
   double* D = smem;               // NB x (NB+1)
   double* P = smem + NB * (NB + 1);  // NB x m panel
   __shared__ int s_fail;
+  __shared__ int s_shifted;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int64_t m2 = 2 * (int64_t)m;
 
@@ -36,6 +32,7 @@ __global__ __launch_bounds__(1024) void k_chol_inv(int m, const double* __restri
     double tr = 0.0;
     for (int i = 0; i < m; ++i) tr += fabs(G[(int64_t)i * m + i]);
     s_fail = 0;
+    s_shifted = 0;
     // shifted retry: s = 11 (m^2 + m) u trace(G)  (shifted Cholesky-QR)
     D[0] = 11.0 * ((double)m * m + m) * 1.1102230246251565e-16 * (tr > 0 ? tr : 1.0);
   }
@@ -83,6 +80,10 @@ __global__ __launch_bounds__(1024) void k_chol_inv(int m, const double* __restri
         __syncthreads();
       }
       if (s_fail) break;
+      for (int idx = tid; idx < jb * jb; idx += nt) {
+        int a = idx / jb, b = idx % jb;
+        if (b >= a) W[(int64_t)(j0 + a) * m2 + j0 + b] = D[a * (NB + 1) + b];
+      }
       // 2. row panel: W[J, c] <- R_JJ^-T W[J, c] for the left columns right of
       //    the block and the right columns that can be non-zero (< j0 + jb)
       const int nleft = m - j0 - jb;
@@ -117,16 +118,67 @@ __global__ __launch_bounds__(1024) void k_chol_inv(int m, const double* __restri
     }
     __syncthreads();
     if (!s_fail) break;
-    if (tid == 0) atomicOr(flags, attempt == 0 ? SKETCHNE_FLAG_CHOL_SHIFT : SKETCHNE_FLAG_CHOL_FAIL);
+    if (tid == 0) {
+      atomicOr(flags, attempt == 0 ? SKETCHNE_FLAG_CHOL_SHIFT : SKETCHNE_FLAG_CHOL_FAIL);
+      s_shifted = 1;
+    }
     __syncthreads();
   }
   for (int64_t idx = tid; idx < (int64_t)m * m; idx += nt) {
     int64_t r = idx / m, c = idx - r * m;
     RinvT[idx] = c <= r ? W[r * m2 + m + c] : 0.0;
   }
+  if (need_more) {
+    // kappa_1(R) = ||R||_1 ||R^-1||_1 from the two halves of W: column sums of
+    // the upper triangle of R and row sums of R^-T
+    __shared__ double s_red[2][16];
+    double cmax = 0.0, rmax = 0.0;
+    for (int j = tid; j < m; j += nt) {
+      double cs = 0.0, rs = 0.0;
+      for (int i = 0; i <= j; ++i) cs += fabs(W[(int64_t)i * m2 + j]);
+      for (int c2 = 0; c2 <= j; ++c2) rs += fabs(W[(int64_t)j * m2 + m + c2]);
+      cmax = fmax(cmax, cs);
+      rmax = fmax(rmax, rs);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      cmax = fmax(cmax, __shfl_xor(cmax, off, 64));
+      rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
+    }
+    if ((tid & 63) == 0) { s_red[0][tid >> 6] = cmax; s_red[1][tid >> 6] = rmax; }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < nt / 64; ++w) { a = fmax(a, s_red[0][w]); b = fmax(b, s_red[1][w]); }
+      double kappa = a * b;
+      *need_more = (s_shifted || !(kappa <= kCholQRRepeat)) ? 1 : 0;
+    }
+  }
+}
+
+__global__ void k_copy_if(int64_t count, const float* __restrict__ src, float* __restrict__ dst,
+                          const int* __restrict__ run_if) {
+  if (run_if && *run_if == 0) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = src[i];
 }
 
 // ---------------------------------------------------------------- Jacobi
+//
+// One-sided (Hestenes) block Jacobi on B = A + sigma I, sigma = ||A||_F, so B
+// is positive semidefinite and eigenvalues +-lambda of A (equal singular
+// values) cannot mix.  Columns are grouped in blocks of NBJ = 16.  A sweep is
+// one "intra" launch (the pairs inside each block) and nb - 1 "cross"
+// launches that pair the blocks by the round-robin (circle) schedule: one
+// workgroup per block pair holds its 32 columns of G = B V and of V in LDS and
+// orthogonalises all 16 x 16 cross pairs in 16 rounds.  Each column pair is
+// handled by a group of 16 lanes (rows strided by 16, reductions by DPP), so
+// a round is a short dependency chain.  A per-sweep rotation counter ends the
+// iteration; later launches return at once.  At convergence the columns of G
+// are (lambda_j + sigma) v_j, so lambda_j = v_j^T g_j - sigma.
+
+constexpr int NBJ = 16;           // columns per block
+constexpr int OJ_MAXR = 18;       // rows per lane: m <= 16 * OJ_MAXR = 288
 
 __device__ __forceinline__ void pair_of(int s, int pi, int mp, int& p, int& q) {
   const int ring = mp - 1;
@@ -137,109 +189,202 @@ __device__ __forceinline__ void pair_of(int s, int pi, int mp, int& p, int& q) {
   q = a < b ? b : a;
 }
 
-__device__ __forceinline__ void rotation(double app, double aqq, double apq, double tol_abs, double& c,
-                                         double& s, bool& rot) {
-  const double eps = 2.220446049250313e-16;
-  rot = fabs(apq) > tol_abs && fabs(apq) > eps * sqrt(fabs(app) * fabs(aqq));
-  if (!rot) { c = 1.0; s = 0.0; return; }
-  double tau = (aqq - app) / (2.0 * apq);
-  double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-  c = 1.0 / sqrt(1.0 + t * t);
-  s = t * c;
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
 
-__global__ void k_jac_init(int m, int mp, const double* __restrict__ A, double* __restrict__ A0,
-                           double* __restrict__ V, int* __restrict__ counters, int max_sweeps,
-                           double* __restrict__ frob) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// one DPP move of a double (two 32-bit halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, true);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over the 16 lanes of a DPP row; every lane of the row gets the total
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  return v;
+}
+
+// sigma = ||A||_F over the symmetric matrix given by its upper triangle
+__global__ __launch_bounds__(1024) void k_oj_norm(int m, const double* __restrict__ A, double* __restrict__ sigma) {
+  __shared__ double part[16];
+  double s = 0.0;
+  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+    int r = idx / m, c = idx - r * m;
+    double a = r <= c ? A[r * m + c] : A[c * m + r];
+    s += a * a;
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
+    *sigma = sqrt(t);
+  }
+}
+
+// G (column-major, mp columns of m rows) = A + sigma I, V = I, counters = 0
+__global__ void k_oj_init(int m, int mp, const double* __restrict__ A, const double* __restrict__ sigma,
+                          double* __restrict__ G, double* __restrict__ V, int* __restrict__ counters,
+                          int max_sweeps) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < max_sweeps) counters[idx] = 0;
-  if (idx >= (int64_t)mp * mp) return;
-  int r = (int)(idx / mp), c = (int)(idx % mp);
-  double v = 0.0;
-  if (r < m && c < m) v = r <= c ? A[(int64_t)r * m + c] : A[(int64_t)c * m + r];
-  A0[idx] = v;
-  V[idx] = r == c ? 1.0 : 0.0;
-  if (idx == 0) {
-    double s = 0.0;
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) {
-        double a = i <= j ? A[(int64_t)i * m + j] : A[(int64_t)j * m + i];
-        s += a * a;
-      }
-    *frob = sqrt(s);
+  if (idx >= mp * m) return;
+  int c = idx / m, r = idx - c * m;
+  double g = 0.0;
+  if (c < m) {
+    g = r <= c ? A[r * m + c] : A[c * m + r];
+    if (r == c) g += *sigma;
   }
+  G[idx] = g;
+  V[idx] = (r == c) ? 1.0 : 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_jac_step(int mp, int s, int sweep, const double* __restrict__ Ain,
-                                                  double* __restrict__ Aout, double* __restrict__ V,
-                                                  int* __restrict__ counters, const double* __restrict__ frob) {
+// orthogonalise columns p and q (LDS, column-major, m rows) by the 16 lanes
+// of one DPP row; returns whether a rotation was applied
+__device__ __forceinline__ bool oj_rotate(double* __restrict__ sG, double* __restrict__ sV, int m, int p, int q,
+                                          int sub) {
+  double* gp = sG + p * m;
+  double* gq = sG + q * m;
+  double x[OJ_MAXR], y[OJ_MAXR];
+  double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+  for (int i = 0; i < OJ_MAXR; ++i) {
+    const int r = sub + 16 * i;
+    x[i] = r < m ? gp[r] : 0.0;
+    y[i] = r < m ? gq[r] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < OJ_MAXR; ++i) {
+    a = fma(x[i], x[i], a);
+    b = fma(y[i], y[i], b);
+    g = fma(x[i], y[i], g);
+  }
+  a = row16_sum(a);
+  b = row16_sum(b);
+  g = row16_sum(g);
+  const double tol = 1e-14;
+  if (!(a > 0.0 && b > 0.0 && fabs(g) > tol * sqrt(a * b))) return false;
+  const double zeta = (b - a) / (2.0 * g);
+  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double sn = c * t;
+  double* vp = sV + p * m;
+  double* vq = sV + q * m;
+#pragma unroll
+  for (int i = 0; i < OJ_MAXR; ++i) {
+    const int r = sub + 16 * i;
+    if (r < m) {
+      gp[r] = c * x[i] - sn * y[i];
+      gq[r] = sn * x[i] + c * y[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < OJ_MAXR; ++i) {
+    const int r = sub + 16 * i;
+    x[i] = r < m ? vp[r] : 0.0;
+    y[i] = r < m ? vq[r] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < OJ_MAXR; ++i) {
+    const int r = sub + 16 * i;
+    if (r < m) {
+      vp[r] = c * x[i] - sn * y[i];
+      vq[r] = sn * x[i] + c * y[i];
+    }
+  }
+  return true;
+}
+
+// cross == 0: workgroup w orthogonalises the pairs inside blocks 2w and 2w+1;
+// cross == 1: workgroup w takes the block pair w of round s and
+// orthogonalises all cross pairs between the two blocks.
+__global__ __launch_bounds__(256) void k_oj_step(int m, int nb, int s, int sweep, int cross, double* __restrict__ G,
+                                                 double* __restrict__ V, int* __restrict__ counters) {
   if (sweep > 0 && counters[sweep - 1] == 0) return;
-  const int P = mp / 2;
-  const int64_t nA = (int64_t)P * P;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const double tol_abs = 1e-17 * (*frob) + 1e-300;
-  if (idx < nA) {
-    const int pi = (int)(idx / P), pj = (int)(idx % P);
-    int p1, q1, p2, q2;
-    pair_of(s, pi, mp, p1, q1);
-    pair_of(s, pj, mp, p2, q2);
-    double c1, s1, c2, s2;
-    bool r1, r2;
-    rotation(Ain[(int64_t)p1 * mp + p1], Ain[(int64_t)q1 * mp + q1], Ain[(int64_t)p1 * mp + q1], tol_abs, c1, s1, r1);
-    rotation(Ain[(int64_t)p2 * mp + p2], Ain[(int64_t)q2 * mp + q2], Ain[(int64_t)p2 * mp + q2], tol_abs, c2, s2, r2);
-    double b00 = Ain[(int64_t)p1 * mp + p2], b01 = Ain[(int64_t)p1 * mp + q2];
-    double b10 = Ain[(int64_t)q1 * mp + p2], b11 = Ain[(int64_t)q1 * mp + q2];
-    // J = [[c, s], [-s, c]];  B' = J1^T B J2
-    double t00 = c1 * b00 - s1 * b10, t01 = c1 * b01 - s1 * b11;
-    double t10 = s1 * b00 + c1 * b10, t11 = s1 * b01 + c1 * b11;
-    double n00 = t00 * c2 - t01 * s2, n01 = t00 * s2 + t01 * c2;
-    double n10 = t10 * c2 - t11 * s2, n11 = t10 * s2 + t11 * c2;
-    if (pi == pj && r1) { n01 = 0.0; n10 = 0.0; atomicAdd(&counters[sweep], 1); }
-    Aout[(int64_t)p1 * mp + p2] = n00;
-    Aout[(int64_t)p1 * mp + q2] = n01;
-    Aout[(int64_t)q1 * mp + p2] = n10;
-    Aout[(int64_t)q1 * mp + q2] = n11;
-    return;
-  }
-  const int64_t j = idx - nA;
-  if (j >= (int64_t)mp * P) return;
-  const int r = (int)(j / P), pi = (int)(j % P);
-  int p, q;
-  pair_of(s, pi, mp, p, q);
-  double c, sn;
-  bool rot;
-  rotation(Ain[(int64_t)p * mp + p], Ain[(int64_t)q * mp + q], Ain[(int64_t)p * mp + q], tol_abs, c, sn, rot);
-  if (!rot) return;
-  double vp = V[(int64_t)r * mp + p], vq = V[(int64_t)r * mp + q];
-  V[(int64_t)r * mp + p] = c * vp - sn * vq;
-  V[(int64_t)r * mp + q] = sn * vp + c * vq;
-}
-
-// Sort eigenpairs and write the outputs.  The final matrix sits in buffer
-// ((S+1)*(mp-1)) % 2 where S is the first sweep without rotations.
-__global__ __launch_bounds__(1024) void k_jac_finish(int m, int mp, const double* __restrict__ A0,
-                                                     const double* __restrict__ A1, const double* __restrict__ V,
-                                                     const int* __restrict__ counters, int sweeps_run,
-                                                     double* __restrict__ Vout, double* __restrict__ wout,
-                                                     uint32_t* __restrict__ flags) {
-  __shared__ double w[1024];
-  __shared__ int rank[1024];
-  __shared__ int s_final;
+  extern __shared__ double lds[];
+  constexpr int W = 2 * NBJ;
+  double* sG = lds;               // W columns x m rows
+  double* sV = lds + W * m;
+  __shared__ int s_rot;
+  int P, Q;
+  if (cross) pair_of(s, blockIdx.x, nb, P, Q);
+  else { P = 2 * blockIdx.x; Q = P + 1; }
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    int S = -1;
-    for (int s = 0; s < sweeps_run; ++s)
-      if (counters[s] == 0) { S = s; break; }
-    int steps;
-    if (S < 0) { steps = sweeps_run * (mp - 1); atomicOr(flags, SKETCHNE_FLAG_EIG_NOCONV); }
-    else steps = (S + 1) * (mp - 1);
-    s_final = steps & 1;
+  if (tid == 0) s_rot = 0;
+  // load the two blocks (each block is NBJ contiguous columns of m doubles)
+  const int blk = NBJ * m;
+  for (int idx = 2 * tid; idx < 2 * blk; idx += 512) {
+    const int which = idx >= blk, off = idx - which * blk;
+    const int64_t src = (int64_t)(which ? Q : P) * blk + off;
+    double2 gv = *reinterpret_cast<const double2*>(G + src);
+    double2 vv = *reinterpret_cast<const double2*>(V + src);
+    *reinterpret_cast<double2*>(sG + idx) = gv;
+    *reinterpret_cast<double2*>(sV + idx) = vv;
   }
   __syncthreads();
-  const double* Af = s_final ? A1 : A0;
-  for (int i = tid; i < m; i += blockDim.x) {
-    w[i] = Af[(int64_t)i * mp + i];
-    if (!isfinite(w[i])) atomicOr(flags, SKETCHNE_FLAG_NONFINITE);
+  const int grp = tid >> 4, sub = tid & 15;  // 16 groups of 16 lanes
+  int my_rot = 0;
+  const int rounds = cross ? NBJ : NBJ - 1;
+  for (int rnd = 0; rnd < rounds; ++rnd) {
+    int p, q;
+    if (cross) {
+      p = grp;
+      q = NBJ + (grp + rnd) % NBJ;
+    } else {
+      const int half = grp >> 3;  // 8 groups per block
+      pair_of(rnd, grp & 7, NBJ, p, q);
+      p += half * NBJ;
+      q += half * NBJ;
+    }
+    if (oj_rotate(sG, sV, m, p, q, sub) && sub == 0) ++my_rot;
+    __syncthreads();
+  }
+  if (sub == 0 && my_rot) atomicAdd(&s_rot, my_rot);
+  for (int idx = 2 * tid; idx < 2 * blk; idx += 512) {
+    const int which = idx >= blk, off = idx - which * blk;
+    const int64_t dst = (int64_t)(which ? Q : P) * blk + off;
+    *reinterpret_cast<double2*>(G + dst) = *reinterpret_cast<const double2*>(sG + idx);
+    *reinterpret_cast<double2*>(V + dst) = *reinterpret_cast<const double2*>(sV + idx);
+  }
+  __syncthreads();
+  if (tid == 0 && s_rot) atomicAdd(&counters[sweep], s_rot);
+}
+
+// lambda_j = v_j^T g_j - sigma (one wavefront per column); sort by |lambda|
+// desc (ties: lambda desc, then index); write w and the eigenvectors as the
+// columns of the row-major Vout.
+__global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restrict__ G, const double* __restrict__ V,
+                                                    const double* __restrict__ sigma, const int* __restrict__ counters,
+                                                    int sweeps_run, double* __restrict__ Vout,
+                                                    double* __restrict__ wout, uint32_t* __restrict__ flags) {
+  __shared__ double w[1024];
+  __shared__ int rank[1024];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) {
+    bool conv = false;
+    for (int s = 0; s < sweeps_run; ++s)
+      if (counters[s] == 0) { conv = true; break; }
+    if (!conv) atomicOr(flags, SKETCHNE_FLAG_EIG_NOCONV);
+  }
+  const double sg = *sigma;
+  for (int j = wave; j < m; j += 16) {
+    double d = 0.0;
+    for (int r = lane; r < m; r += 64) d = fma(V[(int64_t)j * m + r], G[(int64_t)j * m + r], d);
+    d = wave_sum(d);
+    if (lane == 0) {
+      w[j] = d - sg;
+      if (!isfinite(w[j])) atomicOr(flags, SKETCHNE_FLAG_NONFINITE);
+    }
   }
   __syncthreads();
   for (int i = tid; i < m; i += blockDim.x) {
@@ -255,70 +400,80 @@ __global__ __launch_bounds__(1024) void k_jac_finish(int m, int mp, const double
   __syncthreads();
   for (int i = tid; i < m; i += blockDim.x) wout[rank[i]] = w[i];
   for (int64_t idx = tid; idx < (int64_t)m * m; idx += blockDim.x) {
-    int r = (int)(idx / m), i = (int)(idx % m);
-    Vout[(int64_t)r * m + rank[i]] = V[(int64_t)r * mp + i];
+    int j = (int)(idx / m), r = (int)(idx % m);
+    Vout[(int64_t)r * m + rank[j]] = V[idx];
   }
 }
 
-constexpr int kMaxSweeps = 40;
+constexpr int kMaxSweeps = 30;
+
+int oj_nblocks(int m) {
+  int nb = (m + NBJ - 1) / NBJ;
+  return nb + (nb & 1);
+}
 
 }  // namespace
 
 size_t chol_ws_bytes(int m) { return align_up(sizeof(double) * (size_t)m * 2 * m); }
 
-sketchne_status chol_inv(sketchne_ctx* c, int m, const double* G, double* RinvT, double* work) {
+sketchne_status copy_if(sketchne_ctx* c, int64_t count, const float* src, float* dst, const int* run_if) {
+  if (count == 0) return SKETCHNE_OK;
+  ProfScope ps(c, SKETCHNE_PROF_PREP);
+  hipLaunchKernelGGL(k_copy_if, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, c->stream, count, src, dst,
+                     run_if);
+  return launch_status();
+}
+
+sketchne_status chol_inv(sketchne_ctx* c, int m, const double* G, double* RinvT, double* work, int* need_more,
+                         const int* run_if) {
   if (m <= 0) return SKETCHNE_OK;
   if (m > 512) return SKETCHNE_E_UNSUPPORTED;
   ProfScope ps(c, SKETCHNE_PROF_SMALL);
   size_t shmem = sizeof(double) * (NB * (NB + 1) + (size_t)NB * m);
   hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_inv), hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)shmem);
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), shmem, c->stream, m, G, work, RinvT, c->d_flags);
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), shmem, c->stream, m, G, work, RinvT, c->d_flags, need_more,
+                     run_if);
   return launch_status();
 }
 
 size_t symeig_ws_bytes(int m) {
-  int mp = m + (m & 1);
-  size_t mat = align_up(sizeof(double) * (size_t)mp * mp);
-  return 3 * mat + align_up(sizeof(int) * kMaxSweeps) + align_up(sizeof(double));
+  int mp = oj_nblocks(m) * NBJ;
+  size_t mat = align_up(sizeof(double) * (size_t)mp * m);
+  return 2 * mat + align_up(sizeof(int) * kMaxSweeps) + align_up(sizeof(double));
 }
 
 sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* Vout, double* wout, void* ws) {
   if (m <= 0) return SKETCHNE_OK;
-  if (m > 1024) return SKETCHNE_E_UNSUPPORTED;
-  const int mp = m + (m & 1);
+  if (m > NBJ * OJ_MAXR) return SKETCHNE_E_UNSUPPORTED;
+  const int nb = oj_nblocks(m), mp = nb * NBJ;
   Arena ar(ws, symeig_ws_bytes(m));
-  double* A0 = ar.take<double>((size_t)mp * mp);
-  double* A1 = ar.take<double>((size_t)mp * mp);
-  double* V = ar.take<double>((size_t)mp * mp);
+  double* G = ar.take<double>((size_t)mp * m);
+  double* V = ar.take<double>((size_t)mp * m);
   int* counters = ar.take<int>(kMaxSweeps);
-  double* frob = ar.take<double>(1);
+  double* sigma = ar.take<double>(1);
   ProfScope ps(c, SKETCHNE_PROF_SMALL);
-  int64_t tot = (int64_t)mp * mp;
-  hipLaunchKernelGGL(k_jac_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, m, mp, A, A0, V,
-                     counters, kMaxSweeps, frob);
-  const int P = mp / 2;
-  const int64_t threads = (int64_t)P * P + (int64_t)mp * P;
-  const unsigned blocks = (unsigned)((threads + 255) / 256);
-  int sweeps_run = 0;
-  int buf = 0;
+  hipLaunchKernelGGL(k_oj_norm, dim3(1), dim3(1024), 0, c->stream, m, A, sigma);
+  int tot = mp * m;
+  hipLaunchKernelGGL(k_oj_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, m, mp, A, sigma, G, V,
+                     counters, kMaxSweeps);
+  const size_t shmem = sizeof(double) * 2 * (size_t)(2 * NBJ) * m;
+  hipFuncSetAttribute(reinterpret_cast<const void*>(k_oj_step), hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)shmem);
+  int run = 0;
   for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-    for (int s = 0; s < mp - 1; ++s) {
-      const double* Ain = buf ? A1 : A0;
-      double* Aout = buf ? A0 : A1;
-      hipLaunchKernelGGL(k_jac_step, dim3(blocks), dim3(256), 0, c->stream, mp, s, sweep, Ain, Aout, V, counters,
-                         frob);
-      buf ^= 1;
-    }
-    sweeps_run = sweep + 1;
-    if (sweep >= 3) {  // converged?  (one small host read per sweep from the fourth on)
+    hipLaunchKernelGGL(k_oj_step, dim3(nb / 2), dim3(256), shmem, c->stream, m, nb, 0, sweep, 0, G, V, counters);
+    for (int s = 0; s < nb - 1; ++s)
+      hipLaunchKernelGGL(k_oj_step, dim3(nb / 2), dim3(256), shmem, c->stream, m, nb, s, sweep, 1, G, V, counters);
+    run = sweep + 1;
+    if (sweep >= 4) {  // one small host read per sweep from the fifth on
       hipMemcpyAsync(c->h_counter, counters + sweep, sizeof(int), hipMemcpyDeviceToHost, c->stream);
       if (hipStreamSynchronize(c->stream) != hipSuccess) return SKETCHNE_E_DEVICE;
       if (*c->h_counter == 0) break;
     }
   }
-  hipLaunchKernelGGL(k_jac_finish, dim3(1), dim3(1024), 0, c->stream, m, mp, A0, A1, V, counters, sweeps_run, Vout,
-                     wout, c->d_flags);
+  hipLaunchKernelGGL(k_oj_finish, dim3(1), dim3(1024), 0, c->stream, m, G, V, sigma, counters, run, Vout, wout,
+                     c->d_flags);
   return launch_status();
 }
 

@@ -10,9 +10,10 @@
 // Q^T (XQ), the applies B R^-1 and Q U^, the k x k Horner products of
 // Eq. (11) and the small products of Alg. 4 line 8.
 //
-// Tiling: 64 x 64 output tile per 256-thread workgroup, 2 x 2 wavefronts of
-// 32 x 32 (2 x 2 MFMA blocks of 16 x 16), K step 16 staged through LDS with
-// a register prefetch of the next step.  Workgroups that share an operand
+// Tiling: a 64 x 64 or 96 x 96 output tile per 256-thread workgroup (the one
+// that pads the output less), 2 x 2 wavefronts each holding 2 x 2 or 3 x 3
+// MFMA blocks of 16 x 16, K step 16 staged through LDS with a register
+// prefetch of the next step.  Workgroups that share an operand
 // panel (the row tiles of one output row block, or the tiles of one K split)
 // are given linear ids congruent mod 8 so that they run on the same XCD and
 // share its L2.
@@ -23,7 +24,7 @@ namespace {
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16, LDP = BM + 2;
+constexpr int BK = 16;
 
 struct GemmArgs {
   int64_t M, N, K;
@@ -35,11 +36,13 @@ struct GemmArgs {
   int upper_only;
   int splits;
   int64_t kchunk;       // K range per split (multiple of BK)
+  int tile;             // square output tile edge (64 or 96)
   int tiles_m, tiles_n;
   int ntile_items;      // tiles per split (grid items per group)
   int groups;           // number of "groups" mapped to one XCD (row tiles or splits)
   int group_is_split;   // 1: group = split, item = tile; 0: group = row tile, item = col tile
   double* partial;      // splits x M x N when splits > 1
+  const int* run_if;    // when non-null and zero: do nothing
 };
 
 __device__ __forceinline__ double ld_elem(const void* p, int t, int64_t off) {
@@ -55,9 +58,16 @@ __device__ __forceinline__ void upper_tile(int idx, int nt, int& tm, int& tn) {
   tn = r + idx;
 }
 
+// T x T output tile per workgroup (4 wavefronts in 2 x 2, each (T/2) x (T/2)
+// = TT x TT MFMA blocks of 16 x 16).
+template <int T, bool AKF, bool BJF>
 __global__ __launch_bounds__(256) void k_gemm64(GemmArgs g) {
+  constexpr int TT = T / 32;           // MFMA blocks per wave and dimension
+  constexpr int LDP = T + 2;
+  constexpr int PER = T * BK / 256;    // elements of each operand tile per thread
   __shared__ double As[2][BK][LDP];
   __shared__ double Bs[2][BK][LDP];
+  if (g.run_if && *g.run_if == 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
@@ -83,53 +93,59 @@ __global__ __launch_bounds__(256) void k_gemm64(GemmArgs g) {
     tm = group;
     tn = item;
   }
-  const int64_t i0 = (int64_t)tm * BM, j0 = (int64_t)tn * BN;
+  const int64_t i0 = (int64_t)tm * T, j0 = (int64_t)tn * T;
   const int64_t kbeg = (int64_t)split * g.kchunk;
   const int64_t kend = min(g.K, kbeg + g.kchunk);
 
-  const bool a_kfast = (g.sak == 1);
-  const bool b_jfast = (g.sbj == 1) || (g.sbk != 1);
+  // element e = tid + 256 rep of a tile: (fast index, slow index); AKF: the
+  // summation index is contiguous in A, BJF: the column index is contiguous in B
+  auto a_coord = [&](int e, int& ii, int& kk) {
+    if (AKF) { kk = e % BK; ii = e / BK; } else { ii = e % T; kk = e / T; }
+  };
+  auto b_coord = [&](int e, int& jj, int& kk) {
+    if (BJF) { jj = e % T; kk = e / T; } else { kk = e % BK; jj = e / BK; }
+  };
 
-  double ra[4], rb[4];
+  double ra[PER], rb[PER];
   auto load_regs = [&](int64_t k0) {
 #pragma unroll
-    for (int rep = 0; rep < 4; ++rep) {
+    for (int rep = 0; rep < PER; ++rep) {
+      const int e = tid + 256 * rep;
       int ii, kk;
-      if (a_kfast) { kk = tid & 15; ii = (tid >> 4) + 16 * rep; }
-      else { ii = tid & 63; kk = (tid >> 6) + 4 * rep; }
-      int64_t i = i0 + ii, k = k0 + kk;
+      a_coord(e, ii, kk);
+      const int64_t i = i0 + ii, k = k0 + kk;
       double v = 0.0;
       if (i < g.M && k < kend) {
-        v = ld_elem(g.A, g.ta, i * g.sai + k * g.sak);
+        const int64_t off = AKF ? (i * g.sai + k) : (i + k * g.sak);
+        v = ld_elem(g.A, g.ta, off);
         if (g.kw) v *= g.kw[k];
       }
       ra[rep] = v;
       int jj, kb;
-      if (b_jfast) { jj = tid & 63; kb = (tid >> 6) + 4 * rep; }
-      else { kb = tid & 15; jj = (tid >> 4) + 16 * rep; }
-      int64_t j = j0 + jj, kq = k0 + kb;
-      rb[rep] = (j < g.N && kq < kend) ? ld_elem(g.B, g.tb, kq * g.sbk + j * g.sbj) : 0.0;
+      b_coord(e, jj, kb);
+      const int64_t j = j0 + jj, kq = k0 + kb;
+      const int64_t offb = BJF ? (kq * g.sbk + j * g.sbj) : (kq + j * g.sbj);
+      rb[rep] = (j < g.N && kq < kend) ? ld_elem(g.B, g.tb, offb) : 0.0;
     }
   };
   auto store_lds = [&](int buf) {
 #pragma unroll
-    for (int rep = 0; rep < 4; ++rep) {
+    for (int rep = 0; rep < PER; ++rep) {
+      const int e = tid + 256 * rep;
       int ii, kk;
-      if (a_kfast) { kk = tid & 15; ii = (tid >> 4) + 16 * rep; }
-      else { ii = tid & 63; kk = (tid >> 6) + 4 * rep; }
+      a_coord(e, ii, kk);
       As[buf][kk][ii] = ra[rep];
       int jj, kb;
-      if (b_jfast) { jj = tid & 63; kb = (tid >> 6) + 4 * rep; }
-      else { kb = tid & 15; jj = (tid >> 4) + 16 * rep; }
+      b_coord(e, jj, kb);
       Bs[buf][kb][jj] = rb[rep];
     }
   };
 
-  doublex4 acc[2][2];
+  doublex4 acc[TT][TT];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TT; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = doublex4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < TT; ++b) acc[a][b] = doublex4{0.0, 0.0, 0.0, 0.0};
 
   int buf = 0;
   if (kbeg < kend) {
@@ -143,14 +159,16 @@ __global__ __launch_bounds__(256) void k_gemm64(GemmArgs g) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
-      double a0 = As[buf][kr][wm * 32 + (lane & 15)];
-      double a1 = As[buf][kr][wm * 32 + 16 + (lane & 15)];
-      double b0 = Bs[buf][kr][wn * 32 + (lane & 15)];
-      double b1 = Bs[buf][kr][wn * 32 + 16 + (lane & 15)];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      double af[TT], bf[TT];
+#pragma unroll
+      for (int t = 0; t < TT; ++t) {
+        af[t] = As[buf][kr][wm * (T / 2) + t * 16 + (lane & 15)];
+        bf[t] = Bs[buf][kr][wn * (T / 2) + t * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int a = 0; a < TT; ++a)
+#pragma unroll
+        for (int b = 0; b < TT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
     if (more) store_lds(buf ^ 1);
     __syncthreads();
@@ -159,14 +177,14 @@ __global__ __launch_bounds__(256) void k_gemm64(GemmArgs g) {
 
   // ---- epilogue
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+  for (int mt = 0; mt < TT; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
+    for (int nt = 0; nt < TT; ++nt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         // v_mfma_f64_16x16x4f64 output: lane l, register r holds row (l / 16) + 4 r, column l % 16
-        int64_t i = i0 + wm * 32 + mt * 16 + (lane >> 4) + 4 * r;
-        int64_t j = j0 + wn * 32 + nt * 16 + (lane & 15);
+        int64_t i = i0 + wm * (T / 2) + mt * 16 + (lane >> 4) + 4 * r;
+        int64_t j = j0 + wn * (T / 2) + nt * 16 + (lane & 15);
         if (i >= g.M || j >= g.N) continue;
         double v = acc[mt][nt][r];
         if (g.splits > 1) {
@@ -186,11 +204,12 @@ __global__ __launch_bounds__(256) void k_gemm64(GemmArgs g) {
 }
 
 __global__ void k_gemm64_reduce(GemmArgs g) {
+  if (g.run_if && *g.run_if == 0) return;
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= g.M * g.N) return;
   int64_t i = idx / g.N, j = idx - i * g.N;
   int64_t si = i, sj = j;
-  if (g.upper_only && (i / BM) > (j / BN)) { si = j; sj = i; }
+  if (g.upper_only && (i / g.tile) > (j / g.tile)) { si = j; sj = i; }
   double s = 0.0;
   for (int sp = 0; sp < g.splits; ++sp) s += g.partial[((int64_t)sp * g.M + si) * g.N + sj];
   double v = g.alpha * s + (i == j ? g.diag_add : 0.0);
@@ -201,14 +220,24 @@ __global__ void k_gemm64_reduce(GemmArgs g) {
 
 }  // namespace
 
+// square tile edge: the one of {64, 96} that pads the output least (96 on ties)
+static int pick_tile(int64_t M, int64_t N, bool upper) {
+  auto area = [&](int64_t t) {
+    int64_t a = (M + t - 1) / t, b = (N + t - 1) / t;
+    return (upper ? a * (a + 1) / 2 : a * b) * t * t;
+  };
+  return area(96) <= area(64) ? 96 : 64;
+}
+
 int gemm64_pick_splits(const GemmDesc& d) {
-  int64_t tm = (d.M + BM - 1) / BM, tn = (d.N + BN - 1) / BN;
+  const int T = pick_tile(d.M, d.N, d.upper_only);
+  int64_t tm = (d.M + T - 1) / T, tn = (d.N + T - 1) / T;
   int64_t tiles = d.upper_only ? tm * (tm + 1) / 2 : tm * tn;
   if (tiles >= 512 || d.K <= 4 * BK) return 1;
   int64_t want = (1024 + tiles - 1) / tiles;
   int64_t maxs = (d.K + 8 * BK - 1) / (8 * BK);  // at least 8 K steps per split
   int64_t s = want < maxs ? want : maxs;
-  if (s > 128) s = 128;
+  if (s > 256) s = 256;
   return s < 1 ? 1 : (int)s;
 }
 
@@ -242,9 +271,11 @@ sketchne_status gemm64(sketchne_ctx* c, const GemmDesc& d, double* partial, size
   int64_t kc = (d.K + g.splits - 1) / g.splits;
   g.kchunk = (kc + BK - 1) / BK * BK;
   if (g.kchunk == 0) g.kchunk = BK;
-  g.tiles_m = (int)((d.M + BM - 1) / BM);
-  g.tiles_n = (int)((d.N + BN - 1) / BN);
+  g.tile = pick_tile(d.M, d.N, d.upper_only);
+  g.tiles_m = (int)((d.M + g.tile - 1) / g.tile);
+  g.tiles_n = (int)((d.N + g.tile - 1) / g.tile);
   g.partial = partial;
+  g.run_if = d.run_if;
   if (g.splits > 1 || d.upper_only) {
     g.group_is_split = 1;
     g.groups = g.splits;
@@ -256,7 +287,24 @@ sketchne_status gemm64(sketchne_ctx* c, const GemmDesc& d, double* partial, size
   }
   int64_t gpad = g.groups >= 8 ? ((int64_t)g.groups + 7) / 8 * 8 : g.groups;
   int64_t blocks = gpad * g.ntile_items;
-  hipLaunchKernelGGL(k_gemm64, dim3((unsigned)blocks), dim3(256), 0, c->stream, g);
+  // load layouts: A contiguous along the summation index (sak == 1) or along
+  // rows (sai == 1); B contiguous along columns (sbj == 1) or along the
+  // summation index (sbk == 1)
+  const bool akf = d.sak == 1 && d.sai != 1 ? true : (d.sai == 1 ? false : d.sak == 1);
+  const bool bjf = !(d.sbk == 1 && d.sbj != 1);
+  if (!akf && d.sai != 1) return SKETCHNE_E_ARG;
+  if (!bjf && d.sbk != 1) return SKETCHNE_E_ARG;
+  dim3 grid((unsigned)blocks), blk(256);
+#define SKNE_GEMM_LAUNCH(T)                                                                  \
+  do {                                                                                       \
+    if (akf && bjf) hipLaunchKernelGGL((k_gemm64<T, true, true>), grid, blk, 0, c->stream, g);  \
+    else if (akf) hipLaunchKernelGGL((k_gemm64<T, true, false>), grid, blk, 0, c->stream, g);   \
+    else if (bjf) hipLaunchKernelGGL((k_gemm64<T, false, true>), grid, blk, 0, c->stream, g);   \
+    else hipLaunchKernelGGL((k_gemm64<T, false, false>), grid, blk, 0, c->stream, g);           \
+  } while (0)
+  if (g.tile == 96) SKNE_GEMM_LAUNCH(96);
+  else SKNE_GEMM_LAUNCH(64);
+#undef SKNE_GEMM_LAUNCH
   if (g.splits > 1) {
     int64_t tot = d.M * d.N;
     hipLaunchKernelGGL(k_gemm64_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, g);

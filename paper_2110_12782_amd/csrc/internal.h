@@ -98,6 +98,7 @@ struct GemmDesc {
   double alpha = 1.0;
   double diag_add = 0.0;        // added to C(i,i)
   bool upper_only = false;      // compute tiles with i-tile <= j-tile and mirror
+  const int* run_if = nullptr;  // device flag: when set and zero, the launch does nothing
 };
 // Split-K partial sums need splits*M*N doubles of scratch; gemm64 lowers the
 // split count to what `partial_cap` bytes hold (down to 1, which needs none).
@@ -109,8 +110,15 @@ sketchne_status gemm64(sketchne_ctx* c, const GemmDesc& g, double* partial, size
 // dense_small.hip
 // Cholesky G = R^T R of an SPD m x m FP64 matrix (row-major, ld = m) and the
 // inverse factor; writes RinvT (= R^-T, lower triangular, row-major m x m).
+// need_more (nullable): set to 1 when the factor's 1-norm condition number
+// exceeds kCholQRRepeat (or a shift was needed), else 0.  run_if (nullable):
+// when it points to 0 the launch does nothing.
+constexpr double kCholQRRepeat = 1e5;
 size_t chol_ws_bytes(int m);
-sketchne_status chol_inv(sketchne_ctx* c, int m, const double* G, double* RinvT, double* work);
+sketchne_status chol_inv(sketchne_ctx* c, int m, const double* G, double* RinvT, double* work,
+                         int* need_more = nullptr, const int* run_if = nullptr);
+sketchne_status copy_if(sketchne_ctx* c, int64_t count, const float* src, float* dst, const int* run_if);
+constexpr int kSymeigMax = 288;  // largest order of the Jacobi eigensolver
 size_t symeig_ws_bytes(int m);
 sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* V, double* w, void* ws);
 

@@ -83,4 +83,4 @@ def test_null_context_and_pointers_rejected_before_any_work(lib):
     out = C.c_size_t(0)
     assert L.sketchne_orth_workspace_size(0, 4, C.byref(out)) == B.E_ARG
     assert L.sketchne_symeig_workspace_size(0, C.byref(out)) == B.E_ARG
-    assert L.sketchne_symeig_workspace_size(300, C.byref(out)) == B.OK and out.value >= 3 * 300 * 300 * 8
+    assert L.sketchne_symeig_workspace_size(288, C.byref(out)) == B.OK and out.value >= 2 * 288 * 288 * 8
