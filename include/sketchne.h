@@ -121,7 +121,8 @@ sketchne_status sketchne_workspace_size(const sketchne_params* p, int64_t n, int
  *           Gaussian block on the device from p->seed.
  *   U:      n x k row-major FP32 output (orthonormal columns).
  *   lambda: k FP64 output.
- * Requires k + s_eig <= 288 (order of the Rayleigh-Ritz eigensolver).
+ * Requires k + s_eig <= 288 (order of the Rayleigh-Ritz eigensolver) and
+ * (k + s_eig) % 4 == 0.
  * Orthonormalisation is Cholesky-QR with FP64 Gram and Cholesky; a second
  * pass runs only when the first factor's 1-norm condition number exceeds
  * 1e5 or its Cholesky needed a diagonal shift. */
@@ -136,7 +137,8 @@ sketchne_status sketchne_eig(sketchne_ctx* ctx, const sketchne_graph* A, const s
  * visiting only the rows/columns of f(L'R') that S and O touch (Eq. 4).
  * If generate != 0, S and O are drawn on the device from p->seed and written
  * into S->rows/signs and O->rows/signs; otherwise they are read from there.
- * S->cols must equal h, O->cols must equal l, and both z must equal p->z. */
+ * S->cols must equal h, O->cols must equal l, and both z must equal p->z.
+ * Requires z <= 8 and k % 4 == 0. */
 sketchne_status sketchne_sketch(sketchne_ctx* ctx, const sketchne_graph* A, const sketchne_params* p,
                                 const float* U, const double* lambda,
                                 sketchne_sparse_sign* S, sketchne_sparse_sign* O, int generate,

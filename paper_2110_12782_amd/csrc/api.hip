@@ -50,18 +50,6 @@ struct OrthWs {
   int* need2;
 };
 
-GemmDesc gram_desc(int64_t n, int m, const float* X, int64_t ld, bool transposed, double* G) {
-  GemmDesc g;
-  g.M = m; g.N = m; g.K = n;
-  g.A = X; g.ta = Ty::F32;
-  g.B = X; g.tb = Ty::F32;
-  if (!transposed) { g.sai = 1; g.sak = ld; g.sbk = ld; g.sbj = 1; }
-  else { g.sai = ld; g.sak = 1; g.sbk = 1; g.sbj = ld; }
-  g.C = G; g.tc = Ty::F64; g.sci = m; g.scj = 1;
-  g.upper_only = true;
-  return g;
-}
-
 GemmDesc apply_desc(int64_t n, int m, const float* X, int64_t ld, bool transposed, const double* RinvT, float* out) {
   GemmDesc g;
   if (!transposed) {  // out (n x m) = X (n x m) * R^-1 ;  R^-1 (k, j) = RinvT[j][k]
@@ -85,10 +73,8 @@ size_t max_bytes(std::initializer_list<size_t> v) {
 }
 
 size_t orth_partial_bytes(int64_t n, int m, bool transposed) {
-  GemmDesc g = gram_desc(n, m, nullptr, transposed ? n : m, transposed, nullptr);
   GemmDesc a = apply_desc(n, m, nullptr, transposed ? n : m, transposed, nullptr, nullptr);
-  return max_bytes({gemm64_partial_bytes(g.M, g.N, g.K, g.upper_only),
-                    gemm64_partial_bytes(a.M, a.N, a.K, a.upper_only)});
+  return max_bytes({gram_ws_bytes(n, m), gemm64_partial_bytes(a.M, a.N, a.K, a.upper_only)});
 }
 
 OrthWs carve_orth(Arena& ar, int64_t n, int m, bool transposed) {
@@ -106,9 +92,8 @@ OrthWs carve_orth(Arena& ar, int64_t n, int m, bool transposed) {
 // second pass is needed; run_if: the pass runs only when it points to 1.
 sketchne_status orth_pass(sketchne_ctx* c, int64_t n, int m, const float* src, float* dst, int64_t ld,
                           bool transposed, const OrthWs& w, int* need_more, const int* run_if) {
-  GemmDesc g = gram_desc(n, m, src, ld, transposed, w.G);
-  g.run_if = run_if;
-  SK_TRY(gemm64(c, g, w.partial, w.partial_cap));
+  if (!transposed) SK_TRY(gram_tall(c, n, m, src, ld, 1, nullptr, 0, 0, nullptr, w.G, w.partial, w.partial_cap, run_if));
+  else SK_TRY(gram_tall(c, n, m, src, 1, ld, nullptr, 0, 0, nullptr, w.G, w.partial, w.partial_cap, run_if));
   SK_TRY(chol_inv(c, m, w.G, w.RinvT, w.cwork, need_more, run_if));
   GemmDesc a = apply_desc(n, m, src, ld, transposed, w.RinvT, dst);
   a.run_if = run_if;
@@ -176,7 +161,7 @@ EigWs carve_eig(Arena& ar, const sketchne_params* p, int64_t n, int64_t nnz) {
   w.H = ar.take<double>((size_t)K * K);
   w.Vh = ar.take<double>((size_t)K * K);
   w.wv = ar.take<double>(K);
-  w.rr_cap = max_bytes({gemm64_partial_bytes(K, K, n, true), gemm64_partial_bytes(n, p->k, K, false)});
+  w.rr_cap = max_bytes({gram_ws_bytes(n, K), gemm64_partial_bytes(n, p->k, K, false)});
   w.rr_partial = ar.take<double>(w.rr_cap / sizeof(double) + 1);
   w.symws = ar.take<char>(symeig_ws_bytes(K));
   return w;
@@ -236,7 +221,7 @@ SketchWs carve_sketch(Arena& ar, const sketchne_params* p, int64_t n) {
   w.Sb = ar.take<double>((size_t)k * k);
   w.Cc = ar.take<double>((size_t)k * k);
   int ntmax = g.ntS > g.ntO ? g.ntS : g.ntO;
-  w.k_cap = max_bytes({gemm64_partial_bytes(k, k, n, true), gemm64_partial_bytes(k, k, k, false),
+  w.k_cap = max_bytes({gram_ws_bytes(n, k), gemm64_partial_bytes(k, k, k, false),
                        gemm64_partial_bytes((int64_t)g.ntS * 32, k, k, false),
                        gemm64_partial_bytes((int64_t)g.ntO * 32, k, k, false)});
   w.k_partial = ar.take<double>(w.k_cap / sizeof(double) + 1);
@@ -419,15 +404,8 @@ sketchne_status sketchne_eig(sketchne_ctx* c, const sketchne_graph* A, const ske
   }
   // line 9: H = Q^T X Q
   SK_TRY(spmm(c, n, A->nnz, A->rowptr, A->colidx, w.dscale, w.Q, K, K, w.P1, K, w.spmm_part));
-  {
-    GemmDesc g;
-    g.M = K; g.N = K; g.K = n;
-    g.A = w.Q; g.ta = Ty::F32; g.sai = 1; g.sak = K;
-    g.B = w.P1; g.tb = Ty::F32; g.sbk = K; g.sbj = 1;
-    g.C = w.H; g.tc = Ty::F64; g.sci = K; g.scj = 1;
-    g.upper_only = true;  // Q^T X Q is symmetric: compute its upper tiles and mirror
-    SK_TRY(gemm64(c, g, w.rr_partial, w.rr_cap));
-  }
+  // Q^T X Q is symmetric: upper blocks computed and mirrored
+  SK_TRY(gram_tall(c, n, K, w.Q, K, 1, w.P1, K, 1, nullptr, w.H, w.rr_partial, w.rr_cap, nullptr));
   // line 10: eigendecomposition, sorted by |lambda|
   SK_TRY(symeig(c, K, w.H, w.Vh, w.wv, w.symws));
   // line 11: U = Q U^(:, 1:k)
@@ -454,6 +432,7 @@ sketchne_status sketchne_sketch(sketchne_ctx* c, const sketchne_graph* A, const 
   if (S->cols != p->h || O->cols != p->l || S->z != p->z || O->z != p->z) return SKETCHNE_E_ARG;
   if (!S->rows || !S->signs || !O->rows || !O->signs) return SKETCHNE_E_ARG;
   if (p->z > 8) return SKETCHNE_E_UNSUPPORTED;  // group of one lane's accumulators
+  if (p->k % 4) return SKETCHNE_E_UNSUPPORTED;  // float4 rows of U
   SketchGeo g = sketch_geo(p, A->n);
   if (g.KS == 0) return SKETCHNE_E_UNSUPPORTED;
   if (g.zl >= ((int64_t)1 << 31)) return SKETCHNE_E_UNSUPPORTED;
@@ -470,17 +449,9 @@ sketchne_status sketchne_sketch(sketchne_ctx* c, const sketchne_graph* A, const 
   }
   SK_TRY(degree_powers(c, n, A->rowptr, p->alpha, w.d1, w.d2));
   // Alg. 6 line 2: K = U^T D^(-1+2a) U Lambda
-  {
-    GemmDesc gd;
-    gd.M = k; gd.N = k; gd.K = n;
-    gd.A = U; gd.ta = Ty::F32; gd.sai = 1; gd.sak = k;
-    gd.B = U; gd.tb = Ty::F32; gd.sbk = k; gd.sbj = 1;
-    gd.C = w.Kmat; gd.tc = Ty::F64; gd.sci = k; gd.scj = 1;
-    gd.kw = w.d2;
-    gd.upper_only = true;  // U^T D U is symmetric; Lambda is applied after
-    SK_TRY(gemm64(c, gd, w.k_partial, w.k_cap));
-    SK_TRY(scale_cols(c, k, k, w.Kmat, lambda));
-  }
+  // U^T D U is symmetric (upper blocks, mirrored); Lambda is applied after
+  SK_TRY(gram_tall(c, n, k, U, k, 1, nullptr, 0, 0, w.d2, w.Kmat, w.k_partial, w.k_cap, nullptr));
+  SK_TRY(scale_cols(c, k, k, w.Kmat, lambda));
   // Alg. 6 line 3: sum_{r=1..T} K^(r-1) by Horner, C = Lambda * sum
   SK_TRY(identity(c, k, w.Sa));
   double* cur = w.Sa;

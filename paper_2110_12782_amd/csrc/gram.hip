@@ -1,0 +1,291 @@
+// Tall-skinny symmetric products on the FP64 matrix cores:
+//
+//   G = X^T diag(w) Y      (X, Y: n x m FP32, m <= 288; w optional FP64)
+//
+// computed on the upper 16 x 16 blocks only and mirrored, which is exact for
+// the symmetric products of the path (Gram matrices B^T B, Q^T (X Q) and
+// U^T D U).  Each workgroup owns a contiguous range of rows: it
+// (512 threads) streams them through LDS in chunks of 32 rows (double
+// buffered, next chunk
+// prefetched through registers) and keeps the accumulators of its share of
+// the upper blocks of the m x m result in registers.  The blocks are split
+// into two groups handled by two workgroups on the same XCD, so the rows are
+// read from memory once and from the XCD's L2 the second time.  Per-workgroup
+// partial sums are added in a fixed order by a second kernel.
+#include "internal.h"
+
+namespace skne {
+namespace {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int GR_CHUNK = 32;      // rows per LDS chunk
+constexpr int GR_MAXB = 18;       // m <= 16 * GR_MAXB
+constexpr int GR_GROUPS = 2;      // block groups (workgroups per row range)
+constexpr int GR_THREADS = 512;
+constexpr int GR_WAVES = GR_THREADS / 64;
+
+struct GramArgs {
+  int64_t n;
+  int m, nbk, nblk, stride;     // stride: LDS row length in floats
+  const float* X; int64_t xr, xc;   // element (r, i) at X[r*xr + i*xc]
+  const float* Y; int64_t yr, yc;
+  const double* w;
+  int64_t rows_per_wg;
+  int nranges;                  // row ranges
+  int gsize;                    // blocks per group
+  double* partial;              // nranges x nblk x 256
+  const int* run_if;            // when non-null and zero: do nothing
+};
+
+__device__ __forceinline__ void blk_coords(int b, int nbk, int& I, int& J) {
+  int r = 0, len = nbk;
+  while (b >= len) { b -= len; ++r; --len; }
+  I = r;
+  J = r + b;
+}
+
+// ROWMAJ: X and Y rows are contiguous (xc == 1); else columns are (xr == 1).
+template <bool TWO, bool ROWMAJ, int PW>
+__global__ __launch_bounds__(GR_THREADS) void k_gram_tall(GramArgs g) {
+  if (g.run_if && *g.run_if == 0) return;
+  // XCD-aware decode: the two block groups of a row range get linear ids
+  // L and L + 8, i.e. the same XCD, dispatched back to back
+  const int L = blockIdx.x;
+  const int q = L >> 3;
+  const int grp = q % GR_GROUPS;
+  const int range = (q / GR_GROUPS) * 8 + (L & 7);
+  if (range >= g.nranges) return;
+  extern __shared__ float lds[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int S = g.stride;
+  const int CH = GR_CHUNK * S;               // floats per matrix chunk
+  float* bufX[2] = {lds, lds + (TWO ? 2 : 1) * CH};
+  float* bufY[2] = {TWO ? lds + CH : lds, TWO ? lds + 3 * CH : lds + CH};
+  __shared__ double wsh[2][GR_CHUNK];
+
+  const int64_t r0 = (int64_t)range * g.rows_per_wg;
+  const int64_t r1 = min(g.n, r0 + g.rows_per_wg);
+
+  // this wavefront's blocks: slot t is block blk0 + wave + 16 t of the group;
+  // slots past the group compute a copy of its first block and are not stored
+  const int uw = __builtin_amdgcn_readfirstlane(wave);
+  const int blk0 = grp * g.gsize;
+  const int blk1 = min(g.nblk, blk0 + g.gsize);
+  int bI[PW], bJ[PW];
+#pragma unroll
+  for (int t = 0; t < PW; ++t) {
+    int b = blk0 + uw + GR_WAVES * t;
+    if (b >= blk1) b = blk0;
+    blk_coords(b, g.nbk, bI[t], bJ[t]);
+  }
+  doublex4 acc[PW];
+#pragma unroll
+  for (int t = 0; t < PW; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+
+  // chunk loader: element (rr, i) of the chunk starting at row c0
+  const int cols4 = (g.m + 3) / 4;
+  constexpr int MAXV = (GR_CHUNK * GR_MAXB * 16 / 4 + GR_THREADS - 1) / GR_THREADS;  // float4 / thread / matrix
+  float4 px[MAXV], py[MAXV];
+  double pw = 1.0;
+  auto fetch = [&](int64_t c0) {
+#pragma unroll
+    for (int u = 0; u < MAXV; ++u) {
+      int v = tid + GR_THREADS * u;
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+      if (ROWMAJ) {  // m % 4 == 0: whole float4 per row segment
+        int rr = v / cols4, c4 = v - rr * cols4;
+        int64_t r = c0 + rr;
+        if (rr < GR_CHUNK && r < r1) {
+          a = *reinterpret_cast<const float4*>(g.X + r * g.xr + 4 * c4);
+          if (TWO) b = *reinterpret_cast<const float4*>(g.Y + r * g.yr + 4 * c4);
+        }
+      } else {
+        // column-contiguous: 4 consecutive rows of one column
+        int i = v / (GR_CHUNK / 4), q = v - i * (GR_CHUNK / 4);
+        int64_t r = c0 + 4 * q;
+        if (i < g.m) {
+          const float* px0 = g.X + (int64_t)i * g.xc + r;
+          a.x = r < r1 ? px0[0] : 0.f;
+          a.y = r + 1 < r1 ? px0[1] : 0.f;
+          a.z = r + 2 < r1 ? px0[2] : 0.f;
+          a.w = r + 3 < r1 ? px0[3] : 0.f;
+          if (TWO) {
+            const float* py0 = g.Y + (int64_t)i * g.yc + r;
+            b.x = r < r1 ? py0[0] : 0.f;
+            b.y = r + 1 < r1 ? py0[1] : 0.f;
+            b.z = r + 2 < r1 ? py0[2] : 0.f;
+            b.w = r + 3 < r1 ? py0[3] : 0.f;
+          }
+        }
+      }
+      px[u] = a;
+      py[u] = b;
+    }
+    if (g.w && tid < GR_CHUNK) pw = (c0 + tid < r1) ? g.w[c0 + tid] : 0.0;
+  };
+  auto stash = [&](int buf) {
+    float* dx = bufX[buf];
+    float* dy = bufY[buf];
+#pragma unroll
+    for (int u = 0; u < MAXV; ++u) {
+      int v = tid + GR_THREADS * u;
+      if (ROWMAJ) {
+        int rr = v / cols4, c4 = v - rr * cols4;
+        if (rr < GR_CHUNK) {
+          *reinterpret_cast<float4*>(dx + rr * S + 4 * c4) = px[u];
+          if (TWO) *reinterpret_cast<float4*>(dy + rr * S + 4 * c4) = py[u];
+        }
+      } else {
+        int i = v / (GR_CHUNK / 4), q = v - i * (GR_CHUNK / 4);
+        if (i < g.m) {
+          dx[(4 * q) * S + i] = px[u].x;
+          dx[(4 * q + 1) * S + i] = px[u].y;
+          dx[(4 * q + 2) * S + i] = px[u].z;
+          dx[(4 * q + 3) * S + i] = px[u].w;
+          if (TWO) {
+            dy[(4 * q) * S + i] = py[u].x;
+            dy[(4 * q + 1) * S + i] = py[u].y;
+            dy[(4 * q + 2) * S + i] = py[u].z;
+            dy[(4 * q + 3) * S + i] = py[u].w;
+          }
+        }
+      }
+    }
+    if (tid < GR_CHUNK) wsh[buf][tid] = pw;
+  };
+
+  // zero the padding columns of both buffers once (never written by stash)
+  for (int idx = tid; idx < 2 * (TWO ? 2 : 1) * CH; idx += GR_THREADS) {
+    int col = (idx % CH) % S;
+    if (col >= g.m) lds[idx] = 0.f;
+  }
+  int buf = 0;
+  if (r0 < r1) {
+    fetch(r0);
+    stash(0);
+  }
+  __syncthreads();
+  for (int64_t c0 = r0; c0 < r1; c0 += GR_CHUNK) {
+    const bool more = c0 + GR_CHUNK < r1;
+    if (more) fetch(c0 + GR_CHUNK);
+    const float* xs = bufX[buf];
+    const float* ys = bufY[buf];
+#pragma unroll 1
+    for (int s = 0; s < GR_CHUNK / 4; ++s) {
+      const int rr = 4 * s + (lane >> 4);
+      const double wr = g.w ? wsh[buf][rr] : 1.0;
+#pragma unroll
+      for (int t = 0; t < PW; ++t) {
+        double a = (double)xs[rr * S + bI[t] * 16 + (lane & 15)] * wr;
+        double b = (double)ys[rr * S + bJ[t] * 16 + (lane & 15)];
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+      }
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  double* part = g.partial + (int64_t)range * g.nblk * 256;
+#pragma unroll
+  for (int t = 0; t < PW; ++t) {
+    const int b = blk0 + uw + GR_WAVES * t;
+    if (b < blk1) {
+      double* pb = part + (int64_t)b * 256 + lane * 4;
+      pb[0] = acc[t][0];
+      pb[1] = acc[t][1];
+      pb[2] = acc[t][2];
+      pb[3] = acc[t][3];
+    }
+  }
+}
+
+// G[i][j] = G[j][i] = sum over workgroups; element (block, lane, r) of the
+// MFMA output is row I*16 + lane/16 + 4r, column J*16 + lane%16.
+__global__ void k_gram_reduce(int m, int nbk, int nblk, int nwg, const double* __restrict__ partial,
+                              double* __restrict__ G, const int* __restrict__ run_if) {
+  if (run_if && *run_if == 0) return;
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nblk * 256) return;
+  int b = idx >> 8, e = idx & 255, lane = e >> 2, r = e & 3;
+  int I, J;
+  blk_coords(b, nbk, I, J);
+  int i = I * 16 + (lane >> 4) + 4 * r, j = J * 16 + (lane & 15);
+  if (i >= m || j >= m) return;
+  double s = 0.0;
+  for (int w = 0; w < nwg; ++w) s += partial[((int64_t)w * nblk + b) * 256 + e];
+  G[(int64_t)i * m + j] = s;
+  if (I != J) G[(int64_t)j * m + i] = s;
+}
+
+}  // namespace
+
+int gram_nwg(int64_t n) {
+  int64_t chunks = (n + GR_CHUNK - 1) / GR_CHUNK;
+  int64_t nr = chunks < 256 ? chunks : 256;
+  return nr < 1 ? 1 : (int)nr;
+}
+
+size_t gram_ws_bytes(int64_t n, int m) {
+  int nbk = (m + 15) / 16;
+  int nblk = nbk * (nbk + 1) / 2;
+  return align_up(sizeof(double) * (size_t)gram_nwg(n) * nblk * 256);
+}
+
+// X, Y: element (r, i) at X[r*xr + i*xc]; either xc == 1 (rows contiguous)
+// or xr == 1 (columns contiguous).  Y may equal X (then pass Y = nullptr).
+sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int64_t xr, int64_t xc, const float* Y,
+                          int64_t yr, int64_t yc, const double* w, double* G, double* partial, size_t partial_cap,
+                          const int* run_if) {
+  if (m < 1 || m > 16 * GR_MAXB) return SKETCHNE_E_UNSUPPORTED;
+  const bool rowmaj = (xc == 1);
+  if (!rowmaj && xr != 1) return SKETCHNE_E_ARG;
+  if (Y && ((rowmaj && yc != 1) || (!rowmaj && yr != 1))) return SKETCHNE_E_ARG;
+  if (rowmaj && ((m % 4) || (xr % 4) || (Y && (yr % 4)))) return SKETCHNE_E_ARG;  // float4 rows
+  if (partial_cap < gram_ws_bytes(n, m)) return SKETCHNE_E_WORKSPACE;
+  GramArgs g{};
+  g.n = n;
+  g.m = m;
+  g.nbk = (m + 15) / 16;
+  g.nblk = g.nbk * (g.nbk + 1) / 2;
+  // LDS row length: the 16-aligned width, moved off multiples of 32 floats so
+  // the 4 rows read by one MFMA fragment fall in distinct banks
+  g.stride = (m + 15) / 16 * 16;
+  if (g.stride % 64 == 0 || g.stride % 64 == 32) g.stride += 16;
+  g.X = X; g.xr = xr; g.xc = xc;
+  g.Y = Y ? Y : X; g.yr = Y ? yr : xr; g.yc = Y ? yc : xc;
+  g.w = w;
+  const int nr = gram_nwg(n);
+  int64_t rpw = (n + nr - 1) / nr;
+  g.rows_per_wg = (rpw + GR_CHUNK - 1) / GR_CHUNK * GR_CHUNK;
+  g.nranges = nr;
+  g.gsize = (g.nblk + GR_GROUPS - 1) / GR_GROUPS;
+  g.partial = partial;
+  g.run_if = run_if;
+  const bool two = Y != nullptr;
+  const size_t shmem = sizeof(float) * (size_t)2 * (two ? 2 : 1) * GR_CHUNK * g.stride;
+  const int pw = (g.gsize + GR_WAVES - 1) / GR_WAVES;
+  const unsigned blocks = (unsigned)((nr + 7) / 8 * 8 * GR_GROUPS);
+  ProfScope ps(c, SKETCHNE_PROF_GEMM64);
+#define SKNE_GRAM(T, R, P)                                                                                 \
+  do {                                                                                                     \
+    hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_tall<T, R, P>),                               \
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);                           \
+    hipLaunchKernelGGL((k_gram_tall<T, R, P>), dim3(blocks), dim3(GR_THREADS), shmem, c->stream, g);       \
+  } while (0)
+#define SKNE_GRAM_PW(T, R)                 \
+  do {                                     \
+    if (pw <= 4) SKNE_GRAM(T, R, 4);       \
+    else if (pw <= 8) SKNE_GRAM(T, R, 8);  \
+    else SKNE_GRAM(T, R, 11);              \
+  } while (0)
+  if (two) { if (rowmaj) SKNE_GRAM_PW(true, true); else SKNE_GRAM_PW(true, false); }
+  else { if (rowmaj) SKNE_GRAM_PW(false, true); else SKNE_GRAM_PW(false, false); }
+#undef SKNE_GRAM_PW
+#undef SKNE_GRAM
+  hipLaunchKernelGGL(k_gram_reduce, dim3((g.nblk * 256 + 255) / 256), dim3(256), 0, c->stream, m, g.nbk, g.nblk, nr,
+                     partial, G, run_if);
+  return launch_status();
+}
+
+}  // namespace skne

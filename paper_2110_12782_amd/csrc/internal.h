@@ -107,6 +107,13 @@ int gemm64_pick_splits(const GemmDesc& g);
 size_t gemm64_partial_bytes(int64_t M, int64_t N, int64_t K, bool upper);
 sketchne_status gemm64(sketchne_ctx* c, const GemmDesc& g, double* partial, size_t partial_cap);
 
+// gram.hip : G = X^T diag(w) Y (symmetric products), X, Y tall FP32
+int gram_nwg(int64_t n);
+size_t gram_ws_bytes(int64_t n, int m);
+sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int64_t xr, int64_t xc, const float* Y,
+                          int64_t yr, int64_t yc, const double* w, double* G, double* partial, size_t partial_cap,
+                          const int* run_if);
+
 // dense_small.hip
 // Cholesky G = R^T R of an SPD m x m FP64 matrix (row-major, ld = m) and the
 // inverse factor; writes RinvT (= R^-T, lower triangular, row-major m x m).
