@@ -187,7 +187,7 @@ sketchne_status sketchne_symeig(sketchne_ctx* ctx, int32_t m, const double* A, d
                                 void* ws, size_t ws_bytes);
 
 /* Device generators (counter-based SplitMix64, Steele, Lea & Flood 2014).
- * gauss: n x cols standard normal block (Box-Muller in FP64, stored FP32).
+ * gauss: n x cols standard normal block (Box-Muller in FP32).
  * sparse_sign: fills out->rows/signs for an n-row test matrix (Alg. 3). */
 sketchne_status sketchne_gen_gauss(sketchne_ctx* ctx, int64_t n, int32_t cols, uint64_t seed,
                                    float* out);

@@ -35,6 +35,14 @@ __global__ void k_embed_map(int h, int d, const double* __restrict__ V, const do
   Map[idx] = V[i * h + j] * sqrt(fabs(w[j]));
 }
 
+// out = A^T (m x m)
+__global__ void k_transpose(int m, const double* __restrict__ A, double* __restrict__ out) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * m) return;
+  int i = idx / m, j = idx % m;
+  out[idx] = A[j * m + i];
+}
+
 bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & (kAlign - 1)) == 0; }
 
 // ------------------------------------------------------------- orthonormalise
@@ -239,9 +247,11 @@ SketchWs carve_sketch(Arena& ar, const sketchne_params* p, int64_t n) {
 
 // ------------------------------------------------------------- embed
 struct EmbedWs {
-  float* Q1;
-  float* Q2;
-  OrthWs ow;
+  float* Q1;        // Y R1^-1 (transposed), formed only for the second Cholesky-QR pass
+  OrthWs ow;        // ow.RinvT holds R1^-T
+  double* RT2;
+  double* Rci;      // Rc^-1 with Y = Q Rc
+  double* OY;
   double* Bm;
   double* Bq1;
   double* Bq;
@@ -257,6 +267,7 @@ struct EmbedWs {
   double* Vw;
   double* ww;
   double* Map;
+  double* Map2;
   double* s_partial;
   size_t s_cap;
   void* symws;
@@ -266,8 +277,10 @@ EmbedWs carve_embed(Arena& ar, const sketchne_params* p, int64_t n) {
   const int h = p->h, l = p->l, d = p->d;
   EmbedWs w;
   w.Q1 = ar.take<float>((size_t)h * n);
-  w.Q2 = ar.take<float>((size_t)h * n);
   w.ow = carve_orth(ar, n, h, true);
+  w.RT2 = ar.take<double>((size_t)h * h);
+  w.Rci = ar.take<double>((size_t)h * h);
+  w.OY = ar.take<double>((size_t)l * h);
   w.Bm = ar.take<double>((size_t)l * h);
   w.Bq1 = ar.take<double>((size_t)l * h);
   w.Bq = ar.take<double>((size_t)l * h);
@@ -283,10 +296,12 @@ EmbedWs carve_embed(Arena& ar, const sketchne_params* p, int64_t n) {
   w.Vw = ar.take<double>((size_t)h * h);
   w.ww = ar.take<double>(h);
   w.Map = ar.take<double>((size_t)h * d);
-  // the largest split-K partial of the small products and of E = Q Map
+  w.Map2 = ar.take<double>((size_t)h * d);
+  // the largest split-K partial of the small products and of E = Y Map2
   w.s_cap = max_bytes({gemm64_partial_bytes(h, h, l, true), gemm64_partial_bytes(l, h, h, false),
                        gemm64_partial_bytes(h, h, h, false), gemm64_partial_bytes(h, l, l, false),
-                       gemm64_partial_bytes(h, h, l, false), gemm64_partial_bytes(n, d, h, false)});
+                       gemm64_partial_bytes(h, h, l, false), gemm64_partial_bytes(h, d, h, false),
+                       gemm64_partial_bytes(n, d, h, false)});
   w.s_partial = ar.take<double>(w.s_cap / sizeof(double) + 1);
   w.symws = ar.take<char>(symeig_ws_bytes(h));
   return w;
@@ -514,35 +529,50 @@ sketchne_status sketchne_embed(sketchne_ctx* c, const sketchne_params* p, int64_
   EmbedWs w = carve_embed(ar, p, n);
   if (ar.overflow) return SKETCHNE_E_WORKSPACE;
 
-  // Alg. 4 line 5: Q = orth(Y), Y held transposed (h x n)
-  SK_TRY(orth2(c, n, h, Yt, w.Q1, w.Q2, n, true, w.ow));
-  const float* Qt = w.Q2;
-  // B = O^T Q (l x h)
-  SK_TRY(ot_q(c, l, p->z, h, O->rows, O->signs, Qt, n, 1.0 / sqrt((double)p->z), w.Bm));
-  // QR of B by Cholesky-QR twice in FP64: B = Bq R, R^-1 = R1^-1 R2^-1
   auto small = [&](int64_t M, int64_t N, int64_t K, const void* Ap, Ty ta, int64_t sai, int64_t sak, const void* Bp,
-                   Ty tb, int64_t sbk, int64_t sbj, double* C, bool upper) -> sketchne_status {
+                   Ty tb, int64_t sbk, int64_t sbj, double* C, bool upper, const int* run_if) -> sketchne_status {
     GemmDesc gd;
     gd.M = M; gd.N = N; gd.K = K;
     gd.A = Ap; gd.ta = ta; gd.sai = sai; gd.sak = sak;
     gd.B = Bp; gd.tb = tb; gd.sbk = sbk; gd.sbj = sbj;
     gd.C = C; gd.tc = Ty::F64; gd.sci = N; gd.scj = 1;
     gd.upper_only = upper;
+    gd.run_if = run_if;
     return gemm64(c, gd, w.s_partial, w.s_cap);
   };
-  SK_TRY(small(h, h, l, w.Bm, Ty::F64, 1, h, w.Bm, Ty::F64, h, 1, w.Gb, true));
+  // Alg. 4 line 5: Q = orth(Y), kept implicit as Q = Y Rc^-1 (Y = Q Rc), so
+  // the n x h matrix Q is never written: Cholesky-QR factor of Y (Y held
+  // transposed, h x n), and a second pass only when Y is ill-conditioned.
+  const OrthWs& ow = w.ow;
+  SK_TRY(gram_tall(c, n, h, Yt, 1, n, nullptr, 0, 0, nullptr, ow.G, ow.partial, ow.partial_cap, nullptr));
+  SK_TRY(chol_inv(c, h, ow.G, ow.RinvT, ow.cwork, ow.need2, nullptr));
+  hipLaunchKernelGGL(k_transpose, dim3((h * h + 255) / 256), dim3(256), 0, c->stream, h, ow.RinvT, w.Rci);
+  SK_TRY(launch_status());
+  {  // second pass (device-side condition): Q1 = Y R1^-1, R2 from Q1^T Q1, Rc^-1 = R1^-1 R2^-1
+    GemmDesc a = apply_desc(n, h, Yt, n, true, ow.RinvT, w.Q1);
+    a.run_if = ow.need2;
+    SK_TRY(gemm64(c, a, ow.partial, ow.partial_cap));
+    SK_TRY(gram_tall(c, n, h, w.Q1, 1, n, nullptr, 0, 0, nullptr, ow.G, ow.partial, ow.partial_cap, ow.need2));
+    SK_TRY(chol_inv(c, h, ow.G, w.RT2, ow.cwork, nullptr, ow.need2));
+    SK_TRY(small(h, h, h, ow.RinvT, Ty::F64, 1, h, w.RT2, Ty::F64, 1, h, w.Rci, false, ow.need2));
+  }
+  // B = O^T Q = (O^T Y) Rc^-1   (l x h)
+  SK_TRY(ot_q(c, l, p->z, h, O->rows, O->signs, Yt, n, 1.0 / sqrt((double)p->z), w.OY));
+  SK_TRY(small(l, h, h, w.OY, Ty::F64, h, 1, w.Rci, Ty::F64, h, 1, w.Bm, false, nullptr));
+  // QR of B by Cholesky-QR twice in FP64: B = Bq R, R^-1 = R1^-1 R2^-1
+  SK_TRY(small(h, h, l, w.Bm, Ty::F64, 1, h, w.Bm, Ty::F64, h, 1, w.Gb, true, nullptr));
   SK_TRY(chol_inv(c, h, w.Gb, w.Rb1, w.cwork));
-  SK_TRY(small(l, h, h, w.Bm, Ty::F64, h, 1, w.Rb1, Ty::F64, 1, h, w.Bq1, false));
-  SK_TRY(small(h, h, l, w.Bq1, Ty::F64, 1, h, w.Bq1, Ty::F64, h, 1, w.Gb, true));
+  SK_TRY(small(l, h, h, w.Bm, Ty::F64, h, 1, w.Rb1, Ty::F64, 1, h, w.Bq1, false, nullptr));
+  SK_TRY(small(h, h, l, w.Bq1, Ty::F64, 1, h, w.Bq1, Ty::F64, h, 1, w.Gb, true, nullptr));
   SK_TRY(chol_inv(c, h, w.Gb, w.Rb2, w.cwork));
-  SK_TRY(small(l, h, h, w.Bq1, Ty::F64, h, 1, w.Rb2, Ty::F64, 1, h, w.Bq, false));
+  SK_TRY(small(l, h, h, w.Bq1, Ty::F64, h, 1, w.Rb2, Ty::F64, 1, h, w.Bq, false, nullptr));
   // Rinv = R1^-1 R2^-1, with R^-1(i, j) = RinvT[j][i]
-  SK_TRY(small(h, h, h, w.Rb1, Ty::F64, 1, h, w.Rb2, Ty::F64, 1, h, w.Rinv, false));
+  SK_TRY(small(h, h, h, w.Rb1, Ty::F64, 1, h, w.Rb2, Ty::F64, 1, h, w.Rinv, false, nullptr));
   // W = Rinv (Bq^T Z Bq) Rinv^T  (Alg. 4 line 8, two least-squares solves)
-  SK_TRY(small(h, l, l, w.Bq, Ty::F64, 1, h, Z, Ty::F32, l, 1, w.M1, false));
-  SK_TRY(small(h, h, l, w.M1, Ty::F64, l, 1, w.Bq, Ty::F64, h, 1, w.M2, false));
-  SK_TRY(small(h, h, h, w.Rinv, Ty::F64, h, 1, w.M2, Ty::F64, h, 1, w.M3, false));
-  SK_TRY(small(h, h, h, w.M3, Ty::F64, h, 1, w.Rinv, Ty::F64, 1, h, w.W, false));
+  SK_TRY(small(h, l, l, w.Bq, Ty::F64, 1, h, Z, Ty::F32, l, 1, w.M1, false, nullptr));
+  SK_TRY(small(h, h, l, w.M1, Ty::F64, l, 1, w.Bq, Ty::F64, h, 1, w.M2, false, nullptr));
+  SK_TRY(small(h, h, h, w.Rinv, Ty::F64, h, 1, w.M2, Ty::F64, h, 1, w.M3, false, nullptr));
+  SK_TRY(small(h, h, h, w.M3, Ty::F64, h, 1, w.Rinv, Ty::F64, 1, h, w.W, false, nullptr));
   hipLaunchKernelGGL(k_symmetrize, dim3((h * h + 255) / 256), dim3(256), 0, c->stream, h, w.W, w.M2);
   SK_TRY(launch_status());
   // Alg. 4 line 9: SVD of the symmetric W from its eigendecomposition
@@ -550,12 +580,13 @@ sketchne_status sketchne_embed(sketchne_ctx* c, const sketchne_params* p, int64_
   hipLaunchKernelGGL(k_embed_map, dim3((h * d + 255) / 256), dim3(256), 0, c->stream, h, d, w.Vw, w.ww, w.Map,
                      sigma);
   SK_TRY(launch_status());
-  // Alg. 4 line 10 and Alg. 6 line 5: E = Q U^(:, 1:d) Sigma^(1/2)
+  // Alg. 4 line 10 and Alg. 6 line 5: E = Q U^(:, 1:d) Sigma^(1/2) = Y (Rc^-1 U^ Sigma^(1/2))
+  SK_TRY(small(h, d, h, w.Rci, Ty::F64, h, 1, w.Map, Ty::F64, d, 1, w.Map2, false, nullptr));
   {
     GemmDesc gd;
     gd.M = n; gd.N = d; gd.K = h;
-    gd.A = Qt; gd.ta = Ty::F32; gd.sai = 1; gd.sak = n;
-    gd.B = w.Map; gd.tb = Ty::F64; gd.sbk = d; gd.sbj = 1;
+    gd.A = Yt; gd.ta = Ty::F32; gd.sai = 1; gd.sak = n;
+    gd.B = w.Map2; gd.tb = Ty::F64; gd.sbk = d; gd.sbj = 1;
     gd.C = E; gd.tc = Ty::F32; gd.sci = d; gd.scj = 1;
     SK_TRY(gemm64(c, gd, w.s_partial, w.s_cap));
   }

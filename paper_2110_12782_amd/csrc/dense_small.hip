@@ -321,15 +321,30 @@ __global__ __launch_bounds__(256) void k_oj_step(int m, int nb, int s, int sweep
   else { P = 2 * blockIdx.x; Q = P + 1; }
   const int tid = threadIdx.x;
   if (tid == 0) s_rot = 0;
-  // load the two blocks (each block is NBJ contiguous columns of m doubles)
+  // load the two blocks (each block is NBJ contiguous columns of m doubles),
+  // OJ_BATCH double2 of G and of V in flight per thread
   const int blk = NBJ * m;
-  for (int idx = 2 * tid; idx < 2 * blk; idx += 512) {
-    const int which = idx >= blk, off = idx - which * blk;
-    const int64_t src = (int64_t)(which ? Q : P) * blk + off;
-    double2 gv = *reinterpret_cast<const double2*>(G + src);
-    double2 vv = *reinterpret_cast<const double2*>(V + src);
-    *reinterpret_cast<double2*>(sG + idx) = gv;
-    *reinterpret_cast<double2*>(sV + idx) = vv;
+  constexpr int OJ_BATCH = 6;
+  for (int base = 2 * tid; base < 2 * blk; base += 512 * OJ_BATCH) {
+    double2 gv[OJ_BATCH], vv[OJ_BATCH];
+#pragma unroll
+    for (int u = 0; u < OJ_BATCH; ++u) {
+      const int idx = base + 512 * u;
+      if (idx < 2 * blk) {
+        const int which = idx >= blk, off = idx - which * blk;
+        const int64_t src = (int64_t)(which ? Q : P) * blk + off;
+        gv[u] = *reinterpret_cast<const double2*>(G + src);
+        vv[u] = *reinterpret_cast<const double2*>(V + src);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < OJ_BATCH; ++u) {
+      const int idx = base + 512 * u;
+      if (idx < 2 * blk) {
+        *reinterpret_cast<double2*>(sG + idx) = gv[u];
+        *reinterpret_cast<double2*>(sV + idx) = vv[u];
+      }
+    }
   }
   __syncthreads();
   const int grp = tid >> 4, sub = tid & 15;  // 16 groups of 16 lanes
@@ -379,7 +394,11 @@ __global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restr
   const double sg = *sigma;
   for (int j = wave; j < m; j += 16) {
     double d = 0.0;
-    for (int r = lane; r < m; r += 64) d = fma(V[(int64_t)j * m + r], G[(int64_t)j * m + r], d);
+#pragma unroll
+    for (int i = 0; i < (16 * OJ_MAXR + 63) / 64; ++i) {
+      const int r = lane + 64 * i;
+      if (r < m) d = fma(V[(int64_t)j * m + r], G[(int64_t)j * m + r], d);
+    }
     d = wave_sum(d);
     if (lane == 0) {
       w[j] = d - sg;

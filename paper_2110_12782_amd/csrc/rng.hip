@@ -22,23 +22,30 @@ __device__ __forceinline__ uint64_t draw(uint64_t seed, uint64_t ctr) {
   return mix64(seed + kGamma * (ctr + 1));
 }
 
-__device__ __forceinline__ double unit_open(uint64_t r) {
-  // (0, 1]: 53 random bits, shifted away from 0 so the logarithm is finite
-  return (double)((r >> 11) + 1) * (1.0 / 9007199254740992.0);
-}
-
+// Box-Muller in FP32: one pair of uniforms gives two normals, written to
+// consecutive elements 2e and 2e+1 of the row-major block.
 __global__ void k_gauss(int64_t n, int cols, int64_t ld, uint64_t seed, float* __restrict__ out) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t total = n * cols;
-  if (idx >= total) return;
-  int64_t i = idx / cols;
-  int j = (int)(idx - i * cols);
+  int64_t i0 = 2 * e;
+  if (i0 >= total) return;
   uint64_t s = mix64(seed ^ 0x6a09e667f3bcc909ULL);
-  double u1 = unit_open(draw(s, 2 * (uint64_t)idx));
-  double u2 = unit_open(draw(s, 2 * (uint64_t)idx + 1));
-  // Box-Muller
-  double g = sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925 * u2);
-  out[i * ld + j] = (float)g;
+  uint64_t r = draw(s, (uint64_t)e);
+  // two 32-bit uniforms in (0, 1]
+  float u1 = ((float)((uint32_t)(r >> 40)) + 1.0f) * (1.0f / 16777216.0f);
+  float u2 = (float)((uint32_t)(r >> 8) & 0xffffffu) * (1.0f / 16777216.0f);
+  float rad = sqrtf(-2.0f * logf(u1));
+  float sn, cs;
+  sincosf(6.28318530717958647692f * u2, &sn, &cs);
+  int64_t a = i0 / cols;
+  int b = (int)(i0 - a * cols);
+  out[a * ld + b] = rad * cs;
+  int64_t i1 = i0 + 1;
+  if (i1 < total) {
+    int64_t a1 = i1 / cols;
+    int b1 = (int)(i1 - a1 * cols);
+    out[a1 * ld + b1] = rad * sn;
+  }
 }
 
 // One thread per column: z distinct rows uniformly from [0, n), independent
@@ -78,7 +85,7 @@ sketchne_status gen_gauss(sketchne_ctx* c, int64_t n, int cols, int64_t ld, uint
   int64_t total = n * cols;
   if (total == 0) return SKETCHNE_OK;
   ProfScope ps(c, SKETCHNE_PROF_PREP);
-  int64_t blocks = (total + 255) / 256;
+  int64_t blocks = ((total + 1) / 2 + 255) / 256;
   hipLaunchKernelGGL(k_gauss, dim3((unsigned)blocks), dim3(256), 0, c->stream, n, cols, ld, seed, out);
   return launch_status();
 }
