@@ -48,7 +48,9 @@ def main():
     ap.add_argument("--mean-degree", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison form")
-    ap.add_argument("--cpu-rows", type=int, default=16384)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the oracle Y row sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB device copy first (PMC byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is single-GPU in this "
@@ -62,6 +64,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     lib = Library.get()
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del src, dst
     n = 1 << args.scale
     t0 = time.time()
     rowptr, colidx = synth.chung_lu(n, 2.1, args.mean_degree, 2, 1003)
@@ -143,9 +153,17 @@ def main():
                          "per_class_ms": {kk: vv[0] / s32 for kk, vv in prof32.items()}}
         ref_form = out32
 
+    if ref_form is not None:
+        # the two forms draw the same Omega, S and O (same seed); their embeddings
+        # differ only by the precision of the fused GEMM (and the eig rounding)
+        forms[args.precision]["sin_theta_E_vs_fp32"] = sin_theta(out[6], ref_form[6])
+        forms[args.precision]["rel_diff_sigma_vs_fp32"] = float(
+            np.max(np.abs(out[7].cpu().numpy() - ref_form[7].cpu().numpy()) / ref_form[7].cpu().numpy()))
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, n, rowptr, colidx, out, ref_form, forms)
+    traffic = pmc_traffic(args.precision, args.scale, y_launches)
 
     line = {
         "metric": "sketched NetMF entries/s + embed time at n=1M; BF16-MFMA vs FP32 at equal error",
@@ -170,7 +188,7 @@ def main():
         "embed_time_ms": dt * 1e3,
         "sketch_entries_per_s": sketch_rate,
         "roofline": {"bound": "mfma", "kernel": "k_fused_sketch (Y pass)", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "launch_ms": y_ms, "algorithmic_flops": y_flops, "executed_flops": executed,
                      "launches_per_step": y_launches},
         "roofline_spmm": {"bound": "hbm", "kernel": "k_spmm", "achieved": sp_gbs, "peak": HBM_PEAK,
@@ -182,42 +200,102 @@ def main():
     print(json.dumps(line))
 
 
+def sin_theta(A, B) -> float:
+    """||sin Theta||_F / sqrt(d) between the column spans of two n x d device blocks."""
+    import torch
+    Qa = torch.linalg.qr(A.double().cpu(), mode="reduced")[0]
+    Qb = torch.linalg.qr(B.double().cpu(), mode="reduced")[0]
+    R = Qa - Qb @ (Qb.T @ Qa)
+    s = torch.linalg.svdvals(R).clamp(0, 1)
+    return float(torch.sqrt((s * s).sum() / s.numel()))
+
+
+def source_digest() -> str:
+    """SHA-256 over the HIP sources of the fused sketch kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("sketch.hip", "sketch.h"):
+        with open(os.path.join(ROOT, "paper_2110_12782_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_traffic(prec, scale, launches):
+    """HBM bytes per launch of the fused Y kernel, from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when that summary was taken on
+    another workload or on kernel sources that have changed since."""
+    path = os.path.join(ROOT, "profiles", f"fused_sketch_y_chunglu_n2p{scale}_{prec}_hbm_bytes.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != source_digest():
+        log("pmc summary is stale (kernel sources changed); traffic = null")
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(args, n, rowptr, colidx, out, ref_form, forms):
-    """The FP64 oracle timed on a row sample of Y (rows of Y are independent,
-    Eq. 4), on the same U, lambda and S the GPU step used; the same rows give
-    each GPU form's error against FP64."""
+    """The FP64 oracle timed on the host: Eq. 4 for Y on random row chunks
+    (rows of Y are independent) until the time budget is spent, plus all of Z
+    (Alg. 4 line 7), on the same U, lambda, S and O as the GPU step.  The same
+    rows give each GPU form's error against FP64."""
     from oracle import netmf, sketch as sk, metrics
     U, lam, Yt, Z, S, O, E, sig = out
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else 1
+    except Exception:
+        cores = 1
     t0 = time.time()
     A = netmf.adjacency(rowptr, colidx)
+    deg, vol = netmf.degrees(A), netmf.volume(A)
     U64 = U.cpu().numpy().astype(np.float64)
-    lam64 = lam.cpu().numpy()
-    rows = np.random.default_rng(5).choice(n, size=min(args.cpu_rows, n), replace=False)
-    rows.sort()
-    Lp, Rp, _ = netmf.eq11_factors(U64, lam64, netmf.degrees(A), netmf.volume(A), 0.5, 10, 1.0)
-    rS = S[0].cpu().numpy()
-    sS = S[1].cpu().numpy()
-    log(f"cpu baseline: factors ready in {time.time() - t0:.1f}s; timing Eq. 4 on {len(rows)} rows")
-    t = time.perf_counter()
-    Yo = sk.sketch_y_sampled(Lp, Rp, rS, sS, row_subset=rows)
-    dt = time.perf_counter() - t
+    Lp, Rp, _ = netmf.eq11_factors(U64, lam.cpu().numpy(), deg, vol, 0.5, 10, 1.0)
+    rS, sS = S[0].cpu().numpy(), S[1].cpu().numpy()
+    rO, sO = O[0].cpu().numpy(), O[1].cpu().numpy()
     vS = len(np.unique(rS))
-    rate = len(rows) * vS / dt
-    errs = {args.precision: metrics.rel_fro(Yt.cpu().numpy()[:, rows].T, Yo)}
+    vO = len(np.unique(rO))
+    log(f"cpu baseline: factors ready in {time.time() - t0:.1f}s; Eq. 4 on row chunks for {args.cpu_seconds:g}s")
+    order = np.random.default_rng(5).permutation(n)
+    chunk = 4096
+    done = []
+    parts = []
+    t = time.perf_counter()
+    while len(done) * chunk < n and time.perf_counter() - t < args.cpu_seconds:
+        rows = np.sort(order[len(done) * chunk:(len(done) + 1) * chunk])
+        parts.append(sk.sketch_y_sampled(Lp, Rp, rS, sS, row_subset=rows))
+        done.append(rows)
+    ty = time.perf_counter() - t
+    t = time.perf_counter()
+    Zo = sk.sketch_z_sampled(Lp, Rp, rO, sO)
+    tz = time.perf_counter() - t
+    rows = np.concatenate(done)
+    Yo = np.concatenate(parts)
+    entries = len(rows) * vS + vO * vO
+    rate = entries / (ty + tz)
+    Yg = Yt.cpu().numpy()[:, rows].T
+    errs = {args.precision: {"Y_rows": metrics.rel_fro(Yg, Yo), "Z": metrics.rel_fro(Z.cpu().numpy(), Zo)}}
     if ref_form is not None:
-        # the FP32 form drew the same S (same seed), but its U comes from its own eig
+        # the FP32 form drew the same S and O (same seed); its U comes from its own eig
         U2 = ref_form[0].cpu().numpy().astype(np.float64)
-        Lp2, Rp2, _ = netmf.eq11_factors(U2, ref_form[1].cpu().numpy(), netmf.degrees(A), netmf.volume(A),
-                                         0.5, 10, 1.0)
-        Yo2 = sk.sketch_y_sampled(Lp2, Rp2, ref_form[4][0].cpu().numpy(), ref_form[4][1].cpu().numpy(),
-                                  row_subset=rows)
-        errs["fp32"] = metrics.rel_fro(ref_form[2].cpu().numpy()[:, rows].T, Yo2)
+        Lp2, Rp2, _ = netmf.eq11_factors(U2, ref_form[1].cpu().numpy(), deg, vol, 0.5, 10, 1.0)
+        sub = rows[: min(len(rows), 16384)]
+        Yo2 = sk.sketch_y_sampled(Lp2, Rp2, rS, sS, row_subset=np.sort(sub))
+        errs["fp32"] = {"Y_rows": metrics.rel_fro(ref_form[2].cpu().numpy()[:, np.sort(sub)].T, Yo2)}
     for kk, e in errs.items():
-        forms[kk]["rel_err_Y_rows_vs_fp64"] = e
-    log(f"cpu baseline: {dt:.1f}s for {len(rows) * vS:.3g} entries; errors {errs}")
-    return {"value": rate, "unit": "entries/s", "cores": os.cpu_count(), "kind": "oracle",
-            "sample": f"Eq. 4 (f(L'R'(:,p)) S(p,:)) in FP64 NumPy for {len(rows)} random rows of Y "
-                      f"x all {vS} sampled columns, same U, lambda, S as the GPU step"}
+        forms[kk]["rel_err_vs_fp64"] = e
+    log(f"cpu baseline: Y {ty:.1f}s for {len(rows)} rows, Z {tz:.1f}s; errors {errs}")
+    return {"value": rate, "unit": "entries/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 NumPy oracle: Eq. 4 for {len(rows)} random rows of Y x all {vS} sampled columns "
+                      f"plus all of Z ({vO} x {vO} sampled block), same U, lambda, S, O as the GPU step; "
+                      f"{ty + tz:.1f}s of CPU work"}
 
 
 if __name__ == "__main__":

@@ -172,7 +172,8 @@ sketchne_status sketchne_spmm(sketchne_ctx* ctx, const sketchne_graph* A, double
 
 /* In-place orthonormalisation of the columns of B (n x cols, FP32, packed:
  * ldb == cols): Cholesky-QR with FP64 Gram and Cholesky, repeated once when
- * the first factor is ill-conditioned (the orth of Alg. 5).  cols <= 512.
+ * the first factor is ill-conditioned (the orth of Alg. 5).  cols <= 288
+ * (SKETCHNE_E_UNSUPPORTED beyond, or when ldb != cols).
  * Workspace: sketchne_orth_workspace_size(). */
 sketchne_status sketchne_orth_workspace_size(int64_t n, int32_t cols, size_t* bytes);
 sketchne_status sketchne_orth(sketchne_ctx* ctx, int64_t n, int32_t cols, float* B, int64_t ldb,

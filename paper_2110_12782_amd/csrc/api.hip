@@ -634,7 +634,7 @@ sketchne_status sketchne_orth_workspace_size(int64_t n, int32_t cols, size_t* by
 sketchne_status sketchne_orth(sketchne_ctx* c, int64_t n, int32_t cols, float* B, int64_t ldb, void* ws,
                               size_t ws_bytes) {
   if (!c || !B || n < 1 || cols < 1 || cols > n || ldb < cols) return SKETCHNE_E_ARG;
-  if (cols > 512) return SKETCHNE_E_UNSUPPORTED;
+  if (cols > kSymeigMax || ldb != cols) return SKETCHNE_E_UNSUPPORTED;  // Gram kernel order; tmp shares ldb
   size_t need = 0;
   SK_TRY(sketchne_orth_workspace_size(n, cols, &need));
   SK_TRY(check_ws(ws, ws_bytes, need));
@@ -642,7 +642,6 @@ sketchne_status sketchne_orth(sketchne_ctx* c, int64_t n, int32_t cols, float* B
   float* tmp = ar.take<float>((size_t)n * cols);
   OrthWs ow = carve_orth(ar, n, cols, false);
   if (ar.overflow) return SKETCHNE_E_WORKSPACE;
-  if (ldb != cols) return SKETCHNE_E_UNSUPPORTED;  // tmp shares B's leading dimension
   // in place: B -> tmp, copy back, then the conditional second pass B -> tmp -> B
   SK_TRY(orth_pass(c, n, cols, B, tmp, ldb, false, ow, ow.need2, nullptr));
   SK_TRY(copy_if(c, n * ldb, tmp, B, nullptr));
