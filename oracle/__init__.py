@@ -22,4 +22,4 @@ in the order and notation of the paper (SketchNE, TKDE 2023, arXiv
 * ``mlp``      -- the warm-start MLP (not from the paper: parity unpinned
                   against the paper, pinned by finite differences).
 """
-from . import netmf, freigs, sketch, pipeline, metrics  # noqa: F401
+from . import netmf, freigs, sketch, pipeline, metrics, mlp  # noqa: F401

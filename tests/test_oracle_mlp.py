@@ -1,0 +1,120 @@
+"""Pins of the warm-start oracle (oracle/mlp.py): closed forms, invariances and
+central finite differences.  CPU only."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp
+
+
+def _orthonormal(n, k, seed):
+    q, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((n, k)))
+    return q
+
+
+def _small_problem(seed=0, n=96, width=16, out=8):
+    rng = np.random.default_rng(seed)
+    phi = rng.standard_normal((n, mlp.FEAT))
+    phi[:, mlp.N_RAW:] = 0.0
+    theta = np.concatenate([
+        rng.standard_normal(mlp.FEAT * width) * np.sqrt(2 / mlp.FEAT), rng.standard_normal(width) * 0.1,
+        rng.standard_normal(width * width) * np.sqrt(2 / width), rng.standard_normal(width) * 0.1,
+        rng.standard_normal(width * out) * np.sqrt(2 / width), rng.standard_normal(out) * 0.1])
+    U = _orthonormal(n, out, seed + 1)
+    return phi, theta, U, width, out
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.1, 1.0])
+def test_gradient_matches_central_differences(mu):
+    phi, theta, U, width, out = _small_problem()
+    L, gvec = mlp.grad(theta, phi, U, mu, width, out)
+    rng = np.random.default_rng(3)
+    idx = rng.choice(theta.size, size=60, replace=False)
+    h = 1e-6
+    for i in idx:
+        tp = theta.copy(); tp[i] += h
+        tm = theta.copy(); tm[i] -= h
+        fd = (mlp.grad(tp, phi, U, mu, width, out)[0] - mlp.grad(tm, phi, U, mu, width, out)[0]) / (2 * h)
+        assert abs(fd - gvec[i]) <= 1e-6 * max(1.0, np.abs(gvec).max()), (i, fd, gvec[i])
+
+
+def test_loss_grad_matches_central_differences_in_F():
+    rng = np.random.default_rng(4)
+    n, k = 40, 6
+    F = rng.standard_normal((n, k))
+    U = _orthonormal(n, k, 5)
+    G = mlp.loss_grad(F, U, 0.3)
+    h = 1e-6
+    for (i, j) in [(0, 0), (3, 2), (39, 5), (17, 1)]:
+        Fp = F.copy(); Fp[i, j] += h
+        Fm = F.copy(); Fm[i, j] -= h
+        fd = (mlp.loss(Fp, U, 0.3) - mlp.loss(Fm, U, 0.3)) / (2 * h)
+        assert abs(fd - G[i, j]) < 1e-7
+
+
+def test_loss_closed_forms():
+    n, k = 50, 5
+    U = _orthonormal(n, k, 6)
+    # an orthogonal basis of span(U) with equal column norms: both terms vanish
+    Qr = _orthonormal(k, k, 7)
+    assert mlp.loss(3.7 * U @ Qr, U, 1.0) < 1e-24
+    # scale invariance
+    F = np.random.default_rng(8).standard_normal((n, k))
+    assert abs(mlp.loss(F, U, 0.5) - mlp.loss(-0.01 * F, U, 0.5)) < 1e-12
+    # F orthogonal to span(U): the subspace term is exactly 1
+    W = _orthonormal(n, 2 * k, 9)
+    P = W[:, k:] - U @ (U.T @ W[:, k:])
+    assert abs(mlp.loss(P, U, 0.0) - 1.0) < 1e-12
+    # half of each column in span(U): subspace term = 1/2
+    V = (np.eye(n) - U @ U.T) @ np.random.default_rng(10).standard_normal((n, k))
+    V /= np.linalg.norm(V, axis=0)
+    F = U + V
+    assert abs(mlp.loss(F, U, 0.0) - 0.5) < 1e-12
+
+
+def test_adam_first_step_closed_form():
+    g = np.array([3.0, -2.0, 1e-3, 0.0])
+    th, m, v = mlp.adam(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, lr=0.01)
+    # bias-corrected moments of the first step are g and g^2
+    assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_features_on_cycle_closed_form():
+    n = 64
+    rowptr, colidx = synth.cycle(n)
+    g = synth.rademacher(n, 11).astype(np.float64)
+    phi = mlp.features(rowptr, colidx, 0.5, g)
+    # 2-regular: X = A / 2, so X g is the average of the two ring neighbours
+    raw = np.zeros((n, 4))
+    v = g.copy()
+    for t in range(4):
+        v = 0.5 * (np.roll(v, 1) + np.roll(v, -1))
+        raw[:, t] = v
+    for t in range(4):
+        expect = (raw[:, t] - raw[:, t].mean()) / raw[:, t].std()
+        assert np.allclose(phi[:, 1 + t], expect, atol=1e-12)
+    # constant degree: the log-degree column has no spread and is set to 0
+    assert np.all(phi[:, 0] == 0.0)
+    assert np.all(phi[:, mlp.N_RAW:] == 0.0)
+
+
+def test_features_standardised_and_isolated_vertices():
+    rowptr, colidx = synth.chung_lu(3000, 2.3, 6, 1, 77)
+    # append three isolated vertices
+    rowptr = np.concatenate([rowptr, [rowptr[-1]] * 3])
+    g = synth.rademacher(len(rowptr) - 1, 12).astype(np.float64)
+    phi = mlp.features(rowptr, colidx, 0.5, g)
+    assert np.allclose(phi[:, :mlp.N_RAW].mean(axis=0), 0, atol=1e-12)
+    assert np.allclose(phi[:, :mlp.N_RAW].std(axis=0), 1, atol=1e-12)
+    # isolated vertices: every raw feature is 0 (log max(0, 1) = 0, no neighbours), so their rows coincide
+    assert np.allclose(phi[-1], phi[-2]) and np.allclose(phi[-1], phi[-3])
+
+
+def test_bf16_round_ties_to_even():
+    one = 1.0
+    vals = np.array([one, one + 2 ** -8, one + 3 * 2 ** -8, one + 2 ** -7, -2.5, 1e-40])
+    r = mlp.bf16_round(vals)
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2 ** -6 and r[3] == 1.0 + 2 ** -7
+    assert r[4] == -2.5
+    assert abs(mlp.bf16_round(np.pi) - np.pi) <= 2 ** -8 * np.pi
