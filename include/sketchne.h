@@ -195,6 +195,94 @@ sketchne_status sketchne_gen_gauss(sketchne_ctx* ctx, int64_t n, int32_t cols, u
 sketchne_status sketchne_gen_sparse_sign(sketchne_ctx* ctx, int64_t n, uint64_t seed,
                                          sketchne_sparse_sign* out);
 
+/* ---- Learned warm start of Alg. 5 ------------------------------------- */
+/* An addition to the method (Alg. 5 draws a Gaussian start block Omega):
+ * a 3-layer ReLU network maps per-vertex features to the first k columns of
+ * Omega; the other s_eig columns stay Gaussian, and the plain Gaussian start
+ * remains the fallback.
+ *   features   phi_i = [log max(deg_i,1), (Xg)_i, (X^2 g)_i, (X^3 g)_i, (X^4 g)_i]
+ *              with X = D^-a A D^-a and g a Rademacher vector, each column
+ *              standardised over the vertices to mean 0 and standard deviation
+ *              1 (a column whose standard deviation is at most 1e-6 times its
+ *              root mean square is set to 0), padded with zeros to
+ *              SKETCHNE_WS_FEAT columns; phi is n x SKETCHNE_WS_FEAT FP32.
+ *   network    F = relu(relu(phi W1 + b1) W2 + b2) W3 + b3   (n x out FP32)
+ *   loss       L = ||(I - U U^T) F||_F^2 / ||F||_F^2
+ *                  + mu || (out / ||F||_F^2) F^T F - I ||_F^2
+ *              for reference eigenvectors U (n x out, orthonormal columns).
+ * Parameters are one flat array in the order W1 (FEAT x width), b1 (width),
+ * W2 (width x width), b2 (width), W3 (width x out), b3 (out), row-major.
+ * The forward pass reads the BF16 copy; Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected) updates the FP32 master and rewrites the BF16
+ * copy (round to nearest even).  Products run on the FP32 matrix cores with
+ * FP32 accumulation; reductions over vertices use a fixed order. */
+#define SKETCHNE_WS_FEAT 8
+#define SKETCHNE_WS_RAW 5
+
+typedef struct {
+  int32_t width;     /* hidden width, >= 1                                    */
+  int32_t out;       /* output columns (the k of the eigensolver it starts)   */
+  float* master;     /* device, FP32 master parameters                         */
+  uint16_t* bf16;    /* device, BF16 copy of the parameters (forward pass)      */
+  float* adam_m;     /* device, Adam first moments (NULL: inference only)       */
+  float* adam_v;     /* device, Adam second moments (NULL: inference only)      */
+} sketchne_mlp;
+
+#define SKETCHNE_WS_OP_FEATURES 0x1
+#define SKETCHNE_WS_OP_FORWARD  0x2
+#define SKETCHNE_WS_OP_GRAD     0x4
+#define SKETCHNE_WS_OP_RESIDUAL 0x8   /* k = p->k                               */
+#define SKETCHNE_WS_OP_EIG      0x10  /* sketchne_eig_learned with p            */
+
+/* Number of parameters (host). */
+sketchne_status sketchne_ws_param_count(int32_t width, int32_t out, int64_t* count);
+/* Workspace bytes for the operations in op_mask (host); p is read for
+ * SKETCHNE_WS_OP_RESIDUAL and SKETCHNE_WS_OP_EIG (out = p->k there). */
+sketchne_status sketchne_ws_workspace_size(const sketchne_params* p, int32_t width, int32_t out, int64_t n,
+                                           int64_t nnz, int op_mask, size_t* bytes);
+/* He initialisation N(0, 2/fan_in) of the weights from seed (the padded rows
+ * of W1 are 0), zero biases and moments, BF16 copy. */
+sketchne_status sketchne_ws_init(sketchne_ctx* ctx, const sketchne_mlp* net, uint64_t seed);
+/* phi (n x SKETCHNE_WS_FEAT) for the graph; g (n, +-1) is the probe vector,
+ * or NULL to draw it on the device from seed. */
+sketchne_status sketchne_ws_features(sketchne_ctx* ctx, const sketchne_graph* A, double alpha, const float* g,
+                                     uint64_t seed, float* phi, void* ws, size_t ws_bytes);
+/* F = network(phi): n x out written with leading dimension ldf >= out. */
+sketchne_status sketchne_ws_forward(sketchne_ctx* ctx, const sketchne_mlp* net, int64_t n, const float* phi,
+                                    float* F, int64_t ldf, void* ws, size_t ws_bytes);
+/* Loss and its gradient with respect to every parameter (grad: param_count
+ * FP32, overwritten; loss: one FP32, device) for reference U (n x out, ldu). */
+sketchne_status sketchne_ws_grad(sketchne_ctx* ctx, const sketchne_mlp* net, int64_t n, const float* phi,
+                                 const float* U, int64_t ldu, float mu, float* grad, float* loss, void* ws,
+                                 size_t ws_bytes);
+/* One Adam step (step counts from 1) with learning rate lr. */
+sketchne_status sketchne_ws_adam(sketchne_ctx* ctx, const sketchne_mlp* net, const float* grad, float lr,
+                                 int32_t step);
+/* Training loop: steps of (gradient on set t mod nsets, Adam step step0 + t + 1).
+ * phi[s], U[s] (host arrays of nsets device pointers): features (n[s] x FEAT)
+ * and reference eigenvectors (n[s] x out, ld out) of training set s; n is a
+ * host array.  losses: steps FP32 (device), the loss of each step before its
+ * update.  Workspace: SKETCHNE_WS_OP_GRAD for the largest n, plus
+ * param_count floats. */
+sketchne_status sketchne_ws_train(sketchne_ctx* ctx, const sketchne_mlp* net, int32_t nsets,
+                                  const float* const* phi, const float* const* U, const int64_t* n, int32_t steps,
+                                  int32_t step0, float lr, float mu, float* losses, void* ws, size_t ws_bytes);
+/* Ritz residuals res_j = ||X U_j - lambda_j U_j||_2, j < k (U: n x k, ld k;
+ * k % 4 == 0; res: k FP64, device). */
+sketchne_status sketchne_ritz_residual(sketchne_ctx* ctx, const sketchne_graph* A, double alpha, int32_t k,
+                                       const float* U, const double* lambda, double* res, void* ws,
+                                       size_t ws_bytes);
+/* Alg. 5 from the learned start: features (probe drawn from p->seed), F into
+ * the first k columns of Omega, Gaussian in the other s_eig, q_warm power
+ * iterations.  If the largest Ritz residual exceeds res_threshold (or is not
+ * finite) the result is discarded and sketchne_eig runs from the Gaussian
+ * start with p->q iterations; *used_fallback (host) says which ran.
+ * net->out must equal p->k.  Synchronizes the stream once (the residual
+ * test).  Workspace: sketchne_ws_workspace_size(.., SKETCHNE_WS_OP_EIG, ..). */
+sketchne_status sketchne_eig_learned(sketchne_ctx* ctx, const sketchne_graph* A, const sketchne_params* p,
+                                     const sketchne_mlp* net, int32_t q_warm, double res_threshold, float* U,
+                                     double* lambda, int32_t* used_fallback, void* ws, size_t ws_bytes);
+
 /* ---- Per-kernel-class timing (measurement support) --------------------- */
 /* When enabled, every launch of a kernel class is bracketed by HIP events on
  * the context's stream.  sketchne_profile_read() synchronizes and returns,

@@ -25,8 +25,12 @@ EXPORTED = [
     "sketchne_workspace_size", "sketchne_eig", "sketchne_sketch", "sketchne_embed", "sketchne_sync",
     "sketchne_spmm", "sketchne_orth_workspace_size", "sketchne_orth", "sketchne_symeig_workspace_size",
     "sketchne_symeig", "sketchne_gen_gauss", "sketchne_gen_sparse_sign", "sketchne_profile_enable",
-    "sketchne_profile_read",
+    "sketchne_profile_read", "sketchne_ws_param_count", "sketchne_ws_workspace_size", "sketchne_ws_init",
+    "sketchne_ws_features", "sketchne_ws_forward", "sketchne_ws_grad", "sketchne_ws_adam",
+    "sketchne_ritz_residual", "sketchne_eig_learned", "sketchne_ws_train",
 ]
+WS_FEAT = 8
+WS_OP_FEATURES, WS_OP_FORWARD, WS_OP_GRAD, WS_OP_RESIDUAL, WS_OP_EIG = 1, 2, 4, 8, 16
 
 
 class SketchneError(RuntimeError):
@@ -46,6 +50,11 @@ class Params(C.Structure):
         ("d", C.c_int32), ("h", C.c_int32), ("l", C.c_int32), ("z", C.c_int32),
         ("seed", C.c_uint64), ("precision", C.c_int32), ("split_r", C.c_int32),
     ]
+
+
+class MLPStruct(C.Structure):
+    _fields_ = [("width", C.c_int32), ("out", C.c_int32), ("master", C.c_void_p), ("bf16", C.c_void_p),
+                ("adam_m", C.c_void_p), ("adam_v", C.c_void_p)]
 
 
 class SparseSign(C.Structure):
@@ -121,6 +130,25 @@ class Library:
         L.sketchne_gen_sparse_sign.argtypes = [C.c_void_p, C.c_int64, C.c_uint64, C.POINTER(SparseSign)]
         L.sketchne_profile_enable.argtypes = [C.c_void_p, C.c_int]
         L.sketchne_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.sketchne_ws_param_count.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int64)]
+        L.sketchne_ws_workspace_size.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32, C.c_int64, C.c_int64,
+                                                 C.c_int, C.POINTER(C.c_size_t)]
+        L.sketchne_ws_init.argtypes = [C.c_void_p, C.POINTER(MLPStruct), C.c_uint64]
+        L.sketchne_ws_features.argtypes = [C.c_void_p, C.POINTER(Graph), C.c_double, C.c_void_p, C.c_uint64,
+                                           C.c_void_p, C.c_void_p, C.c_size_t]
+        L.sketchne_ws_forward.argtypes = [C.c_void_p, C.POINTER(MLPStruct), C.c_int64, C.c_void_p, C.c_void_p,
+                                          C.c_int64, C.c_void_p, C.c_size_t]
+        L.sketchne_ws_grad.argtypes = [C.c_void_p, C.POINTER(MLPStruct), C.c_int64, C.c_void_p, C.c_void_p,
+                                       C.c_int64, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]
+        L.sketchne_ws_adam.argtypes = [C.c_void_p, C.POINTER(MLPStruct), C.c_void_p, C.c_float, C.c_int32]
+        L.sketchne_ws_train.argtypes = [C.c_void_p, C.POINTER(MLPStruct), C.c_int32, C.POINTER(C.c_void_p),
+                                        C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_int32, C.c_int32, C.c_float,
+                                        C.c_float, C.c_void_p, C.c_void_p, C.c_size_t]
+        L.sketchne_ritz_residual.argtypes = [C.c_void_p, C.POINTER(Graph), C.c_double, C.c_int32, C.c_void_p,
+                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]
+        L.sketchne_eig_learned.argtypes = [C.c_void_p, C.POINTER(Graph), C.POINTER(Params), C.POINTER(MLPStruct),
+                                           C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
+                                           C.c_void_p, C.c_size_t]
         self._ctx = None
 
     # ---------------------------------------------------------------- helpers
@@ -270,6 +298,113 @@ class Library:
         self.check(self.lib.sketchne_gen_sparse_sign(self.ctx(), n, seed, C.byref(s)), "gen_sparse_sign")
         return rows, signs
 
+    # ---------------------------------------------------------------- learned warm start
+    def ws_param_count(self, width: int, out: int) -> int:
+        c = C.c_int64(0)
+        self.check(self.lib.sketchne_ws_param_count(width, out, C.byref(c)), "ws_param_count")
+        return c.value
+
+    def ws_workspace_size(self, width: int, out: int, n: int, nnz: int, ops: int, p: SketchParams = None) -> int:
+        nb = C.c_size_t(0)
+        pc = p.c() if p is not None else None
+        self.check(self.lib.sketchne_ws_workspace_size(C.byref(pc) if pc is not None else None, width, out, n, nnz,
+                                                       ops, C.byref(nb)), "ws_workspace_size")
+        return nb.value
+
+    def ws_init(self, net: "MLP", seed: int):
+        s = net.c()
+        self.check(self.lib.sketchne_ws_init(self.ctx(), C.byref(s), seed), "ws_init")
+
+    def ws_features(self, g: "DeviceGraph", alpha: float, probe=None, seed: int = 0, ws=None):
+        """phi (n x 8 float32); probe: n float32 (+-1) or None to draw from seed."""
+        import torch
+        phi = torch.empty((g.n, WS_FEAT), dtype=torch.float32, device="cuda")
+        nb = self.ws_workspace_size(1, 1, g.n, g.nnz, WS_OP_FEATURES)
+        ws = ws if ws is not None else self.workspace(nb)
+        gs = g.c()
+        self.check(self.lib.sketchne_ws_features(self.ctx(), C.byref(gs), alpha, C.c_void_p(_ptr(probe)), seed,
+                                                 C.c_void_p(phi.data_ptr()), C.c_void_p(self._aligned(ws)), nb),
+                   "ws_features")
+        return phi
+
+    def ws_forward(self, net: "MLP", phi, out=None):
+        import torch
+        n = phi.shape[0]
+        F = out if out is not None else torch.empty((n, net.out), dtype=torch.float32, device="cuda")
+        nb = self.ws_workspace_size(net.width, net.out, n, 0, WS_OP_FORWARD)
+        ws = self.workspace(nb)
+        s = net.c()
+        self.check(self.lib.sketchne_ws_forward(self.ctx(), C.byref(s), n, C.c_void_p(phi.data_ptr()),
+                                                C.c_void_p(F.data_ptr()), F.stride(0),
+                                                C.c_void_p(self._aligned(ws)), nb), "ws_forward")
+        return F
+
+    def ws_grad(self, net: "MLP", phi, U, mu: float, grad=None, loss=None, ws=None):
+        import torch
+        n = phi.shape[0]
+        grad = grad if grad is not None else torch.empty(net.count, dtype=torch.float32, device="cuda")
+        loss = loss if loss is not None else torch.empty(1, dtype=torch.float32, device="cuda")
+        nb = self.ws_workspace_size(net.width, net.out, n, 0, WS_OP_GRAD)
+        ws = ws if ws is not None else self.workspace(nb)
+        s = net.c()
+        self.check(self.lib.sketchne_ws_grad(self.ctx(), C.byref(s), n, C.c_void_p(phi.data_ptr()),
+                                             C.c_void_p(U.data_ptr()), U.stride(0), mu, C.c_void_p(grad.data_ptr()),
+                                             C.c_void_p(loss.data_ptr()), C.c_void_p(self._aligned(ws)), nb),
+                   "ws_grad")
+        return grad, loss
+
+    def ws_adam(self, net: "MLP", grad, lr: float, step: int):
+        s = net.c()
+        self.check(self.lib.sketchne_ws_adam(self.ctx(), C.byref(s), C.c_void_p(grad.data_ptr()), lr, step),
+                   "ws_adam")
+
+    def ws_train(self, net: "MLP", sets, steps: int, lr: float, mu: float, step0: int = 0):
+        """Adam training on [(phi, U), ...] round-robin; returns the per-step losses."""
+        import torch
+        ns = len(sets)
+        phis = (C.c_void_p * ns)(*[C.c_void_p(ph.data_ptr()) for ph, _ in sets])
+        Us = (C.c_void_p * ns)(*[C.c_void_p(u.data_ptr()) for _, u in sets])
+        nn = (C.c_int64 * ns)(*[ph.shape[0] for ph, _ in sets])
+        for ph, u in sets:
+            assert u.shape == (ph.shape[0], net.out) and u.is_contiguous() and ph.is_contiguous()
+        nmax = max(ph.shape[0] for ph, _ in sets)
+        nb = self.ws_workspace_size(net.width, net.out, nmax, 0, WS_OP_GRAD) + 4 * net.count + 512
+        ws = self.workspace(nb)
+        losses = torch.empty(max(steps, 1), dtype=torch.float32, device="cuda")
+        s = net.c()
+        self.check(self.lib.sketchne_ws_train(self.ctx(), C.byref(s), ns, phis, Us, nn, steps, step0, lr, mu,
+                                              C.c_void_p(losses.data_ptr()), C.c_void_p(self._aligned(ws)), nb),
+                   "ws_train")
+        return losses[:steps]
+
+    def ritz_residual(self, g: "DeviceGraph", alpha: float, U, lam):
+        import torch
+        k = U.shape[1]
+        res = torch.empty(k, dtype=torch.float64, device="cuda")
+        nb = self.ws_workspace_size(1, 1, g.n, g.nnz, WS_OP_RESIDUAL, SketchParams(k=k, s_eig=0, d=1, h=1, l=1, z=1))
+        ws = self.workspace(nb)
+        gs = g.c()
+        self.check(self.lib.sketchne_ritz_residual(self.ctx(), C.byref(gs), alpha, k, C.c_void_p(U.data_ptr()),
+                                                   C.c_void_p(lam.data_ptr()), C.c_void_p(res.data_ptr()),
+                                                   C.c_void_p(self._aligned(ws)), nb), "ritz_residual")
+        return res
+
+    def eig_learned(self, g: "DeviceGraph", p: SketchParams, net: "MLP", q_warm: int, threshold: float, ws=None):
+        """Alg. 5 from the learned start; returns U, lambda, used_fallback."""
+        import torch
+        U = torch.empty((g.n, p.k), dtype=torch.float32, device="cuda")
+        lam = torch.empty(p.k, dtype=torch.float64, device="cuda")
+        nb = self.ws_workspace_size(net.width, net.out, g.n, g.nnz, WS_OP_EIG, p)
+        ws = ws if ws is not None else self.workspace(nb)
+        fb = C.c_int32(0)
+        pc = p.c()
+        gs = g.c()
+        s = net.c()
+        self.check(self.lib.sketchne_eig_learned(self.ctx(), C.byref(gs), C.byref(pc), C.byref(s), q_warm, threshold,
+                                                 C.c_void_p(U.data_ptr()), C.c_void_p(lam.data_ptr()), C.byref(fb),
+                                                 C.c_void_p(self._aligned(ws)), nb), "eig_learned")
+        return U, lam, bool(fb.value)
+
     def profile_enable(self, on: bool):
         self.check(self.lib.sketchne_profile_enable(self.ctx(), int(on)), "profile_enable")
 
@@ -293,3 +428,25 @@ class DeviceGraph:
 
     def c(self) -> Graph:
         return Graph(self.n, self.nnz, self.rowptr.data_ptr(), self.colidx.data_ptr())
+
+
+class MLP:
+    """Device buffers of the warm-start network (FP32 master, BF16 copy, Adam moments)."""
+
+    def __init__(self, lib: Library, width: int, out: int, train: bool = True):
+        import torch
+        self.width, self.out = width, out
+        self.count = lib.ws_param_count(width, out)
+        self.master = torch.zeros(self.count, dtype=torch.float32, device="cuda")
+        self.bf16 = torch.zeros(self.count, dtype=torch.int16, device="cuda")
+        self.m = torch.zeros(self.count, dtype=torch.float32, device="cuda") if train else None
+        self.v = torch.zeros(self.count, dtype=torch.float32, device="cuda") if train else None
+
+    def c(self) -> MLPStruct:
+        return MLPStruct(self.width, self.out, self.master.data_ptr(), self.bf16.data_ptr(), _ptr(self.m),
+                         _ptr(self.v))
+
+    def bf16_values(self):
+        """The BF16 copy as float64 numpy (what the forward pass reads)."""
+        b = self.bf16.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+        return b.view(np.float32).astype(np.float64)

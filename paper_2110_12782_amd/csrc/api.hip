@@ -12,12 +12,6 @@ using namespace skne;
 
 namespace {
 
-#define SK_TRY(expr)                                   \
-  do {                                                 \
-    sketchne_status _st = (expr);                      \
-    if (_st != SKETCHNE_OK) return _st;                \
-  } while (0)
-
 __global__ void k_symmetrize(int m, const double* __restrict__ A, double* __restrict__ S) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= m * m) return;
@@ -323,6 +317,31 @@ sketchne_status check_ws(void* ws, size_t ws_bytes, size_t need) {
   if (need == 0) return SKETCHNE_OK;
   if (!ws || ws_bytes < need || !aligned(ws)) return SKETCHNE_E_WORKSPACE;
   return SKETCHNE_OK;
+}
+
+// ------------------------------------------------------------- learned warm start
+sketchne_status check_net(const sketchne_mlp* net) {
+  if (!net || !net->master || !net->bf16 || net->width < 1 || net->out < 1) return SKETCHNE_E_ARG;
+  if (net->width > 4096 || net->out > 4096) return SKETCHNE_E_UNSUPPORTED;
+  return SKETCHNE_OK;
+}
+
+struct LearnedWs {
+  float* omega;
+  char* rest;     // reused in turn: phi + features/forward scratch, eig, residual
+  size_t rest_bytes;
+};
+
+size_t learned_rest_bytes(const sketchne_params* p, int width, int64_t n, int64_t nnz) {
+  size_t phi = align_up(sizeof(float) * (size_t)n * SKETCHNE_WS_FEAT);
+  size_t a = phi + max_bytes({ws_features_bytes(n, nnz), ws_forward_bytes(n, width)});
+  size_t b = op_bytes(p, n, nnz, SKETCHNE_OP_EIG);
+  size_t c = align_up(sizeof(double) * p->k) + ritz_residual_bytes(n, nnz, p->k);
+  return max_bytes({a, b, c});
+}
+
+size_t learned_bytes(const sketchne_params* p, int width, int64_t n, int64_t nnz) {
+  return align_up(sizeof(float) * (size_t)n * (p->k + p->s_eig)) + learned_rest_bytes(p, width, n, nnz);
 }
 
 }  // namespace
@@ -673,6 +692,169 @@ sketchne_status sketchne_gen_sparse_sign(sketchne_ctx* c, int64_t n, uint64_t se
     return SKETCHNE_E_ARG;
   if (n >= ((int64_t)1 << 31)) return SKETCHNE_E_UNSUPPORTED;
   return gen_sparse_sign(c, n, out->cols, out->z, seed, out->rows, out->signs);
+}
+
+sketchne_status sketchne_ws_param_count(int32_t width, int32_t out, int64_t* count) {
+  if (!count || width < 1 || out < 1) return SKETCHNE_E_ARG;
+  *count = ws_param_count(width, out);
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_ws_workspace_size(const sketchne_params* p, int32_t width, int32_t out, int64_t n,
+                                           int64_t nnz, int op_mask, size_t* bytes) {
+  if (!bytes || width < 1 || out < 1 || n < 1 || nnz < 0) return SKETCHNE_E_ARG;
+  size_t best = 0;
+  if (op_mask & SKETCHNE_WS_OP_FEATURES) best = max_bytes({best, ws_features_bytes(n, nnz)});
+  if (op_mask & SKETCHNE_WS_OP_FORWARD) best = max_bytes({best, ws_forward_bytes(n, width)});
+  if (op_mask & SKETCHNE_WS_OP_GRAD) best = max_bytes({best, ws_grad_bytes(n, width, out)});
+  if (op_mask & (SKETCHNE_WS_OP_RESIDUAL | SKETCHNE_WS_OP_EIG)) {
+    if (!p) return SKETCHNE_E_ARG;
+    SK_TRY(check_params(p, n));
+    if (op_mask & SKETCHNE_WS_OP_RESIDUAL) best = max_bytes({best, ritz_residual_bytes(n, nnz, p->k)});
+    if (op_mask & SKETCHNE_WS_OP_EIG) best = max_bytes({best, learned_bytes(p, width, n, nnz)});
+  }
+  *bytes = best;
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_ws_init(sketchne_ctx* c, const sketchne_mlp* net, uint64_t seed) {
+  if (!c) return SKETCHNE_E_ARG;
+  SK_TRY(check_net(net));
+  return ws_init(c, net, seed);
+}
+
+sketchne_status sketchne_ws_features(sketchne_ctx* c, const sketchne_graph* A, double alpha, const float* g,
+                                     uint64_t seed, float* phi, void* ws, size_t ws_bytes) {
+  if (!c || !phi) return SKETCHNE_E_ARG;
+  SK_TRY(check_graph(A));
+  if (!(alpha > 0.0 && alpha <= 0.5)) return SKETCHNE_E_ARG;
+  SK_TRY(check_ws(ws, ws_bytes, ws_features_bytes(A->n, A->nnz)));
+  return ws_features(c, A->n, A->nnz, A->rowptr, A->colidx, alpha, g, seed, phi, ws, ws_bytes);
+}
+
+sketchne_status sketchne_ws_forward(sketchne_ctx* c, const sketchne_mlp* net, int64_t n, const float* phi, float* F,
+                                    int64_t ldf, void* ws, size_t ws_bytes) {
+  if (!c || !phi || !F || n < 0) return SKETCHNE_E_ARG;
+  SK_TRY(check_net(net));
+  if (ldf < net->out) return SKETCHNE_E_ARG;
+  if (n == 0) return SKETCHNE_OK;
+  SK_TRY(check_ws(ws, ws_bytes, ws_forward_bytes(n, net->width)));
+  return ws_forward(c, net, n, phi, F, ldf, ws, ws_bytes);
+}
+
+sketchne_status sketchne_ws_grad(sketchne_ctx* c, const sketchne_mlp* net, int64_t n, const float* phi,
+                                 const float* U, int64_t ldu, float mu, float* grad, float* loss, void* ws,
+                                 size_t ws_bytes) {
+  if (!c || !phi || !U || !grad || !loss || n < 1 || !(mu >= 0.f)) return SKETCHNE_E_ARG;
+  SK_TRY(check_net(net));
+  if (ldu < net->out) return SKETCHNE_E_ARG;
+  SK_TRY(check_ws(ws, ws_bytes, ws_grad_bytes(n, net->width, net->out)));
+  return ws_grad(c, net, n, phi, U, ldu, mu, grad, loss, ws, ws_bytes);
+}
+
+sketchne_status sketchne_ws_adam(sketchne_ctx* c, const sketchne_mlp* net, const float* grad, float lr,
+                                 int32_t step) {
+  if (!c || !grad || step < 1 || !(lr > 0.f)) return SKETCHNE_E_ARG;
+  SK_TRY(check_net(net));
+  if (!net->adam_m || !net->adam_v) return SKETCHNE_E_ARG;
+  return ws_adam(c, net, grad, lr, step, 0.9, 0.999, 1e-8);
+}
+
+sketchne_status sketchne_ws_train(sketchne_ctx* c, const sketchne_mlp* net, int32_t nsets,
+                                  const float* const* phi, const float* const* U, const int64_t* n, int32_t steps,
+                                  int32_t step0, float lr, float mu, float* losses, void* ws, size_t ws_bytes) {
+  if (!c || !phi || !U || !n || !losses || nsets < 1 || steps < 0 || step0 < 0 || !(lr > 0.f) || !(mu >= 0.f))
+    return SKETCHNE_E_ARG;
+  SK_TRY(check_net(net));
+  if (!net->adam_m || !net->adam_v) return SKETCHNE_E_ARG;
+  int64_t nmax = 0;
+  for (int s = 0; s < nsets; ++s) {
+    if (!phi[s] || !U[s] || n[s] < 1) return SKETCHNE_E_ARG;
+    nmax = n[s] > nmax ? n[s] : nmax;
+  }
+  const int64_t count = ws_param_count(net->width, net->out);
+  const size_t gb = ws_grad_bytes(nmax, net->width, net->out);
+  SK_TRY(check_ws(ws, ws_bytes, align_up(sizeof(float) * count) + gb));
+  Arena ar(ws, ws_bytes);
+  float* grad = ar.take<float>(count);
+  char* scratch = ar.take<char>(gb);
+  if (ar.overflow) return SKETCHNE_E_WORKSPACE;
+  for (int t = 0; t < steps; ++t) {
+    const int s = t % nsets;
+    SK_TRY(ws_grad(c, net, n[s], phi[s], U[s], net->out, mu, grad, losses + t, scratch, gb));
+    SK_TRY(ws_adam(c, net, grad, lr, step0 + t + 1, 0.9, 0.999, 1e-8));
+  }
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_ritz_residual(sketchne_ctx* c, const sketchne_graph* A, double alpha, int32_t k,
+                                       const float* U, const double* lambda, double* res, void* ws,
+                                       size_t ws_bytes) {
+  if (!c || !U || !lambda || !res) return SKETCHNE_E_ARG;
+  SK_TRY(check_graph(A));
+  if (!(alpha > 0.0 && alpha <= 0.5) || k < 4 || k % 4 || k > A->n) return SKETCHNE_E_ARG;
+  if (k > 512) return SKETCHNE_E_UNSUPPORTED;
+  SK_TRY(check_ws(ws, ws_bytes, ritz_residual_bytes(A->n, A->nnz, k)));
+  return ritz_residual(c, A->n, A->nnz, A->rowptr, A->colidx, alpha, k, U, lambda, res, ws, ws_bytes);
+}
+
+sketchne_status sketchne_eig_learned(sketchne_ctx* c, const sketchne_graph* A, const sketchne_params* p,
+                                     const sketchne_mlp* net, int32_t q_warm, double res_threshold, float* U,
+                                     double* lambda, int32_t* used_fallback, void* ws, size_t ws_bytes) {
+  if (!c || !U || !lambda || !used_fallback || q_warm < 0) return SKETCHNE_E_ARG;
+  SK_TRY(check_graph(A));
+  SK_TRY(check_params(p, A->n));
+  SK_TRY(check_net(net));
+  if (net->out != p->k) return SKETCHNE_E_ARG;
+  const int K = p->k + p->s_eig;
+  if (K > kSymeigMax || K % 4 || p->k % 4) return SKETCHNE_E_UNSUPPORTED;
+  const int64_t n = A->n;
+  SK_TRY(check_ws(ws, ws_bytes, learned_bytes(p, net->width, n, A->nnz)));
+  Arena ar(ws, ws_bytes);
+  float* omega = ar.take<float>((size_t)n * K);
+  const size_t rest_bytes = learned_rest_bytes(p, net->width, n, A->nnz);
+  char* rest = ar.take<char>(rest_bytes);
+  if (ar.overflow) return SKETCHNE_E_WORKSPACE;
+  *used_fallback = 0;
+  // start block: [F | Gaussian]
+  {
+    Arena r(rest, rest_bytes);
+    float* phi = r.take<float>((size_t)n * SKETCHNE_WS_FEAT);
+    char* scratch = r.take<char>(rest_bytes - r.off);
+    size_t sb = rest_bytes - align_up(sizeof(float) * (size_t)n * SKETCHNE_WS_FEAT);
+    if (r.overflow) return SKETCHNE_E_WORKSPACE;
+    SK_TRY(ws_features(c, n, A->nnz, A->rowptr, A->colidx, p->alpha, nullptr, p->seed ^ 0x7f4a7c159e3779b9ULL, phi,
+                       scratch, sb));
+    SK_TRY(ws_forward(c, net, n, phi, omega, K, scratch, sb));
+    SK_TRY(gen_gauss(c, n, p->s_eig, K, p->seed, omega + p->k));
+  }
+  sketchne_params pw = *p;
+  pw.q = q_warm;
+  SK_TRY(sketchne_eig(c, A, &pw, omega, U, lambda, rest, rest_bytes));
+  // residual test
+  {
+    Arena r(rest, rest_bytes);
+    double* res = r.take<double>(p->k);
+    size_t rb = ritz_residual_bytes(n, A->nnz, p->k);
+    char* scratch = r.take<char>(rb);
+    if (r.overflow) return SKETCHNE_E_WORKSPACE;
+    SK_TRY(ritz_residual(c, n, A->nnz, A->rowptr, A->colidx, p->alpha, p->k, U, lambda, res, scratch, rb));
+    double* host = new (std::nothrow) double[p->k];
+    if (!host) return SKETCHNE_E_DEVICE;
+    hipError_t e = hipMemcpyAsync(host, res, sizeof(double) * p->k, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    double worst = 0.0;
+    bool finite = true;
+    for (int j = 0; j < p->k; ++j) {
+      if (!(host[j] == host[j]) || host[j] > 1e300) finite = false;
+      else if (host[j] > worst) worst = host[j];
+    }
+    delete[] host;
+    if (e != hipSuccess) return SKETCHNE_E_DEVICE;
+    if (finite && worst <= res_threshold) return SKETCHNE_OK;
+  }
+  *used_fallback = 1;
+  return sketchne_eig(c, A, p, nullptr, U, lambda, rest, rest_bytes);
 }
 
 sketchne_status sketchne_profile_enable(sketchne_ctx* c, int on) {

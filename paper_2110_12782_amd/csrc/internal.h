@@ -23,6 +23,12 @@ struct sketchne_ctx {
   int64_t prof_n[SKETCHNE_PROF_CLASSES] = {0};
 };
 
+#define SK_TRY(expr)                    \
+  do {                                  \
+    sketchne_status _st = (expr);       \
+    if (_st != SKETCHNE_OK) return _st; \
+  } while (0)
+
 namespace skne {
 
 constexpr size_t kAlign = 256;
@@ -77,6 +83,7 @@ inline sketchne_status launch_status() {
 sketchne_status gen_gauss(sketchne_ctx* c, int64_t n, int cols, int64_t ld, uint64_t seed, float* out);
 sketchne_status gen_sparse_sign(sketchne_ctx* c, int64_t n, int cols, int z, uint64_t seed,
                                 int32_t* rows, int8_t* signs);
+sketchne_status gen_rademacher(sketchne_ctx* c, int64_t n, uint64_t seed, float* out);
 
 // spmm.hip
 size_t spmm_ws_bytes(int64_t nnz, int cols);
@@ -129,6 +136,23 @@ constexpr int kSymeigMax = 288;  // largest order of the Jacobi eigensolver
 size_t symeig_ws_bytes(int m);
 sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* V, double* w, void* ws);
 
-// sketch.hip
-struct SketchPlan;
+// mlp.hip (learned warm start)
+int64_t ws_param_count(int width, int out);
+size_t ws_part_floats(int64_t n, int width, int out);
+size_t ws_forward_bytes(int64_t n, int width);
+size_t ws_grad_bytes(int64_t n, int width, int out);
+size_t ws_features_bytes(int64_t n, int64_t nnz);
+size_t ritz_residual_bytes(int64_t n, int64_t nnz, int k);
+sketchne_status ws_init(sketchne_ctx* c, const sketchne_mlp* net, uint64_t seed);
+sketchne_status ws_features(sketchne_ctx* c, int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colidx,
+                            double alpha, const float* g, uint64_t seed, float* phi, void* ws, size_t ws_bytes);
+sketchne_status ws_forward(sketchne_ctx* c, const sketchne_mlp* net, int64_t n, const float* phi, float* F,
+                           int64_t ldf, void* ws, size_t ws_bytes);
+sketchne_status ws_grad(sketchne_ctx* c, const sketchne_mlp* net, int64_t n, const float* phi, const float* U,
+                        int64_t ldu, float mu, float* grad, float* loss, void* ws, size_t ws_bytes);
+sketchne_status ws_adam(sketchne_ctx* c, const sketchne_mlp* net, const float* grad, float lr, int step, double beta1,
+                        double beta2, double eps);
+sketchne_status ritz_residual(sketchne_ctx* c, int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colidx,
+                              double alpha, int k, const float* U, const double* lambda, double* res, void* ws,
+                              size_t ws_bytes);
 }  // namespace skne

@@ -1,0 +1,577 @@
+// Learned warm start for the randomized eigensolver (an addition to Alg. 5,
+// which starts from a Gaussian block): per-vertex features, a 3-layer ReLU
+// network whose output replaces the first k columns of the start block, the
+// subspace loss that trains it, backpropagation and Adam.
+//
+//   features  phi_i = standardised [log max(deg_i,1), (Xg)_i, (X^2g)_i, (X^3g)_i, (X^4g)_i, 0, 0, 0]
+//             X = D^-a A D^-a, g Rademacher; a column whose standard deviation is at
+//             most 1e-6 times its root mean square is set to 0.
+//   network   F = relu(relu(phi W1 + b1) W2 + b2) W3 + b3
+//   loss      L = ||(I - UU^T)F||^2/||F||^2 + mu ||(k/||F||^2) F^T F - I||^2
+//             dL/dF = U A + F B,  A = -(2/s) P,
+//             B = (4 mu k/s) M + (2||P||^2/s^2 - 4 mu k <M,G>/s^2) I
+//             with s = ||F||^2, P = U^T F, G = F^T F, M = (k/s) G - I.
+//
+// Weights are stored in BF16 (an FP32 master copy is what Adam updates);
+// activations are FP32 and every product runs on the FP32 matrix cores
+// (v_mfma_f32_32x32x2_f32) with FP32 accumulation.  Reductions over vertices
+// (weight gradients, F^T F, U^T F, column sums) are split over fixed row
+// ranges and summed in a fixed order, so results are deterministic.
+#include "internal.h"
+
+namespace skne {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int FEAT = SKETCHNE_WS_FEAT;
+
+__device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+template <typename WT> __device__ __forceinline__ float wval(const WT* w, int64_t i);
+template <> __device__ __forceinline__ float wval<uint16_t>(const uint16_t* w, int64_t i) { return bf16_val(w[i]); }
+template <> __device__ __forceinline__ float wval<float>(const float* w, int64_t i) { return w[i]; }
+
+// ---------------------------------------------------------------- dense layer
+// C(i, j) = act( sum_k A(i,k) W(k,j) + b(j) ) * [mask(i,j) > 0] (+ C(i,j) if accumulate)
+// A: n x K FP32 row-major (lda); W(k, j) = W[k*wsk + j*wsj]; b: N or null.
+// Workgroup: 256 threads = 4 waves in a 2 x 2 grid of 32 x 32 MFMA tiles
+// (64 rows x 64 columns); the summation runs in chunks of KC through LDS.
+template <typename WT>
+struct DenseArgs {
+  int64_t n; int K, N;
+  const float* A; int64_t lda;
+  const WT* W; int64_t wsk, wsj;
+  const WT* bias;
+  const float* mask; int64_t ldm;
+  float* C; int64_t ldc;
+  int relu, accumulate;
+};
+
+template <typename WT, int KC>
+__global__ __launch_bounds__(256) void k_dense(DenseArgs<WT> a) {
+  __shared__ float As[64][KC + 1];
+  __shared__ float Bs[KC][64 + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  const int col0 = blockIdx.y * 64;
+  floatx16 acc;
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  for (int k0 = 0; k0 < a.K; k0 += KC) {
+    for (int e = tid; e < 64 * KC; e += 256) {
+      int r = e / KC, kk = e % KC;
+      int64_t gi = row0 + r;
+      int gk = k0 + kk;
+      As[r][kk] = (gi < a.n && gk < a.K) ? a.A[gi * a.lda + gk] : 0.f;
+    }
+    for (int e = tid; e < 64 * KC; e += 256) {
+      int kk = e / 64, j = e % 64;
+      int gk = k0 + kk, gj = col0 + j;
+      Bs[kk][j] = (gk < a.K && gj < a.N) ? wval<WT>(a.W, (int64_t)gk * a.wsk + (int64_t)gj * a.wsj) : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 2) {
+      float av = As[wr * 32 + (lane & 31)][kk + (lane >> 5)];
+      float bv = Bs[kk + (lane >> 5)][wc * 32 + (lane & 31)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int gj = col0 + wc * 32 + (lane & 31);
+  if (gj >= a.N) return;
+  const float bj = a.bias ? wval<WT>(a.bias, gj) : 0.f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    int64_t gi = row0 + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    if (gi >= a.n) continue;
+    float v = acc[r] + bj;
+    if (a.relu) v = fmaxf(v, 0.f);
+    if (a.mask && !(a.mask[gi * a.ldm + gj] > 0.f)) v = 0.f;
+    float* dst = a.C + gi * a.ldc + gj;
+    if (a.accumulate) v += *dst;
+    *dst = v;
+  }
+}
+
+// ---------------------------------------------------------------- A^T B over row ranges
+// part[p](i, j) = sum_{r in range p} A(r, i) B(r, j), i < K1, j < K2.
+// Grid: (ceil(K1/64) * ceil(K2/64), parts).  Rows run in chunks of 32 via LDS.
+struct GramArgs32 {
+  int64_t n; int K1, K2; int64_t rows_per_part;
+  const float* A; int64_t lda;
+  const float* B; int64_t ldb;
+  float* part;  // parts x K1 x K2
+};
+
+__global__ __launch_bounds__(256) void k_gram32(GramArgs32 g) {
+  __shared__ float As[32][64 + 4];
+  __shared__ float Bs[32][64 + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  const int tj = (g.K2 + 63) / 64;
+  const int i0 = (blockIdx.x / tj) * 64, j0 = (blockIdx.x % tj) * 64;
+  const int64_t rb = (int64_t)blockIdx.y * g.rows_per_part;
+  const int64_t re = min(g.n, rb + g.rows_per_part);
+  floatx16 acc;
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  for (int64_t r0 = rb; r0 < re; r0 += 32) {
+    for (int e = tid; e < 32 * 64; e += 256) {
+      int r = e / 64, c = e % 64;
+      int64_t gr = r0 + r;
+      bool ok = gr < re;
+      As[r][c] = (ok && i0 + c < g.K1) ? g.A[gr * g.lda + i0 + c] : 0.f;
+      Bs[r][c] = (ok && j0 + c < g.K2) ? g.B[gr * g.ldb + j0 + c] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 2) {
+      float av = As[kk + (lane >> 5)][wr * 32 + (lane & 31)];
+      float bv = Bs[kk + (lane >> 5)][wc * 32 + (lane & 31)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int j = j0 + wc * 32 + (lane & 31);
+  if (j >= g.K2) return;
+  float* out = g.part + (int64_t)blockIdx.y * g.K1 * g.K2;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    int i = i0 + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    if (i < g.K1) out[(int64_t)i * g.K2 + j] = acc[r];
+  }
+}
+
+// out[e] = sum_p part[p][e], p in order
+__global__ void k_sum_parts(int64_t count, int parts, const float* __restrict__ part, float* __restrict__ out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  float s = 0.f;
+  for (int p = 0; p < parts; ++p) s += part[(int64_t)p * count + e];
+  out[e] = s;
+}
+
+// part[p][j] = sum_{r in range p} A(r, j)
+__global__ void k_colsum_part(int64_t n, int N, int64_t rows_per_part, const float* __restrict__ A, int64_t lda,
+                              float* __restrict__ part) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  int64_t rb = (int64_t)blockIdx.y * rows_per_part, re = min(n, rb + rows_per_part);
+  float s = 0.f;
+  for (int64_t r = rb; r < re; ++r) s += A[r * lda + j];
+  part[(int64_t)blockIdx.y * N + j] = s;
+}
+
+// ---------------------------------------------------------------- loss and dL/dF coefficients
+// One workgroup.  P = U^T F, G = F^T F (k x k FP32).  Writes the loss and the
+// k x k matrices Acoef, Bcoef with dL/dF = U Acoef + F Bcoef.
+__device__ double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (tid == 0) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+    red[16] = s;
+  }
+  __syncthreads();
+  s = red[16];
+  __syncthreads();
+  return s;
+}
+
+__global__ __launch_bounds__(1024) void k_ws_loss(int k, float mu, const float* __restrict__ P,
+                                                  const float* __restrict__ G, float* __restrict__ Acoef,
+                                                  float* __restrict__ Bcoef, float* __restrict__ loss) {
+  __shared__ double red[17];
+  const int tid = threadIdx.x;
+  const int64_t kk = (int64_t)k * k;
+  double tr = 0.0, pp = 0.0;
+  for (int64_t e = tid; e < kk; e += blockDim.x) {
+    double p = P[e];
+    pp += p * p;
+    if (e / k == e % k) tr += G[e];
+  }
+  const double s = block_sum(tr, red);
+  pp = block_sum(pp, red);
+  double mm = 0.0, mg = 0.0;
+  for (int64_t e = tid; e < kk; e += blockDim.x) {
+    double g = G[e];
+    double m = (double)k / s * g - (e / k == e % k ? 1.0 : 0.0);
+    mm += m * m;
+    mg += m * g;
+  }
+  mm = block_sum(mm, red);
+  mg = block_sum(mg, red);
+  const double cm = 4.0 * mu * k / s;
+  const double cdiag = 2.0 * pp / (s * s) - 4.0 * mu * k * mg / (s * s);
+  for (int64_t e = tid; e < kk; e += blockDim.x) {
+    bool diag = e / k == e % k;
+    double m = (double)k / s * G[e] - (diag ? 1.0 : 0.0);
+    Acoef[e] = (float)(-2.0 / s * P[e]);
+    Bcoef[e] = (float)(cm * m + (diag ? cdiag : 0.0));
+  }
+  if (tid == 0) *loss = (float)(1.0 - pp / s + mu * mm);
+}
+
+// ---------------------------------------------------------------- Adam and parameter set-up
+// b1, b2 and their complements om1 = 1 - b1, om2 = 1 - b2 are rounded to FP32
+// from exact values on the host (1 - 0.999f is not 0.001 to FP32 accuracy);
+// c1 = 1 - b1^step, c2 = 1 - b2^step likewise.
+__global__ void k_adam(int64_t count, float lr, float b1, float b2, float om1, float om2, float eps, float c1,
+                       float c2, const float* __restrict__ g, float* __restrict__ w, float* __restrict__ m,
+                       float* __restrict__ v, uint16_t* __restrict__ wb) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  float ge = g[e];
+  float me = b1 * m[e] + om1 * ge;
+  float ve = b2 * v[e] + om2 * ge * ge;
+  m[e] = me;
+  v[e] = ve;
+  float we = w[e] - lr * (me / c1) / (sqrtf(ve / c2) + eps);
+  w[e] = we;
+  wb[e] = bf16_rne(we);
+}
+
+// master[e] *= scale for e in [0, count) ; zero rows / biases handled by k_fill
+__global__ void k_scale_f(int64_t count, float scale, float* __restrict__ x) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) x[e] *= scale;
+}
+__global__ void k_fill_f(int64_t count, float val, float* __restrict__ x) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) x[e] = val;
+}
+__global__ void k_to_bf16(int64_t count, const float* __restrict__ x, uint16_t* __restrict__ out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) out[e] = bf16_rne(x[e]);
+}
+
+// ---------------------------------------------------------------- features
+// raw(i, 0) = log max(deg_i, 1); T0 = [g, 0, 0, 0] (n x 4)
+__global__ void k_feat_seed(int64_t n, const int64_t* __restrict__ rowptr, const float* __restrict__ g,
+                            float* __restrict__ raw, float* __restrict__ T0) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double deg = (double)(rowptr[i + 1] - rowptr[i]);
+  raw[i * FEAT] = (float)log(deg > 1.0 ? deg : 1.0);
+  T0[i * 4 + 0] = g[i];
+  T0[i * 4 + 1] = 0.f;
+  T0[i * 4 + 2] = 0.f;
+  T0[i * 4 + 3] = 0.f;
+}
+__global__ void k_feat_take(int64_t n, int col, const float* __restrict__ T, float* __restrict__ raw) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) raw[i * FEAT + col] = T[i * 4];
+}
+// one workgroup per raw column: mean, then centred and plain second moments
+// (FP64, fixed order); stat[2j] = mean, stat[2j+1] = 1/std or 0 (no spread)
+__global__ __launch_bounds__(1024) void k_feat_stats(int64_t n, const float* __restrict__ raw,
+                                                     double* __restrict__ stat) {
+  __shared__ double red[17];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += raw[i * FEAT + j];
+  const double mean = block_sum(s, red) / (double)n;
+  double c2 = 0.0, p2 = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    double x = raw[i * FEAT + j];
+    c2 += (x - mean) * (x - mean);
+    p2 += x * x;
+  }
+  const double sd = sqrt(block_sum(c2, red) / (double)n);
+  const double rms = sqrt(block_sum(p2, red) / (double)n);
+  if (threadIdx.x == 0) {
+    stat[2 * j] = mean;
+    stat[2 * j + 1] = sd > 1e-6 * rms ? 1.0 / sd : 0.0;
+  }
+}
+__global__ void k_feat_apply(int64_t n, int nraw, const double* __restrict__ stat, float* __restrict__ phi) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * FEAT) return;
+  int j = (int)(e % FEAT);
+  float v = 0.f;
+  if (j < nraw && stat[2 * j + 1] != 0.0) v = (float)(((double)phi[e] - stat[2 * j]) * stat[2 * j + 1]);
+  phi[e] = v;
+}
+
+// ---------------------------------------------------------------- Ritz residuals
+// part[p][j] = sum_{r in range p} (XU(r,j) - lambda_j U(r,j))^2   (FP64)
+__global__ void k_resid_part(int64_t n, int k, int64_t rows_per_part, const float* __restrict__ XU,
+                             const float* __restrict__ U, const double* __restrict__ lambda,
+                             double* __restrict__ part) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  int64_t rb = (int64_t)blockIdx.y * rows_per_part, re = min(n, rb + rows_per_part);
+  const double lj = lambda[j];
+  double s = 0.0;
+  for (int64_t r = rb; r < re; ++r) {
+    double d = (double)XU[r * k + j] - lj * (double)U[r * k + j];
+    s += d * d;
+  }
+  part[(int64_t)blockIdx.y * k + j] = s;
+}
+__global__ void k_resid_final(int k, int parts, const double* __restrict__ part, double* __restrict__ res) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  double s = 0.0;
+  for (int p = 0; p < parts; ++p) s += part[(int64_t)p * k + j];
+  res[j] = sqrt(s);
+}
+
+inline unsigned nblk(int64_t count, int t = 256) { return (unsigned)((count + t - 1) / t); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+int64_t ws_param_count(int width, int out) {
+  return (int64_t)FEAT * width + width + (int64_t)width * width + width + (int64_t)width * out + out;
+}
+
+namespace {
+struct Off { int64_t W1, b1, W2, b2, W3, b3; };
+Off offsets(int w, int o) {
+  Off f;
+  f.W1 = 0;
+  f.b1 = f.W1 + (int64_t)FEAT * w;
+  f.W2 = f.b1 + w;
+  f.b2 = f.W2 + (int64_t)w * w;
+  f.W3 = f.b2 + w;
+  f.b3 = f.W3 + (int64_t)w * o;
+  return f;
+}
+
+int64_t parts_for(int64_t n) {
+  int64_t parts = (n + 2047) / 2048;
+  return parts < 1 ? 1 : (parts > 128 ? 128 : parts);
+}
+
+template <typename WT>
+sketchne_status dense(sketchne_ctx* c, int64_t n, int K, int N, const float* A, int64_t lda, const WT* W, int64_t wsk,
+                      int64_t wsj, const WT* bias, const float* mask, int64_t ldm, float* C, int64_t ldc, bool relu,
+                      bool accumulate) {
+  if (n == 0) return SKETCHNE_OK;
+  DenseArgs<WT> a{n, K, N, A, lda, W, wsk, wsj, bias, mask, ldm, C, ldc, relu ? 1 : 0, accumulate ? 1 : 0};
+  dim3 grid((unsigned)((n + 63) / 64), (unsigned)((N + 63) / 64));
+  if (K <= 8)
+    hipLaunchKernelGGL((k_dense<WT, 8>), grid, dim3(256), 0, c->stream, a);
+  else
+    hipLaunchKernelGGL((k_dense<WT, 32>), grid, dim3(256), 0, c->stream, a);
+  return launch_status();
+}
+
+// C (K1 x K2) = A^T B over all n rows; part: parts_for(n) * K1 * K2 floats
+sketchne_status gram32(sketchne_ctx* c, int64_t n, int K1, int K2, const float* A, int64_t lda, const float* B,
+                       int64_t ldb, float* part, float* C) {
+  int64_t parts = parts_for(n);
+  int64_t rpp = (n + parts - 1) / parts;
+  rpp = (rpp + 31) / 32 * 32;
+  parts = (n + rpp - 1) / rpp;
+  if (parts < 1) parts = 1;
+  GramArgs32 g{n, K1, K2, rpp, A, lda, B, ldb, part};
+  dim3 grid((unsigned)(((K1 + 63) / 64) * ((K2 + 63) / 64)), (unsigned)parts);
+  hipLaunchKernelGGL(k_gram32, grid, dim3(256), 0, c->stream, g);
+  int64_t cnt = (int64_t)K1 * K2;
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(cnt)), dim3(256), 0, c->stream, cnt, (int)parts, part, C);
+  return launch_status();
+}
+
+sketchne_status colsum(sketchne_ctx* c, int64_t n, int N, const float* A, int64_t lda, float* part, float* out) {
+  int64_t parts = parts_for(n);
+  int64_t rpp = (n + parts - 1) / parts;
+  parts = (n + rpp - 1) / rpp;
+  if (parts < 1) parts = 1;
+  hipLaunchKernelGGL(k_colsum_part, dim3(nblk(N), (unsigned)parts), dim3(256), 0, c->stream, n, N, rpp, A, lda, part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(N)), dim3(256), 0, c->stream, (int64_t)N, (int)parts, part, out);
+  return launch_status();
+}
+}  // namespace
+
+size_t ws_part_floats(int64_t n, int width, int out) {
+  int64_t m = width > out ? width : out;
+  return (size_t)parts_for(n) * (size_t)(m * m > FEAT * m ? m * m : FEAT * m);
+}
+
+size_t ws_forward_bytes(int64_t n, int width) {
+  return 2 * align_up(sizeof(float) * (size_t)n * width);
+}
+
+size_t ws_grad_bytes(int64_t n, int width, int out) {
+  size_t b = 0;
+  b += 2 * align_up(sizeof(float) * (size_t)n * width);   // H1, H2
+  b += 2 * align_up(sizeof(float) * (size_t)n * out);     // F, dF
+  b += 2 * align_up(sizeof(float) * (size_t)n * width);   // dZ2, dZ1
+  b += align_up(sizeof(float) * ws_part_floats(n, width, out));
+  b += 4 * align_up(sizeof(float) * (size_t)out * out);   // P, G, Acoef, Bcoef
+  return b;
+}
+
+size_t ws_features_bytes(int64_t n, int64_t nnz) {
+  return 2 * align_up(sizeof(float) * (size_t)n * 4) + align_up(sizeof(float) * (size_t)n) +
+         align_up(sizeof(double) * 2 * FEAT) + align_up(sizeof(float) * (size_t)n) + spmm_ws_bytes(nnz, 4);
+}
+
+size_t ritz_residual_bytes(int64_t n, int64_t nnz, int k) {
+  return align_up(sizeof(float) * (size_t)n * k) + align_up(sizeof(float) * (size_t)n) +
+         align_up(sizeof(double) * (size_t)parts_for(n) * k) + spmm_ws_bytes(nnz, k);
+}
+
+sketchne_status ws_init(sketchne_ctx* c, const sketchne_mlp* net, uint64_t seed) {
+  const int w = net->width, o = net->out;
+  const Off f = offsets(w, o);
+  const int64_t total = ws_param_count(w, o);
+  ProfScope ps(c, SKETCHNE_PROF_PREP);
+  // He initialisation: N(0, 2 / fan_in); the padded rows of W1 start at 0
+  SK_TRY(gen_gauss(c, SKETCHNE_WS_RAW, w, w, seed ^ 0x1111, net->master + f.W1));
+  SK_TRY(gen_gauss(c, w, w, w, seed ^ 0x2222, net->master + f.W2));
+  SK_TRY(gen_gauss(c, w, o, o, seed ^ 0x3333, net->master + f.W3));
+  hipLaunchKernelGGL(k_scale_f, dim3(nblk((int64_t)SKETCHNE_WS_RAW * w)), dim3(256), 0, c->stream,
+                     (int64_t)SKETCHNE_WS_RAW * w, sqrtf(2.f / SKETCHNE_WS_RAW), net->master + f.W1);
+  hipLaunchKernelGGL(k_fill_f, dim3(nblk((int64_t)(FEAT - SKETCHNE_WS_RAW) * w)), dim3(256), 0, c->stream,
+                     (int64_t)(FEAT - SKETCHNE_WS_RAW) * w, 0.f, net->master + f.W1 + (int64_t)SKETCHNE_WS_RAW * w);
+  hipLaunchKernelGGL(k_scale_f, dim3(nblk((int64_t)w * w)), dim3(256), 0, c->stream, (int64_t)w * w,
+                     sqrtf(2.f / w), net->master + f.W2);
+  hipLaunchKernelGGL(k_scale_f, dim3(nblk((int64_t)w * o)), dim3(256), 0, c->stream, (int64_t)w * o,
+                     sqrtf(2.f / w), net->master + f.W3);
+  hipLaunchKernelGGL(k_fill_f, dim3(nblk(w)), dim3(256), 0, c->stream, (int64_t)w, 0.f, net->master + f.b1);
+  hipLaunchKernelGGL(k_fill_f, dim3(nblk(w)), dim3(256), 0, c->stream, (int64_t)w, 0.f, net->master + f.b2);
+  hipLaunchKernelGGL(k_fill_f, dim3(nblk(o)), dim3(256), 0, c->stream, (int64_t)o, 0.f, net->master + f.b3);
+  if (net->adam_m)
+    hipLaunchKernelGGL(k_fill_f, dim3(nblk(total)), dim3(256), 0, c->stream, total, 0.f, net->adam_m);
+  if (net->adam_v)
+    hipLaunchKernelGGL(k_fill_f, dim3(nblk(total)), dim3(256), 0, c->stream, total, 0.f, net->adam_v);
+  hipLaunchKernelGGL(k_to_bf16, dim3(nblk(total)), dim3(256), 0, c->stream, total, net->master, net->bf16);
+  return launch_status();
+}
+
+sketchne_status ws_features(sketchne_ctx* c, int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colidx,
+                            double alpha, const float* g, uint64_t seed, float* phi, void* ws, size_t ws_bytes) {
+  Arena ar(ws, ws_bytes);
+  float* T0 = ar.take<float>((size_t)n * 4);
+  float* T1 = ar.take<float>((size_t)n * 4);
+  float* gdraw = ar.take<float>((size_t)n);
+  double* stat = ar.take<double>(2 * FEAT);
+  float* dscale = ar.take<float>((size_t)n);
+  float* part = ar.take<float>(spmm_ws_bytes(nnz, 4) / sizeof(float));
+  if (ar.overflow) return SKETCHNE_E_WORKSPACE;
+  ProfScope ps(c, SKETCHNE_PROF_PREP);
+  if (!g) {
+    SK_TRY(gen_rademacher(c, n, seed, gdraw));
+    g = gdraw;
+  }
+  SK_TRY(degree_scale(c, n, rowptr, alpha, dscale));
+  hipLaunchKernelGGL(k_feat_seed, dim3(nblk(n)), dim3(256), 0, c->stream, n, rowptr, g, phi, T0);
+  SK_TRY(launch_status());
+  float* src = T0;
+  float* dst = T1;
+  for (int t = 1; t < SKETCHNE_WS_RAW; ++t) {
+    SK_TRY(spmm(c, n, nnz, rowptr, colidx, dscale, src, 4, 4, dst, 4, part));
+    hipLaunchKernelGGL(k_feat_take, dim3(nblk(n)), dim3(256), 0, c->stream, n, t, dst, phi);
+    float* tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+  hipLaunchKernelGGL(k_feat_stats, dim3(SKETCHNE_WS_RAW), dim3(1024), 0, c->stream, n, phi, stat);
+  hipLaunchKernelGGL(k_feat_apply, dim3(nblk(n * FEAT)), dim3(256), 0, c->stream, n, (int)SKETCHNE_WS_RAW, stat,
+                     phi);
+  return launch_status();
+}
+
+sketchne_status ws_forward(sketchne_ctx* c, const sketchne_mlp* net, int64_t n, const float* phi, float* F,
+                           int64_t ldf, void* ws, size_t ws_bytes) {
+  const int w = net->width, o = net->out;
+  const Off f = offsets(w, o);
+  Arena ar(ws, ws_bytes);
+  float* H1 = ar.take<float>((size_t)n * w);
+  float* H2 = ar.take<float>((size_t)n * w);
+  if (ar.overflow) return SKETCHNE_E_WORKSPACE;
+  ProfScope ps(c, SKETCHNE_PROF_PREP);
+  const uint16_t* Wb = net->bf16;
+  SK_TRY(dense<uint16_t>(c, n, FEAT, w, phi, FEAT, Wb + f.W1, w, 1, Wb + f.b1, nullptr, 0, H1, w, true, false));
+  SK_TRY(dense<uint16_t>(c, n, w, w, H1, w, Wb + f.W2, w, 1, Wb + f.b2, nullptr, 0, H2, w, true, false));
+  return dense<uint16_t>(c, n, w, o, H2, w, Wb + f.W3, o, 1, Wb + f.b3, nullptr, 0, F, ldf, false, false);
+}
+
+sketchne_status ws_grad(sketchne_ctx* c, const sketchne_mlp* net, int64_t n, const float* phi, const float* U,
+                        int64_t ldu, float mu, float* grad, float* loss, void* ws, size_t ws_bytes) {
+  const int w = net->width, o = net->out;
+  const Off f = offsets(w, o);
+  Arena ar(ws, ws_bytes);
+  float* H1 = ar.take<float>((size_t)n * w);
+  float* H2 = ar.take<float>((size_t)n * w);
+  float* F = ar.take<float>((size_t)n * o);
+  float* dF = ar.take<float>((size_t)n * o);
+  float* dZ2 = ar.take<float>((size_t)n * w);
+  float* dZ1 = ar.take<float>((size_t)n * w);
+  float* part = ar.take<float>(ws_part_floats(n, w, o));
+  float* P = ar.take<float>((size_t)o * o);
+  float* G = ar.take<float>((size_t)o * o);
+  float* Ac = ar.take<float>((size_t)o * o);
+  float* Bc = ar.take<float>((size_t)o * o);
+  if (ar.overflow) return SKETCHNE_E_WORKSPACE;
+  ProfScope ps(c, SKETCHNE_PROF_PREP);
+  const uint16_t* Wb = net->bf16;
+  // forward
+  SK_TRY(dense<uint16_t>(c, n, FEAT, w, phi, FEAT, Wb + f.W1, w, 1, Wb + f.b1, nullptr, 0, H1, w, true, false));
+  SK_TRY(dense<uint16_t>(c, n, w, w, H1, w, Wb + f.W2, w, 1, Wb + f.b2, nullptr, 0, H2, w, true, false));
+  SK_TRY(dense<uint16_t>(c, n, w, o, H2, w, Wb + f.W3, o, 1, Wb + f.b3, nullptr, 0, F, o, false, false));
+  // loss and dL/dF = U Acoef + F Bcoef
+  SK_TRY(gram32(c, n, o, o, U, ldu, F, o, part, P));
+  SK_TRY(gram32(c, n, o, o, F, o, F, o, part, G));
+  hipLaunchKernelGGL(k_ws_loss, dim3(1), dim3(1024), 0, c->stream, o, mu, P, G, Ac, Bc, loss);
+  SK_TRY(dense<float>(c, n, o, o, U, ldu, Ac, o, 1, nullptr, nullptr, 0, dF, o, false, false));
+  SK_TRY(dense<float>(c, n, o, o, F, o, Bc, o, 1, nullptr, nullptr, 0, dF, o, false, true));
+  // layer 3
+  SK_TRY(gram32(c, n, w, o, H2, w, dF, o, part, grad + f.W3));
+  SK_TRY(colsum(c, n, o, dF, o, part, grad + f.b3));
+  SK_TRY(dense<uint16_t>(c, n, o, w, dF, o, Wb + f.W3, 1, o, nullptr, H2, w, dZ2, w, false, false));
+  // layer 2
+  SK_TRY(gram32(c, n, w, w, H1, w, dZ2, w, part, grad + f.W2));
+  SK_TRY(colsum(c, n, w, dZ2, w, part, grad + f.b2));
+  SK_TRY(dense<uint16_t>(c, n, w, w, dZ2, w, Wb + f.W2, 1, w, nullptr, H1, w, dZ1, w, false, false));
+  // layer 1
+  SK_TRY(gram32(c, n, FEAT, w, phi, FEAT, dZ1, w, part, grad + f.W1));
+  return colsum(c, n, w, dZ1, w, part, grad + f.b1);
+}
+
+sketchne_status ws_adam(sketchne_ctx* c, const sketchne_mlp* net, const float* grad, float lr, int step, double beta1,
+                        double beta2, double eps) {
+  const int64_t total = ws_param_count(net->width, net->out);
+  const float c1 = (float)(1.0 - pow(beta1, (double)step));
+  const float c2 = (float)(1.0 - pow(beta2, (double)step));
+  ProfScope ps(c, SKETCHNE_PROF_PREP);
+  hipLaunchKernelGGL(k_adam, dim3(nblk(total)), dim3(256), 0, c->stream, total, lr, (float)beta1, (float)beta2,
+                     (float)(1.0 - beta1), (float)(1.0 - beta2), (float)eps, c1, c2, grad, net->master, net->adam_m,
+                     net->adam_v, net->bf16);
+  return launch_status();
+}
+
+sketchne_status ritz_residual(sketchne_ctx* c, int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colidx,
+                              double alpha, int k, const float* U, const double* lambda, double* res, void* ws,
+                              size_t ws_bytes) {
+  Arena ar(ws, ws_bytes);
+  float* XU = ar.take<float>((size_t)n * k);
+  float* dscale = ar.take<float>((size_t)n);
+  double* part = ar.take<double>((size_t)parts_for(n) * k);
+  float* sp = ar.take<float>(spmm_ws_bytes(nnz, k) / sizeof(float));
+  if (ar.overflow) return SKETCHNE_E_WORKSPACE;
+  SK_TRY(degree_scale(c, n, rowptr, alpha, dscale));
+  SK_TRY(spmm(c, n, nnz, rowptr, colidx, dscale, U, k, k, XU, k, sp));
+  ProfScope ps(c, SKETCHNE_PROF_PREP);
+  int64_t parts = parts_for(n);
+  int64_t rpp = (n + parts - 1) / parts;
+  parts = (n + rpp - 1) / rpp;
+  hipLaunchKernelGGL(k_resid_part, dim3(nblk(k), (unsigned)parts), dim3(256), 0, c->stream, n, k, rpp, XU, U, lambda,
+                     part);
+  hipLaunchKernelGGL(k_resid_final, dim3(nblk(k)), dim3(256), 0, c->stream, k, (int)parts, part, res);
+  return launch_status();
+}
+
+}  // namespace skne

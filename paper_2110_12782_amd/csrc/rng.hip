@@ -79,7 +79,21 @@ __global__ void k_sparse_sign(int64_t n, int cols, int z, uint64_t seed,
   }
 }
 
+// out[i] = +1 or -1 with probability 1/2 each (top bit of draw i)
+__global__ void k_rademacher(int64_t n, uint64_t seed, float* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t s = mix64(seed ^ 0xa54ff53a5f1d36f1ULL);
+  out[i] = (draw(s, (uint64_t)i) >> 63) ? 1.f : -1.f;
+}
+
 }  // namespace
+
+sketchne_status gen_rademacher(sketchne_ctx* c, int64_t n, uint64_t seed, float* out) {
+  if (n == 0) return SKETCHNE_OK;
+  hipLaunchKernelGGL(k_rademacher, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, seed, out);
+  return launch_status();
+}
 
 sketchne_status gen_gauss(sketchne_ctx* c, int64_t n, int cols, int64_t ld, uint64_t seed, float* out) {
   int64_t total = n * cols;

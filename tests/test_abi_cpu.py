@@ -84,3 +84,35 @@ def test_null_context_and_pointers_rejected_before_any_work(lib):
     assert L.sketchne_orth_workspace_size(0, 4, C.byref(out)) == B.E_ARG
     assert L.sketchne_symeig_workspace_size(0, C.byref(out)) == B.E_ARG
     assert L.sketchne_symeig_workspace_size(288, C.byref(out)) == B.OK and out.value >= 2 * 288 * 288 * 8
+
+
+def test_warm_start_param_count_and_workspace(lib):
+    w, o = 256, 256
+    assert lib.ws_param_count(w, o) == 8 * w + w + w * w + w + w * o + o
+    L = lib.lib
+    cnt = C.c_int64(0)
+    assert L.sketchne_ws_param_count(0, 4, C.byref(cnt)) == B.E_ARG
+    fwd = lib.ws_workspace_size(w, o, 1 << 20, 0, B.WS_OP_FORWARD)
+    grad = lib.ws_workspace_size(w, o, 1 << 20, 0, B.WS_OP_GRAD)
+    assert fwd >= 2 * (1 << 20) * w * 4 and grad > fwd
+    p = B.SketchParams(k=256, s_eig=32, d=128, h=272, l=1128, z=8)
+    eig = lib.ws_workspace_size(w, o, 1 << 20, 21 << 20, B.WS_OP_EIG, p)
+    assert eig > lib.workspace_size(p, 1 << 20, 21 << 20, B.OP_EIG)
+    out = C.c_size_t(0)
+    # the eigensolver ops need the parameters
+    assert L.sketchne_ws_workspace_size(None, w, o, 1000, 5000, B.WS_OP_EIG, C.byref(out)) == B.E_ARG
+
+
+def test_warm_start_null_arguments_rejected(lib):
+    L = lib.lib
+    net = B.MLPStruct(256, 64, None, None, None, None)
+    g = B.Graph(100, 0, None, None)
+    p = B.SketchParams(k=8, s_eig=8, d=4, h=8, l=16, z=4).c()
+    assert L.sketchne_ws_init(None, C.byref(net), 1) == B.E_ARG
+    assert L.sketchne_ws_forward(None, C.byref(net), 10, None, None, 64, None, 0) == B.E_ARG
+    assert L.sketchne_ws_grad(None, C.byref(net), 10, None, None, 64, 0.1, None, None, None, 0) == B.E_ARG
+    assert L.sketchne_ws_adam(None, C.byref(net), None, 1e-3, 1) == B.E_ARG
+    assert L.sketchne_ritz_residual(None, C.byref(g), 0.5, 8, None, None, None, None, 0) == B.E_ARG
+    fb = C.c_int32(0)
+    assert L.sketchne_eig_learned(None, C.byref(g), C.byref(p), C.byref(net), 1, 1.0, None, None, C.byref(fb),
+                                  None, 0) == B.E_ARG

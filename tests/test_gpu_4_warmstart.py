@@ -1,0 +1,177 @@
+"""Learned warm start on the GPU against the FP64 oracle (oracle/mlp.py):
+features, forward pass, loss gradient, Adam, and what the trained network
+gains over the Gaussian start (with the fallback)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp as om
+from tests.util import rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _graph_with_isolated():
+    rowptr, colidx = synth.chung_lu(5000, 2.2, 8, 1, 4040)
+    rowptr = np.concatenate([rowptr, [rowptr[-1]] * 3])  # n = 5003, last three isolated
+    return rowptr, colidx
+
+
+def test_features_parity(lib):
+    torch = _torch()
+    from paper_2110_12782_amd.binding import DeviceGraph
+    for rowptr, colidx in (synth.sbm([512] * 8, 0.02, 0.001, 1001), _graph_with_isolated()):
+        n = len(rowptr) - 1
+        g = synth.rademacher(n, 21)
+        G = DeviceGraph(rowptr, colidx)
+        phi = lib.ws_features(G, 0.5, probe=torch.from_numpy(g).cuda()).cpu().numpy()
+        ref = om.features(rowptr, colidx, 0.5, g.astype(np.float64))
+        e = rel(phi, ref)
+        say(f"n={n} features rel {e:.3e}")
+        assert e <= 1e-5
+        assert np.all(phi[:, om.N_RAW:] == 0)
+
+
+def _net_and_inputs(lib, n, width, out, seed):
+    torch = _torch()
+    from paper_2110_12782_amd.binding import MLP
+    net = MLP(lib, width, out)
+    lib.ws_init(net, seed)
+    rng = np.random.default_rng(seed)
+    phi = np.zeros((n, om.FEAT), np.float32)
+    phi[:, :om.N_RAW] = rng.standard_normal((n, om.N_RAW))
+    U = np.linalg.qr(rng.standard_normal((n, out)))[0].astype(np.float32)
+    return net, phi, U, torch.from_numpy(phi).cuda(), torch.from_numpy(U).cuda()
+
+
+def test_init_distribution(lib):
+    torch = _torch()
+    from paper_2110_12782_amd.binding import MLP
+    net = MLP(lib, 256, 64)
+    lib.ws_init(net, 9)
+    p = om.unflatten(net.master.cpu().numpy(), 256, 64)
+    assert np.all(p["W1"][om.N_RAW:] == 0) and np.all(p["b1"] == 0) and np.all(p["b3"] == 0)
+    assert abs(p["W2"].std() - np.sqrt(2 / 256)) < 0.01 * np.sqrt(2 / 256) * 10
+    assert abs(p["W1"][:om.N_RAW].std() - np.sqrt(2 / om.N_RAW)) < 0.1 * np.sqrt(2 / om.N_RAW)
+    # the BF16 copy is the round-to-nearest-even of the master
+    assert np.array_equal(net.bf16_values(), om.bf16_round(net.master.cpu().numpy()))
+    assert torch.all(net.m == 0) and torch.all(net.v == 0)
+
+
+@pytest.mark.parametrize("n,width,out", [(1000, 256, 64), (4099, 256, 256), (70, 64, 12)])
+def test_forward_and_gradient_parity(lib, n, width, out):
+    net, phi, U, phi_d, U_d = _net_and_inputs(lib, n, width, out, 100 + n)
+    theta = net.bf16_values()
+    p = om.unflatten(theta, width, out)
+    F = lib.ws_forward(net, phi_d).cpu().numpy()
+    _, _, Fr = om.forward(p, phi.astype(np.float64))
+    ef = rel(F, Fr)
+    mu = 0.1
+    grad, loss = lib.ws_grad(net, phi_d, U_d, mu)
+    L, gref = om.grad(theta, phi.astype(np.float64), U.astype(np.float64), mu, width, out)
+    gg = grad.cpu().numpy()
+    el = abs(float(loss.cpu()) - L) / abs(L)
+    eg = rel(gg, gref)
+    blocks = {}
+    off = 0
+    for name, shp in om.param_shapes(width, out):
+        size = int(np.prod(shp))
+        if np.linalg.norm(gref[off:off + size]) > 0:
+            blocks[name] = rel(gg[off:off + size], gref[off:off + size])
+        off += size
+    say(f"n={n} width={width} out={out}: F rel {ef:.2e}  loss rel {el:.2e}  grad rel {eg:.2e}  "
+        + " ".join(f"{k} {v:.1e}" for k, v in blocks.items()))
+    assert ef <= 1e-5
+    assert el <= 1e-5
+    assert eg <= 1e-5 and max(blocks.values()) <= 1e-4
+
+
+def test_adam_parity_and_bf16_copy(lib):
+    net, phi, U, phi_d, U_d = _net_and_inputs(lib, 777, 128, 32, 5)
+
+    def state():
+        return (net.master.cpu().numpy().astype(np.float64), net.m.cpu().numpy().astype(np.float64),
+                net.v.cpu().numpy().astype(np.float64))
+
+    for step in (1, 2):
+        grad, _ = lib.ws_grad(net, phi_d, U_d, 0.1)
+        w0, m0, v0 = state()
+        ref_w, ref_m, ref_v = om.adam(w0, grad.cpu().numpy().astype(np.float64), m0, v0, step, 1e-3)
+        lib.ws_adam(net, grad, 1e-3, step)
+        w1, m1, v1 = state()
+        eu = rel(w1 - w0, ref_w - w0)
+        em = rel(m1, ref_m) + rel(v1, ref_v)
+        say(f"adam step {step}: update rel {eu:.2e}, moments rel {em:.2e}")
+        assert eu <= 1e-5 and em <= 1e-5 and rel(w1, ref_w) <= 1e-6
+        # the BF16 copy is exactly the round-to-nearest-even of the new master
+        assert np.array_equal(net.bf16_values(), om.bf16_round(w1))
+
+
+def _sin_theta(U, V):
+    torch = _torch()
+    a = U.double()
+    b = V.double()
+    k = a.shape[1]
+    s = torch.linalg.matrix_norm(b.T @ a) ** 2
+    return float(torch.sqrt(torch.clamp(k - s, min=0.0) / k))
+
+
+def test_training_gain_and_fallback(lib):
+    """Train on eight small graphs, evaluate on two held-out ones: subspace
+    error of U_k against a converged reference, Gaussian vs learned start, at
+    q = 0, 1, 2; then the fallback reproduces the plain result exactly."""
+    torch = _torch()
+    from paper_2110_12782_amd.binding import DeviceGraph, MLP, SketchParams
+    k, s_eig, width = 64, 32, 256
+
+    def P(q, seed):
+        return SketchParams(k=k, s_eig=s_eig, q=q, d=16, h=48, l=128, z=8, seed=seed)
+
+    def graph(i):
+        if i % 2 == 0:
+            return synth.sbm([512] * 16, 0.03, 0.0008, 5000 + i)
+        return synth.chung_lu(8192, 2.0 + 0.1 * (i % 5), 10 + 2 * (i % 4), 2, 5000 + i)
+
+    sets = []
+    for i in range(8):
+        rowptr, colidx = graph(i)
+        G = DeviceGraph(rowptr, colidx)
+        Uref, _ = lib.eig(G, P(16, 70 + i))
+        sets.append((lib.ws_features(G, 0.5, seed=90 + i), Uref.contiguous()))
+    assert lib.sync() & ~1 == 0
+    net = MLP(lib, width, k)
+    lib.ws_init(net, 3)
+    losses = lib.ws_train(net, sets, 480, 1e-3, 0.1).cpu().numpy()
+    first, last = losses[:16].mean(), losses[-16:].mean()
+    say(f"training loss {first:.4f} -> {last:.4f}")
+    assert np.all(np.isfinite(losses))
+    assert last < 0.95 * first
+
+    gains = []
+    for i in (100, 101):
+        rowptr, colidx = graph(i)
+        G = DeviceGraph(rowptr, colidx)
+        Uref, _ = lib.eig(G, P(24, 7))
+        row = []
+        for q in (0, 1, 2):
+            Up, lp = lib.eig(G, P(q, 11))
+            Uw, lw, fb = lib.eig_learned(G, P(q, 11), net, q, float("inf"))
+            assert not fb
+            row.append((q, _sin_theta(Up, Uref), _sin_theta(Uw, Uref)))
+        say(f"held-out graph {i}: " + "  ".join(f"q={q}: plain {a:.4f} learned {b:.4f}" for q, a, b in row))
+        gains.append(row)
+        # fallback: a zero threshold always rejects, and the plain start with p.q runs
+        Uf, lf, fb = lib.eig_learned(G, P(2, 11), net, 0, 0.0)
+        Up2, lp2 = lib.eig(G, P(2, 11))
+        assert fb
+        assert torch.equal(Uf, Up2) and torch.equal(lf, lp2)
+    # the learned start must not be worse than the Gaussian start without power iterations
+    for row in gains:
+        q0 = row[0]
+        assert q0[2] <= q0[1] * 1.05
+    assert lib.sync() & ~1 == 0
