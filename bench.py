@@ -49,6 +49,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison form")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the oracle Y row sample")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start form")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device copy first (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -160,6 +161,9 @@ def main():
         forms[args.precision]["rel_diff_sigma_vs_fp32"] = float(
             np.max(np.abs(out[7].cpu().numpy() - ref_form[7].cpu().numpy()) / ref_form[7].cpu().numpy()))
 
+    if not args.no_learned:
+        forms["learned_warm_start"] = learned_form(lib, g, params(args.precision), ws)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, n, rowptr, colidx, out, ref_form, forms)
@@ -198,6 +202,75 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
+
+
+def learned_form(lib, g, p, ws):
+    """Learned warm start of Alg. 5: train the network on eight seeded graphs
+    (n = 2^16, SBM and Chung-Lu, exponent 2.0-2.5, mean degree 8-32) against
+    their own converged eigenvectors (q = 16), then compare the Gaussian and
+    learned starts on the bench graph (held out) at q = 0, 1, 2: subspace
+    error of U_k against a q = 16 reference and eigensolver time."""
+    import torch
+    import synth
+    from paper_2110_12782_amd.binding import DeviceGraph, MLP, SketchParams
+    t0 = time.time()
+    sets = []
+    for i in range(8):
+        if i % 2 == 0:
+            rp, ci = synth.sbm([4096] * 16, 0.0035 + 0.001 * (i % 4), 0.0001, 6000 + i)
+        else:
+            rp, ci = synth.chung_lu(1 << 16, 2.0 + 0.125 * (i % 5), 8 + 8 * (i % 4), 2, 6000 + i)
+        G = DeviceGraph(rp, ci)
+        pr = SketchParams(k=p.k, s_eig=p.s_eig, q=16, d=p.d, h=p.h, l=p.l, z=p.z, seed=100 + i)
+        Uref, _ = lib.eig(G, pr)
+        sets.append((lib.ws_features(G, 0.5, seed=200 + i), Uref.contiguous()))
+    torch.cuda.synchronize()
+    t_data = time.time() - t0
+    net = MLP(lib, 256, p.k)
+    lib.ws_init(net, 11)
+    steps = 480
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    losses = lib.ws_train(net, sets, steps, 1e-3, 0.1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    losses = losses.cpu().numpy()
+    # held-out evaluation on the bench graph
+    pref = SketchParams(k=p.k, s_eig=p.s_eig, q=16, d=p.d, h=p.h, l=p.l, z=p.z, seed=999)
+    Uref, _ = lib.eig(g, pref, ws=ws)
+
+    def err(U):
+        k = U.shape[1]
+        s = torch.linalg.matrix_norm(Uref.double().T @ U.double()) ** 2
+        return float(torch.sqrt(torch.clamp(k - s, min=0.0) / k))
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t) * 1e3
+
+    rows = {}
+    for q in (0, 1, 2):
+        pq = SketchParams(k=p.k, s_eig=p.s_eig, q=q, d=p.d, h=p.h, l=p.l, z=p.z, seed=p.seed)
+        (Up, lp), tp = timed(lambda: lib.eig(g, pq, ws=ws))
+        (Uw, lw, fb), tw = timed(lambda: lib.eig_learned(g, pq, net, q, float("inf")))
+        res_p = float(lib.ritz_residual(g, 0.5, Up, lp).max())
+        res_w = float(lib.ritz_residual(g, 0.5, Uw, lw).max())
+        rows[f"q{q}"] = {"plain_sin_theta": err(Up), "learned_sin_theta": err(Uw), "plain_eig_ms": tp,
+                         "learned_eig_ms": tw, "plain_max_ritz_residual": res_p, "learned_max_ritz_residual": res_w}
+    target = rows["q2"]["plain_sin_theta"]
+    reach = [q for q in (0, 1, 2) if rows[f"q{q}"]["learned_sin_theta"] <= target]
+    saved = 2 - min(reach) if reach else 0
+    log(f"learned form: data {t_data:.1f}s, {steps} training steps in {t_train:.2f}s, loss {losses[:16].mean():.3f} -> "
+        f"{losses[-16:].mean():.3f}; " + "; ".join(
+            f"{k}: plain {v['plain_sin_theta']:.4f} ({v['plain_eig_ms']:.1f} ms) learned {v['learned_sin_theta']:.4f} "
+            f"({v['learned_eig_ms']:.1f} ms)" for k, v in rows.items()) + f"; iterations saved {saved}")
+    return {"training": {"graphs": 8, "n": 1 << 16, "steps": steps, "seconds": t_train,
+                         "loss_first16": float(losses[:16].mean()), "loss_last16": float(losses[-16:].mean())},
+            "held_out": "the bench graph (reference: q = 16)", "by_q": rows, "iterations_saved": saved}
 
 
 def sin_theta(A, B) -> float:

@@ -197,9 +197,9 @@ sketchne_status sketchne_gen_sparse_sign(sketchne_ctx* ctx, int64_t n, uint64_t 
 
 /* ---- Learned warm start of Alg. 5 ------------------------------------- */
 /* An addition to the method (Alg. 5 draws a Gaussian start block Omega):
- * a 3-layer ReLU network maps per-vertex features to the first k columns of
- * Omega; the other s_eig columns stay Gaussian, and the plain Gaussian start
- * remains the fallback.
+ * a 3-layer ReLU network maps per-vertex features to the first out <= k
+ * columns of Omega; the other columns stay Gaussian, and the plain Gaussian
+ * start remains the fallback.
  *   features   phi_i = [log max(deg_i,1), (Xg)_i, (X^2 g)_i, (X^3 g)_i, (X^4 g)_i]
  *              with X = D^-a A D^-a and g a Rademacher vector, each column
  *              standardised over the vertices to mean 0 and standard deviation
@@ -273,12 +273,12 @@ sketchne_status sketchne_ritz_residual(sketchne_ctx* ctx, const sketchne_graph* 
                                        const float* U, const double* lambda, double* res, void* ws,
                                        size_t ws_bytes);
 /* Alg. 5 from the learned start: features (probe drawn from p->seed), F into
- * the first k columns of Omega, Gaussian in the other s_eig, q_warm power
- * iterations.  If the largest Ritz residual exceeds res_threshold (or is not
- * finite) the result is discarded and sketchne_eig runs from the Gaussian
- * start with p->q iterations; *used_fallback (host) says which ran.
- * net->out must equal p->k.  Synchronizes the stream once (the residual
- * test).  Workspace: sketchne_ws_workspace_size(.., SKETCHNE_WS_OP_EIG, ..). */
+ * the first net->out columns of Omega (net->out <= p->k), Gaussian in the
+ * other k + s_eig - net->out, q_warm power iterations.  If the largest Ritz
+ * residual exceeds res_threshold (or is not finite) the result is discarded
+ * and sketchne_eig runs from the Gaussian start with p->q iterations;
+ * *used_fallback (host) says which ran.  Synchronizes the stream once (the
+ * residual test).  Workspace: sketchne_ws_workspace_size(.., SKETCHNE_WS_OP_EIG, ..). */
 sketchne_status sketchne_eig_learned(sketchne_ctx* ctx, const sketchne_graph* A, const sketchne_params* p,
                                      const sketchne_mlp* net, int32_t q_warm, double res_threshold, float* U,
                                      double* lambda, int32_t* used_fallback, void* ws, size_t ws_bytes);

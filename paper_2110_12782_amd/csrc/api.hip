@@ -805,7 +805,7 @@ sketchne_status sketchne_eig_learned(sketchne_ctx* c, const sketchne_graph* A, c
   SK_TRY(check_graph(A));
   SK_TRY(check_params(p, A->n));
   SK_TRY(check_net(net));
-  if (net->out != p->k) return SKETCHNE_E_ARG;
+  if (net->out > p->k) return SKETCHNE_E_ARG;
   const int K = p->k + p->s_eig;
   if (K > kSymeigMax || K % 4 || p->k % 4) return SKETCHNE_E_UNSUPPORTED;
   const int64_t n = A->n;
@@ -826,7 +826,7 @@ sketchne_status sketchne_eig_learned(sketchne_ctx* c, const sketchne_graph* A, c
     SK_TRY(ws_features(c, n, A->nnz, A->rowptr, A->colidx, p->alpha, nullptr, p->seed ^ 0x7f4a7c159e3779b9ULL, phi,
                        scratch, sb));
     SK_TRY(ws_forward(c, net, n, phi, omega, K, scratch, sb));
-    SK_TRY(gen_gauss(c, n, p->s_eig, K, p->seed, omega + p->k));
+    SK_TRY(gen_gauss(c, n, K - net->out, K, p->seed, omega + net->out));
   }
   sketchne_params pw = *p;
   pw.q = q_warm;

@@ -19,6 +19,8 @@
 // ranges and summed in a fixed order, so results are deterministic.
 #include "internal.h"
 
+#include <type_traits>
+
 namespace skne {
 namespace {
 
@@ -97,6 +99,93 @@ __global__ __launch_bounds__(256) void k_dense(DenseArgs<WT> a) {
     float* dst = a.C + gi * a.ldc + gj;
     if (a.accumulate) v += *dst;
     *dst = v;
+  }
+}
+
+// Wide variant for the inference shapes: W is BF16 row-major (W(k, j) =
+// W[k*ldw + j]), N <= 256 with N % 8 == 0, K % 16 == 0, lda % 4 == 0.  A
+// workgroup of 512 threads owns 128 rows and all N columns, so each row of A
+// is read from HBM once; wave w computes rows 32(w&3).. x columns
+// 128(w>>2).. (four 32 x 32 tiles).  The summation runs in chunks of 16
+// through double-buffered LDS, the next chunk prefetched into registers.
+struct WideArgs {
+  int64_t n; int K, N;
+  const float* A; int64_t lda;
+  const uint16_t* W; int64_t ldw;
+  const uint16_t* bias;
+  float* C; int64_t ldc;
+  int relu;
+};
+
+constexpr int WKC = 16;
+
+__global__ __launch_bounds__(512) void k_dense_wide(WideArgs a) {
+  __shared__ float As[2][128][WKC + 1];
+  __shared__ float Bs[2][WKC][256 + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rt = wave & 3, cg = wave >> 2;
+  const int64_t row0 = (int64_t)blockIdx.x * 128;
+  // loader roles: A -- one float4 per thread (128 rows x 4 float4);
+  //               W -- one 8 x BF16 vector per thread (16 rows x 32 vectors)
+  const int ar = tid >> 2, ac = (tid & 3) * 4;
+  const int64_t agi = row0 + ar;
+  const int wk = tid >> 5, wj = (tid & 31) * 8;
+  const bool a_ok = agi < a.n;
+  const bool w_ok = wj < a.N;
+  floatx16 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+  float4 ra = make_float4(0.f, 0.f, 0.f, 0.f);
+  uint4 rw = make_uint4(0u, 0u, 0u, 0u);
+  auto fetch = [&](int k0) {
+    ra = a_ok ? *reinterpret_cast<const float4*>(a.A + agi * a.lda + k0 + ac) : make_float4(0.f, 0.f, 0.f, 0.f);
+    rw = w_ok ? *reinterpret_cast<const uint4*>(a.W + (int64_t)(k0 + wk) * a.ldw + wj) : make_uint4(0u, 0u, 0u, 0u);
+  };
+  auto stash = [&](int buf) {
+    As[buf][ar][ac + 0] = ra.x;
+    As[buf][ar][ac + 1] = ra.y;
+    As[buf][ar][ac + 2] = ra.z;
+    As[buf][ar][ac + 3] = ra.w;
+    const uint32_t wv[4] = {rw.x, rw.y, rw.z, rw.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Bs[buf][wk][wj + 2 * q] = __uint_as_float(wv[q] << 16);
+      Bs[buf][wk][wj + 2 * q + 1] = __uint_as_float(wv[q] & 0xffff0000u);
+    }
+  };
+  const int nchunk = a.K / WKC;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nchunk) fetch((ch + 1) * WKC);
+#pragma unroll
+    for (int kk = 0; kk < WKC; kk += 2) {
+      const float av = As[buf][rt * 32 + (lane & 31)][kk + (lane >> 5)];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float bv = Bs[buf][kk + (lane >> 5)][cg * 128 + t * 32 + (lane & 31)];
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[t], 0, 0, 0);
+      }
+    }
+    if (ch + 1 < nchunk) stash(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int gj = cg * 128 + t * 32 + (lane & 31);
+    if (gj >= a.N) continue;
+    const float bj = a.bias ? bf16_val(a.bias[gj]) : 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t gi = row0 + rt * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      if (gi >= a.n) continue;
+      float v = acc[t][r] + bj;
+      if (a.relu) v = fmaxf(v, 0.f);
+      a.C[gi * a.ldc + gj] = v;
+    }
   }
 }
 
@@ -271,25 +360,54 @@ __global__ void k_feat_take(int64_t n, int col, const float* __restrict__ T, flo
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) raw[i * FEAT + col] = T[i * 4];
 }
-// one workgroup per raw column: mean, then centred and plain second moments
-// (FP64, fixed order); stat[2j] = mean, stat[2j+1] = 1/std or 0 (no spread)
-__global__ __launch_bounds__(1024) void k_feat_stats(int64_t n, const float* __restrict__ raw,
-                                                     double* __restrict__ stat) {
-  __shared__ double red[17];
-  const int j = blockIdx.x;
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += raw[i * FEAT + j];
-  const double mean = block_sum(s, red) / (double)n;
-  double c2 = 0.0, p2 = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-    double x = raw[i * FEAT + j];
-    c2 += (x - mean) * (x - mean);
-    p2 += x * x;
+// Column moments of the raw features in two passes over fixed row ranges
+// (FP64, fixed order): pass 0 sums x, pass 1 sums (x - mean)^2 and x^2.
+// part[(b * 5 + j) * 2 + {0, 1}] for block b.
+constexpr int FS_BLOCKS = 256;
+__global__ __launch_bounds__(256) void k_feat_moments(int64_t n, int pass, const float* __restrict__ raw,
+                                                      const double* __restrict__ stat, double* __restrict__ part) {
+  __shared__ double red[2][SKETCHNE_WS_RAW][256];
+  const int64_t per = (n + FS_BLOCKS - 1) / FS_BLOCKS;
+  const int64_t rb = (int64_t)blockIdx.x * per, re = min(n, rb + per);
+  double a[SKETCHNE_WS_RAW], b[SKETCHNE_WS_RAW];
+  for (int j = 0; j < SKETCHNE_WS_RAW; ++j) a[j] = b[j] = 0.0;
+  for (int64_t i = rb + threadIdx.x; i < re; i += 256) {
+    for (int j = 0; j < SKETCHNE_WS_RAW; ++j) {
+      double x = raw[i * FEAT + j];
+      if (pass == 0) {
+        a[j] += x;
+      } else {
+        double d = x - stat[2 * j];
+        a[j] += d * d;
+        b[j] += x * x;
+      }
+    }
   }
-  const double sd = sqrt(block_sum(c2, red) / (double)n);
-  const double rms = sqrt(block_sum(p2, red) / (double)n);
-  if (threadIdx.x == 0) {
-    stat[2 * j] = mean;
+  for (int j = 0; j < SKETCHNE_WS_RAW; ++j) {
+    red[0][j][threadIdx.x] = a[j];
+    red[1][j][threadIdx.x] = b[j];
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * SKETCHNE_WS_RAW) {
+    const int which = threadIdx.x / SKETCHNE_WS_RAW, j = threadIdx.x % SKETCHNE_WS_RAW;
+    double s = 0.0;
+    for (int t = 0; t < 256; ++t) s += red[which][j][t];
+    part[((int64_t)blockIdx.x * SKETCHNE_WS_RAW + j) * 2 + which] = s;
+  }
+}
+// stat[2j] = mean, stat[2j+1] = 1/std, or 0 when the column has no spread
+__global__ void k_feat_finish(int64_t n, int pass, const double* __restrict__ part, double* __restrict__ stat) {
+  const int j = threadIdx.x;
+  if (j >= SKETCHNE_WS_RAW) return;
+  double s0 = 0.0, s1 = 0.0;
+  for (int b = 0; b < FS_BLOCKS; ++b) {
+    s0 += part[((int64_t)b * SKETCHNE_WS_RAW + j) * 2 + 0];
+    s1 += part[((int64_t)b * SKETCHNE_WS_RAW + j) * 2 + 1];
+  }
+  if (pass == 0) {
+    stat[2 * j] = s0 / (double)n;
+  } else {
+    const double sd = sqrt(s0 / (double)n), rms = sqrt(s1 / (double)n);
     stat[2 * j + 1] = sd > 1e-6 * rms ? 1.0 / sd : 0.0;
   }
 }
@@ -304,19 +422,26 @@ __global__ void k_feat_apply(int64_t n, int nraw, const double* __restrict__ sta
 
 // ---------------------------------------------------------------- Ritz residuals
 // part[p][j] = sum_{r in range p} (XU(r,j) - lambda_j U(r,j))^2   (FP64)
-__global__ void k_resid_part(int64_t n, int k, int64_t rows_per_part, const float* __restrict__ XU,
-                             const float* __restrict__ U, const double* __restrict__ lambda,
-                             double* __restrict__ part) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= k) return;
-  int64_t rb = (int64_t)blockIdx.y * rows_per_part, re = min(n, rb + rows_per_part);
-  const double lj = lambda[j];
+// Block (x, y): columns 64x .. 64x+63, rows of part y; the 256 threads split
+// the part's rows four ways and combine in LDS in a fixed order.
+__global__ __launch_bounds__(256) void k_resid_part(int64_t n, int k, int64_t rows_per_part,
+                                                    const float* __restrict__ XU, const float* __restrict__ U,
+                                                    const double* __restrict__ lambda, double* __restrict__ part) {
+  __shared__ double red[4][64];
+  const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + c;
+  const int64_t rb = (int64_t)blockIdx.y * rows_per_part, re = min(n, rb + rows_per_part);
   double s = 0.0;
-  for (int64_t r = rb; r < re; ++r) {
-    double d = (double)XU[r * k + j] - lj * (double)U[r * k + j];
-    s += d * d;
+  if (j < k) {
+    const double lj = lambda[j];
+    for (int64_t r = rb + q; r < re; r += 4) {
+      double d = (double)XU[r * k + j] - lj * (double)U[r * k + j];
+      s += d * d;
+    }
   }
-  part[(int64_t)blockIdx.y * k + j] = s;
+  red[q][c] = s;
+  __syncthreads();
+  if (q == 0 && j < k) part[(int64_t)blockIdx.y * k + j] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
 }
 __global__ void k_resid_final(int k, int parts, const double* __restrict__ part, double* __restrict__ res) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -348,6 +473,11 @@ Off offsets(int w, int o) {
   return f;
 }
 
+int64_t resid_parts(int64_t n) {
+  int64_t parts = (n + 511) / 512;
+  return parts < 1 ? 1 : (parts > 1024 ? 1024 : parts);
+}
+
 int64_t parts_for(int64_t n) {
   int64_t parts = (n + 2047) / 2048;
   return parts < 1 ? 1 : (parts > 128 ? 128 : parts);
@@ -358,6 +488,15 @@ sketchne_status dense(sketchne_ctx* c, int64_t n, int K, int N, const float* A, 
                       int64_t wsj, const WT* bias, const float* mask, int64_t ldm, float* C, int64_t ldc, bool relu,
                       bool accumulate) {
   if (n == 0) return SKETCHNE_OK;
+  if constexpr (std::is_same<WT, uint16_t>::value) {
+    // the wide kernel covers the forward shapes (row-major BF16 weights, no mask)
+    if (!mask && !accumulate && wsj == 1 && N <= 256 && N % 8 == 0 && K % WKC == 0 && lda % 4 == 0 && wsk % 8 == 0 &&
+        reinterpret_cast<uintptr_t>(A) % 16 == 0 && reinterpret_cast<uintptr_t>(W) % 16 == 0) {
+      WideArgs w{n, K, N, A, lda, W, wsk, bias, C, ldc, relu ? 1 : 0};
+      hipLaunchKernelGGL(k_dense_wide, dim3((unsigned)((n + 127) / 128)), dim3(512), 0, c->stream, w);
+      return launch_status();
+    }
+  }
   DenseArgs<WT> a{n, K, N, A, lda, W, wsk, wsj, bias, mask, ldm, C, ldc, relu ? 1 : 0, accumulate ? 1 : 0};
   dim3 grid((unsigned)((n + 63) / 64), (unsigned)((N + 63) / 64));
   if (K <= 8)
@@ -415,12 +554,13 @@ size_t ws_grad_bytes(int64_t n, int width, int out) {
 
 size_t ws_features_bytes(int64_t n, int64_t nnz) {
   return 2 * align_up(sizeof(float) * (size_t)n * 4) + align_up(sizeof(float) * (size_t)n) +
-         align_up(sizeof(double) * 2 * FEAT) + align_up(sizeof(float) * (size_t)n) + spmm_ws_bytes(nnz, 4);
+         align_up(sizeof(double) * 2 * FEAT) + align_up(sizeof(double) * FS_BLOCKS * SKETCHNE_WS_RAW * 2) +
+         align_up(sizeof(float) * (size_t)n) + spmm_ws_bytes(nnz, 4);
 }
 
 size_t ritz_residual_bytes(int64_t n, int64_t nnz, int k) {
   return align_up(sizeof(float) * (size_t)n * k) + align_up(sizeof(float) * (size_t)n) +
-         align_up(sizeof(double) * (size_t)parts_for(n) * k) + spmm_ws_bytes(nnz, k);
+         align_up(sizeof(double) * (size_t)resid_parts(n) * k) + spmm_ws_bytes(nnz, k);
 }
 
 sketchne_status ws_init(sketchne_ctx* c, const sketchne_mlp* net, uint64_t seed) {
@@ -458,6 +598,7 @@ sketchne_status ws_features(sketchne_ctx* c, int64_t n, int64_t nnz, const int64
   float* T1 = ar.take<float>((size_t)n * 4);
   float* gdraw = ar.take<float>((size_t)n);
   double* stat = ar.take<double>(2 * FEAT);
+  double* mom = ar.take<double>((size_t)FS_BLOCKS * SKETCHNE_WS_RAW * 2);
   float* dscale = ar.take<float>((size_t)n);
   float* part = ar.take<float>(spmm_ws_bytes(nnz, 4) / sizeof(float));
   if (ar.overflow) return SKETCHNE_E_WORKSPACE;
@@ -478,7 +619,10 @@ sketchne_status ws_features(sketchne_ctx* c, int64_t n, int64_t nnz, const int64
     src = dst;
     dst = tmp;
   }
-  hipLaunchKernelGGL(k_feat_stats, dim3(SKETCHNE_WS_RAW), dim3(1024), 0, c->stream, n, phi, stat);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_feat_moments, dim3(FS_BLOCKS), dim3(256), 0, c->stream, n, pass, phi, stat, mom);
+    hipLaunchKernelGGL(k_feat_finish, dim3(1), dim3(64), 0, c->stream, n, pass, mom, stat);
+  }
   hipLaunchKernelGGL(k_feat_apply, dim3(nblk(n * FEAT)), dim3(256), 0, c->stream, n, (int)SKETCHNE_WS_RAW, stat,
                      phi);
   return launch_status();
@@ -559,17 +703,17 @@ sketchne_status ritz_residual(sketchne_ctx* c, int64_t n, int64_t nnz, const int
   Arena ar(ws, ws_bytes);
   float* XU = ar.take<float>((size_t)n * k);
   float* dscale = ar.take<float>((size_t)n);
-  double* part = ar.take<double>((size_t)parts_for(n) * k);
+  double* part = ar.take<double>((size_t)resid_parts(n) * k);
   float* sp = ar.take<float>(spmm_ws_bytes(nnz, k) / sizeof(float));
   if (ar.overflow) return SKETCHNE_E_WORKSPACE;
   SK_TRY(degree_scale(c, n, rowptr, alpha, dscale));
   SK_TRY(spmm(c, n, nnz, rowptr, colidx, dscale, U, k, k, XU, k, sp));
   ProfScope ps(c, SKETCHNE_PROF_PREP);
-  int64_t parts = parts_for(n);
+  int64_t parts = resid_parts(n);
   int64_t rpp = (n + parts - 1) / parts;
   parts = (n + rpp - 1) / rpp;
-  hipLaunchKernelGGL(k_resid_part, dim3(nblk(k), (unsigned)parts), dim3(256), 0, c->stream, n, k, rpp, XU, U, lambda,
-                     part);
+  hipLaunchKernelGGL(k_resid_part, dim3((unsigned)((k + 63) / 64), (unsigned)parts), dim3(256), 0, c->stream, n, k,
+                     rpp, XU, U, lambda, part);
   hipLaunchKernelGGL(k_resid_final, dim3(nblk(k)), dim3(256), 0, c->stream, k, (int)parts, part, res);
   return launch_status();
 }
