@@ -90,6 +90,22 @@ OrthWs carve_orth(Arena& ar, int64_t n, int m, bool transposed) {
   return w;
 }
 
+// dst = src R^-1 (R^-1 upper triangular, given as RinvT = R^-T row-major):
+// the tall FP64 apply when it takes the shape, the general GEMM otherwise.
+sketchne_status apply_rinv(sketchne_ctx* c, int64_t n, int m, const float* src, int64_t ld, bool transposed,
+                           const double* RinvT, float* dst, const OrthWs& w, const int* run_if) {
+  ApplyDesc d;
+  d.n = n; d.K = m; d.N = m;
+  d.A = src; d.lda = ld; d.acol = transposed;
+  d.B = RinvT; d.ldb = m; d.bcol = true; d.upper = true;
+  d.C = dst; d.ldc = ld; d.ccol = transposed;
+  d.run_if = run_if;
+  if (apply_tall_supported(d)) return apply_tall(c, d);
+  GemmDesc a = apply_desc(n, m, src, ld, transposed, RinvT, dst);
+  a.run_if = run_if;
+  return gemm64(c, a, w.partial, w.partial_cap);
+}
+
 // One Cholesky-QR pass src -> dst.  need_more: set by the Cholesky when a
 // second pass is needed; run_if: the pass runs only when it points to 1.
 sketchne_status orth_pass(sketchne_ctx* c, int64_t n, int m, const float* src, float* dst, int64_t ld,
@@ -97,9 +113,7 @@ sketchne_status orth_pass(sketchne_ctx* c, int64_t n, int m, const float* src, f
   if (!transposed) SK_TRY(gram_tall(c, n, m, src, ld, 1, nullptr, 0, 0, nullptr, w.G, w.partial, w.partial_cap, run_if));
   else SK_TRY(gram_tall(c, n, m, src, 1, ld, nullptr, 0, 0, nullptr, w.G, w.partial, w.partial_cap, run_if));
   SK_TRY(chol_inv(c, m, w.G, w.RinvT, w.cwork, need_more, run_if));
-  GemmDesc a = apply_desc(n, m, src, ld, transposed, w.RinvT, dst);
-  a.run_if = run_if;
-  return gemm64(c, a, w.partial, w.partial_cap);
+  return apply_rinv(c, n, m, src, ld, transposed, w.RinvT, dst, w, run_if);
 }
 
 // Cholesky-QR with FP64 Gram and Cholesky: src -> dst, and a second pass
@@ -443,7 +457,14 @@ sketchne_status sketchne_eig(sketchne_ctx* c, const sketchne_graph* A, const ske
   // line 10: eigendecomposition, sorted by |lambda|
   SK_TRY(symeig(c, K, w.H, w.Vh, w.wv, w.symws));
   // line 11: U = Q U^(:, 1:k)
-  {
+  ApplyDesc ad;
+  ad.n = n; ad.K = K; ad.N = p->k;
+  ad.A = w.Q; ad.lda = K;
+  ad.B = w.Vh; ad.ldb = K;
+  ad.C = U; ad.ldc = p->k;
+  if (apply_tall_supported(ad)) {
+    SK_TRY(apply_tall(c, ad));
+  } else {
     GemmDesc g;
     g.M = n; g.N = p->k; g.K = K;
     g.A = w.Q; g.ta = Ty::F32; g.sai = K; g.sak = 1;
@@ -568,9 +589,7 @@ sketchne_status sketchne_embed(sketchne_ctx* c, const sketchne_params* p, int64_
   hipLaunchKernelGGL(k_transpose, dim3((h * h + 255) / 256), dim3(256), 0, c->stream, h, ow.RinvT, w.Rci);
   SK_TRY(launch_status());
   {  // second pass (device-side condition): Q1 = Y R1^-1, R2 from Q1^T Q1, Rc^-1 = R1^-1 R2^-1
-    GemmDesc a = apply_desc(n, h, Yt, n, true, ow.RinvT, w.Q1);
-    a.run_if = ow.need2;
-    SK_TRY(gemm64(c, a, ow.partial, ow.partial_cap));
+    SK_TRY(apply_rinv(c, n, h, Yt, n, true, ow.RinvT, w.Q1, ow, ow.need2));
     SK_TRY(gram_tall(c, n, h, w.Q1, 1, n, nullptr, 0, 0, nullptr, ow.G, ow.partial, ow.partial_cap, ow.need2));
     SK_TRY(chol_inv(c, h, ow.G, w.RT2, ow.cwork, nullptr, ow.need2));
     SK_TRY(small(h, h, h, ow.RinvT, Ty::F64, 1, h, w.RT2, Ty::F64, 1, h, w.Rci, false, ow.need2));
@@ -601,15 +620,18 @@ sketchne_status sketchne_embed(sketchne_ctx* c, const sketchne_params* p, int64_
   SK_TRY(launch_status());
   // Alg. 4 line 10 and Alg. 6 line 5: E = Q U^(:, 1:d) Sigma^(1/2) = Y (Rc^-1 U^ Sigma^(1/2))
   SK_TRY(small(h, d, h, w.Rci, Ty::F64, h, 1, w.Map, Ty::F64, d, 1, w.Map2, false, nullptr));
-  {
-    GemmDesc gd;
-    gd.M = n; gd.N = d; gd.K = h;
-    gd.A = Yt; gd.ta = Ty::F32; gd.sai = 1; gd.sak = n;
-    gd.B = w.Map2; gd.tb = Ty::F64; gd.sbk = d; gd.sbj = 1;
-    gd.C = E; gd.tc = Ty::F32; gd.sci = d; gd.scj = 1;
-    SK_TRY(gemm64(c, gd, w.s_partial, w.s_cap));
-  }
-  return SKETCHNE_OK;
+  ApplyDesc ad;
+  ad.n = n; ad.K = h; ad.N = d;
+  ad.A = Yt; ad.lda = n; ad.acol = true;
+  ad.B = w.Map2; ad.ldb = d;
+  ad.C = E; ad.ldc = d;
+  if (apply_tall_supported(ad)) return apply_tall(c, ad);
+  GemmDesc gd;
+  gd.M = n; gd.N = d; gd.K = h;
+  gd.A = Yt; gd.ta = Ty::F32; gd.sai = 1; gd.sak = n;
+  gd.B = w.Map2; gd.tb = Ty::F64; gd.sbk = d; gd.sbj = 1;
+  gd.C = E; gd.tc = Ty::F32; gd.sci = d; gd.scj = 1;
+  return gemm64(c, gd, w.s_partial, w.s_cap);
 }
 
 sketchne_status sketchne_sync(sketchne_ctx* c, uint32_t* flags) {

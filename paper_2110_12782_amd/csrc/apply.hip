@@ -1,0 +1,219 @@
+// Tall-skinny apply on the FP64 matrix cores:  C = A B  with A an n x K FP32
+// block (n large) and B a small K x N FP64 matrix (N, K <= 288).
+//
+// This is the shape of every apply of the path: Q = B R^-1 in Cholesky-QR
+// (R^-1 upper triangular), U = Q U^(:, 1:k) after Rayleigh-Ritz, and
+// E = Y (R^-1 U^ Sigma^1/2) in the embedding.  A workgroup owns 128 rows and
+// every output column, so each row of A is read from HBM once and written
+// once; B streams from L2 in chunks of 16 summation indices through double
+// buffered LDS (next chunk prefetched into registers during the MFMAs).  With
+// a triangular B, chunk c only meets column blocks >= c, which halves the
+// work of the Cholesky-QR apply; entries below the diagonal are masked on
+// load, whatever the buffer holds there.
+//
+// 8 wavefronts: wave w owns rows 32 (w & 3) .. +32 (two 16-row MFMA blocks)
+// and column blocks (w >> 2) * NBH .. +NBH (16 columns each), i.e. 2 x NBH
+// v_mfma_f64_16x16x4f64 accumulators.
+#include "internal.h"
+
+namespace skne {
+namespace {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int AR = 128;   // rows per workgroup
+constexpr int ABK = 16;   // summation chunk
+
+struct ApplyArgs {
+  int64_t n; int K, N;
+  const float* A; int64_t lda;
+  const double* B; int64_t ldb;
+  float* C; int64_t ldc;
+  const int* run_if;
+};
+
+// ACOL: A(i,k) = A[k*lda + i] (else A[i*lda + k]); BCOL: B(k,j) = B[j*ldb + k]
+// (else B[k*ldb + j]); CCOL: C(i,j) = C[j*ldc + i] (else C[i*ldc + j]);
+// TRI: B(k,j) = 0 for k > j.
+template <int NBH, bool ACOL, bool BCOL, bool CCOL, bool TRI>
+__global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
+  constexpr int NC = 32 * NBH;                        // columns held by the workgroup
+  constexpr int BVEC = ABK * NC / 2;                  // double2 per B chunk
+  constexpr int BPER = (BVEC + 511) / 512;
+  __shared__ double As[2][ABK][AR + 2];
+  __shared__ double Bs[2][ABK][NC + 2];
+  if (g.run_if && *g.run_if == 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rg = wave & 3, ch = wave >> 2;
+  const int64_t i0 = (int64_t)blockIdx.x * AR;
+  const int kend = TRI ? min(g.K, g.N) : g.K;
+
+  float4 ra;
+  double2 rb[BPER];
+  auto fetch = [&](int k0) {
+    if (!ACOL) {
+      const int r = tid >> 2, q = (tid & 3) * 4;
+      const int64_t i = i0 + r;
+      const int k = k0 + q;
+      ra = (i < g.n && k < kend) ? *reinterpret_cast<const float4*>(g.A + i * g.lda + k)
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      const int kk = tid >> 5, q = (tid & 31) * 4;
+      const int k = k0 + kk;
+      const int64_t i = i0 + q;
+      if (k < kend && i + 3 < g.n) {
+        ra = *reinterpret_cast<const float4*>(g.A + (int64_t)k * g.lda + i);
+      } else {
+        const float* p = g.A + (int64_t)k * g.lda + i;
+        ra.x = (k < kend && i + 0 < g.n) ? p[0] : 0.f;
+        ra.y = (k < kend && i + 1 < g.n) ? p[1] : 0.f;
+        ra.z = (k < kend && i + 2 < g.n) ? p[2] : 0.f;
+        ra.w = (k < kend && i + 3 < g.n) ? p[3] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < BPER; ++p) {
+      const int e = tid + 512 * p;
+      double2 v = make_double2(0.0, 0.0);
+      if (e < BVEC) {
+        int j, k;
+        if (BCOL) { j = e >> 3; k = k0 + (e & 7) * 2; }
+        else { k = k0 + e / (NC / 2); j = (e % (NC / 2)) * 2; }
+        if (j < g.N && k < kend) {
+          v = BCOL ? *reinterpret_cast<const double2*>(g.B + (int64_t)j * g.ldb + k)
+                   : *reinterpret_cast<const double2*>(g.B + (int64_t)k * g.ldb + j);
+          if (TRI) {
+            // BCOL: (k, j) and (k+1, j); else (k, j) and (k, j+1)
+            if (BCOL) { if (k > j) v.x = 0.0; if (k + 1 > j) v.y = 0.0; }
+            else { if (k > j) v.x = 0.0; if (k > j + 1) v.y = 0.0; }
+          }
+        }
+      }
+      rb[p] = v;
+    }
+  };
+  auto stash = [&](int buf) {
+    if (!ACOL) {
+      const int r = tid >> 2, q = (tid & 3) * 4;
+      As[buf][q + 0][r] = ra.x;
+      As[buf][q + 1][r] = ra.y;
+      As[buf][q + 2][r] = ra.z;
+      As[buf][q + 3][r] = ra.w;
+    } else {
+      const int kk = tid >> 5, q = (tid & 31) * 4;
+      As[buf][kk][q + 0] = ra.x;
+      As[buf][kk][q + 1] = ra.y;
+      As[buf][kk][q + 2] = ra.z;
+      As[buf][kk][q + 3] = ra.w;
+    }
+#pragma unroll
+    for (int p = 0; p < BPER; ++p) {
+      const int e = tid + 512 * p;
+      if (e < BVEC) {
+        if (BCOL) {
+          const int j = e >> 3, kk = (e & 7) * 2;
+          Bs[buf][kk][j] = rb[p].x;
+          Bs[buf][kk + 1][j] = rb[p].y;
+        } else {
+          const int kk = e / (NC / 2), j = (e % (NC / 2)) * 2;
+          Bs[buf][kk][j] = rb[p].x;
+          Bs[buf][kk][j + 1] = rb[p].y;
+        }
+      }
+    }
+  };
+
+  doublex4 acc[2][NBH];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int t = 0; t < NBH; ++t) acc[m][t] = doublex4{0.0, 0.0, 0.0, 0.0};
+
+  const int nchunk = (kend + ABK - 1) / ABK;
+  if (nchunk > 0) {
+    fetch(0);
+    stash(0);
+  }
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    const int buf = c & 1;
+    const bool more = c + 1 < nchunk;
+    if (more) fetch((c + 1) * ABK);
+#pragma unroll
+    for (int kk = 0; kk < ABK / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      const double a0 = As[buf][kr][32 * rg + (lane & 15)];
+      const double a1 = As[buf][kr][32 * rg + 16 + (lane & 15)];
+#pragma unroll
+      for (int t = 0; t < NBH; ++t) {
+        const int jb = ch * NBH + t;
+        if (TRI && jb < c) continue;  // B(k, j) = 0 for the whole block
+        const double b = Bs[buf][kr][16 * jb + (lane & 15)];
+        acc[0][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][t], 0, 0, 0);
+        acc[1][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][t], 0, 0, 0);
+      }
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+  }
+
+  // v_mfma_f64_16x16x4f64 output: lane l, register r -> row (l / 16) + 4 r, column l % 16
+#pragma unroll
+  for (int t = 0; t < NBH; ++t) {
+    const int j = 16 * (ch * NBH + t) + (lane & 15);
+    if (j >= g.N) continue;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + 32 * rg + 16 * m + (lane >> 4) + 4 * r;
+        if (i >= g.n) continue;
+        const float v = (float)acc[m][t][r];
+        if (CCOL) g.C[(int64_t)j * g.ldc + i] = v;
+        else g.C[i * g.ldc + j] = v;
+      }
+  }
+}
+
+}  // namespace
+
+bool apply_tall_supported(const ApplyDesc& d) {
+  if (d.N < 1 || d.N > 288 || d.K < 1 || d.K > 288) return false;
+  if (d.N % 2 || d.K % 4 || d.lda % 4 || d.ldb % 2) return false;
+  if (d.ccol && !d.acol) return false;
+  if (d.upper && (!d.bcol || d.N != d.K)) return false;
+  if (reinterpret_cast<uintptr_t>(d.A) % 16 || reinterpret_cast<uintptr_t>(d.B) % 16) return false;
+  return true;
+}
+
+sketchne_status apply_tall(sketchne_ctx* c, const ApplyDesc& d) {
+  if (d.n == 0) return SKETCHNE_OK;
+  if (!apply_tall_supported(d)) return SKETCHNE_E_UNSUPPORTED;
+  ProfScope ps(c, SKETCHNE_PROF_GEMM64);
+  ApplyArgs g{d.n, d.K, d.N, d.A, d.lda, d.B, d.ldb, d.C, d.ldc, d.run_if};
+  dim3 grid((unsigned)((d.n + AR - 1) / AR)), blk(512);
+  const int nbh = d.N <= 128 ? 4 : (d.N <= 256 ? 8 : 9);
+#define SKNE_APPLY(NBH)                                                                                       \
+  do {                                                                                                        \
+    if (d.upper) {                                                                                            \
+      if (d.ccol) hipLaunchKernelGGL((k_apply_tall<NBH, true, true, true, true>), grid, blk, 0, c->stream, g); \
+      else if (d.acol) hipLaunchKernelGGL((k_apply_tall<NBH, true, true, false, true>), grid, blk, 0, c->stream, g); \
+      else hipLaunchKernelGGL((k_apply_tall<NBH, false, true, false, true>), grid, blk, 0, c->stream, g);      \
+    } else if (d.bcol) {                                                                                      \
+      if (d.ccol) hipLaunchKernelGGL((k_apply_tall<NBH, true, true, true, false>), grid, blk, 0, c->stream, g); \
+      else if (d.acol) hipLaunchKernelGGL((k_apply_tall<NBH, true, true, false, false>), grid, blk, 0, c->stream, g); \
+      else hipLaunchKernelGGL((k_apply_tall<NBH, false, true, false, false>), grid, blk, 0, c->stream, g);     \
+    } else {                                                                                                  \
+      if (d.ccol) hipLaunchKernelGGL((k_apply_tall<NBH, true, false, true, false>), grid, blk, 0, c->stream, g); \
+      else if (d.acol) hipLaunchKernelGGL((k_apply_tall<NBH, true, false, false, false>), grid, blk, 0, c->stream, g); \
+      else hipLaunchKernelGGL((k_apply_tall<NBH, false, false, false, false>), grid, blk, 0, c->stream, g);    \
+    }                                                                                                         \
+  } while (0)
+  if (nbh == 4) SKNE_APPLY(4);
+  else if (nbh == 8) SKNE_APPLY(8);
+  else SKNE_APPLY(9);
+#undef SKNE_APPLY
+  return launch_status();
+}
+
+}  // namespace skne

@@ -114,6 +114,22 @@ int gemm64_pick_splits(const GemmDesc& g);
 size_t gemm64_partial_bytes(int64_t M, int64_t N, int64_t K, bool upper);
 sketchne_status gemm64(sketchne_ctx* c, const GemmDesc& g, double* partial, size_t partial_cap);
 
+// apply.hip : C = A B, A tall FP32 (n x K), B small FP64 (K x N), C FP32;
+// N, K <= 288.  acol: A(i,k) = A[k*lda + i] (else A[i*lda + k]); bcol:
+// B(k,j) = B[j*ldb + k] (else B[k*ldb + j]); ccol: C(i,j) = C[j*ldc + i];
+// upper: B is upper triangular (needs bcol).  apply_tall_supported() says
+// whether the fast kernel takes the shape.
+struct ApplyDesc {
+  int64_t n = 0; int K = 0, N = 0;
+  const float* A = nullptr; int64_t lda = 0; bool acol = false;
+  const double* B = nullptr; int64_t ldb = 0; bool bcol = false;
+  bool upper = false;
+  float* C = nullptr; int64_t ldc = 0; bool ccol = false;
+  const int* run_if = nullptr;
+};
+bool apply_tall_supported(const ApplyDesc& d);
+sketchne_status apply_tall(sketchne_ctx* c, const ApplyDesc& d);
+
 // gram.hip : G = X^T diag(w) Y (symmetric products), X, Y tall FP32
 int gram_nwg(int64_t n);
 size_t gram_ws_bytes(int64_t n, int m);
