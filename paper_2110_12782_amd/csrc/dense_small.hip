@@ -8,7 +8,7 @@
 // a small diagonal shift (shifted Cholesky-QR) and raises a flag; a second
 // failure raises CHOL_FAIL.
 //
-// Eigensolver: one-sided block Jacobi (see the comment above k_oj_step).
+// Eigensolver: one-sided block Jacobi (see the comment above k_oj_cross).
 #include "internal.h"
 
 namespace skne {
@@ -165,20 +165,26 @@ __global__ void k_copy_if(int64_t count, const float* __restrict__ src, float* _
 
 // ---------------------------------------------------------------- Jacobi
 //
-// One-sided (Hestenes) block Jacobi on B = A + sigma I, sigma = ||A||_F, so B
-// is positive semidefinite and eigenvalues +-lambda of A (equal singular
-// values) cannot mix.  Columns are grouped in blocks of NBJ = 16.  A sweep is
-// one "intra" launch (the pairs inside each block) and nb - 1 "cross"
-// launches that pair the blocks by the round-robin (circle) schedule: one
-// workgroup per block pair holds its 32 columns of G = B V and of V in LDS and
-// orthogonalises all 16 x 16 cross pairs in 16 rounds.  Each column pair is
-// handled by a group of 16 lanes (rows strided by 16, reductions by DPP), so
-// a round is a short dependency chain.  A per-sweep rotation counter ends the
-// iteration; later launches return at once.  At convergence the columns of G
-// are (lambda_j + sigma) v_j, so lambda_j = v_j^T g_j - sigma.
-
+// One-sided (Hestenes) block Jacobi on B = A + c I with c = 1.5 ||A||_F, so
+// the eigenvalues of B lie in [0.5, 2.5] ||A||_F: B is positive definite with
+// condition number at most 5, eigenvalues +-lambda of A cannot mix, and at
+// convergence the columns of G = B V are (lambda_j + c) v_j.  The
+// eigenvectors are therefore the normalised columns of G (accurate to a few
+// units of rounding because B is well conditioned) and lambda_j =
+// ||g_j|| - c; V itself is never formed.
+//
+// Columns are grouped in blocks of NBJ = 16.  A sweep is one "intra" launch
+// (the pairs inside each block) and nb - 1 "cross" launches that pair the
+// blocks by the round-robin (circle) schedule.  In a cross launch one
+// workgroup takes a block pair (P, Q); group g of 16 lanes keeps column g of P
+// in registers for all 16 rounds and meets column (g + round) mod 16 of Q,
+// which is the only data that moves (through LDS).  Rows are strided by 16
+// over the lanes of a group and the three inner products are reduced by DPP.
+// A per-sweep rotation counter ends the iteration; later launches return at
+// once.
 constexpr int NBJ = 16;           // columns per block
 constexpr int OJ_MAXR = 18;       // rows per lane: m <= 16 * OJ_MAXR = 288
+constexpr double OJ_SHIFT = 1.5;  // c = OJ_SHIFT * ||A||_F
 
 __device__ __forceinline__ void pair_of(int s, int pi, int mp, int& p, int& q) {
   const int ring = mp - 1;
@@ -213,8 +219,8 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
-// sigma = ||A||_F over the symmetric matrix given by its upper triangle
-__global__ __launch_bounds__(1024) void k_oj_norm(int m, const double* __restrict__ A, double* __restrict__ sigma) {
+// c = OJ_SHIFT * ||A||_F over the symmetric matrix given by its upper triangle
+__global__ __launch_bounds__(1024) void k_oj_norm(int m, const double* __restrict__ A, double* __restrict__ shift) {
   __shared__ double part[16];
   double s = 0.0;
   for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
@@ -228,14 +234,13 @@ __global__ __launch_bounds__(1024) void k_oj_norm(int m, const double* __restric
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
-    *sigma = sqrt(t);
+    *shift = OJ_SHIFT * sqrt(t);
   }
 }
 
-// G (column-major, mp columns of m rows) = A + sigma I, V = I, counters = 0
-__global__ void k_oj_init(int m, int mp, const double* __restrict__ A, const double* __restrict__ sigma,
-                          double* __restrict__ G, double* __restrict__ V, int* __restrict__ counters,
-                          int max_sweeps) {
+// G (column-major, mp columns of m rows) = A + c I (zero padding columns), counters = 0
+__global__ void k_oj_init(int m, int mp, const double* __restrict__ A, const double* __restrict__ shift,
+                          double* __restrict__ G, int* __restrict__ counters, int max_sweeps) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < max_sweeps) counters[idx] = 0;
   if (idx >= mp * m) return;
@@ -243,16 +248,26 @@ __global__ void k_oj_init(int m, int mp, const double* __restrict__ A, const dou
   double g = 0.0;
   if (c < m) {
     g = r <= c ? A[r * m + c] : A[c * m + r];
-    if (r == c) g += *sigma;
+    if (r == c) g += *shift;
   }
   G[idx] = g;
-  V[idx] = (r == c) ? 1.0 : 0.0;
 }
 
-// orthogonalise columns p and q (LDS, column-major, m rows) by the 16 lanes
-// of one DPP row; returns whether a rotation was applied
-__device__ __forceinline__ bool oj_rotate(double* __restrict__ sG, double* __restrict__ sV, int m, int p, int q,
-                                          int sub) {
+// Jacobi rotation that orthogonalises the pair (x, y) given a = x.x, b = y.y,
+// g = x.y; returns false when the pair is already orthogonal to 1e-14.
+__device__ __forceinline__ bool oj_angle(double a, double b, double g, double& c, double& sn) {
+  const double tol = 1e-14;
+  if (!(a > 0.0 && b > 0.0 && fabs(g) > tol * sqrt(a * b))) return false;
+  const double zeta = (b - a) / (2.0 * g);
+  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  c = 1.0 / sqrt(1.0 + t * t);
+  sn = c * t;
+  return true;
+}
+
+// orthogonalise columns p and q of sG (LDS, column-major, m rows) by the 16
+// lanes of one DPP row; returns whether a rotation was applied
+__device__ __forceinline__ bool oj_rotate_lds(double* __restrict__ sG, int m, int p, int q, int sub) {
   double* gp = sG + p * m;
   double* gq = sG + q * m;
   double x[OJ_MAXR], y[OJ_MAXR];
@@ -272,14 +287,8 @@ __device__ __forceinline__ bool oj_rotate(double* __restrict__ sG, double* __res
   a = row16_sum(a);
   b = row16_sum(b);
   g = row16_sum(g);
-  const double tol = 1e-14;
-  if (!(a > 0.0 && b > 0.0 && fabs(g) > tol * sqrt(a * b))) return false;
-  const double zeta = (b - a) / (2.0 * g);
-  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double c = 1.0 / sqrt(1.0 + t * t);
-  const double sn = c * t;
-  double* vp = sV + p * m;
-  double* vq = sV + q * m;
+  double c, sn;
+  if (!oj_angle(a, b, g, c, sn)) return false;
 #pragma unroll
   for (int i = 0; i < OJ_MAXR; ++i) {
     const int r = sub + 16 * i;
@@ -288,101 +297,130 @@ __device__ __forceinline__ bool oj_rotate(double* __restrict__ sG, double* __res
       gq[r] = sn * x[i] + c * y[i];
     }
   }
-#pragma unroll
-  for (int i = 0; i < OJ_MAXR; ++i) {
-    const int r = sub + 16 * i;
-    x[i] = r < m ? vp[r] : 0.0;
-    y[i] = r < m ? vq[r] : 0.0;
-  }
-#pragma unroll
-  for (int i = 0; i < OJ_MAXR; ++i) {
-    const int r = sub + 16 * i;
-    if (r < m) {
-      vp[r] = c * x[i] - sn * y[i];
-      vq[r] = sn * x[i] + c * y[i];
-    }
-  }
   return true;
 }
 
-// cross == 0: workgroup w orthogonalises the pairs inside blocks 2w and 2w+1;
-// cross == 1: workgroup w takes the block pair w of round s and
-// orthogonalises all cross pairs between the two blocks.
-__global__ __launch_bounds__(256) void k_oj_step(int m, int nb, int s, int sweep, int cross, double* __restrict__ G,
-                                                 double* __restrict__ V, int* __restrict__ counters) {
-  if (sweep > 0 && counters[sweep - 1] == 0) return;
-  extern __shared__ double lds[];
-  constexpr int W = 2 * NBJ;
-  double* sG = lds;               // W columns x m rows
-  double* sV = lds + W * m;
-  __shared__ int s_rot;
-  int P, Q;
-  if (cross) pair_of(s, blockIdx.x, nb, P, Q);
-  else { P = 2 * blockIdx.x; Q = P + 1; }
-  const int tid = threadIdx.x;
-  if (tid == 0) s_rot = 0;
-  // load the two blocks (each block is NBJ contiguous columns of m doubles),
-  // OJ_BATCH double2 of G and of V in flight per thread
-  const int blk = NBJ * m;
-  constexpr int OJ_BATCH = 6;
-  for (int base = 2 * tid; base < 2 * blk; base += 512 * OJ_BATCH) {
-    double2 gv[OJ_BATCH], vv[OJ_BATCH];
+// load / store NBJ contiguous columns of m doubles (a block) with double2,
+// `batch` transfers in flight per thread
+__device__ __forceinline__ void oj_block_load(const double* __restrict__ src, double* __restrict__ dst, int count) {
+  constexpr int BATCH = 6;
+  for (int base = 2 * threadIdx.x; base < count; base += 2 * blockDim.x * BATCH) {
+    double2 v[BATCH];
 #pragma unroll
-    for (int u = 0; u < OJ_BATCH; ++u) {
-      const int idx = base + 512 * u;
-      if (idx < 2 * blk) {
-        const int which = idx >= blk, off = idx - which * blk;
-        const int64_t src = (int64_t)(which ? Q : P) * blk + off;
-        gv[u] = *reinterpret_cast<const double2*>(G + src);
-        vv[u] = *reinterpret_cast<const double2*>(V + src);
-      }
+    for (int u = 0; u < BATCH; ++u) {
+      const int idx = base + 2 * blockDim.x * u;
+      v[u] = idx < count ? *reinterpret_cast<const double2*>(src + idx) : make_double2(0.0, 0.0);
     }
 #pragma unroll
-    for (int u = 0; u < OJ_BATCH; ++u) {
-      const int idx = base + 512 * u;
-      if (idx < 2 * blk) {
-        *reinterpret_cast<double2*>(sG + idx) = gv[u];
-        *reinterpret_cast<double2*>(sV + idx) = vv[u];
-      }
+    for (int u = 0; u < BATCH; ++u) {
+      const int idx = base + 2 * blockDim.x * u;
+      if (idx < count) *reinterpret_cast<double2*>(dst + idx) = v[u];
     }
   }
+}
+
+// workgroup w orthogonalises the pairs inside blocks 2w and 2w+1 (both in LDS)
+__global__ __launch_bounds__(256) void k_oj_intra(int m, int sweep, double* __restrict__ G, int* __restrict__ counters) {
+  if (sweep > 0 && counters[sweep - 1] == 0) return;
+  extern __shared__ double lds[];
+  double* sG = lds;  // 2 NBJ columns x m rows
+  __shared__ int s_rot;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_rot = 0;
+  const int blk = NBJ * m;
+  double* g0 = G + (int64_t)(2 * blockIdx.x) * blk;  // blocks 2w, 2w+1 are contiguous
+  oj_block_load(g0, sG, 2 * blk);
   __syncthreads();
-  const int grp = tid >> 4, sub = tid & 15;  // 16 groups of 16 lanes
+  const int grp = tid >> 4, sub = tid & 15;
   int my_rot = 0;
-  const int rounds = cross ? NBJ : NBJ - 1;
-  for (int rnd = 0; rnd < rounds; ++rnd) {
+  for (int rnd = 0; rnd < NBJ - 1; ++rnd) {
+    const int half = grp >> 3;  // 8 groups per block
     int p, q;
-    if (cross) {
-      p = grp;
-      q = NBJ + (grp + rnd) % NBJ;
-    } else {
-      const int half = grp >> 3;  // 8 groups per block
-      pair_of(rnd, grp & 7, NBJ, p, q);
-      p += half * NBJ;
-      q += half * NBJ;
-    }
-    if (oj_rotate(sG, sV, m, p, q, sub) && sub == 0) ++my_rot;
+    pair_of(rnd, grp & 7, NBJ, p, q);
+    if (oj_rotate_lds(sG, m, p + half * NBJ, q + half * NBJ, sub) && sub == 0) ++my_rot;
     __syncthreads();
   }
   if (sub == 0 && my_rot) atomicAdd(&s_rot, my_rot);
-  for (int idx = 2 * tid; idx < 2 * blk; idx += 512) {
-    const int which = idx >= blk, off = idx - which * blk;
-    const int64_t dst = (int64_t)(which ? Q : P) * blk + off;
-    *reinterpret_cast<double2*>(G + dst) = *reinterpret_cast<const double2*>(sG + idx);
-    *reinterpret_cast<double2*>(V + dst) = *reinterpret_cast<const double2*>(sV + idx);
-  }
+  oj_block_load(sG, g0, 2 * blk);
   __syncthreads();
   if (tid == 0 && s_rot) atomicAdd(&counters[sweep], s_rot);
 }
 
-// lambda_j = v_j^T g_j - sigma (one wavefront per column); sort by |lambda|
-// desc (ties: lambda desc, then index); write w and the eigenvectors as the
-// columns of the row-major Vout.
-__global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restrict__ G, const double* __restrict__ V,
-                                                    const double* __restrict__ sigma, const int* __restrict__ counters,
+// workgroup w takes the block pair w of round s: column g of block P stays
+// in the registers of lane group g, the 16 columns of block Q rotate past it
+__global__ __launch_bounds__(256) void k_oj_cross(int m, int nb, int s, int sweep, double* __restrict__ G,
+                                                  int* __restrict__ counters) {
+  if (sweep > 0 && counters[sweep - 1] == 0) return;
+  extern __shared__ double lds[];
+  double* sQ = lds;  // NBJ columns x m rows
+  __shared__ int s_rot;
+  int P, Q;
+  pair_of(s, blockIdx.x, nb, P, Q);
+  const int tid = threadIdx.x, grp = tid >> 4, sub = tid & 15;
+  if (tid == 0) s_rot = 0;
+  const int blk = NBJ * m;
+  double* gpcol = G + (int64_t)P * blk + (int64_t)grp * m;
+  double* gQ = G + (int64_t)Q * blk;
+  double x[OJ_MAXR];
+#pragma unroll
+  for (int i = 0; i < OJ_MAXR; ++i) {
+    const int r = sub + 16 * i;
+    x[i] = r < m ? gpcol[r] : 0.0;
+  }
+  oj_block_load(gQ, sQ, blk);
+  __syncthreads();
+  int my_rot = 0;
+  for (int rnd = 0; rnd < NBJ; ++rnd) {
+    double* gq = sQ + ((grp + rnd) & (NBJ - 1)) * m;
+    double y[OJ_MAXR];
+    double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+    for (int i = 0; i < OJ_MAXR; ++i) {
+      const int r = sub + 16 * i;
+      y[i] = r < m ? gq[r] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < OJ_MAXR; ++i) {
+      a = fma(x[i], x[i], a);
+      b = fma(y[i], y[i], b);
+      g = fma(x[i], y[i], g);
+    }
+    a = row16_sum(a);
+    b = row16_sum(b);
+    g = row16_sum(g);
+    double c, sn;
+    if (oj_angle(a, b, g, c, sn)) {
+#pragma unroll
+      for (int i = 0; i < OJ_MAXR; ++i) {
+        const int r = sub + 16 * i;
+        const double xi = x[i];
+        x[i] = c * xi - sn * y[i];
+        if (r < m) gq[r] = sn * xi + c * y[i];
+      }
+      if (sub == 0) ++my_rot;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < OJ_MAXR; ++i) {
+    const int r = sub + 16 * i;
+    if (r < m) gpcol[r] = x[i];
+  }
+  if (sub == 0 && my_rot) atomicAdd(&s_rot, my_rot);
+  oj_block_load(sQ, gQ, blk);
+  __syncthreads();
+  if (tid == 0 && s_rot) atomicAdd(&counters[sweep], s_rot);
+}
+
+// lambda_j = ||g_j|| - c and v_j = g_j / ||g_j|| (one wavefront per column);
+// sort by |lambda| desc (ties: lambda desc, then index); write w and the
+// eigenvectors as the columns of the row-major Vout.
+__global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restrict__ G,
+                                                    const double* __restrict__ shift, const int* __restrict__ counters,
                                                     int sweeps_run, double* __restrict__ Vout,
                                                     double* __restrict__ wout, uint32_t* __restrict__ flags) {
   __shared__ double w[1024];
+  __shared__ double inv[1024];
   __shared__ int rank[1024];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) {
@@ -391,17 +429,22 @@ __global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restr
       if (counters[s] == 0) { conv = true; break; }
     if (!conv) atomicOr(flags, SKETCHNE_FLAG_EIG_NOCONV);
   }
-  const double sg = *sigma;
+  const double cs = *shift;
   for (int j = wave; j < m; j += 16) {
     double d = 0.0;
 #pragma unroll
     for (int i = 0; i < (16 * OJ_MAXR + 63) / 64; ++i) {
       const int r = lane + 64 * i;
-      if (r < m) d = fma(V[(int64_t)j * m + r], G[(int64_t)j * m + r], d);
+      if (r < m) {
+        const double v = G[(int64_t)j * m + r];
+        d = fma(v, v, d);
+      }
     }
     d = wave_sum(d);
     if (lane == 0) {
-      w[j] = d - sg;
+      const double nrm = sqrt(d);
+      w[j] = nrm - cs;
+      inv[j] = nrm > 0.0 ? 1.0 / nrm : 0.0;
       if (!isfinite(w[j])) atomicOr(flags, SKETCHNE_FLAG_NONFINITE);
     }
   }
@@ -419,8 +462,10 @@ __global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restr
   __syncthreads();
   for (int i = tid; i < m; i += blockDim.x) wout[rank[i]] = w[i];
   for (int64_t idx = tid; idx < (int64_t)m * m; idx += blockDim.x) {
-    int j = (int)(idx / m), r = (int)(idx % m);
-    Vout[(int64_t)r * m + rank[j]] = V[idx];
+    const int j = (int)(idx / m), r = (int)(idx % m);
+    // a zero matrix (c = 0) has G = 0: its eigenvectors are the unit vectors
+    const double v = inv[j] > 0.0 ? G[idx] * inv[j] : (r == j ? 1.0 : 0.0);
+    Vout[(int64_t)r * m + rank[j]] = v;
   }
 }
 
@@ -459,7 +504,7 @@ sketchne_status chol_inv(sketchne_ctx* c, int m, const double* G, double* RinvT,
 size_t symeig_ws_bytes(int m) {
   int mp = oj_nblocks(m) * NBJ;
   size_t mat = align_up(sizeof(double) * (size_t)mp * m);
-  return 2 * mat + align_up(sizeof(int) * kMaxSweeps) + align_up(sizeof(double));
+  return mat + align_up(sizeof(int) * kMaxSweeps) + align_up(sizeof(double));
 }
 
 sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* Vout, double* wout, void* ws) {
@@ -468,22 +513,24 @@ sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* Vout, do
   const int nb = oj_nblocks(m), mp = nb * NBJ;
   Arena ar(ws, symeig_ws_bytes(m));
   double* G = ar.take<double>((size_t)mp * m);
-  double* V = ar.take<double>((size_t)mp * m);
   int* counters = ar.take<int>(kMaxSweeps);
-  double* sigma = ar.take<double>(1);
+  double* shift = ar.take<double>(1);
   ProfScope ps(c, SKETCHNE_PROF_SMALL);
-  hipLaunchKernelGGL(k_oj_norm, dim3(1), dim3(1024), 0, c->stream, m, A, sigma);
+  hipLaunchKernelGGL(k_oj_norm, dim3(1), dim3(1024), 0, c->stream, m, A, shift);
   int tot = mp * m;
-  hipLaunchKernelGGL(k_oj_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, m, mp, A, sigma, G, V,
+  hipLaunchKernelGGL(k_oj_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, m, mp, A, shift, G,
                      counters, kMaxSweeps);
-  const size_t shmem = sizeof(double) * 2 * (size_t)(2 * NBJ) * m;
-  hipFuncSetAttribute(reinterpret_cast<const void*>(k_oj_step), hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)shmem);
+  const size_t sh_intra = sizeof(double) * (size_t)(2 * NBJ) * m;
+  const size_t sh_cross = sizeof(double) * (size_t)NBJ * m;
+  hipFuncSetAttribute(reinterpret_cast<const void*>(k_oj_intra), hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)sh_intra);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(k_oj_cross), hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)sh_cross);
   int run = 0;
   for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-    hipLaunchKernelGGL(k_oj_step, dim3(nb / 2), dim3(256), shmem, c->stream, m, nb, 0, sweep, 0, G, V, counters);
+    hipLaunchKernelGGL(k_oj_intra, dim3(nb / 2), dim3(256), sh_intra, c->stream, m, sweep, G, counters);
     for (int s = 0; s < nb - 1; ++s)
-      hipLaunchKernelGGL(k_oj_step, dim3(nb / 2), dim3(256), shmem, c->stream, m, nb, s, sweep, 1, G, V, counters);
+      hipLaunchKernelGGL(k_oj_cross, dim3(nb / 2), dim3(256), sh_cross, c->stream, m, nb, s, sweep, G, counters);
     run = sweep + 1;
     if (sweep >= 4) {  // one small host read per sweep from the fifth on
       hipMemcpyAsync(c->h_counter, counters + sweep, sizeof(int), hipMemcpyDeviceToHost, c->stream);
@@ -491,7 +538,7 @@ sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* Vout, do
       if (*c->h_counter == 0) break;
     }
   }
-  hipLaunchKernelGGL(k_oj_finish, dim3(1), dim3(1024), 0, c->stream, m, G, V, sigma, counters, run, Vout, wout,
+  hipLaunchKernelGGL(k_oj_finish, dim3(1), dim3(1024), 0, c->stream, m, G, shift, counters, run, Vout, wout,
                      c->d_flags);
   return launch_status();
 }
