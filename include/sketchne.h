@@ -124,8 +124,8 @@ sketchne_status sketchne_workspace_size(const sketchne_params* p, int64_t n, int
  * Requires k + s_eig <= 288 (order of the Rayleigh-Ritz eigensolver) and
  * (k + s_eig) % 4 == 0.
  * Orthonormalisation is Cholesky-QR with FP64 Gram and Cholesky; a second
- * pass runs only when the first factor's 1-norm condition number exceeds
- * 1e5 or its Cholesky needed a diagonal shift. */
+ * pass runs only when the first factor's 1-norm condition number (Gram
+ * scaled to unit diagonal) exceeds 1e5 or its Cholesky needed a shift. */
 sketchne_status sketchne_eig(sketchne_ctx* ctx, const sketchne_graph* A, const sketchne_params* p,
                              const float* omega0, float* U, double* lambda,
                              void* ws, size_t ws_bytes);

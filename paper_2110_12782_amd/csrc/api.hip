@@ -118,7 +118,8 @@ sketchne_status orth_pass(sketchne_ctx* c, int64_t n, int m, const float* src, f
 
 // Cholesky-QR with FP64 Gram and Cholesky: src -> dst, and a second pass
 // (dst -> tmp -> dst) only when the first factor's 1-norm condition number
-// exceeds kCholQRRepeat or its Cholesky needed a shift.  Below that bound one
+// (Gram scaled to unit diagonal) exceeds kCholQRRepeat or its Cholesky needed
+// a shift.  Below that bound one
 // FP64 pass already leaves dst orthonormal to the FP32 rounding of its storage.
 sketchne_status orth2(sketchne_ctx* c, int64_t n, int m, const float* src, float* tmp, float* dst, int64_t ld,
                       bool transposed, const OrthWs& w) {

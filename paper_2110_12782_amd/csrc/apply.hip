@@ -5,15 +5,16 @@
 // (R^-1 upper triangular), U = Q U^(:, 1:k) after Rayleigh-Ritz, and
 // E = Y (R^-1 U^ Sigma^1/2) in the embedding.  A workgroup owns 128 rows and
 // every output column, so each row of A is read from HBM once and written
-// once; B streams from L2 in chunks of 16 summation indices through double
-// buffered LDS (next chunk prefetched into registers during the MFMAs).  With
-// a triangular B, chunk c only meets column blocks >= c, which halves the
-// work of the Cholesky-QR apply; entries below the diagonal are masked on
-// load, whatever the buffer holds there.
+// once; B streams from L2 in chunks of 32 summation indices through LDS, the
+// registers holding the next chunk during the MFMAs.  With a triangular B a
+// chunk only meets the column blocks at or right of its diagonal, which
+// halves the work of the Cholesky-QR apply; entries below the diagonal are
+// masked on load, whatever the buffer holds there.
 //
 // 8 wavefronts: wave w owns rows 32 (w & 3) .. +32 (two 16-row MFMA blocks)
-// and column blocks (w >> 2) * NBH .. +NBH (16 columns each), i.e. 2 x NBH
-// v_mfma_f64_16x16x4f64 accumulators.
+// and the column blocks (16 columns each) of parity w >> 2, i.e. 2 x NBH
+// v_mfma_f64_16x16x4f64 accumulators; interleaving the blocks keeps the two
+// halves equally loaded when a triangular B skips blocks.
 #include "internal.h"
 
 namespace skne {
@@ -22,7 +23,7 @@ namespace {
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int AR = 128;   // rows per workgroup
-constexpr int ABK = 16;   // summation chunk
+constexpr int ABK = 32;   // summation chunk
 
 struct ApplyArgs {
   int64_t n; int K, N;
@@ -38,37 +39,44 @@ struct ApplyArgs {
 template <int NBH, bool ACOL, bool BCOL, bool CCOL, bool TRI>
 __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
   constexpr int NC = 32 * NBH;                        // columns held by the workgroup
+  constexpr int AVEC = AR * ABK / 4;                  // float4 per A chunk
+  constexpr int APER = AVEC / 512;
   constexpr int BVEC = ABK * NC / 2;                  // double2 per B chunk
   constexpr int BPER = (BVEC + 511) / 512;
-  __shared__ double As[2][ABK][AR + 2];
-  __shared__ double Bs[2][ABK][NC + 2];
+  constexpr int BCV = ABK / 2;                        // double2 per column of a BCOL chunk
+  __shared__ double As[ABK][AR + 2];
+  __shared__ double Bs[ABK][NC + 2];
   if (g.run_if && *g.run_if == 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rg = wave & 3, ch = wave >> 2;
   const int64_t i0 = (int64_t)blockIdx.x * AR;
   const int kend = TRI ? min(g.K, g.N) : g.K;
 
-  float4 ra;
+  float4 ra[APER];
   double2 rb[BPER];
   auto fetch = [&](int k0) {
-    if (!ACOL) {
-      const int r = tid >> 2, q = (tid & 3) * 4;
-      const int64_t i = i0 + r;
-      const int k = k0 + q;
-      ra = (i < g.n && k < kend) ? *reinterpret_cast<const float4*>(g.A + i * g.lda + k)
-                                 : make_float4(0.f, 0.f, 0.f, 0.f);
-    } else {
-      const int kk = tid >> 5, q = (tid & 31) * 4;
-      const int k = k0 + kk;
-      const int64_t i = i0 + q;
-      if (k < kend && i + 3 < g.n) {
-        ra = *reinterpret_cast<const float4*>(g.A + (int64_t)k * g.lda + i);
+#pragma unroll
+    for (int p = 0; p < APER; ++p) {
+      const int e = tid + 512 * p;
+      if (!ACOL) {
+        const int r = e / (ABK / 4), q = (e % (ABK / 4)) * 4;
+        const int64_t i = i0 + r;
+        const int k = k0 + q;
+        ra[p] = (i < g.n && k < kend) ? *reinterpret_cast<const float4*>(g.A + i * g.lda + k)
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
       } else {
-        const float* p = g.A + (int64_t)k * g.lda + i;
-        ra.x = (k < kend && i + 0 < g.n) ? p[0] : 0.f;
-        ra.y = (k < kend && i + 1 < g.n) ? p[1] : 0.f;
-        ra.z = (k < kend && i + 2 < g.n) ? p[2] : 0.f;
-        ra.w = (k < kend && i + 3 < g.n) ? p[3] : 0.f;
+        const int kk = e / (AR / 4), q = (e % (AR / 4)) * 4;
+        const int k = k0 + kk;
+        const int64_t i = i0 + q;
+        if (k < kend && i + 3 < g.n) {
+          ra[p] = *reinterpret_cast<const float4*>(g.A + (int64_t)k * g.lda + i);
+        } else {
+          const float* ptr = g.A + (int64_t)k * g.lda + i;
+          ra[p].x = (k < kend && i + 0 < g.n) ? ptr[0] : 0.f;
+          ra[p].y = (k < kend && i + 1 < g.n) ? ptr[1] : 0.f;
+          ra[p].z = (k < kend && i + 2 < g.n) ? ptr[2] : 0.f;
+          ra[p].w = (k < kend && i + 3 < g.n) ? ptr[3] : 0.f;
+        }
       }
     }
 #pragma unroll
@@ -77,9 +85,10 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
       double2 v = make_double2(0.0, 0.0);
       if (e < BVEC) {
         int j, k;
-        if (BCOL) { j = e >> 3; k = k0 + (e & 7) * 2; }
+        if (BCOL) { j = e / BCV; k = k0 + (e % BCV) * 2; }
         else { k = k0 + e / (NC / 2); j = (e % (NC / 2)) * 2; }
-        if (j < g.N && k < kend) {
+        // with a triangular B, whole columns j < k0 are zero in this chunk
+        if (j < g.N && k < kend && !(TRI && j < k0)) {
           v = BCOL ? *reinterpret_cast<const double2*>(g.B + (int64_t)j * g.ldb + k)
                    : *reinterpret_cast<const double2*>(g.B + (int64_t)k * g.ldb + j);
           if (TRI) {
@@ -92,32 +101,36 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
       rb[p] = v;
     }
   };
-  auto stash = [&](int buf) {
-    if (!ACOL) {
-      const int r = tid >> 2, q = (tid & 3) * 4;
-      As[buf][q + 0][r] = ra.x;
-      As[buf][q + 1][r] = ra.y;
-      As[buf][q + 2][r] = ra.z;
-      As[buf][q + 3][r] = ra.w;
-    } else {
-      const int kk = tid >> 5, q = (tid & 31) * 4;
-      As[buf][kk][q + 0] = ra.x;
-      As[buf][kk][q + 1] = ra.y;
-      As[buf][kk][q + 2] = ra.z;
-      As[buf][kk][q + 3] = ra.w;
+  auto stash = [&]() {
+#pragma unroll
+    for (int p = 0; p < APER; ++p) {
+      const int e = tid + 512 * p;
+      if (!ACOL) {
+        const int r = e / (ABK / 4), q = (e % (ABK / 4)) * 4;
+        As[q + 0][r] = ra[p].x;
+        As[q + 1][r] = ra[p].y;
+        As[q + 2][r] = ra[p].z;
+        As[q + 3][r] = ra[p].w;
+      } else {
+        const int kk = e / (AR / 4), q = (e % (AR / 4)) * 4;
+        As[kk][q + 0] = ra[p].x;
+        As[kk][q + 1] = ra[p].y;
+        As[kk][q + 2] = ra[p].z;
+        As[kk][q + 3] = ra[p].w;
+      }
     }
 #pragma unroll
     for (int p = 0; p < BPER; ++p) {
       const int e = tid + 512 * p;
       if (e < BVEC) {
         if (BCOL) {
-          const int j = e >> 3, kk = (e & 7) * 2;
-          Bs[buf][kk][j] = rb[p].x;
-          Bs[buf][kk + 1][j] = rb[p].y;
+          const int j = e / BCV, kk = (e % BCV) * 2;
+          Bs[kk][j] = rb[p].x;
+          Bs[kk + 1][j] = rb[p].y;
         } else {
           const int kk = e / (NC / 2), j = (e % (NC / 2)) * 2;
-          Bs[buf][kk][j] = rb[p].x;
-          Bs[buf][kk][j + 1] = rb[p].y;
+          Bs[kk][j] = rb[p].x;
+          Bs[kk][j + 1] = rb[p].y;
         }
       }
     }
@@ -129,38 +142,43 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
 #pragma unroll
     for (int t = 0; t < NBH; ++t) acc[m][t] = doublex4{0.0, 0.0, 0.0, 0.0};
 
+  // one LDS buffer; the registers run two chunks ahead: chunk c + 1 is
+  // stored once every wave has finished with chunk c, and chunk c + 2 is
+  // fetched while chunk c + 1 is being multiplied
   const int nchunk = (kend + ABK - 1) / ABK;
   if (nchunk > 0) {
     fetch(0);
-    stash(0);
+    stash();
   }
   __syncthreads();
+  if (nchunk > 1) fetch(ABK);
   for (int c = 0; c < nchunk; ++c) {
-    const int buf = c & 1;
-    const bool more = c + 1 < nchunk;
-    if (more) fetch((c + 1) * ABK);
 #pragma unroll
     for (int kk = 0; kk < ABK / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
-      const double a0 = As[buf][kr][32 * rg + (lane & 15)];
-      const double a1 = As[buf][kr][32 * rg + 16 + (lane & 15)];
+      const double a0 = As[kr][32 * rg + (lane & 15)];
+      const double a1 = As[kr][32 * rg + 16 + (lane & 15)];
 #pragma unroll
       for (int t = 0; t < NBH; ++t) {
-        const int jb = ch * NBH + t;
-        if (TRI && jb < c) continue;  // B(k, j) = 0 for the whole block
-        const double b = Bs[buf][kr][16 * jb + (lane & 15)];
+        const int jb = 2 * t + ch;              // column blocks interleaved over the two halves
+        if (TRI && 16 * jb + 15 < ABK * c) continue;  // B(k, j) = 0 for the whole block
+        const double b = Bs[kr][16 * jb + (lane & 15)];
         acc[0][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][t], 0, 0, 0);
         acc[1][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][t], 0, 0, 0);
       }
     }
-    if (more) stash(buf ^ 1);
     __syncthreads();
+    if (c + 1 < nchunk) {
+      stash();
+      __syncthreads();
+      if (c + 2 < nchunk) fetch((c + 2) * ABK);
+    }
   }
 
   // v_mfma_f64_16x16x4f64 output: lane l, register r -> row (l / 16) + 4 r, column l % 16
 #pragma unroll
   for (int t = 0; t < NBH; ++t) {
-    const int j = 16 * (ch * NBH + t) + (lane & 15);
+    const int j = 16 * (2 * t + ch) + (lane & 15);
     if (j >= g.N) continue;
 #pragma unroll
     for (int m = 0; m < 2; ++m)

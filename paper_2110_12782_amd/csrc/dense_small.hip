@@ -1,7 +1,8 @@
 // Small dense FP64 solvers: Cholesky with inverse factor, symmetric eigensolver.
 //
 // Cholesky: G = R^T R for an SPD m x m matrix (m <= 512), right-looking and
-// blocked by 32 inside one 1024-thread workgroup.  The same row operations are
+// blocked by 32 inside one 512-thread workgroup (diagonal blocks factored by
+// one wavefront in registers, trailing updates on the FP64 matrix cores).  The same row operations are
 // applied to an appended identity, so the right half ends up holding R^-T
 // (block row J of [R | R^-T] is R_JJ^-T times the updated block row J of
 // [G | I]).  A pivot that is not positive restarts the factorization once with
@@ -16,24 +17,79 @@ namespace {
 
 constexpr int NB = 32;
 
-__global__ __launch_bounds__(1024) void k_chol_inv(int m, const double* __restrict__ G, double* __restrict__ W,
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Cholesky of the jb x jb diagonal block held in D (LDS, upper triangle, row
+// stride NB + 1) by one wavefront: lane b keeps column b in registers (the
+// block is padded with the identity beyond jb), row t of the factor is
+// exchanged with readlane, so no workgroup barrier is needed.  Sets *fail
+// when a pivot is not positive.
+__device__ void chol_diag_wave(double* D, int jb, int lane, int* fail) {
+  double c[NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    double v = 0.0;
+    if (lane < jb && a < jb) v = a <= lane ? D[a * (NB + 1) + lane] : 0.0;
+    else if (a == lane) v = 1.0;
+    c[a] = v;
+  }
+  bool bad = false;
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    double d = readlane_d(c[t], t);
+    if (!(d > 0.0) || !isfinite(d)) { bad = true; d = 1.0; }
+    d = sqrt(d);
+    if (lane == t) c[t] = d;
+    else if (lane > t) c[t] /= d;
+#pragma unroll
+    for (int a = t + 1; a < NB; ++a) {
+      const double rta = readlane_d(c[t], a);  // R(t, a)
+      if (a <= lane) c[a] = fma(-rta, c[t], c[a]);
+    }
+  }
+  if (lane < jb) {
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+      if (a <= lane) D[a * (NB + 1) + lane] = c[a];
+  }
+  if (bad && lane == 0) *fail = 1;
+}
+
+__global__ __launch_bounds__(512) void k_chol_inv(int m, const double* __restrict__ G, double* __restrict__ W,
                                                    double* __restrict__ RinvT, uint32_t* __restrict__ flags,
                                                    int* __restrict__ need_more, const int* __restrict__ run_if) {
   if (run_if && *run_if == 0) return;
   extern __shared__ double smem[];
   double* D = smem;               // NB x (NB+1)
   double* P = smem + NB * (NB + 1);  // NB x m panel
+  __shared__ double dsc[512];     // column scales sqrt(G_ii) (1 for a zero column)
   __shared__ int s_fail;
   __shared__ int s_shifted;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int64_t m2 = 2 * (int64_t)m;
 
+  // The scaled matrix Gs = S^-1 G S^-1 (S = diag(sqrt(G_ii))) is factored:
+  // Gs = Rs^T Rs gives R = Rs S and R^-T = Rs^-T S^-1.  The span of the
+  // Cholesky-QR basis does not depend on the scaling, and the condition
+  // number that decides a second pass is the scaled one (power iterates
+  // differ mostly in column scale).
+  for (int i = tid; i < m; i += nt) {
+    const double g = G[(int64_t)i * m + i];
+    dsc[i] = (g > 0.0 && isfinite(g)) ? sqrt(g) : 1.0;
+  }
+  __syncthreads();
   if (tid == 0) {
     double tr = 0.0;
-    for (int i = 0; i < m; ++i) tr += fabs(G[(int64_t)i * m + i]);
+    for (int i = 0; i < m; ++i) tr += fabs(G[(int64_t)i * m + i]) / (dsc[i] * dsc[i]);
     s_fail = 0;
     s_shifted = 0;
-    // shifted retry: s = 11 (m^2 + m) u trace(G)  (shifted Cholesky-QR)
+    // shifted retry: s = 11 (m^2 + m) u trace(Gs)  (shifted Cholesky-QR)
     D[0] = 11.0 * ((double)m * m + m) * 1.1102230246251565e-16 * (tr > 0 ? tr : 1.0);
   }
   __syncthreads();
@@ -47,7 +103,7 @@ __global__ __launch_bounds__(1024) void k_chol_inv(int m, const double* __restri
       double v;
       if (c < m) {
         int64_t a = r < c ? r : c, b = r < c ? c : r;  // symmetric: read the upper triangle
-        v = G[a * m + b] + (r == c ? shift : 0.0);
+        v = G[a * m + b] / (dsc[a] * dsc[b]) + (r == c ? shift : 0.0);
       } else {
         v = (c - m == r) ? 1.0 : 0.0;
       }
@@ -58,27 +114,14 @@ __global__ __launch_bounds__(1024) void k_chol_inv(int m, const double* __restri
 
     for (int j0 = 0; j0 < m; j0 += NB) {
       const int jb = min(NB, m - j0);
-      // 1. factor the diagonal block in LDS
+      // 1. factor the diagonal block in LDS (one wavefront)
       for (int idx = tid; idx < jb * jb; idx += nt) {
         int a = idx / jb, b = idx % jb;
         D[a * (NB + 1) + b] = (b >= a) ? W[(int64_t)(j0 + a) * m2 + j0 + b] : 0.0;
       }
       __syncthreads();
-      for (int t = 0; t < jb; ++t) {
-        if (tid == 0) {
-          double d = D[t * (NB + 1) + t];
-          if (!(d > 0.0) || !isfinite(d)) { s_fail = 1; d = 1.0; }
-          D[t * (NB + 1) + t] = sqrt(d);
-        }
-        __syncthreads();
-        if (tid > t && tid < jb) D[t * (NB + 1) + tid] /= D[t * (NB + 1) + t];
-        __syncthreads();
-        for (int idx = tid; idx < jb * jb; idx += nt) {
-          int a = idx / jb, b = idx % jb;
-          if (a > t && b >= a) D[a * (NB + 1) + b] -= D[t * (NB + 1) + a] * D[t * (NB + 1) + b];
-        }
-        __syncthreads();
-      }
+      if (tid < 64) chol_diag_wave(D, jb, tid, &s_fail);
+      __syncthreads();
       if (s_fail) break;
       for (int idx = tid; idx < jb * jb; idx += nt) {
         int a = idx / jb, b = idx % jb;
@@ -90,29 +133,78 @@ __global__ __launch_bounds__(1024) void k_chol_inv(int m, const double* __restri
       for (int pc = tid; pc < m; pc += nt) {
         int64_t col = pc < nleft ? (int64_t)(j0 + jb + pc) : (int64_t)m + (pc - nleft);
         double x[NB];
+        // all loads first (the solve writes the same column back)
+#pragma unroll
+        for (int t = 0; t < NB; ++t) x[t] = t < jb ? W[(int64_t)(j0 + t) * m2 + col] : 0.0;
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
           if (t < jb) {
-            double v = W[(int64_t)(j0 + t) * m2 + col];
+            double v = x[t];
             for (int s2 = 0; s2 < t; ++s2) v -= D[s2 * (NB + 1) + t] * x[s2];
             x[t] = v / D[t * (NB + 1) + t];
-            W[(int64_t)(j0 + t) * m2 + col] = x[t];
-            P[t * m + pc] = x[t];
           }
+        }
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+          if (t < jb) W[(int64_t)(j0 + t) * m2 + col] = x[t];
+          P[t * m + pc] = t < jb ? x[t] : 0.0;  // zero padding rows of a partial last block
         }
       }
       __syncthreads();
-      // 3. trailing update of the rows below the block
-      const int64_t nrows = nleft;
-      for (int64_t idx = tid; idx < nrows * m; idx += nt) {
-        int pr = (int)(idx / m);
-        int pc = (int)(idx - (int64_t)pr * m);
-        if (pc < nleft && pc < pr) continue;  // left part: upper triangle only
-        int64_t r = j0 + jb + pr;
-        int64_t col = pc < nleft ? (int64_t)(j0 + jb + pc) : (int64_t)m + (pc - nleft);
-        double s = 0.0;
-        for (int t = 0; t < jb; ++t) s += P[t * m + pr] * P[t * m + pc];
-        W[r * m2 + col] -= s;
+      // 3. trailing update of the rows below the block on the FP64 matrix
+      //    cores: W[r, col(pc)] -= sum_t P[t][pr] P[t][pc] in 16 x 16 tiles
+      //    (v_mfma_f64_16x16x4f64; A(i, k) = -P[k][pr0 + i], B(k, j) = P[k][pc0 + j];
+      //    output lane l, register q: row (l / 16) + 4 q, column l % 16).  Tiles
+      //    wholly below the diagonal of the left part are skipped; only the
+      //    upper triangle of the left part is written.
+      {
+        const int nrows = nleft;
+        const int tr_n = (nrows + 15) / 16, tc_n = (m + 15) / 16;
+        const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+        // two tiles per pass so that their loads overlap
+        for (int tix0 = 2 * wv; tix0 < tr_n * tc_n; tix0 += 2 * nw) {
+          doublex4 acc[2];
+          int64_t gofs[2][4];
+          bool ok[2][4];
+          bool live[2];
+          int trs[2], pcs[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int tix = tix0 + u;
+            const int tr = tix / tc_n, tc = tix - tr * tc_n;
+            // outside the grid, or strictly below the diagonal of the left part
+            live[u] = tix < tr_n * tc_n && !(16 * tc + 15 < nleft && tc < tr);
+            trs[u] = tr;
+            const int pc = 16 * tc + (lane & 15);
+            pcs[u] = pc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int pr = 16 * tr + (lane >> 4) + 4 * q;
+              ok[u][q] = live[u] && pr < nrows && pc < m && (pc >= nleft || pc >= pr);
+              const int64_t col = pc < nleft ? (int64_t)(j0 + jb + pc) : (int64_t)m + (pc - nleft);
+              gofs[u][q] = (int64_t)(j0 + jb + pr) * m2 + col;
+              acc[u][q] = ok[u][q] ? W[gofs[u][q]] : 0.0;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if (!live[u]) continue;
+            const int pra = 16 * trs[u] + (lane & 15);
+            const int pc = pcs[u];
+#pragma unroll
+            for (int k0 = 0; k0 < NB; k0 += 4) {
+              const int t = k0 + (lane >> 4);
+              const double av = pra < nrows ? -P[t * m + pra] : 0.0;
+              const double bv = pc < m ? P[t * m + pc] : 0.0;
+              acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (ok[u][q]) W[gofs[u][q]] = acc[u][q];
+        }
       }
       __syncthreads();
     }
@@ -126,11 +218,11 @@ __global__ __launch_bounds__(1024) void k_chol_inv(int m, const double* __restri
   }
   for (int64_t idx = tid; idx < (int64_t)m * m; idx += nt) {
     int64_t r = idx / m, c = idx - r * m;
-    RinvT[idx] = c <= r ? W[r * m2 + m + c] : 0.0;
+    RinvT[idx] = c <= r ? W[r * m2 + m + c] / dsc[c] : 0.0;
   }
   if (need_more) {
-    // kappa_1(R) = ||R||_1 ||R^-1||_1 from the two halves of W: column sums of
-    // the upper triangle of R and row sums of R^-T
+    // kappa_1(Rs) = ||Rs||_1 ||Rs^-1||_1 from the two halves of W: column sums
+    // of the upper triangle of Rs and row sums of Rs^-T
     __shared__ double s_red[2][16];
     double cmax = 0.0, rmax = 0.0;
     for (int j = tid; j < m; j += nt) {
@@ -156,11 +248,14 @@ __global__ __launch_bounds__(1024) void k_chol_inv(int m, const double* __restri
   }
 }
 
+// grid-stride copy over a fixed grid, so that a skipped copy costs one launch
 __global__ void k_copy_if(int64_t count, const float* __restrict__ src, float* __restrict__ dst,
                           const int* __restrict__ run_if) {
   if (run_if && *run_if == 0) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) dst[i] = src[i];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  for (; i + 3 < count; i += 4 * stride) *reinterpret_cast<float4*>(dst + i) = *reinterpret_cast<const float4*>(src + i);
+  for (; i < count; ++i) dst[i] = src[i];
 }
 
 // ---------------------------------------------------------------- Jacobi
@@ -483,8 +578,10 @@ size_t chol_ws_bytes(int m) { return align_up(sizeof(double) * (size_t)m * 2 * m
 sketchne_status copy_if(sketchne_ctx* c, int64_t count, const float* src, float* dst, const int* run_if) {
   if (count == 0) return SKETCHNE_OK;
   ProfScope ps(c, SKETCHNE_PROF_PREP);
-  hipLaunchKernelGGL(k_copy_if, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, c->stream, count, src, dst,
-                     run_if);
+  const int64_t want = (count / 4 + 255) / 256;
+  const unsigned blocks = (unsigned)(want < 1 ? 1 : (want > 4096 ? 4096 : want));
+  if (reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16) return SKETCHNE_E_UNSUPPORTED;
+  hipLaunchKernelGGL(k_copy_if, dim3(blocks), dim3(256), 0, c->stream, count, src, dst, run_if);
   return launch_status();
 }
 
@@ -496,7 +593,7 @@ sketchne_status chol_inv(sketchne_ctx* c, int m, const double* G, double* RinvT,
   size_t shmem = sizeof(double) * (NB * (NB + 1) + (size_t)NB * m);
   hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_inv), hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)shmem);
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), shmem, c->stream, m, G, work, RinvT, c->d_flags, need_more,
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(512), shmem, c->stream, m, G, work, RinvT, c->d_flags, need_more,
                      run_if);
   return launch_status();
 }

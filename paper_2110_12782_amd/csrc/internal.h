@@ -140,8 +140,9 @@ sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int
 // dense_small.hip
 // Cholesky G = R^T R of an SPD m x m FP64 matrix (row-major, ld = m) and the
 // inverse factor; writes RinvT (= R^-T, lower triangular, row-major m x m).
-// need_more (nullable): set to 1 when the factor's 1-norm condition number
-// exceeds kCholQRRepeat (or a shift was needed), else 0.  run_if (nullable):
+// The Gram matrix is first scaled to unit diagonal.  need_more (nullable):
+// set to 1 when the scaled factor's 1-norm condition number exceeds
+// kCholQRRepeat (or a shift was needed), else 0.  run_if (nullable):
 // when it points to 0 the launch does nothing.
 constexpr double kCholQRRepeat = 1e5;
 size_t chol_ws_bytes(int m);
