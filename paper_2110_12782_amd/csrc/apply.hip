@@ -43,7 +43,6 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
   constexpr int APER = AVEC / 512;
   constexpr int BVEC = ABK * NC / 2;                  // double2 per B chunk
   constexpr int BPER = (BVEC + 511) / 512;
-  constexpr int BCV = ABK / 2;                        // double2 per column of a BCOL chunk
   __shared__ double As[ABK][AR + 2];
   __shared__ double Bs[ABK][NC + 2];
   if (g.run_if && *g.run_if == 0) return;
@@ -59,7 +58,9 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
     for (int p = 0; p < APER; ++p) {
       const int e = tid + 512 * p;
       if (!ACOL) {
-        const int r = e / (ABK / 4), q = (e % (ABK / 4)) * 4;
+        // consecutive lanes take consecutive rows, so that the LDS stores
+        // below (one k-row of As per store) are conflict-free
+        const int r = e % AR, q = (e / AR) * 4;
         const int64_t i = i0 + r;
         const int k = k0 + q;
         ra[p] = (i < g.n && k < kend) ? *reinterpret_cast<const float4*>(g.A + i * g.lda + k)
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
       double2 v = make_double2(0.0, 0.0);
       if (e < BVEC) {
         int j, k;
-        if (BCOL) { j = e / BCV; k = k0 + (e % BCV) * 2; }
+        if (BCOL) { j = e % NC; k = k0 + (e / NC) * 2; }
         else { k = k0 + e / (NC / 2); j = (e % (NC / 2)) * 2; }
         // with a triangular B, whole columns j < k0 are zero in this chunk
         if (j < g.N && k < kend && !(TRI && j < k0)) {
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
     for (int p = 0; p < APER; ++p) {
       const int e = tid + 512 * p;
       if (!ACOL) {
-        const int r = e / (ABK / 4), q = (e % (ABK / 4)) * 4;
+        const int r = e % AR, q = (e / AR) * 4;
         As[q + 0][r] = ra[p].x;
         As[q + 1][r] = ra[p].y;
         As[q + 2][r] = ra[p].z;
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
       const int e = tid + 512 * p;
       if (e < BVEC) {
         if (BCOL) {
-          const int j = e / BCV, kk = (e % BCV) * 2;
+          const int j = e % NC, kk = (e / NC) * 2;
           Bs[kk][j] = rb[p].x;
           Bs[kk + 1][j] = rb[p].y;
         } else {
