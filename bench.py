@@ -162,7 +162,7 @@ def main():
             np.max(np.abs(out[7].cpu().numpy() - ref_form[7].cpu().numpy()) / ref_form[7].cpu().numpy()))
 
     if not args.no_learned:
-        forms["learned_warm_start"] = learned_form(lib, g, params(args.precision), ws)
+        forms["learned_warm_start"] = learned_form(lib, g, params(args.precision), ws, forms[args.precision])
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -204,7 +204,7 @@ def main():
     print(json.dumps(line))
 
 
-def learned_form(lib, g, p, ws):
+def learned_form(lib, g, p, ws, plain_form):
     """Learned warm start of Alg. 5: train the network on eight seeded graphs
     (n = 2^16, SBM and Chung-Lu, exponent 2.0-2.5, mean degree 8-32) against
     their own converged eigenvectors (q = 16), then compare the Gaussian and
@@ -215,6 +215,7 @@ def learned_form(lib, g, p, ws):
     from paper_2110_12782_amd.binding import DeviceGraph, MLP, SketchParams
     t0 = time.time()
     sets = []
+    calib = []
     for i in range(8):
         if i % 2 == 0:
             rp, ci = synth.sbm([4096] * 16, 0.0035 + 0.001 * (i % 4), 0.0001, 6000 + i)
@@ -224,6 +225,11 @@ def learned_form(lib, g, p, ws):
         pr = SketchParams(k=p.k, s_eig=p.s_eig, q=16, d=p.d, h=p.h, l=p.l, z=p.z, seed=100 + i)
         Uref, _ = lib.eig(G, pr)
         sets.append((lib.ws_features(G, 0.5, seed=200 + i), Uref.contiguous()))
+        # fallback calibration: the largest Ritz residual of the plain start at q = 2
+        p2 = SketchParams(k=p.k, s_eig=p.s_eig, q=2, d=p.d, h=p.h, l=p.l, z=p.z, seed=300 + i)
+        U2, l2 = lib.eig(G, p2)
+        calib.append(float(lib.ritz_residual(G, 0.5, U2, l2).max()))
+    threshold = 1.1 * max(calib)
     torch.cuda.synchronize()
     t_data = time.time() - t0
     net = MLP(lib, 256, p.k)
@@ -264,13 +270,35 @@ def learned_form(lib, g, p, ws):
     target = rows["q2"]["plain_sin_theta"]
     reach = [q for q in (0, 1, 2) if rows[f"q{q}"]["learned_sin_theta"] <= target]
     saved = 2 - min(reach) if reach else 0
+    # whole step with the learned start at the smallest q that reaches the
+    # plain q = 2 error, the fallback armed with the calibrated threshold
+    qw = min(reach) if reach else 2
+    pw = SketchParams(k=p.k, s_eig=p.s_eig, q=2, d=p.d, h=p.h, l=p.l, z=p.z, seed=p.seed, precision=p.precision,
+                      split_r=p.split_r)
+
+    def lstep():
+        U, lam, fb = lib.eig_learned(g, pw, net, qw, threshold, ws=None)
+        Yt, Z, S, O = lib.sketch(g, pw, U, lam, ws=ws)
+        lib.embed(g.n, pw, Yt, Z, O, ws=ws)
+        return fb
+
+    lstep()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    fbs = [lstep() for _ in range(3)]
+    torch.cuda.synchronize()
+    lstep_ms = (time.perf_counter() - t) / 3 * 1e3
     log(f"learned form: data {t_data:.1f}s, {steps} training steps in {t_train:.2f}s, loss {losses[:16].mean():.3f} -> "
         f"{losses[-16:].mean():.3f}; " + "; ".join(
             f"{k}: plain {v['plain_sin_theta']:.4f} ({v['plain_eig_ms']:.1f} ms) learned {v['learned_sin_theta']:.4f} "
-            f"({v['learned_eig_ms']:.1f} ms)" for k, v in rows.items()) + f"; iterations saved {saved}")
+            f"({v['learned_eig_ms']:.1f} ms)" for k, v in rows.items()) + f"; iterations saved {saved}; "
+        f"whole step with the learned start at q={qw}: {lstep_ms:.2f} ms (plain q=2: {plain_form['ms_per_step']:.2f} ms), "
+        f"fallback threshold {threshold:.3f}, fallback used {sum(fbs)}/3")
     return {"training": {"graphs": 8, "n": 1 << 16, "steps": steps, "seconds": t_train,
                          "loss_first16": float(losses[:16].mean()), "loss_last16": float(losses[-16:].mean())},
-            "held_out": "the bench graph (reference: q = 16)", "by_q": rows, "iterations_saved": saved}
+            "held_out": "the bench graph (reference: q = 16)", "by_q": rows, "iterations_saved": saved,
+            "step": {"q_warm": qw, "ms_per_step": lstep_ms, "plain_q2_ms_per_step": plain_form["ms_per_step"],
+                     "fallback_threshold": threshold, "fallback_used": int(sum(fbs)), "steps": 3}}
 
 
 def sin_theta(A, B) -> float:
