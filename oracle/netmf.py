@@ -109,3 +109,25 @@ def core_matrix(lam, Kmat, T: int) -> np.ndarray:
         S += Kp
         Kp = Kp @ Kmat
     return np.diag(lam) @ S
+
+
+def eq11_kmat(U, lam, deg, alpha: float, block: int = 1 << 20):
+    """K = U^T D^(-1+2a) U Lambda of Eq. (11), summed over row blocks of U
+    (the same sum as in eq11_factors, for n too large to widen U at once)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    n, k = U.shape
+    d2 = deg_power(deg, -1.0 + 2.0 * alpha)
+    G = np.zeros((k, k))
+    for r0 in range(0, n, block):
+        Ub = np.asarray(U[r0:r0 + block], dtype=np.float64)
+        G += (Ub.T * d2[r0:r0 + block]) @ Ub
+    return G @ np.diag(lam)
+
+
+def eq11_rows(U_rows, deg_rows, lam, Kmat, vol: float, alpha: float, T: int, b: float):
+    """Rows of L' and the matching columns of R' (Eq. 11) for a subset of
+    vertices: L'(i,:) = vol/(bT) d_i^(-1+a) U_i and R'(:,i) = C d_i^(-1+a) U_i^T."""
+    U_rows = np.asarray(U_rows, dtype=np.float64)
+    d1 = deg_power(deg_rows, -1.0 + alpha)
+    C = core_matrix(lam, Kmat, T)
+    return vol / (b * T) * (d1[:, None] * U_rows), C @ (U_rows.T * d1)

@@ -83,3 +83,18 @@ def reduced_matrix_from_sampled_O(Q, Z, rows, signs):
     B = np.asarray(O.T @ Q)
     Tm = np.linalg.lstsq(B, Z, rcond=None)[0]
     return np.linalg.lstsq(B, Tm.T, rcond=None)[0].T
+
+
+def sketch_y_rows(L_rows, R_cols_p, n: int, rows, signs):
+    """Eq. (4) for some rows of Y: f(L'(I,:) R'(:,p)) S(p,:), with R'(:,p) given
+    for p = unique_rows(rows) in that (sorted) order."""
+    p = unique_rows(rows)
+    S = sparse_sign_matrix(n, rows, signs)[p, :].toarray()
+    return trunc_log(np.asarray(L_rows) @ np.asarray(R_cols_p)) @ S
+
+
+def sketch_z_parts(L_rows_p, R_cols_p, n: int, rows, signs):
+    """Alg. 4 line 7 from the rows of L' and columns of R' at p = unique_rows(rows)."""
+    p = unique_rows(rows)
+    O = sparse_sign_matrix(n, rows, signs)[p, :].toarray()
+    return O.T @ trunc_log(np.asarray(L_rows_p) @ np.asarray(R_cols_p)) @ O

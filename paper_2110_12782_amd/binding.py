@@ -426,6 +426,18 @@ class DeviceGraph:
         cols = np.ascontiguousarray(colidx, dtype=np.int32)
         self.colidx = torch.from_numpy(cols if len(cols) else np.zeros(1, np.int32)).cuda()
 
+    @classmethod
+    def from_device(cls, rowptr, colidx) -> "DeviceGraph":
+        """Wrap CSR arrays already on cuda:0 (rowptr int64, colidx int32)."""
+        import torch
+        assert rowptr.dtype == torch.int64 and colidx.dtype == torch.int32 and rowptr.is_cuda and colidx.is_cuda
+        g = cls.__new__(cls)
+        g.n = rowptr.numel() - 1
+        g.nnz = int(rowptr[-1])
+        g.rowptr = rowptr.contiguous()
+        g.colidx = colidx.contiguous() if colidx.numel() else torch.zeros(1, dtype=torch.int32, device="cuda")
+        return g
+
     def c(self) -> Graph:
         return Graph(self.n, self.nnz, self.rowptr.data_ptr(), self.colidx.data_ptr())
 

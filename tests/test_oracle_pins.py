@@ -312,3 +312,30 @@ def test_principal_angle_metric():
         b = np.cos(th) * e[:, 0] + np.sin(th) * e[:, 1]
         s = metrics.sin_principal_angles(e[:, [0, 5]], np.stack([b, e[:, 5]], 1))
         assert np.allclose(np.sort(s), np.sort([np.sin(th), 0.0]), atol=1e-12)
+
+
+def test_eq11_row_subset_forms_match_full_factors():
+    """The row-subset forms used at large n agree with the full factors."""
+    rowptr, colidx = synth.chung_lu(3000, 2.2, 8, 1, 55)
+    A = netmf.adjacency(rowptr, colidx)
+    deg = netmf.degrees(A)
+    rng = np.random.default_rng(2)
+    U = np.linalg.qr(rng.standard_normal((3000, 12)))[0]
+    lam = np.sort(rng.uniform(-1, 1, 12))[::-1]
+    for alpha in (0.5, 0.4):
+        Lp, Rp, K = netmf.eq11_factors(U, lam, deg, netmf.volume(A), alpha, 10, 1.0)
+        K2 = netmf.eq11_kmat(U, lam, deg, alpha, block=700)
+        assert np.allclose(K2, K, rtol=1e-12, atol=1e-14)
+        idx = np.array([0, 5, 17, 2999])
+        Lr, Rc = netmf.eq11_rows(U[idx], deg[idx], lam, K2, netmf.volume(A), alpha, 10, 1.0)
+        assert np.allclose(Lr, Lp[idx], rtol=1e-12) and np.allclose(Rc, Rp[:, idx], rtol=1e-11, atol=1e-14)
+    rows, signs = synth.sparse_sign(3000, 16, 4, 9)
+    p = sk.unique_rows(rows)
+    Lp, Rp, K = netmf.eq11_factors(U, lam, deg, netmf.volume(A), 0.5, 10, 1.0)
+    sub = np.array([1, 2, 100, 2500])
+    Y1 = sk.sketch_y_sampled(Lp, Rp, rows, signs, row_subset=sub)
+    Y2 = sk.sketch_y_rows(Lp[sub], Rp[:, p], 3000, rows, signs)
+    assert np.allclose(Y1, Y2, rtol=1e-13, atol=1e-15)
+    Z1 = sk.sketch_z_sampled(Lp, Rp, rows, signs)
+    Z2 = sk.sketch_z_parts(Lp[p], Rp[:, p], 3000, rows, signs)
+    assert np.allclose(Z1, Z2, rtol=1e-13, atol=1e-15)
