@@ -97,6 +97,8 @@ sketchne_status apply_rinv(sketchne_ctx* c, int64_t n, int m, const float* src, 
   ApplyDesc d;
   d.n = n; d.K = m; d.N = m;
   d.A = src; d.lda = ld; d.acol = transposed;
+  // R^-1(k, j) = RinvT[j][k]: column-major reads of B (measured faster here
+  // than transposing R^-T and reading rows)
   d.B = RinvT; d.ldb = m; d.bcol = true; d.upper = true;
   d.C = dst; d.ldc = ld; d.ccol = transposed;
   d.run_if = run_if;

@@ -200,7 +200,7 @@ bool apply_tall_supported(const ApplyDesc& d) {
   if (d.N < 1 || d.N > 288 || d.K < 1 || d.K > 288) return false;
   if (d.N % 2 || d.K % 4 || d.lda % 4 || d.ldb % 2) return false;
   if (d.ccol && !d.acol) return false;
-  if (d.upper && (!d.bcol || d.N != d.K)) return false;
+  if (d.upper && d.N != d.K) return false;
   if (reinterpret_cast<uintptr_t>(d.A) % 16 || reinterpret_cast<uintptr_t>(d.B) % 16) return false;
   return true;
 }
@@ -214,10 +214,14 @@ sketchne_status apply_tall(sketchne_ctx* c, const ApplyDesc& d) {
   const int nbh = d.N <= 128 ? 4 : (d.N <= 256 ? 8 : 9);
 #define SKNE_APPLY(NBH)                                                                                       \
   do {                                                                                                        \
-    if (d.upper) {                                                                                            \
+    if (d.upper && d.bcol) {                                                                                  \
       if (d.ccol) hipLaunchKernelGGL((k_apply_tall<NBH, true, true, true, true>), grid, blk, 0, c->stream, g); \
       else if (d.acol) hipLaunchKernelGGL((k_apply_tall<NBH, true, true, false, true>), grid, blk, 0, c->stream, g); \
       else hipLaunchKernelGGL((k_apply_tall<NBH, false, true, false, true>), grid, blk, 0, c->stream, g);      \
+    } else if (d.upper) {                                                                                     \
+      if (d.ccol) hipLaunchKernelGGL((k_apply_tall<NBH, true, false, true, true>), grid, blk, 0, c->stream, g); \
+      else if (d.acol) hipLaunchKernelGGL((k_apply_tall<NBH, true, false, false, true>), grid, blk, 0, c->stream, g); \
+      else hipLaunchKernelGGL((k_apply_tall<NBH, false, false, false, true>), grid, blk, 0, c->stream, g);     \
     } else if (d.bcol) {                                                                                      \
       if (d.ccol) hipLaunchKernelGGL((k_apply_tall<NBH, true, true, true, false>), grid, blk, 0, c->stream, g); \
       else if (d.acol) hipLaunchKernelGGL((k_apply_tall<NBH, true, true, false, false>), grid, blk, 0, c->stream, g); \

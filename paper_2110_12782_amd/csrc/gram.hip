@@ -4,14 +4,14 @@
 //
 // computed on the upper 16 x 16 blocks only and mirrored, which is exact for
 // the symmetric products of the path (Gram matrices B^T B, Q^T (X Q) and
-// U^T D U).  Each workgroup owns a contiguous range of rows: it
-// (512 threads) streams them through LDS in chunks of 32 rows (double
-// buffered, next chunk
+// U^T D U).  Each workgroup owns a contiguous range of rows: it (512 threads)
+// streams them through LDS in chunks of 32 rows (double buffered, next chunk
 // prefetched through registers) and keeps the accumulators of its share of
-// the upper blocks of the m x m result in registers.  The blocks are split
-// into two groups handled by two workgroups on the same XCD, so the rows are
-// read from memory once and from the XCD's L2 the second time.  Per-workgroup
-// partial sums are added in a fixed order by a second kernel.
+// the upper blocks of the m x m result in registers, grouped in 2 x 2
+// super-tiles.  The super-tiles are split into two groups handled by two
+// workgroups on the same XCD, so the rows are read from memory once and from
+// the XCD's L2 the second time.  Per-workgroup partial sums are added in a
+// fixed order by a second kernel.
 #include "internal.h"
 
 namespace skne {
@@ -45,12 +45,18 @@ __device__ __forceinline__ void blk_coords(int b, int nbk, int& I, int& J) {
   J = r + b;
 }
 
-// ROWMAJ: X and Y rows are contiguous (xc == 1); else columns are (xr == 1).
-template <bool TWO, bool ROWMAJ, int PW>
-__global__ __launch_bounds__(GR_THREADS) void k_gram_tall(GramArgs g) {
+// The upper triangle of 16 x 16 blocks is covered by 2 x 2 "super-tiles"
+// (blocks 2pi, 2pi+1 x 2pj, 2pj+1 with pi <= pj; the one lower block of a
+// diagonal super-tile is computed and dropped).  A wavefront takes up to
+// GS_SLOTS super-tiles of its group, so one row step reads two A and two B
+// fragments for four MFMAs (register blocking; eight fragments for four
+// unrelated blocks took 35% longer).  ROWMAJ: X and Y rows are contiguous
+// (xc == 1); else columns are (xr == 1).
+constexpr int GS_SLOTS = 3;
+
+template <bool TWO, bool ROWMAJ>
+__global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
   if (g.run_if && *g.run_if == 0) return;
-  // XCD-aware decode: the two block groups of a row range get linear ids
-  // L and L + 8, i.e. the same XCD, dispatched back to back
   const int L = blockIdx.x;
   const int q = L >> 3;
   const int grp = q % GR_GROUPS;
@@ -59,7 +65,7 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_tall(GramArgs g) {
   extern __shared__ float lds[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int S = g.stride;
-  const int CH = GR_CHUNK * S;               // floats per matrix chunk
+  const int CH = GR_CHUNK * S;
   float* bufX[2] = {lds, lds + (TWO ? 2 : 1) * CH};
   float* bufY[2] = {TWO ? lds + CH : lds, TWO ? lds + 3 * CH : lds + CH};
   __shared__ double wsh[2][GR_CHUNK];
@@ -67,25 +73,28 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_tall(GramArgs g) {
   const int64_t r0 = (int64_t)range * g.rows_per_wg;
   const int64_t r1 = min(g.n, r0 + g.rows_per_wg);
 
-  // this wavefront's blocks: slot t is block blk0 + wave + 16 t of the group;
-  // slots past the group compute a copy of its first block and are not stored
+  // super-tiles of this wavefront: st0 + wave + GR_WAVES t (past the group:
+  // a copy of its first super-tile, not stored)
+  const int npair = (g.nbk + 1) / 2;
+  const int nst = npair * (npair + 1) / 2;
   const int uw = __builtin_amdgcn_readfirstlane(wave);
-  const int blk0 = grp * g.gsize;
-  const int blk1 = min(g.nblk, blk0 + g.gsize);
-  int bI[PW], bJ[PW];
+  const int st0 = grp * g.gsize;
+  const int st1 = min(nst, st0 + g.gsize);
+  int pI[GS_SLOTS], pJ[GS_SLOTS];
 #pragma unroll
-  for (int t = 0; t < PW; ++t) {
-    int b = blk0 + uw + GR_WAVES * t;
-    if (b >= blk1) b = blk0;
-    blk_coords(b, g.nbk, bI[t], bJ[t]);
+  for (int t = 0; t < GS_SLOTS; ++t) {
+    int st = st0 + uw + GR_WAVES * t;
+    if (st >= st1) st = st0;
+    blk_coords(st, npair, pI[t], pJ[t]);
   }
-  doublex4 acc[PW];
+  doublex4 acc[GS_SLOTS][4];
 #pragma unroll
-  for (int t = 0; t < PW; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < GS_SLOTS; ++t)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[t][u] = doublex4{0.0, 0.0, 0.0, 0.0};
 
-  // chunk loader: element (rr, i) of the chunk starting at row c0
   const int cols4 = (g.m + 3) / 4;
-  constexpr int MAXV = (GR_CHUNK * GR_MAXB * 16 / 4 + GR_THREADS - 1) / GR_THREADS;  // float4 / thread / matrix
+  constexpr int MAXV = (GR_CHUNK * GR_MAXB * 16 / 4 + GR_THREADS - 1) / GR_THREADS;
   float4 px[MAXV], py[MAXV];
   double pw = 1.0;
   auto fetch = [&](int64_t c0) {
@@ -93,7 +102,7 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_tall(GramArgs g) {
     for (int u = 0; u < MAXV; ++u) {
       int v = tid + GR_THREADS * u;
       float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
-      if (ROWMAJ) {  // m % 4 == 0: whole float4 per row segment
+      if (ROWMAJ) {
         int rr = v / cols4, c4 = v - rr * cols4;
         int64_t r = c0 + rr;
         if (rr < GR_CHUNK && r < r1) {
@@ -101,9 +110,8 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_tall(GramArgs g) {
           if (TWO) b = *reinterpret_cast<const float4*>(g.Y + r * g.yr + 4 * c4);
         }
       } else {
-        // column-contiguous: 4 consecutive rows of one column
-        int i = v / (GR_CHUNK / 4), q = v - i * (GR_CHUNK / 4);
-        int64_t r = c0 + 4 * q;
+        int i = v / (GR_CHUNK / 4), qq = v - i * (GR_CHUNK / 4);
+        int64_t r = c0 + 4 * qq;
         if (i < g.m) {
           const float* px0 = g.X + (int64_t)i * g.xc + r;
           a.x = r < r1 ? px0[0] : 0.f;
@@ -137,17 +145,17 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_tall(GramArgs g) {
           if (TWO) *reinterpret_cast<float4*>(dy + rr * S + 4 * c4) = py[u];
         }
       } else {
-        int i = v / (GR_CHUNK / 4), q = v - i * (GR_CHUNK / 4);
+        int i = v / (GR_CHUNK / 4), qq = v - i * (GR_CHUNK / 4);
         if (i < g.m) {
-          dx[(4 * q) * S + i] = px[u].x;
-          dx[(4 * q + 1) * S + i] = px[u].y;
-          dx[(4 * q + 2) * S + i] = px[u].z;
-          dx[(4 * q + 3) * S + i] = px[u].w;
+          dx[(4 * qq) * S + i] = px[u].x;
+          dx[(4 * qq + 1) * S + i] = px[u].y;
+          dx[(4 * qq + 2) * S + i] = px[u].z;
+          dx[(4 * qq + 3) * S + i] = px[u].w;
           if (TWO) {
-            dy[(4 * q) * S + i] = py[u].x;
-            dy[(4 * q + 1) * S + i] = py[u].y;
-            dy[(4 * q + 2) * S + i] = py[u].z;
-            dy[(4 * q + 3) * S + i] = py[u].w;
+            dy[(4 * qq) * S + i] = py[u].x;
+            dy[(4 * qq + 1) * S + i] = py[u].y;
+            dy[(4 * qq + 2) * S + i] = py[u].z;
+            dy[(4 * qq + 3) * S + i] = py[u].w;
           }
         }
       }
@@ -155,7 +163,6 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_tall(GramArgs g) {
     if (tid < GR_CHUNK) wsh[buf][tid] = pw;
   };
 
-  // zero the padding columns of both buffers once (never written by stash)
   for (int idx = tid; idx < 2 * (TWO ? 2 : 1) * CH; idx += GR_THREADS) {
     int col = (idx % CH) % S;
     if (col >= g.m) lds[idx] = 0.f;
@@ -171,15 +178,22 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_tall(GramArgs g) {
     if (more) fetch(c0 + GR_CHUNK);
     const float* xs = bufX[buf];
     const float* ys = bufY[buf];
-#pragma unroll 1
-    for (int s = 0; s < GR_CHUNK / 4; ++s) {
-      const int rr = 4 * s + (lane >> 4);
+#pragma unroll 2
+    for (int st = 0; st < GR_CHUNK / 4; ++st) {
+      const int rr = 4 * st + (lane >> 4);
       const double wr = g.w ? wsh[buf][rr] : 1.0;
+      const float* xr = xs + rr * S + (lane & 15);
+      const float* yr = ys + rr * S + (lane & 15);
 #pragma unroll
-      for (int t = 0; t < PW; ++t) {
-        double a = (double)xs[rr * S + bI[t] * 16 + (lane & 15)] * wr;
-        double b = (double)ys[rr * S + bJ[t] * 16 + (lane & 15)];
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+      for (int t = 0; t < GS_SLOTS; ++t) {
+        const double a0 = (double)xr[32 * pI[t]] * wr;
+        const double a1 = (double)xr[32 * pI[t] + 16] * wr;
+        const double b0 = (double)yr[32 * pJ[t]];
+        const double b1 = (double)yr[32 * pJ[t] + 16];
+        acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[t][0], 0, 0, 0);
+        acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[t][1], 0, 0, 0);
+        acc[t][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[t][2], 0, 0, 0);
+        acc[t][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[t][3], 0, 0, 0);
       }
     }
     if (more) stash(buf ^ 1);
@@ -188,14 +202,19 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_tall(GramArgs g) {
   }
   double* part = g.partial + (int64_t)range * g.nblk * 256;
 #pragma unroll
-  for (int t = 0; t < PW; ++t) {
-    const int b = blk0 + uw + GR_WAVES * t;
-    if (b < blk1) {
+  for (int t = 0; t < GS_SLOTS; ++t) {
+    const int st = st0 + uw + GR_WAVES * t;
+    if (st >= st1) continue;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int I = 2 * pI[t] + (u >> 1), J = 2 * pJ[t] + (u & 1);
+      if (I > J || J >= g.nbk) continue;
+      const int b = I * g.nbk - I * (I - 1) / 2 + (J - I);  // index of (I, J) in the upper enumeration
       double* pb = part + (int64_t)b * 256 + lane * 4;
-      pb[0] = acc[t][0];
-      pb[1] = acc[t][1];
-      pb[2] = acc[t][2];
-      pb[3] = acc[t][3];
+      pb[0] = acc[t][u][0];
+      pb[1] = acc[t][u][1];
+      pb[2] = acc[t][u][2];
+      pb[3] = acc[t][u][3];
     }
   }
 }
@@ -248,9 +267,10 @@ sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int
   g.m = m;
   g.nbk = (m + 15) / 16;
   g.nblk = g.nbk * (g.nbk + 1) / 2;
-  // LDS row length: the 16-aligned width, moved off multiples of 32 floats so
-  // the 4 rows read by one MFMA fragment fall in distinct banks
-  g.stride = (m + 15) / 16 * 16;
+  // LDS row length: room for whole super-tiles (32 columns each), moved off
+  // multiples of 32 floats so the 4 rows read by one MFMA fragment fall in
+  // distinct banks
+  g.stride = (m + 31) / 32 * 32;
   if (g.stride % 64 == 0 || g.stride % 64 == 32) g.stride += 16;
   g.X = X; g.xr = xr; g.xc = xc;
   g.Y = Y ? Y : X; g.yr = Y ? yr : xr; g.yc = Y ? yc : xc;
@@ -259,29 +279,24 @@ sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int
   int64_t rpw = (n + nr - 1) / nr;
   g.rows_per_wg = (rpw + GR_CHUNK - 1) / GR_CHUNK * GR_CHUNK;
   g.nranges = nr;
-  g.gsize = (g.nblk + GR_GROUPS - 1) / GR_GROUPS;
+  const int npair = (g.nbk + 1) / 2;
+  const int nst = npair * (npair + 1) / 2;
+  g.gsize = (nst + GR_GROUPS - 1) / GR_GROUPS;  // super-tiles per group
+  if (g.gsize > GR_WAVES * GS_SLOTS) return SKETCHNE_E_UNSUPPORTED;
   g.partial = partial;
   g.run_if = run_if;
   const bool two = Y != nullptr;
   const size_t shmem = sizeof(float) * (size_t)2 * (two ? 2 : 1) * GR_CHUNK * g.stride;
-  const int pw = (g.gsize + GR_WAVES - 1) / GR_WAVES;
   const unsigned blocks = (unsigned)((nr + 7) / 8 * 8 * GR_GROUPS);
   ProfScope ps(c, SKETCHNE_PROF_GEMM64);
-#define SKNE_GRAM(T, R, P)                                                                                 \
+#define SKNE_GRAM(T, R)                                                                                    \
   do {                                                                                                     \
-    hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_tall<T, R, P>),                               \
+    hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_st<T, R>),                                    \
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);                           \
-    hipLaunchKernelGGL((k_gram_tall<T, R, P>), dim3(blocks), dim3(GR_THREADS), shmem, c->stream, g);       \
+    hipLaunchKernelGGL((k_gram_st<T, R>), dim3(blocks), dim3(GR_THREADS), shmem, c->stream, g);            \
   } while (0)
-#define SKNE_GRAM_PW(T, R)                 \
-  do {                                     \
-    if (pw <= 4) SKNE_GRAM(T, R, 4);       \
-    else if (pw <= 8) SKNE_GRAM(T, R, 8);  \
-    else SKNE_GRAM(T, R, 11);              \
-  } while (0)
-  if (two) { if (rowmaj) SKNE_GRAM_PW(true, true); else SKNE_GRAM_PW(true, false); }
-  else { if (rowmaj) SKNE_GRAM_PW(false, true); else SKNE_GRAM_PW(false, false); }
-#undef SKNE_GRAM_PW
+  if (two) { if (rowmaj) SKNE_GRAM(true, true); else SKNE_GRAM(true, false); }
+  else { if (rowmaj) SKNE_GRAM(false, true); else SKNE_GRAM(false, false); }
 #undef SKNE_GRAM
   hipLaunchKernelGGL(k_gram_reduce, dim3((g.nblk * 256 + 255) / 256), dim3(256), 0, c->stream, m, g.nbk, g.nblk, nr,
                      partial, G, run_if);

@@ -117,7 +117,7 @@ sketchne_status gemm64(sketchne_ctx* c, const GemmDesc& g, double* partial, size
 // apply.hip : C = A B, A tall FP32 (n x K), B small FP64 (K x N), C FP32;
 // N, K <= 288.  acol: A(i,k) = A[k*lda + i] (else A[i*lda + k]); bcol:
 // B(k,j) = B[j*ldb + k] (else B[k*ldb + j]); ccol: C(i,j) = C[j*ldc + i];
-// upper: B is upper triangular (needs bcol).  apply_tall_supported() says
+// upper: B is upper triangular (N == K).  apply_tall_supported() says
 // whether the fast kernel takes the shape.
 struct ApplyDesc {
   int64_t n = 0; int K = 0, N = 0;
