@@ -188,7 +188,10 @@ EigWs carve_eig(Arena& ar, const sketchne_params* p, int64_t n, int64_t nnz) {
 
 // ------------------------------------------------------------- sketch
 struct SketchGeo {
-  int prec, r, KS, ntS, ntO, FB;
+  bool ok;       // k and r fit a compiled kernel
+  int prec, r;
+  int KSM, KSS;  // k-step sections (A: KSM + 2*KSS, B: KSM + KSS)
+  int ntS, ntO, FB;
   int64_t nvt_pad, nvtO_pad, zl;
 };
 
@@ -196,8 +199,8 @@ SketchGeo sketch_geo(const sketchne_params* p, int64_t n) {
   SketchGeo g;
   g.prec = p->precision;
   g.r = g.prec == SKETCHNE_FP32 ? 0 : p->split_r;
-  const int kstep = sketch_kstep(g.prec);
-  g.KS = sketch_ks_supported(g.prec, (p->k + 2 * g.r + kstep - 1) / kstep);
+  g.KSM = g.KSS = 0;
+  g.ok = sketch_sections(g.prec, p->k, g.r, &g.KSM, &g.KSS);
   g.FB = sketch_frag_bytes(g.prec);
   g.ntS = (p->h + 3) / 4;
   g.ntO = (p->l + 3) / 4;
@@ -246,12 +249,12 @@ SketchWs carve_sketch(Arena& ar, const sketchne_params* p, int64_t n) {
   w.k_partial = ar.take<double>(w.k_cap / sizeof(double) + 1);
   w.Gsel = ar.take<double>((size_t)ntmax * 32 * k);
   w.RtT = ar.take<double>((size_t)ntmax * 32 * k);
-  w.ApS = ar.take<char>((size_t)g.ntS * g.KS * 64 * g.FB);
-  w.ApO = ar.take<char>((size_t)g.ntO * g.KS * 64 * g.FB);
+  w.ApS = ar.take<char>((size_t)g.ntS * (g.KSM + 2 * g.KSS) * 64 * g.FB);
+  w.ApO = ar.take<char>((size_t)g.ntO * (g.KSM + 2 * g.KSS) * 64 * g.FB);
   w.sgnS = ar.take<float>((size_t)g.ntS * 32);
   w.sgnO = ar.take<float>((size_t)g.ntO * 32);
   int64_t nvtmax = g.nvt_pad > g.nvtO_pad ? g.nvt_pad : g.nvtO_pad;
-  w.Bp = ar.take<char>((size_t)nvtmax * g.KS * 64 * g.FB);
+  w.Bp = ar.take<char>((size_t)nvtmax * (g.KSM + g.KSS) * 64 * g.FB);
   w.T1t = ar.take<float>((size_t)p->l * g.zl);
   return w;
 }
@@ -492,7 +495,7 @@ sketchne_status sketchne_sketch(sketchne_ctx* c, const sketchne_graph* A, const 
   if (p->z > 8) return SKETCHNE_E_UNSUPPORTED;  // group of one lane's accumulators
   if (p->k % 4) return SKETCHNE_E_UNSUPPORTED;  // float4 rows of U
   SketchGeo g = sketch_geo(p, A->n);
-  if (g.KS == 0) return SKETCHNE_E_UNSUPPORTED;
+  if (!g.ok) return SKETCHNE_E_UNSUPPORTED;
   if (g.zl >= ((int64_t)1 << 31)) return SKETCHNE_E_UNSUPPORTED;
   SK_TRY(check_ws(ws, ws_bytes, op_bytes(p, A->n, A->nnz, SKETCHNE_OP_SKETCH)));
   const int64_t n = A->n;
@@ -540,19 +543,20 @@ sketchne_status sketchne_sketch(sketchne_ctx* c, const sketchne_graph* A, const 
     gd.B = w.Cc; gd.tb = Ty::F64; gd.sbk = 1; gd.sbj = k;
     gd.C = w.RtT; gd.tc = Ty::F64; gd.sci = k; gd.scj = 1;
     SK_TRY(gemm64(c, gd, w.k_partial, w.k_cap));
-    SK_TRY(pack_A(c, g.prec, ntiles, g.KS, k, g.r, w.RtT, Ap));
+    SK_TRY(pack_A(c, g.prec, ntiles, g.KSM, g.KSS, k, g.r, w.RtT, Ap));
     return pack_signs(c, ntiles, groups, p->z, T->signs, sgn);
   };
 
   // Alg. 4 line 4: Y = f(L' R'(:, p)) S(p, :)
   SK_TRY(build_A(S, g.ntS, p->h, w.ApS, w.sgnS));
-  SK_TRY(pack_B(c, g.prec, n, n, g.nvt_pad, g.KS, k, g.r, nullptr, U, k, w.d1, w.Bp));
-  SK_TRY(fused_sketch(c, SKETCHNE_PROF_SKETCH_Y, g.prec, n, p->h, g.ntS, g.KS, w.Bp, w.ApS, w.sgnS, Yt, n,
+  SK_TRY(pack_B(c, g.prec, n, n, g.nvt_pad, g.KSM, g.KSS, k, g.r, nullptr, U, k, w.d1, w.Bp));
+  SK_TRY(fused_sketch(c, SKETCHNE_PROF_SKETCH_Y, g.prec, n, p->h, g.ntS, g.KSM, g.KSS, w.Bp, w.ApS, w.sgnS, Yt, n,
                       ln2 * inv_sqrt_z));
   // Alg. 4 line 7: Z = O(p,:)^T f(L'(p,:) R'(:, p)) O(p,:)
   SK_TRY(build_A(O, g.ntO, p->l, w.ApO, w.sgnO));
-  SK_TRY(pack_B(c, g.prec, n, g.zl, g.nvtO_pad, g.KS, k, g.r, O->rows, U, k, w.d1, w.Bp));
-  SK_TRY(fused_sketch(c, SKETCHNE_PROF_SKETCH_Z, g.prec, g.zl, p->l, g.ntO, g.KS, w.Bp, w.ApO, w.sgnO, w.T1t, g.zl,
+  SK_TRY(pack_B(c, g.prec, n, g.zl, g.nvtO_pad, g.KSM, g.KSS, k, g.r, O->rows, U, k, w.d1, w.Bp));
+  SK_TRY(fused_sketch(c, SKETCHNE_PROF_SKETCH_Z, g.prec, g.zl, p->l, g.ntO, g.KSM, g.KSS, w.Bp, w.ApO, w.sgnO, w.T1t,
+                      g.zl,
                       ln2 * inv_sqrt_z));
   SK_TRY(z_reduce(c, p->l, p->z, O->signs, w.T1t, g.zl, inv_sqrt_z, Z));
   return SKETCHNE_OK;

@@ -7,7 +7,7 @@ namespace skne {
 int sketch_kstep(int prec);
 int sketch_frag_bytes(int prec);
 int sketch_vt(int prec);
-int sketch_ks_supported(int prec, int ks_needed);
+bool sketch_sections(int prec, int k, int r, int* KSM, int* KSS);
 
 sketchne_status degree_powers(sketchne_ctx* c, int64_t n, const int64_t* rowptr, double alpha, double* d1,
                               double* d2);
@@ -16,13 +16,14 @@ sketchne_status scale_rows(sketchne_ctx* c, int rows, int cols, const double* M,
 sketchne_status identity(sketchne_ctx* c, int m, double* M);
 sketchne_status gather_expanded(sketchne_ctx* c, int64_t n, int ntiles, int groups, int z, const int32_t* rows,
                                 const float* U, int64_t ldu, int k, const double* d1, double scale, double* Gsel);
-sketchne_status pack_A(sketchne_ctx* c, int prec, int ntiles, int KS, int k, int r, const double* RtT, void* out);
-sketchne_status pack_B(sketchne_ctx* c, int prec, int64_t n, int64_t nrows, int64_t nvt, int KS, int k, int r,
-                       const int32_t* gather, const float* U, int64_t ldu, const double* d1, void* out);
+sketchne_status pack_A(sketchne_ctx* c, int prec, int ntiles, int KSM, int KSS, int k, int r, const double* RtT,
+                       void* out);
+sketchne_status pack_B(sketchne_ctx* c, int prec, int64_t n, int64_t nrows, int64_t nvt, int KSM, int KSS, int k,
+                       int r, const int32_t* gather, const float* U, int64_t ldu, const double* d1, void* out);
 sketchne_status pack_signs(sketchne_ctx* c, int ntiles, int groups, int z, const int8_t* signs, float* sgn);
-sketchne_status fused_sketch(sketchne_ctx* c, int cls, int prec, int64_t nrows, int groups, int ntiles, int KS,
-                             const void* Bpack, const void* Apack, const float* sgn, float* out, int64_t ld_out,
-                             float out_scale);
+sketchne_status fused_sketch(sketchne_ctx* c, int cls, int prec, int64_t nrows, int groups, int ntiles, int KSM,
+                             int KSS, const void* Bpack, const void* Apack, const float* sgn, float* out,
+                             int64_t ld_out, float out_scale);
 sketchne_status z_reduce(sketchne_ctx* c, int l, int z, const int8_t* signs, const float* T1t, int64_t ld_t1,
                          float inv_sqrt_z, float* Z);
 sketchne_status ot_q(sketchne_ctx* c, int l, int z, int hcols, const int32_t* rows, const int8_t* signs,

@@ -25,10 +25,14 @@
 //
 // Precision forms: FP32 operands (v_mfma_f32_32x32x2_f32), or BF16 / FP16
 // operands (v_mfma_f32_32x32x16_{bf16,f16}) with FP32 accumulation.  In the
-// BF16/FP16 forms the first split_r components are carried as hi + lo pairs:
-// the summation index is extended to k + 2r with A = [hi | hi(:r) | lo(:r)]
-// and B = [hi | lo(:r) | hi(:r)], so the GEMM computes
-// hi.hi + hi.lo + lo.hi on the dominant components in one pass.
+// BF16/FP16 forms the first split_r components are carried as hi + lo pairs.
+// The summation index runs over three sections, each zero-padded to whole
+// 16-wide k-steps (KSM main steps, KSS split steps):
+//     A (expanded columns of R'):  [hi(0..k) | hi(0..r) | lo(0..r)]
+//     B (rows of L'):              [hi(0..k) | lo(0..r)]
+// and A's third section meets B's first KSS k-steps (hi(0..r)) again, so the
+// GEMM forms hi.hi + hi.lo + lo.hi on the dominant components in one pass
+// while B stores only KSM + KSS fragments per vertex.
 #include "internal.h"
 
 #include "sketch.h"
@@ -69,16 +73,26 @@ __device__ __forceinline__ void split2(double x, int prec, uint16_t& hi, uint16_
   }
 }
 
-// value of extended column kappa of an operand row, as hi/lo selection
-//   A side (R~): [hi(0..k) | hi(0..r) | lo(0..r)]
-//   B side (L'): [hi(0..k) | lo(0..r) | hi(0..r)]
-__device__ __forceinline__ uint16_t ext_val(const double* row, int k, int r, int kappa, int prec, bool a_side) {
-  if (kappa >= k + 2 * r) return 0;
+// value at summation index kappa of an operand row in the sectioned layout
+// (16*KSM main entries, then 16*KSS split entries, then, A side only, 16*KSS
+// more); zero in the padding
+__device__ __forceinline__ uint16_t sect_val(const double* row, int k, int r, int KSM, int KSS, int kappa, int prec,
+                                             bool a_side) {
   int comp;
   bool want_lo;
-  if (kappa < k) { comp = kappa; want_lo = false; }
-  else if (kappa < k + r) { comp = kappa - k; want_lo = !a_side; }
-  else { comp = kappa - k - r; want_lo = a_side; }
+  if (kappa < 16 * KSM) {
+    comp = kappa < k ? kappa : -1;
+    want_lo = false;
+  } else if (kappa < 16 * (KSM + KSS)) {
+    comp = kappa - 16 * KSM;
+    comp = comp < r ? comp : -1;
+    want_lo = !a_side;
+  } else {
+    comp = kappa - 16 * (KSM + KSS);
+    comp = (a_side && comp < r) ? comp : -1;
+    want_lo = true;
+  }
+  if (comp < 0) return 0;
   uint16_t hi, lo;
   split2(row[comp], prec, hi, lo);
   return want_lo ? lo : hi;
@@ -139,12 +153,15 @@ __global__ void k_gather_expanded(int64_t n, int ntiles, int groups, int z, cons
   Gsel[idx] = v;
 }
 
-// A operand (expanded columns of R'), MFMA fragment order.
+// A operand (expanded columns of R'), MFMA fragment order, KS = KSM + 2*KSS
+// k-steps per tile (FP32: KSS = 0, no split).
 //   RtT: (ntiles*32) x k FP64, row rho in tile order.
 template <int PREC>
-__global__ void k_pack_A(int ntiles, int KS, int k, int r, const double* __restrict__ RtT, void* __restrict__ out) {
+__global__ void k_pack_A(int ntiles, int KSM, int KSS, int k, int r, const double* __restrict__ RtT,
+                         void* __restrict__ out) {
   constexpr int KSTEP = (PREC == SKETCHNE_FP32) ? 2 : 16;
   constexpr int E = (PREC == SKETCHNE_FP32) ? 1 : 8;
+  const int KS = KSM + 2 * KSS;
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one (tile, ks, lane)
   int64_t total = (int64_t)ntiles * KS * 64;
   if (idx >= total) return;
@@ -160,7 +177,7 @@ __global__ void k_pack_A(int ntiles, int KS, int k, int r, const double* __restr
   } else {
     uint16_t v[8];
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = ext_val(row, k, r, kb + e, PREC, true);
+    for (int e = 0; e < E; ++e) v[e] = sect_val(row, k, r, KSM, KSS, kb + e, PREC, true);
     uint4 w;
     w.x = v[0] | ((uint32_t)v[1] << 16);
     w.y = v[2] | ((uint32_t)v[3] << 16);
@@ -170,13 +187,15 @@ __global__ void k_pack_A(int ntiles, int KS, int k, int r, const double* __restr
   }
 }
 
-// B operand (rows of L' = D^(-1+a) U, optionally gathered), fragment order.
+// B operand (rows of L' = D^(-1+a) U, optionally gathered), fragment order,
+// KB = KSM + KSS k-steps per vertex tile (FP32: KSS = 0).
 template <int PREC>
-__global__ void k_pack_B(int64_t n, int64_t nrows, int64_t nvt, int KS, int k, int r,
+__global__ void k_pack_B(int64_t n, int64_t nrows, int64_t nvt, int KSM, int KSS, int k, int r,
                          const int32_t* __restrict__ gather, const float* __restrict__ U, int64_t ldu,
                          const double* __restrict__ d1, void* __restrict__ out, uint32_t* __restrict__ flags) {
   constexpr int KSTEP = (PREC == SKETCHNE_FP32) ? 2 : 16;
   constexpr int E = (PREC == SKETCHNE_FP32) ? 1 : 8;
+  const int KS = KSM + KSS;
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t total = nvt * KS * 64;
   if (idx >= total) return;
@@ -195,25 +214,24 @@ __global__ void k_pack_B(int64_t n, int64_t nrows, int64_t nvt, int KS, int k, i
     if (row >= 0 && kb < k) val = (float)(d1[row] * (double)U[row * ldu + kb]);
     static_cast<float*>(out)[idx] = val;
   } else {
-    double rowv[1];
-    (void)rowv;
     uint16_t vv[8];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       vv[e] = 0;
-      if (row >= 0) {
-        int kappa = kb + e;
-        int comp;
-        bool want_lo;
-        if (kappa < k) { comp = kappa; want_lo = false; }
-        else if (kappa < k + r) { comp = kappa - k; want_lo = true; }
-        else if (kappa < k + 2 * r) { comp = kappa - k - r; want_lo = false; }
-        else { comp = -1; want_lo = false; }
-        if (comp >= 0) {
-          uint16_t hi, lo;
-          split2(d1[row] * (double)U[row * ldu + comp], PREC, hi, lo);
-          vv[e] = want_lo ? lo : hi;
-        }
+      const int kappa = kb + e;
+      int comp = -1;
+      bool want_lo = false;
+      if (kappa < 16 * KSM) {
+        comp = kappa < k ? kappa : -1;
+      } else {
+        comp = kappa - 16 * KSM;
+        comp = comp < r ? comp : -1;
+        want_lo = true;
+      }
+      if (row >= 0 && comp >= 0) {
+        uint16_t hi, lo;
+        split2(d1[row] * (double)U[row * ldu + comp], PREC, hi, lo);
+        vv[e] = want_lo ? lo : hi;
       }
     }
     uint4 w;
@@ -373,6 +391,188 @@ __global__ __launch_bounds__(512) void k_fused_sketch(int64_t nrows, int groups,
   }
 }
 
+// Low-precision fused kernel (BF16 / FP16 operands, FP32 accumulation).
+//   Workgroup: 4 wavefronts (one per SIMD; two workgroups share a CU), wave w
+//   owns vertex tiles 2w, 2w+1 of the workgroup's 8 (256 vertices).  The
+//   vertex fragments of the main section stay in registers for the whole
+//   launch; the split-section (lo) fragments sit in the wave's LDS region.
+//   All waves walk the same sequence of expanded-column tiles: tile t+1 is
+//   copied global -> LDS by the LDS-DMA path (no registers) while tile t is
+//   multiplied, and the trunc_log / signed group sums of tile t-1 run on the
+//   vector ALU interleaved with tile t's MFMAs (two accumulator sets, whose
+//   roles alternate, so every LDS buffer index is static).  Signs are read
+//   through scalar loads: the sign of accumulator register e depends only on
+//   the lane half.  Results leave through buffer stores whose descriptor
+//   covers exactly the tile's output rows, so rows past `groups` and
+//   vertices past `nrows` are dropped by the hardware range check.
+//   out[g * ld_out + v] = out_scale * sum_t s_gt log2(max(x_{v, (g,t)}, 1))
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(const float* base, uint32_t bytes) {
+  // wave-uniform by construction; readfirstlane keeps the descriptor scalar
+  const uint64_t a = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  void* ptr = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+  // dword 3 = 0x00020000: 32-bit data format, the raw-buffer setting of gfx9
+  return __builtin_amdgcn_make_buffer_rsrc(ptr, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
+
+template <int PREC, int KSM, int KSS>
+__global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups, int ntiles,
+                                                       const void* __restrict__ Bpack, const void* Apack,
+                                                       const float* __restrict__ sgn, float* out, int64_t ld_out,
+                                                       float out_scale) {
+  typedef MfmaOp<PREC> Op;
+  typedef typename Op::frag frag;
+  constexpr int VT = 2;
+  constexpr int KS = KSM + 2 * KSS;  // A k-steps per tile
+  constexpr int KB = KSM + KSS;      // B k-steps per vertex tile
+  constexpr int TB = KS * 1024;      // bytes of one A tile
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t vt0 = (int64_t)blockIdx.x * (4 * VT) + wave * VT;
+
+  frag bfr[VT][KSM];
+  const frag* Bp = static_cast<const frag*>(Bpack);
+#pragma unroll
+  for (int v = 0; v < VT; ++v)
+#pragma unroll
+    for (int ks = 0; ks < KSM; ++ks) bfr[v][ks] = Bp[((vt0 + v) * KB + ks) * 64 + lane];
+  char* blo = lds_raw + 2 * TB + wave * (VT * KSS * 1024);
+#pragma unroll
+  for (int v = 0; v < VT; ++v)
+#pragma unroll
+    for (int j = 0; j < KSS; ++j)
+      __builtin_amdgcn_global_load_lds((const void*)(Bp + ((vt0 + v) * KB + KSM + j) * 64 + lane),
+                                       (lds_void*)(blo + (v * KSS + j) * 1024), 16, 0, 0);
+  const frag* Blo = reinterpret_cast<const frag*>(blo);
+  const char* Ag = static_cast<const char*>(Apack);
+  // tile t -> LDS buffer buf: fragment c of the tile is one 1 KiB DMA by wave c % 4
+  auto dma = [&](int t, int buf) {
+#pragma unroll
+    for (int u = 0; u < (KS + 3) / 4; ++u) {
+      const int c = u * 4 + wave;
+      if (KS % 4 == 0 || c < KS)
+        __builtin_amdgcn_global_load_lds((const void*)(Ag + (int64_t)t * TB + c * 1024 + lane * 16),
+                                         (lds_void*)(lds_raw + buf * TB + c * 1024), 16, 0, 0);
+    }
+  };
+  const int64_t vbase = vt0 * 32 + (lane & 31);
+  floatx16 accP[VT], accC[VT];
+  float yv[VT][2];
+  // stores of finished tile tt (nothing for tt < 0): output rows 4tt .. 4tt+3
+  auto store_tile = [&](int tt) {
+    int64_t rows = (int64_t)groups - 4 * (int64_t)tt;
+    rows = tt < 0 ? 0 : (rows < 4 ? rows : 4);
+    const uint32_t nrec = (uint32_t)(rows * ld_out * 4);
+    const __amdgpu_buffer_rsrc_t rs = out_rsrc(out + (int64_t)4 * (tt < 0 ? 0 : tt) * ld_out, nrec);
+    const int r0 = lane >> 5;
+#pragma unroll
+    for (int v = 0; v < VT; ++v) {
+      const int64_t vert = vbase + v * 32;
+      const bool ok = vert < nrows;
+      const uint32_t o0 = ok ? (uint32_t)((r0 * ld_out + vert) * 4) : nrec;
+      const uint32_t o1 = ok ? (uint32_t)(((r0 + 2) * ld_out + vert) * 4) : nrec;
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(yv[v][0]), rs, o0, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(yv[v][1]), rs, o1, 0, 0);
+    }
+  };
+  // signs of tile tt: sgn[tt*32 + hf*16 + e] for lane half hf, register e
+  auto load_signs = [&](int tt, float (&sa)[16], float (&sb)[16]) {
+    const float* st = sgn + (int64_t)(tt < 0 ? 0 : tt) * 32;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      sa[e] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, st[e])));
+      sb[e] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, st[16 + e])));
+    }
+  };
+  // trunc_log and signed group sums: registers 0..7 form group 4tt + hf,
+  // registers 8..15 group 4tt + 2 + hf
+  auto epilogue = [&](floatx16 (&acc)[VT], const float (&sa)[16], const float (&sb)[16]) {
+    const bool hi = lane >= 32;
+    float sv[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) sv[e] = hi ? sb[e] : sa[e];
+#pragma unroll
+    for (int v = 0; v < VT; ++v) {
+      float y0 = 0.0f, y1 = 0.0f;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) y0 = fmaf(sv[e], fmaxf(__builtin_amdgcn_logf(acc[v][e]), 0.0f), y0);
+#pragma unroll
+      for (int e = 8; e < 16; ++e) y1 = fmaf(sv[e], fmaxf(__builtin_amdgcn_logf(acc[v][e]), 0.0f), y1);
+      yv[v][0] = out_scale * y0;
+      yv[v][1] = out_scale * y1;
+    }
+  };
+
+  dma(0, 0);
+#pragma unroll
+  for (int v = 0; v < VT; ++v)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) accP[v][e] = 0.0f;
+#pragma unroll
+  for (int v = 0; v < VT; ++v) yv[v][0] = yv[v][1] = 0.0f;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  // one step: stores of tile t-2, DMA of tile t+1, MFMAs of tile t into cur
+  // with the epilogue of tile t-1 (from prev) spread over them
+  auto step = [&](int t, floatx16 (&cur)[VT], floatx16 (&prev)[VT]) {
+    const int buf = t & 1;
+    store_tile(t - 2);
+    dma(t + 1 < ntiles ? t + 1 : ntiles - 1, buf ^ 1);
+    float sa[16], sb[16];
+    load_signs(t - 1, sa, sb);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int v = 0; v < VT; ++v)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) cur[v][e] = 0.0f;
+    const frag* Al = reinterpret_cast<const frag*>(lds_raw + buf * TB);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const frag a = Al[ks * 64 + lane];
+#pragma unroll
+      for (int v = 0; v < VT; ++v) {
+        frag b;
+        if (ks < KSM) b = bfr[v][ks];
+        else if (ks < KB) b = Blo[(v * KSS + ks - KSM) * 64 + lane];
+        else b = bfr[v][ks - KB];
+        cur[v] = Op::mma(a, b, cur[v]);
+      }
+    }
+    epilogue(prev, sa, sb);
+    // A fragments three ahead of their MFMAs; epilogue ALU work spread over the MFMA stream
+    __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
+#pragma unroll
+    for (int g = 0; g < KS; ++g) {
+      __builtin_amdgcn_sched_group_barrier(0x008, VT, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    // the DMA into the other buffer has landed for every wave before anyone reads it
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  };
+  int t = 0;
+  for (; t + 1 < ntiles; t += 2) {
+    step(t, accC, accP);
+    step(t + 1, accP, accC);
+  }
+  if (t < ntiles) {
+    step(t, accC, accP);
+#pragma unroll
+    for (int v = 0; v < VT; ++v) accP[v] = accC[v];
+  }
+  store_tile(ntiles - 2);
+  {
+    float sa[16], sb[16];
+    load_signs(ntiles - 1, sa, sb);
+    epilogue(accP, sa, sb);
+  }
+  store_tile(ntiles - 1);
+}
+
 // Z[c'][c] = inv_sqrt_z * sum_t s_{c't} * T1t[c][c' z + t]
 __global__ void k_z_reduce(int l, int z, const int8_t* __restrict__ signs, const float* __restrict__ T1t,
                            int64_t ld_t1, float inv_sqrt_z, float* __restrict__ Z) {
@@ -415,15 +615,30 @@ sketchne_status launch_fused(sketchne_ctx* c, int cls, int64_t nrows, int groups
   return launch_status();
 }
 
+template <int PREC, int KSM, int KSS>
+sketchne_status launch_lowp(sketchne_ctx* c, int cls, int64_t nrows, int groups, int ntiles, const void* Bpack,
+                            const void* Apack, const float* sgn, float* out, int64_t ld_out, float out_scale) {
+  constexpr int KS = KSM + 2 * KSS;
+  const size_t shmem = (size_t)2 * KS * 1024 + (size_t)4 * 2 * KSS * 1024;
+  const int64_t nvt = (nrows + 31) / 32;
+  const int64_t blocks = (nvt + 7) / 8;
+  auto kern = k_fused_lowp<PREC, KSM, KSS>;
+  hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  ProfScope ps(c, cls);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), shmem, c->stream, nrows, groups, ntiles, Bpack, Apack,
+                     sgn, out, ld_out, out_scale);
+  return launch_status();
+}
+
 template <int PREC>
-sketchne_status fused_lowp(sketchne_ctx* c, int cls, int64_t nrows, int groups, int ntiles, int KS, const void* Bpack,
-                           const void* Apack, const float* sgn, float* out, int64_t ld_out, float out_scale) {
-  switch (KS) {
-    case 8: return launch_fused<PREC, 2, 8>(c, cls, nrows, groups, ntiles, Bpack, Apack, sgn, out, ld_out, out_scale);
-    case 12: return launch_fused<PREC, 2, 12>(c, cls, nrows, groups, ntiles, Bpack, Apack, sgn, out, ld_out, out_scale);
-    case 16: return launch_fused<PREC, 2, 16>(c, cls, nrows, groups, ntiles, Bpack, Apack, sgn, out, ld_out, out_scale);
-    case 20: return launch_fused<PREC, 2, 20>(c, cls, nrows, groups, ntiles, Bpack, Apack, sgn, out, ld_out, out_scale);
-  }
+sketchne_status fused_lowp(sketchne_ctx* c, int cls, int64_t nrows, int groups, int ntiles, int KSM, int KSS,
+                           const void* Bpack, const void* Apack, const float* sgn, float* out, int64_t ld_out,
+                           float out_scale) {
+#define SK_LOWP(m, s)                                                                                             \
+  if (KSM == m && KSS == s)                                                                                       \
+    return launch_lowp<PREC, m, s>(c, cls, nrows, groups, ntiles, Bpack, Apack, sgn, out, ld_out, out_scale);
+  SK_LOWP(8, 0) SK_LOWP(8, 1) SK_LOWP(8, 2) SK_LOWP(16, 0) SK_LOWP(16, 1) SK_LOWP(16, 2)
+#undef SK_LOWP
   return SKETCHNE_E_UNSUPPORTED;
 }
 
@@ -435,17 +650,24 @@ int sketch_kstep(int prec) { return prec == SKETCHNE_FP32 ? 2 : 16; }
 int sketch_frag_bytes(int prec) { return prec == SKETCHNE_FP32 ? 4 : 16; }
 int sketch_vt(int prec) { return prec == SKETCHNE_FP32 ? 1 : 2; }
 
-// k-step counts with a compiled kernel; the summation range is zero-padded up
-// to the next one (0 if the range is too long)
-int sketch_ks_supported(int prec, int ks_needed) {
-  static const int f32[] = {32, 64, 128};
-  static const int lowp[] = {8, 12, 16, 20};
+// k-step sections with a compiled kernel (each section zero-padded up to the
+// next one): FP32 KSM in {32, 64, 128} steps of 2, KSS = 0; BF16/FP16 KSM in
+// {8, 16} steps of 16 (k <= 256) and KSS = ceil(r/16) <= 2 (r <= 32).
+// Returns false when k or r is beyond them.
+bool sketch_sections(int prec, int k, int r, int* KSM, int* KSS) {
   if (prec == SKETCHNE_FP32) {
-    for (int v : f32) if (ks_needed <= v) return v;
-  } else {
-    for (int v : lowp) if (ks_needed <= v) return v;
+    static const int f32[] = {32, 64, 128};
+    const int need = (k + 1) / 2;
+    for (int v : f32)
+      if (need <= v) { *KSM = v; *KSS = 0; return true; }
+    return false;
   }
-  return 0;
+  const int need = (k + 15) / 16;
+  const int kss = (r + 15) / 16;
+  if (need > 16 || kss > 2) return false;
+  *KSM = need <= 8 ? 8 : 16;
+  *KSS = kss;
+  return true;
 }
 
 sketchne_status degree_powers(sketchne_ctx* c, int64_t n, const int64_t* rowptr, double alpha, double* d1,
@@ -481,32 +703,36 @@ sketchne_status gather_expanded(sketchne_ctx* c, int64_t n, int ntiles, int grou
   return launch_status();
 }
 
-sketchne_status pack_A(sketchne_ctx* c, int prec, int ntiles, int KS, int k, int r, const double* RtT, void* out) {
-  int64_t tot = (int64_t)ntiles * KS * 64;
+sketchne_status pack_A(sketchne_ctx* c, int prec, int ntiles, int KSM, int KSS, int k, int r, const double* RtT,
+                       void* out) {
+  int64_t tot = (int64_t)ntiles * (KSM + 2 * KSS) * 64;
   unsigned blocks = (unsigned)((tot + 255) / 256);
   ProfScope ps(c, SKETCHNE_PROF_PREP);
   if (prec == SKETCHNE_FP32)
-    hipLaunchKernelGGL(k_pack_A<SKETCHNE_FP32>, dim3(blocks), dim3(256), 0, c->stream, ntiles, KS, k, r, RtT, out);
+    hipLaunchKernelGGL(k_pack_A<SKETCHNE_FP32>, dim3(blocks), dim3(256), 0, c->stream, ntiles, KSM, KSS, k, r, RtT,
+                       out);
   else if (prec == SKETCHNE_BF16)
-    hipLaunchKernelGGL(k_pack_A<SKETCHNE_BF16>, dim3(blocks), dim3(256), 0, c->stream, ntiles, KS, k, r, RtT, out);
+    hipLaunchKernelGGL(k_pack_A<SKETCHNE_BF16>, dim3(blocks), dim3(256), 0, c->stream, ntiles, KSM, KSS, k, r, RtT,
+                       out);
   else
-    hipLaunchKernelGGL(k_pack_A<SKETCHNE_FP16>, dim3(blocks), dim3(256), 0, c->stream, ntiles, KS, k, r, RtT, out);
+    hipLaunchKernelGGL(k_pack_A<SKETCHNE_FP16>, dim3(blocks), dim3(256), 0, c->stream, ntiles, KSM, KSS, k, r, RtT,
+                       out);
   return launch_status();
 }
 
-sketchne_status pack_B(sketchne_ctx* c, int prec, int64_t n, int64_t nrows, int64_t nvt, int KS, int k, int r,
-                       const int32_t* gather, const float* U, int64_t ldu, const double* d1, void* out) {
-  int64_t tot = nvt * KS * 64;
+sketchne_status pack_B(sketchne_ctx* c, int prec, int64_t n, int64_t nrows, int64_t nvt, int KSM, int KSS, int k,
+                       int r, const int32_t* gather, const float* U, int64_t ldu, const double* d1, void* out) {
+  int64_t tot = nvt * (KSM + KSS) * 64;
   unsigned blocks = (unsigned)((tot + 255) / 256);
   ProfScope ps(c, SKETCHNE_PROF_PREP);
   if (prec == SKETCHNE_FP32)
-    hipLaunchKernelGGL(k_pack_B<SKETCHNE_FP32>, dim3(blocks), dim3(256), 0, c->stream, n, nrows, nvt, KS, k, r,
+    hipLaunchKernelGGL(k_pack_B<SKETCHNE_FP32>, dim3(blocks), dim3(256), 0, c->stream, n, nrows, nvt, KSM, KSS, k, r,
                        gather, U, ldu, d1, out, c->d_flags);
   else if (prec == SKETCHNE_BF16)
-    hipLaunchKernelGGL(k_pack_B<SKETCHNE_BF16>, dim3(blocks), dim3(256), 0, c->stream, n, nrows, nvt, KS, k, r,
+    hipLaunchKernelGGL(k_pack_B<SKETCHNE_BF16>, dim3(blocks), dim3(256), 0, c->stream, n, nrows, nvt, KSM, KSS, k, r,
                        gather, U, ldu, d1, out, c->d_flags);
   else
-    hipLaunchKernelGGL(k_pack_B<SKETCHNE_FP16>, dim3(blocks), dim3(256), 0, c->stream, n, nrows, nvt, KS, k, r,
+    hipLaunchKernelGGL(k_pack_B<SKETCHNE_FP16>, dim3(blocks), dim3(256), 0, c->stream, n, nrows, nvt, KSM, KSS, k, r,
                        gather, U, ldu, d1, out, c->d_flags);
   return launch_status();
 }
@@ -517,12 +743,12 @@ sketchne_status pack_signs(sketchne_ctx* c, int ntiles, int groups, int z, const
   return launch_status();
 }
 
-sketchne_status fused_sketch(sketchne_ctx* c, int cls, int prec, int64_t nrows, int groups, int ntiles, int KS,
-                             const void* Bpack, const void* Apack, const float* sgn, float* out, int64_t ld_out,
-                             float out_scale) {
+sketchne_status fused_sketch(sketchne_ctx* c, int cls, int prec, int64_t nrows, int groups, int ntiles, int KSM,
+                             int KSS, const void* Bpack, const void* Apack, const float* sgn, float* out,
+                             int64_t ld_out, float out_scale) {
   if (nrows == 0 || groups == 0) return SKETCHNE_OK;
   if (prec == SKETCHNE_FP32) {
-    switch (KS) {
+    switch (KSM) {
       case 32:
         return launch_fused<SKETCHNE_FP32, 1, 32>(c, cls, nrows, groups, ntiles, Bpack, Apack, sgn, out, ld_out,
                                                   out_scale);
@@ -535,9 +761,13 @@ sketchne_status fused_sketch(sketchne_ctx* c, int cls, int prec, int64_t nrows, 
     }
     return SKETCHNE_E_UNSUPPORTED;
   }
+  // the buffer descriptor of one tile's four output rows holds < 2^32 bytes
+  if (ld_out >= ((int64_t)1 << 28)) return SKETCHNE_E_UNSUPPORTED;
   if (prec == SKETCHNE_BF16)
-    return fused_lowp<SKETCHNE_BF16>(c, cls, nrows, groups, ntiles, KS, Bpack, Apack, sgn, out, ld_out, out_scale);
-  return fused_lowp<SKETCHNE_FP16>(c, cls, nrows, groups, ntiles, KS, Bpack, Apack, sgn, out, ld_out, out_scale);
+    return fused_lowp<SKETCHNE_BF16>(c, cls, nrows, groups, ntiles, KSM, KSS, Bpack, Apack, sgn, out, ld_out,
+                                     out_scale);
+  return fused_lowp<SKETCHNE_FP16>(c, cls, nrows, groups, ntiles, KSM, KSS, Bpack, Apack, sgn, out, ld_out,
+                                   out_scale);
 }
 
 sketchne_status z_reduce(sketchne_ctx* c, int l, int z, const int8_t* signs, const float* T1t, int64_t ld_t1,
