@@ -191,7 +191,8 @@ def main():
         },
         "embed_time_ms": dt * 1e3,
         "sketch_entries_per_s": sketch_rate,
-        "roofline": {"bound": "mfma", "kernel": "k_fused_sketch (Y pass)", "achieved": achieved, "peak": peak,
+        "roofline": {"bound": "mfma", "kernel": ("k_fused_sketch" if args.precision == "fp32" else "k_fused_lowp")
+                     + " (Y pass)", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "launch_ms": y_ms, "algorithmic_flops": y_flops, "executed_flops": executed,
                      "launches_per_step": y_launches},

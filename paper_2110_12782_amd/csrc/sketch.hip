@@ -419,7 +419,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(const float* base, ui
 }
 
 template <int PREC, int KSM, int KSS>
-__global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups, int ntiles,
+__global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups, int ntiles, int tiles_per_block,
                                                        const void* __restrict__ Bpack, const void* Apack,
                                                        const float* __restrict__ sgn, float* out, int64_t ld_out,
                                                        float out_scale) {
@@ -432,6 +432,11 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
   extern __shared__ __attribute__((aligned(16))) char lds_raw[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t vt0 = (int64_t)blockIdx.x * (4 * VT) + wave * VT;
+  // this workgroup's expanded-column tiles: tb .. tb + nt - 1 (blockIdx.y splits
+  // the tile range when there are too few vertex blocks to fill the chip)
+  const int tb = blockIdx.y * tiles_per_block;
+  const int nt = ntiles - tb < tiles_per_block ? ntiles - tb : tiles_per_block;
+  if (nt <= 0) return;
 
   frag bfr[VT][KSM];
   const frag* Bp = static_cast<const frag*>(Bpack);
@@ -506,7 +511,7 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
     }
   };
 
-  dma(0, 0);
+  dma(tb, 0);
 #pragma unroll
   for (int v = 0; v < VT; ++v)
 #pragma unroll
@@ -519,10 +524,10 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
   // with the epilogue of tile t-1 (from prev) spread over them
   auto step = [&](int t, floatx16 (&cur)[VT], floatx16 (&prev)[VT]) {
     const int buf = t & 1;
-    store_tile(t - 2);
-    dma(t + 1 < ntiles ? t + 1 : ntiles - 1, buf ^ 1);
+    store_tile(t >= 2 ? tb + t - 2 : -1);
+    dma(tb + (t + 1 < nt ? t + 1 : nt - 1), buf ^ 1);
     float sa[16], sb[16];
-    load_signs(t - 1, sa, sb);
+    load_signs(t >= 1 ? tb + t - 1 : -1, sa, sb);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int v = 0; v < VT; ++v)
@@ -555,22 +560,22 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
     __syncthreads();
   };
   int t = 0;
-  for (; t + 1 < ntiles; t += 2) {
+  for (; t + 1 < nt; t += 2) {
     step(t, accC, accP);
     step(t + 1, accP, accC);
   }
-  if (t < ntiles) {
+  if (t < nt) {
     step(t, accC, accP);
 #pragma unroll
     for (int v = 0; v < VT; ++v) accP[v] = accC[v];
   }
-  store_tile(ntiles - 2);
+  store_tile(nt >= 2 ? tb + nt - 2 : -1);
   {
     float sa[16], sb[16];
-    load_signs(ntiles - 1, sa, sb);
+    load_signs(tb + nt - 1, sa, sb);
     epilogue(accP, sa, sb);
   }
-  store_tile(ntiles - 1);
+  store_tile(tb + nt - 1);
 }
 
 // Z[c'][c] = inv_sqrt_z * sum_t s_{c't} * T1t[c][c' z + t]
@@ -622,11 +627,18 @@ sketchne_status launch_lowp(sketchne_ctx* c, int cls, int64_t nrows, int groups,
   const size_t shmem = (size_t)2 * KS * 1024 + (size_t)4 * 2 * KSS * 1024;
   const int64_t nvt = (nrows + 31) / 32;
   const int64_t blocks = (nvt + 7) / 8;
+  // few vertex blocks (the Z pass): split the tile range so that about 1024
+  // workgroups run, keeping at least 8 tiles per workgroup
+  int64_t ysplit = (1024 + blocks - 1) / blocks;
+  const int64_t ymax = ntiles / 8 > 1 ? ntiles / 8 : 1;
+  ysplit = ysplit < ymax ? ysplit : ymax;
+  const int tpb = (int)((ntiles + ysplit - 1) / ysplit);
+  const int64_t ny = (ntiles + tpb - 1) / tpb;
   auto kern = k_fused_lowp<PREC, KSM, KSS>;
   hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   ProfScope ps(c, cls);
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), shmem, c->stream, nrows, groups, ntiles, Bpack, Apack,
-                     sgn, out, ld_out, out_scale);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks, (unsigned)ny), dim3(256), shmem, c->stream, nrows, groups, ntiles,
+                     tpb, Bpack, Apack, sgn, out, ld_out, out_scale);
   return launch_status();
 }
 
