@@ -10,7 +10,9 @@
 // read of cols*4 bytes.  A row that crosses a slice boundary is written as
 // partial sums (one "head" and one "tail" slot per wavefront) and a fixup
 // kernel adds the partials of each such row in slice order, so the result is
-// deterministic (no floating-point atomics).
+// deterministic (no floating-point atomics).  The row containing the first
+// entry of every slice is found once per call (one binary search per slice,
+// all in parallel) and read by both kernels.
 #include "internal.h"
 
 namespace skne {
@@ -36,13 +38,22 @@ __device__ __forceinline__ int64_t row_of(const int64_t* __restrict__ rowptr, in
   return lo;
 }
 
+// brow[w] = row containing stored entry w*P, for every slice w
+__global__ void k_spmm_bounds(int64_t n, const int64_t* __restrict__ rowptr, int64_t nwaves,
+                              int64_t* __restrict__ brow) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nwaves) return;
+  brow[w] = row_of(rowptr, n, w * kP);
+}
+
 template <int NIT>
 __global__ __launch_bounds__(256) void k_spmm(int64_t n, int64_t nnz, const int64_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ colidx,
                                               const float* __restrict__ dscale,
                                               const float* __restrict__ B, int64_t ldb, int cols,
                                               float* __restrict__ C, int64_t ldc,
-                                              float* __restrict__ partial, int64_t nwaves) {
+                                              float* __restrict__ partial, const int64_t* __restrict__ brow,
+                                              int64_t nwaves) {
   const int lane = threadIdx.x & 63;
   int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   w = __builtin_amdgcn_readfirstlane((int)w);
@@ -50,7 +61,7 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, int64_t nnz, const int6
   const int nc4 = cols >> 2;
   const int64_t e0 = w * kP;
   const int64_t e1 = min(e0 + (int64_t)kP, nnz);
-  int64_t r = row_of(rowptr, n, e0);
+  int64_t r = brow[w];
   while (true) {
     const int64_t rs = rowptr[r], re = rowptr[r + 1];
     const int64_t a = max(rs, e0), bnd = min(re, e1);
@@ -128,7 +139,8 @@ __global__ __launch_bounds__(256) void k_spmm_c32(int64_t n, int64_t nnz, const 
                                                   const float* __restrict__ dscale,
                                                   const float* __restrict__ B, int64_t ldb, int cw,
                                                   float* __restrict__ C, int64_t ldc,
-                                                  float* __restrict__ partial, int64_t nwaves) {
+                                                  float* __restrict__ partial, const int64_t* __restrict__ brow,
+                                                  int64_t nwaves) {
   const int lane = threadIdx.x & 63;
   int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   w = __builtin_amdgcn_readfirstlane((int)w);
@@ -137,7 +149,7 @@ __global__ __launch_bounds__(256) void k_spmm_c32(int64_t n, int64_t nnz, const 
   const bool colok = c4 < cw;
   const int64_t e0 = w * kP;
   const int64_t e1 = min(e0 + (int64_t)kP, nnz);
-  int64_t r = row_of(rowptr, n, e0);
+  int64_t r = brow[w];
   while (true) {
     const int64_t rs = rowptr[r], re = rowptr[r + 1];
     const int64_t a = max(rs, e0), bnd = min(re, e1);
@@ -188,12 +200,13 @@ __global__ __launch_bounds__(256) void k_spmm_c32(int64_t n, int64_t nnz, const 
 // earlier slice and b is the first boundary it crosses, is finished here.
 __global__ __launch_bounds__(256) void k_spmm_fixup(int64_t n, int64_t nnz, const int64_t* __restrict__ rowptr,
                                                     int cols, float* __restrict__ C, int64_t ldc,
-                                                    const float* __restrict__ partial, int64_t nwaves) {
+                                                    const float* __restrict__ partial,
+                                                    const int64_t* __restrict__ brow, int64_t nwaves) {
   const int lane = threadIdx.x & 63;
   int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6) + 1;
   if (b >= nwaves) return;
   const int64_t e = b * kP;
-  const int64_t r = row_of(rowptr, n, e);
+  const int64_t r = brow[b];
   const int64_t rs = rowptr[r], re = rowptr[r + 1];
   if (rs >= e) return;                 // row starts at this boundary: not split here
   const int64_t ws = rs / kP;
@@ -220,9 +233,12 @@ __global__ void k_zero_empty(int64_t n, const int64_t* __restrict__ rowptr, int 
 
 }  // namespace
 
+// workspace: the slice rows (nwaves int64), then the head/tail partials
+static size_t spmm_brow_bytes(int64_t nwaves) { return align_up(sizeof(int64_t) * (size_t)(nwaves + 1)); }
+
 size_t spmm_ws_bytes(int64_t nnz, int cols) {
   int64_t nwaves = (nnz + kP - 1) / kP;
-  return align_up(sizeof(float) * (size_t)(2 * nwaves + 2) * (size_t)cols);
+  return spmm_brow_bytes(nwaves) + align_up(sizeof(float) * (size_t)(2 * nwaves + 2) * (size_t)cols);
 }
 
 sketchne_status degree_scale(sketchne_ctx* c, int64_t n, const int64_t* rowptr, double alpha, float* dscale) {
@@ -243,25 +259,29 @@ sketchne_status spmm(sketchne_ctx* c, int64_t n, int64_t nnz, const int64_t* row
   if (nnz == 0) return launch_status();
   int64_t nwaves = (nnz + kP - 1) / kP;
   unsigned blocks = (unsigned)((nwaves + 3) / 4);
+  int64_t* brow = reinterpret_cast<int64_t*>(partial);
+  partial = reinterpret_cast<float*>(reinterpret_cast<char*>(partial) + spmm_brow_bytes(nwaves));
+  hipLaunchKernelGGL(k_spmm_bounds, dim3((unsigned)((nwaves + 255) / 256)), dim3(256), 0, c->stream, n, rowptr, nwaves,
+                     brow);
   if (cols > 32) {
     if (cols <= 256)
       hipLaunchKernelGGL(k_spmm<1>, dim3(blocks), dim3(256), 0, c->stream, n, nnz, rowptr, colidx, dscale, B, ldb,
-                         cols, C, ldc, partial, nwaves);
+                         cols, C, ldc, partial, brow, nwaves);
     else
       hipLaunchKernelGGL(k_spmm<2>, dim3(blocks), dim3(256), 0, c->stream, n, nnz, rowptr, colidx, dscale, B, ldb,
-                         cols, C, ldc, partial, nwaves);
+                         cols, C, ldc, partial, brow, nwaves);
     if (nwaves > 1)
       hipLaunchKernelGGL(k_spmm_fixup, dim3((unsigned)((nwaves - 1 + 3) / 4)), dim3(256), 0, c->stream, n, nnz,
-                         rowptr, cols, C, ldc, partial, nwaves);
+                         rowptr, cols, C, ldc, partial, brow, nwaves);
     return launch_status();
   }
   // narrow blocks (<= 32 columns): eight neighbours per wavefront at once
   const int cw = cols / 4;
   hipLaunchKernelGGL(k_spmm_c32, dim3(blocks), dim3(256), 0, c->stream, n, nnz, rowptr, colidx, dscale, B, ldb, cw,
-                     C, ldc, partial, nwaves);
+                     C, ldc, partial, brow, nwaves);
   if (nwaves > 1)
     hipLaunchKernelGGL(k_spmm_fixup, dim3((unsigned)((nwaves - 1 + 3) / 4)), dim3(256), 0, c->stream, n, nnz,
-                       rowptr, cols, C, ldc, partial, nwaves);
+                       rowptr, cols, C, ldc, partial, brow, nwaves);
   return launch_status();
 }
 
