@@ -250,6 +250,13 @@ sketchne_status sketchne_ws_features(sketchne_ctx* ctx, const sketchne_graph* A,
 /* F = network(phi): n x out written with leading dimension ldf >= out. */
 sketchne_status sketchne_ws_forward(sketchne_ctx* ctx, const sketchne_mlp* net, int64_t n, const float* phi,
                                     float* F, int64_t ldf, void* ws, size_t ws_bytes);
+/* The inference pass that sketchne_eig_learned runs: as sketchne_ws_forward,
+ * but each hidden layer's output is rounded to BF16 (round to nearest even)
+ * and layers 2 and 3 run on the BF16 matrix cores with FP32 accumulation.
+ * Requires width == 256 and out a multiple of 32 up to 256
+ * (SKETCHNE_E_UNSUPPORTED otherwise).  Workspace: SKETCHNE_WS_OP_FORWARD. */
+sketchne_status sketchne_ws_infer(sketchne_ctx* ctx, const sketchne_mlp* net, int64_t n, const float* phi,
+                                  float* F, int64_t ldf, void* ws, size_t ws_bytes);
 /* Loss and its gradient with respect to every parameter (grad: param_count
  * FP32, overwritten; loss: one FP32, device) for reference U (n x out, ldu). */
 sketchne_status sketchne_ws_grad(sketchne_ctx* ctx, const sketchne_mlp* net, int64_t n, const float* phi,
@@ -277,11 +284,15 @@ sketchne_status sketchne_ritz_residual(sketchne_ctx* ctx, const sketchne_graph* 
  * other k + s_eig - net->out, q_warm power iterations.  If the largest Ritz
  * residual exceeds res_threshold (or is not finite) the result is discarded
  * and sketchne_eig runs from the Gaussian start with p->q iterations;
- * *used_fallback (host) says which ran.  Synchronizes the stream once (the
- * residual test).  Workspace: sketchne_ws_workspace_size(.., SKETCHNE_WS_OP_EIG, ..). */
+ * *used_fallback (host) says which ran.  The residuals come from the
+ * Rayleigh-Ritz data of the warm run (||XQv||^2 - lambda^2 with XQ already
+ * formed), not from a further SpMM; *worst_residual (host, may be NULL)
+ * receives their maximum.  Synchronizes the stream once (the residual test).
+ * Workspace: sketchne_ws_workspace_size(.., SKETCHNE_WS_OP_EIG, ..). */
 sketchne_status sketchne_eig_learned(sketchne_ctx* ctx, const sketchne_graph* A, const sketchne_params* p,
                                      const sketchne_mlp* net, int32_t q_warm, double res_threshold, float* U,
-                                     double* lambda, int32_t* used_fallback, void* ws, size_t ws_bytes);
+                                     double* lambda, int32_t* used_fallback, double* worst_residual, void* ws,
+                                     size_t ws_bytes);
 
 /* ---- Per-kernel-class timing (measurement support) --------------------- */
 /* When enabled, every launch of a kernel class is bracketed by HIP events on

@@ -93,6 +93,15 @@ def forward(p: dict, phi):
     return H1, H2, F
 
 
+def forward_bf16(p: dict, phi):
+    """The inference pass with BF16 hidden activations (the start block only
+    seeds the power iteration): each hidden layer's output is rounded to the
+    nearest bfloat16 before it enters the next product.  Returns F."""
+    H1 = bf16_round(np.maximum(phi @ p["W1"] + p["b1"], 0.0))
+    H2 = bf16_round(np.maximum(H1 @ p["W2"] + p["b2"], 0.0))
+    return H2 @ p["W3"] + p["b3"]
+
+
 def loss(F, U, mu: float) -> float:
     k = F.shape[1]
     s = float(np.sum(F * F))

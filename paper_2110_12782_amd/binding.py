@@ -27,7 +27,7 @@ EXPORTED = [
     "sketchne_symeig", "sketchne_gen_gauss", "sketchne_gen_sparse_sign", "sketchne_profile_enable",
     "sketchne_profile_read", "sketchne_ws_param_count", "sketchne_ws_workspace_size", "sketchne_ws_init",
     "sketchne_ws_features", "sketchne_ws_forward", "sketchne_ws_grad", "sketchne_ws_adam",
-    "sketchne_ritz_residual", "sketchne_eig_learned", "sketchne_ws_train",
+    "sketchne_ritz_residual", "sketchne_eig_learned", "sketchne_ws_train", "sketchne_ws_infer",
 ]
 WS_FEAT = 8
 WS_OP_FEATURES, WS_OP_FORWARD, WS_OP_GRAD, WS_OP_RESIDUAL, WS_OP_EIG = 1, 2, 4, 8, 16
@@ -138,6 +138,7 @@ class Library:
                                            C.c_void_p, C.c_void_p, C.c_size_t]
         L.sketchne_ws_forward.argtypes = [C.c_void_p, C.POINTER(MLPStruct), C.c_int64, C.c_void_p, C.c_void_p,
                                           C.c_int64, C.c_void_p, C.c_size_t]
+        L.sketchne_ws_infer.argtypes = L.sketchne_ws_forward.argtypes
         L.sketchne_ws_grad.argtypes = [C.c_void_p, C.POINTER(MLPStruct), C.c_int64, C.c_void_p, C.c_void_p,
                                        C.c_int64, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]
         L.sketchne_ws_adam.argtypes = [C.c_void_p, C.POINTER(MLPStruct), C.c_void_p, C.c_float, C.c_int32]
@@ -148,7 +149,7 @@ class Library:
                                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]
         L.sketchne_eig_learned.argtypes = [C.c_void_p, C.POINTER(Graph), C.POINTER(Params), C.POINTER(MLPStruct),
                                            C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
-                                           C.c_void_p, C.c_size_t]
+                                           C.POINTER(C.c_double), C.c_void_p, C.c_size_t]
         self._ctx = None
 
     # ---------------------------------------------------------------- helpers
@@ -339,6 +340,19 @@ class Library:
                                                 C.c_void_p(self._aligned(ws)), nb), "ws_forward")
         return F
 
+    def ws_infer(self, net: "MLP", phi, out=None):
+        """The BF16-activation inference pass of sketchne_eig_learned."""
+        import torch
+        n = phi.shape[0]
+        F = out if out is not None else torch.empty((n, net.out), dtype=torch.float32, device="cuda")
+        nb = self.ws_workspace_size(net.width, net.out, n, 0, WS_OP_FORWARD)
+        ws = self.workspace(nb)
+        s = net.c()
+        self.check(self.lib.sketchne_ws_infer(self.ctx(), C.byref(s), n, C.c_void_p(phi.data_ptr()),
+                                              C.c_void_p(F.data_ptr()), F.stride(0),
+                                              C.c_void_p(self._aligned(ws)), nb), "ws_infer")
+        return F
+
     def ws_grad(self, net: "MLP", phi, U, mu: float, grad=None, loss=None, ws=None):
         import torch
         n = phi.shape[0]
@@ -389,20 +403,25 @@ class Library:
                                                    C.c_void_p(self._aligned(ws)), nb), "ritz_residual")
         return res
 
-    def eig_learned(self, g: "DeviceGraph", p: SketchParams, net: "MLP", q_warm: int, threshold: float, ws=None):
-        """Alg. 5 from the learned start; returns U, lambda, used_fallback."""
+    def eig_learned(self, g: "DeviceGraph", p: SketchParams, net: "MLP", q_warm: int, threshold: float, ws=None,
+                    with_residual: bool = False):
+        """Alg. 5 from the learned start; returns U, lambda, used_fallback
+        (and the largest Ritz residual of the warm run with with_residual)."""
         import torch
         U = torch.empty((g.n, p.k), dtype=torch.float32, device="cuda")
         lam = torch.empty(p.k, dtype=torch.float64, device="cuda")
         nb = self.ws_workspace_size(net.width, net.out, g.n, g.nnz, WS_OP_EIG, p)
         ws = ws if ws is not None else self.workspace(nb)
         fb = C.c_int32(0)
+        worst = C.c_double(0.0)
         pc = p.c()
         gs = g.c()
         s = net.c()
         self.check(self.lib.sketchne_eig_learned(self.ctx(), C.byref(gs), C.byref(pc), C.byref(s), q_warm, threshold,
                                                  C.c_void_p(U.data_ptr()), C.c_void_p(lam.data_ptr()), C.byref(fb),
-                                                 C.c_void_p(self._aligned(ws)), nb), "eig_learned")
+                                                 C.byref(worst), C.c_void_p(self._aligned(ws)), nb), "eig_learned")
+        if with_residual:
+            return U, lam, bool(fb.value), worst.value
         return U, lam, bool(fb.value)
 
     def profile_enable(self, on: bool):

@@ -354,14 +354,15 @@ struct LearnedWs {
 
 size_t learned_rest_bytes(const sketchne_params* p, int width, int64_t n, int64_t nnz) {
   size_t phi = align_up(sizeof(float) * (size_t)n * SKETCHNE_WS_FEAT);
-  size_t a = phi + max_bytes({ws_features_bytes(n, nnz), ws_forward_bytes(n, width)});
+  size_t a = phi + max_bytes({ws_features_bytes(n, nnz), ws_forward_bytes(n, width), ws_infer_bytes()});
   size_t b = op_bytes(p, n, nnz, SKETCHNE_OP_EIG);
-  size_t c = align_up(sizeof(double) * p->k) + ritz_residual_bytes(n, nnz, p->k);
-  return max_bytes({a, b, c});
+  return max_bytes({a, b});
 }
 
+// start block, Ritz residuals, then the space shared by the network and Alg. 5
 size_t learned_bytes(const sketchne_params* p, int width, int64_t n, int64_t nnz) {
-  return align_up(sizeof(float) * (size_t)n * (p->k + p->s_eig)) + learned_rest_bytes(p, width, n, nnz);
+  return align_up(sizeof(float) * (size_t)n * (p->k + p->s_eig)) + align_up(sizeof(double) * p->k) +
+         learned_rest_bytes(p, width, n, nnz);
 }
 
 }  // namespace
@@ -427,8 +428,23 @@ sketchne_status sketchne_workspace_size(const sketchne_params* p, int64_t n, int
   return SKETCHNE_OK;
 }
 
+// Alg. 5; when res is given (device, k doubles) it also receives the Ritz
+// residuals ||X u_j - lambda_j u_j|| of the returned pairs, from the
+// Rayleigh-Ritz data rather than a further SpMM: with Q orthonormal, H = Q^T X Q,
+// u_j = Q v_j and v_j^T H v_j = lambda_j,
+//   ||X Q v_j - lambda_j Q v_j||^2 = v_j^T (XQ)^T (XQ) v_j - lambda_j^2.
+static sketchne_status eig_impl(sketchne_ctx* c, const sketchne_graph* A, const sketchne_params* p,
+                                const float* omega0, float* U, double* lambda, double* res, void* ws,
+                                size_t ws_bytes);
+
 sketchne_status sketchne_eig(sketchne_ctx* c, const sketchne_graph* A, const sketchne_params* p,
                              const float* omega0, float* U, double* lambda, void* ws, size_t ws_bytes) {
+  return eig_impl(c, A, p, omega0, U, lambda, nullptr, ws, ws_bytes);
+}
+
+static sketchne_status eig_impl(sketchne_ctx* c, const sketchne_graph* A, const sketchne_params* p,
+                                const float* omega0, float* U, double* lambda, double* res, void* ws,
+                                size_t ws_bytes) {
   if (!c || !U || !lambda) return SKETCHNE_E_ARG;
   SK_TRY(check_graph(A));
   SK_TRY(check_params(p, A->n));
@@ -480,6 +496,11 @@ sketchne_status sketchne_eig(sketchne_ctx* c, const sketchne_graph* A, const ske
   }
   if (hipMemcpyAsync(lambda, w.wv, sizeof(double) * p->k, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
     return SKETCHNE_E_DEVICE;
+  if (res) {
+    // (XQ)^T (XQ) into H (free once the eigensolver has read it); P1 still holds XQ
+    SK_TRY(gram_tall(c, n, K, w.P1, K, 1, nullptr, 0, 0, nullptr, w.H, w.rr_partial, w.rr_cap, nullptr));
+    SK_TRY(ritz_from_gram(c, K, p->k, w.H, w.Vh, w.wv, res));
+  }
   return SKETCHNE_OK;
 }
 
@@ -734,7 +755,7 @@ sketchne_status sketchne_ws_workspace_size(const sketchne_params* p, int32_t wid
   if (!bytes || width < 1 || out < 1 || n < 1 || nnz < 0) return SKETCHNE_E_ARG;
   size_t best = 0;
   if (op_mask & SKETCHNE_WS_OP_FEATURES) best = max_bytes({best, ws_features_bytes(n, nnz)});
-  if (op_mask & SKETCHNE_WS_OP_FORWARD) best = max_bytes({best, ws_forward_bytes(n, width)});
+  if (op_mask & SKETCHNE_WS_OP_FORWARD) best = max_bytes({best, ws_forward_bytes(n, width), ws_infer_bytes()});
   if (op_mask & SKETCHNE_WS_OP_GRAD) best = max_bytes({best, ws_grad_bytes(n, width, out)});
   if (op_mask & (SKETCHNE_WS_OP_RESIDUAL | SKETCHNE_WS_OP_EIG)) {
     if (!p) return SKETCHNE_E_ARG;
@@ -769,6 +790,16 @@ sketchne_status sketchne_ws_forward(sketchne_ctx* c, const sketchne_mlp* net, in
   if (n == 0) return SKETCHNE_OK;
   SK_TRY(check_ws(ws, ws_bytes, ws_forward_bytes(n, net->width)));
   return ws_forward(c, net, n, phi, F, ldf, ws, ws_bytes);
+}
+
+sketchne_status sketchne_ws_infer(sketchne_ctx* c, const sketchne_mlp* net, int64_t n, const float* phi, float* F,
+                                  int64_t ldf, void* ws, size_t ws_bytes) {
+  if (!c || !phi || !F || n < 0) return SKETCHNE_E_ARG;
+  SK_TRY(check_net(net));
+  if (ldf < net->out) return SKETCHNE_E_ARG;
+  if (!ws_infer_supported(net)) return SKETCHNE_E_UNSUPPORTED;
+  SK_TRY(check_ws(ws, ws_bytes, ws_infer_bytes()));
+  return ws_infer(c, net, n, phi, F, ldf, ws, ws_bytes);
 }
 
 sketchne_status sketchne_ws_grad(sketchne_ctx* c, const sketchne_mlp* net, int64_t n, const float* phi,
@@ -829,7 +860,8 @@ sketchne_status sketchne_ritz_residual(sketchne_ctx* c, const sketchne_graph* A,
 
 sketchne_status sketchne_eig_learned(sketchne_ctx* c, const sketchne_graph* A, const sketchne_params* p,
                                      const sketchne_mlp* net, int32_t q_warm, double res_threshold, float* U,
-                                     double* lambda, int32_t* used_fallback, void* ws, size_t ws_bytes) {
+                                     double* lambda, int32_t* used_fallback, double* worst_residual, void* ws,
+                                     size_t ws_bytes) {
   if (!c || !U || !lambda || !used_fallback || q_warm < 0) return SKETCHNE_E_ARG;
   SK_TRY(check_graph(A));
   SK_TRY(check_params(p, A->n));
@@ -841,6 +873,7 @@ sketchne_status sketchne_eig_learned(sketchne_ctx* c, const sketchne_graph* A, c
   SK_TRY(check_ws(ws, ws_bytes, learned_bytes(p, net->width, n, A->nnz)));
   Arena ar(ws, ws_bytes);
   float* omega = ar.take<float>((size_t)n * K);
+  double* res = ar.take<double>(p->k);
   const size_t rest_bytes = learned_rest_bytes(p, net->width, n, A->nnz);
   char* rest = ar.take<char>(rest_bytes);
   if (ar.overflow) return SKETCHNE_E_WORKSPACE;
@@ -854,20 +887,15 @@ sketchne_status sketchne_eig_learned(sketchne_ctx* c, const sketchne_graph* A, c
     if (r.overflow) return SKETCHNE_E_WORKSPACE;
     SK_TRY(ws_features(c, n, A->nnz, A->rowptr, A->colidx, p->alpha, nullptr, p->seed ^ 0x7f4a7c159e3779b9ULL, phi,
                        scratch, sb));
-    SK_TRY(ws_forward(c, net, n, phi, omega, K, scratch, sb));
+    if (ws_infer_supported(net)) SK_TRY(ws_infer(c, net, n, phi, omega, K, scratch, sb));
+    else SK_TRY(ws_forward(c, net, n, phi, omega, K, scratch, sb));
     SK_TRY(gen_gauss(c, n, K - net->out, K, p->seed, omega + net->out));
   }
   sketchne_params pw = *p;
   pw.q = q_warm;
-  SK_TRY(sketchne_eig(c, A, &pw, omega, U, lambda, rest, rest_bytes));
-  // residual test
+  SK_TRY(eig_impl(c, A, &pw, omega, U, lambda, res, rest, rest_bytes));
+  // residual test on the Ritz residuals of the warm-started pairs
   {
-    Arena r(rest, rest_bytes);
-    double* res = r.take<double>(p->k);
-    size_t rb = ritz_residual_bytes(n, A->nnz, p->k);
-    char* scratch = r.take<char>(rb);
-    if (r.overflow) return SKETCHNE_E_WORKSPACE;
-    SK_TRY(ritz_residual(c, n, A->nnz, A->rowptr, A->colidx, p->alpha, p->k, U, lambda, res, scratch, rb));
     double* host = new (std::nothrow) double[p->k];
     if (!host) return SKETCHNE_E_DEVICE;
     hipError_t e = hipMemcpyAsync(host, res, sizeof(double) * p->k, hipMemcpyDeviceToHost, c->stream);
@@ -880,6 +908,7 @@ sketchne_status sketchne_eig_learned(sketchne_ctx* c, const sketchne_graph* A, c
     }
     delete[] host;
     if (e != hipSuccess) return SKETCHNE_E_DEVICE;
+    if (worst_residual) *worst_residual = finite ? worst : HUGE_VAL;
     if (finite && worst <= res_threshold) return SKETCHNE_OK;
   }
   *used_fallback = 1;

@@ -275,11 +275,18 @@ __global__ void k_copy_if(int64_t count, const float* __restrict__ src, float* _
 // in registers for all 16 rounds and meets column (g + round) mod 16 of Q,
 // which is the only data that moves (through LDS).  Rows are strided by 16
 // over the lanes of a group and the three inner products are reduced by DPP.
-// A per-sweep rotation counter ends the iteration; later launches return at
-// once.
+// Every sweep counts its rotations and its "large" rotations (|g| above
+// OJ_BIG sqrt(ab)).  A sweep without a large rotation ends the iteration:
+// the off-diagonal it leaves is of the order of the square of that bound
+// (cyclic Jacobi converges quadratically), so a further sweep would only
+// confirm it.  Launches of later sweeps return at once.
 constexpr int NBJ = 16;           // columns per block
-constexpr int OJ_MAXR = 18;       // rows per lane: m <= 16 * OJ_MAXR = 288
+constexpr int OJ_GL = 16;         // lanes per column (one DPP row)
+constexpr int OJ_MAXR = 18;       // rows per lane: m <= OJ_GL * OJ_MAXR = 288
+constexpr int OJ_THREADS = NBJ * OJ_GL;
 constexpr double OJ_SHIFT = 1.5;  // c = OJ_SHIFT * ||A||_F
+constexpr double OJ_BIG = 1e-8;   // a rotation with |g| > OJ_BIG sqrt(ab) is large
+constexpr int kMaxSweeps = 30;
 
 __device__ __forceinline__ void pair_of(int s, int pi, int mp, int& p, int& q) {
   const int ring = mp - 1;
@@ -311,6 +318,13 @@ __device__ __forceinline__ double row16_sum(double v) {
   v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
   v += dpp_d<0x141>(v);  // row_half_mirror
   v += dpp_d<0x140>(v);  // row_mirror
+  return v;
+}
+
+// sum over the OJ_GL lanes of a column group; every lane gets it
+__device__ __forceinline__ double group_sum(double v) {
+  v = row16_sum(v);
+  if (OJ_GL == 32) v += __shfl_xor(v, 16, 64);
   return v;
 }
 
@@ -349,27 +363,34 @@ __global__ void k_oj_init(int m, int mp, const double* __restrict__ A, const dou
 }
 
 // Jacobi rotation that orthogonalises the pair (x, y) given a = x.x, b = y.y,
-// g = x.y; returns false when the pair is already orthogonal to 1e-14.
-__device__ __forceinline__ bool oj_angle(double a, double b, double g, double& c, double& sn) {
+// g = x.y; returns false when the pair is already orthogonal to 1e-14; `big`
+// reports |g| > OJ_BIG sqrt(ab).  With d = b - a and r = sqrt(d^2 + 4 g^2),
+// t = tan(theta) = sgn(d) 2g / (|d| + r) is the smaller root of
+// t^2 + (d/g) t - 1 = 0, c = 1 / sqrt(1 + t^2), s = c t.
+__device__ __forceinline__ bool oj_angle(double a, double b, double g, double& c, double& sn, bool& big) {
   const double tol = 1e-14;
-  if (!(a > 0.0 && b > 0.0 && fabs(g) > tol * sqrt(a * b))) return false;
-  const double zeta = (b - a) / (2.0 * g);
-  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  c = 1.0 / sqrt(1.0 + t * t);
+  const double g2 = g * g, ab = a * b;
+  big = false;
+  if (!(a > 0.0 && b > 0.0 && g2 > (tol * tol) * ab)) return false;
+  big = g2 > (OJ_BIG * OJ_BIG) * ab;
+  const double d = b - a;
+  const double r = sqrt(fma(d, d, 4.0 * g2));
+  const double t = (d >= 0.0 ? 2.0 * g : -2.0 * g) / (fabs(d) + r);
+  c = rsqrt(fma(t, t, 1.0));
   sn = c * t;
   return true;
 }
 
-// orthogonalise columns p and q of sG (LDS, column-major, m rows) by the 16
-// lanes of one DPP row; returns whether a rotation was applied
-__device__ __forceinline__ bool oj_rotate_lds(double* __restrict__ sG, int m, int p, int q, int sub) {
+// orthogonalise columns p and q of sG (LDS, column-major, m rows) by the
+// lanes of one column group; returns whether a rotation was applied
+__device__ __forceinline__ bool oj_rotate_lds(double* __restrict__ sG, int m, int p, int q, int sub, bool& big) {
   double* gp = sG + p * m;
   double* gq = sG + q * m;
   double x[OJ_MAXR], y[OJ_MAXR];
   double a = 0.0, b = 0.0, g = 0.0;
 #pragma unroll
   for (int i = 0; i < OJ_MAXR; ++i) {
-    const int r = sub + 16 * i;
+    const int r = sub + OJ_GL * i;
     x[i] = r < m ? gp[r] : 0.0;
     y[i] = r < m ? gq[r] : 0.0;
   }
@@ -379,14 +400,14 @@ __device__ __forceinline__ bool oj_rotate_lds(double* __restrict__ sG, int m, in
     b = fma(y[i], y[i], b);
     g = fma(x[i], y[i], g);
   }
-  a = row16_sum(a);
-  b = row16_sum(b);
-  g = row16_sum(g);
+  a = group_sum(a);
+  b = group_sum(b);
+  g = group_sum(g);
   double c, sn;
-  if (!oj_angle(a, b, g, c, sn)) return false;
+  if (!oj_angle(a, b, g, c, sn, big)) return false;
 #pragma unroll
   for (int i = 0; i < OJ_MAXR; ++i) {
-    const int r = sub + 16 * i;
+    const int r = sub + OJ_GL * i;
     if (r < m) {
       gp[r] = c * x[i] - sn * y[i];
       gq[r] = sn * x[i] + c * y[i];
@@ -415,63 +436,69 @@ __device__ __forceinline__ void oj_block_load(const double* __restrict__ src, do
 }
 
 // workgroup w orthogonalises the pairs inside blocks 2w and 2w+1 (both in LDS)
-__global__ __launch_bounds__(256) void k_oj_intra(int m, int sweep, double* __restrict__ G, int* __restrict__ counters) {
-  if (sweep > 0 && counters[sweep - 1] == 0) return;
+__global__ __launch_bounds__(OJ_THREADS) void k_oj_intra(int m, int sweep, double* __restrict__ G, int* __restrict__ counters) {
+  if (sweep > 0 && counters[kMaxSweeps + sweep - 1] == 0) return;
   extern __shared__ double lds[];
   double* sG = lds;  // 2 NBJ columns x m rows
-  __shared__ int s_rot;
+  __shared__ int s_rot, s_big;
   const int tid = threadIdx.x;
-  if (tid == 0) s_rot = 0;
+  if (tid == 0) s_rot = s_big = 0;
   const int blk = NBJ * m;
   double* g0 = G + (int64_t)(2 * blockIdx.x) * blk;  // blocks 2w, 2w+1 are contiguous
   oj_block_load(g0, sG, 2 * blk);
   __syncthreads();
-  const int grp = tid >> 4, sub = tid & 15;
-  int my_rot = 0;
+  const int grp = tid / OJ_GL, sub = tid % OJ_GL;
+  int my_rot = 0, my_big = 0;
   for (int rnd = 0; rnd < NBJ - 1; ++rnd) {
     const int half = grp >> 3;  // 8 groups per block
     int p, q;
     pair_of(rnd, grp & 7, NBJ, p, q);
-    if (oj_rotate_lds(sG, m, p + half * NBJ, q + half * NBJ, sub) && sub == 0) ++my_rot;
+    bool big;
+    if (oj_rotate_lds(sG, m, p + half * NBJ, q + half * NBJ, sub, big) && sub == 0) {
+      ++my_rot;
+      my_big += big;
+    }
     __syncthreads();
   }
   if (sub == 0 && my_rot) atomicAdd(&s_rot, my_rot);
+  if (sub == 0 && my_big) atomicAdd(&s_big, my_big);
   oj_block_load(sG, g0, 2 * blk);
   __syncthreads();
   if (tid == 0 && s_rot) atomicAdd(&counters[sweep], s_rot);
+  if (tid == 0 && s_big) atomicAdd(&counters[kMaxSweeps + sweep], s_big);
 }
 
 // workgroup w takes the block pair w of round s: column g of block P stays
 // in the registers of lane group g, the 16 columns of block Q rotate past it
-__global__ __launch_bounds__(256) void k_oj_cross(int m, int nb, int s, int sweep, double* __restrict__ G,
+__global__ __launch_bounds__(OJ_THREADS) void k_oj_cross(int m, int nb, int s, int sweep, double* __restrict__ G,
                                                   int* __restrict__ counters) {
-  if (sweep > 0 && counters[sweep - 1] == 0) return;
+  if (sweep > 0 && counters[kMaxSweeps + sweep - 1] == 0) return;
   extern __shared__ double lds[];
   double* sQ = lds;  // NBJ columns x m rows
-  __shared__ int s_rot;
+  __shared__ int s_rot, s_big;
   int P, Q;
   pair_of(s, blockIdx.x, nb, P, Q);
-  const int tid = threadIdx.x, grp = tid >> 4, sub = tid & 15;
-  if (tid == 0) s_rot = 0;
+  const int tid = threadIdx.x, grp = tid / OJ_GL, sub = tid % OJ_GL;
+  if (tid == 0) s_rot = s_big = 0;
   const int blk = NBJ * m;
   double* gpcol = G + (int64_t)P * blk + (int64_t)grp * m;
   double* gQ = G + (int64_t)Q * blk;
   double x[OJ_MAXR];
 #pragma unroll
   for (int i = 0; i < OJ_MAXR; ++i) {
-    const int r = sub + 16 * i;
+    const int r = sub + OJ_GL * i;
     x[i] = r < m ? gpcol[r] : 0.0;
   }
   oj_block_load(gQ, sQ, blk);
   __syncthreads();
-  int my_rot = 0;
+  int my_rot = 0, my_big = 0;
   for (int rnd = 0; rnd < NBJ; ++rnd) {
     double* gq = sQ + ((grp + rnd) & (NBJ - 1)) * m;
     double y[OJ_MAXR];
     double a = 0.0, b = 0.0, g = 0.0;
 #pragma unroll
     for (int i = 0; i < OJ_MAXR; ++i) {
-      const int r = sub + 16 * i;
+      const int r = sub + OJ_GL * i;
       y[i] = r < m ? gq[r] : 0.0;
     }
 #pragma unroll
@@ -480,31 +507,37 @@ __global__ __launch_bounds__(256) void k_oj_cross(int m, int nb, int s, int swee
       b = fma(y[i], y[i], b);
       g = fma(x[i], y[i], g);
     }
-    a = row16_sum(a);
-    b = row16_sum(b);
-    g = row16_sum(g);
+    a = group_sum(a);
+    b = group_sum(b);
+    g = group_sum(g);
     double c, sn;
-    if (oj_angle(a, b, g, c, sn)) {
+    bool big;
+    if (oj_angle(a, b, g, c, sn, big)) {
 #pragma unroll
       for (int i = 0; i < OJ_MAXR; ++i) {
-        const int r = sub + 16 * i;
+        const int r = sub + OJ_GL * i;
         const double xi = x[i];
         x[i] = c * xi - sn * y[i];
         if (r < m) gq[r] = sn * xi + c * y[i];
       }
-      if (sub == 0) ++my_rot;
+      if (sub == 0) {
+        ++my_rot;
+        my_big += big;
+      }
     }
     __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < OJ_MAXR; ++i) {
-    const int r = sub + 16 * i;
+    const int r = sub + OJ_GL * i;
     if (r < m) gpcol[r] = x[i];
   }
   if (sub == 0 && my_rot) atomicAdd(&s_rot, my_rot);
+  if (sub == 0 && my_big) atomicAdd(&s_big, my_big);
   oj_block_load(sQ, gQ, blk);
   __syncthreads();
   if (tid == 0 && s_rot) atomicAdd(&counters[sweep], s_rot);
+  if (tid == 0 && s_big) atomicAdd(&counters[kMaxSweeps + sweep], s_big);
 }
 
 // lambda_j = ||g_j|| - c and v_j = g_j / ||g_j|| (one wavefront per column);
@@ -521,14 +554,14 @@ __global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restr
   if (tid == 0) {
     bool conv = false;
     for (int s = 0; s < sweeps_run; ++s)
-      if (counters[s] == 0) { conv = true; break; }
+      if (counters[kMaxSweeps + s] == 0) { conv = true; break; }
     if (!conv) atomicOr(flags, SKETCHNE_FLAG_EIG_NOCONV);
   }
   const double cs = *shift;
   for (int j = wave; j < m; j += 16) {
     double d = 0.0;
 #pragma unroll
-    for (int i = 0; i < (16 * OJ_MAXR + 63) / 64; ++i) {
+    for (int i = 0; i < (OJ_GL * OJ_MAXR + 63) / 64; ++i) {
       const int r = lane + 64 * i;
       if (r < m) {
         const double v = G[(int64_t)j * m + r];
@@ -564,8 +597,6 @@ __global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restr
   }
 }
 
-constexpr int kMaxSweeps = 30;
-
 int oj_nblocks(int m) {
   int nb = (m + NBJ - 1) / NBJ;
   return nb + (nb & 1);
@@ -598,25 +629,57 @@ sketchne_status chol_inv(sketchne_ctx* c, int m, const double* G, double* RinvT,
   return launch_status();
 }
 
+namespace {
+
+// one wavefront per column j: t = G v_j (lanes over rows), s = v_j . t
+__global__ __launch_bounds__(256) void k_ritz_from_gram(int m, int k, const double* __restrict__ G,
+                                                        const double* __restrict__ V, const double* __restrict__ lam,
+                                                        double* __restrict__ res) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= k) return;
+  double s = 0.0;
+  for (int r = lane; r < m; r += 64) {
+    double t = 0.0;
+    for (int col = 0; col < m; ++col) t = fma(G[(int64_t)r * m + col], V[(int64_t)col * m + j], t);
+    s = fma(V[(int64_t)r * m + j], t, s);
+  }
+  s = wave_sum(s);
+  if (lane == 0) {
+    const double d = s - lam[j] * lam[j];
+    res[j] = d > 0.0 ? sqrt(d) : 0.0;
+  }
+}
+
+}  // namespace
+
+sketchne_status ritz_from_gram(sketchne_ctx* c, int m, int k, const double* G, const double* V, const double* lam,
+                               double* res) {
+  if (k <= 0) return SKETCHNE_OK;
+  ProfScope ps(c, SKETCHNE_PROF_SMALL);
+  hipLaunchKernelGGL(k_ritz_from_gram, dim3((unsigned)((k + 3) / 4)), dim3(256), 0, c->stream, m, k, G, V, lam, res);
+  return launch_status();
+}
+
 size_t symeig_ws_bytes(int m) {
   int mp = oj_nblocks(m) * NBJ;
   size_t mat = align_up(sizeof(double) * (size_t)mp * m);
-  return mat + align_up(sizeof(int) * kMaxSweeps) + align_up(sizeof(double));
+  return mat + align_up(sizeof(int) * 2 * kMaxSweeps) + align_up(sizeof(double));
 }
 
 sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* Vout, double* wout, void* ws) {
   if (m <= 0) return SKETCHNE_OK;
-  if (m > NBJ * OJ_MAXR) return SKETCHNE_E_UNSUPPORTED;
+  if (m > OJ_GL * OJ_MAXR) return SKETCHNE_E_UNSUPPORTED;
   const int nb = oj_nblocks(m), mp = nb * NBJ;
   Arena ar(ws, symeig_ws_bytes(m));
   double* G = ar.take<double>((size_t)mp * m);
-  int* counters = ar.take<int>(kMaxSweeps);
+  int* counters = ar.take<int>(2 * kMaxSweeps);  // rotations, then large rotations, per sweep
   double* shift = ar.take<double>(1);
   ProfScope ps(c, SKETCHNE_PROF_SMALL);
   hipLaunchKernelGGL(k_oj_norm, dim3(1), dim3(1024), 0, c->stream, m, A, shift);
   int tot = mp * m;
   hipLaunchKernelGGL(k_oj_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, m, mp, A, shift, G,
-                     counters, kMaxSweeps);
+                     counters, 2 * kMaxSweeps);
   const size_t sh_intra = sizeof(double) * (size_t)(2 * NBJ) * m;
   const size_t sh_cross = sizeof(double) * (size_t)NBJ * m;
   hipFuncSetAttribute(reinterpret_cast<const void*>(k_oj_intra), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -625,12 +688,13 @@ sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* Vout, do
                       (int)sh_cross);
   int run = 0;
   for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-    hipLaunchKernelGGL(k_oj_intra, dim3(nb / 2), dim3(256), sh_intra, c->stream, m, sweep, G, counters);
+    hipLaunchKernelGGL(k_oj_intra, dim3(nb / 2), dim3(OJ_THREADS), sh_intra, c->stream, m, sweep, G, counters);
     for (int s = 0; s < nb - 1; ++s)
-      hipLaunchKernelGGL(k_oj_cross, dim3(nb / 2), dim3(256), sh_cross, c->stream, m, nb, s, sweep, G, counters);
+      hipLaunchKernelGGL(k_oj_cross, dim3(nb / 2), dim3(OJ_THREADS), sh_cross, c->stream, m, nb, s, sweep, G,
+                         counters);
     run = sweep + 1;
     if (sweep >= 4) {  // one small host read per sweep from the fifth on
-      hipMemcpyAsync(c->h_counter, counters + sweep, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+      hipMemcpyAsync(c->h_counter, counters + kMaxSweeps + sweep, sizeof(int), hipMemcpyDeviceToHost, c->stream);
       if (hipStreamSynchronize(c->stream) != hipSuccess) return SKETCHNE_E_DEVICE;
       if (*c->h_counter == 0) break;
     }

@@ -160,9 +160,18 @@ size_t ws_forward_bytes(int64_t n, int width);
 size_t ws_grad_bytes(int64_t n, int width, int out);
 size_t ws_features_bytes(int64_t n, int64_t nnz);
 size_t ritz_residual_bytes(int64_t n, int64_t nnz, int k);
+// res_j = sqrt(max(v_j^T G v_j - lam_j^2, 0)), j < k: G m x m symmetric,
+// V m x m row-major with v_j its column j
+sketchne_status ritz_from_gram(sketchne_ctx* c, int m, int k, const double* G, const double* V, const double* lam,
+                               double* res);
 sketchne_status ws_init(sketchne_ctx* c, const sketchne_mlp* net, uint64_t seed);
 sketchne_status ws_features(sketchne_ctx* c, int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colidx,
                             double alpha, const float* g, uint64_t seed, float* phi, void* ws, size_t ws_bytes);
+// BF16-activation inference pass (width 256, out % 32 == 0, out <= 256)
+bool ws_infer_supported(const sketchne_mlp* net);
+size_t ws_infer_bytes();
+sketchne_status ws_infer(sketchne_ctx* c, const sketchne_mlp* net, int64_t n, const float* phi, float* F, int64_t ldf,
+                         void* ws, size_t ws_bytes);
 sketchne_status ws_forward(sketchne_ctx* c, const sketchne_mlp* net, int64_t n, const float* phi, float* F,
                            int64_t ldf, void* ws, size_t ws_bytes);
 sketchne_status ws_grad(sketchne_ctx* c, const sketchne_mlp* net, int64_t n, const float* phi, const float* U,

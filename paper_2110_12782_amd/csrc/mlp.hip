@@ -189,6 +189,148 @@ __global__ __launch_bounds__(512) void k_dense_wide(WideArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- inference pass in BF16
+// The start block only seeds the power iteration, so inference may round the
+// hidden activations to BF16 and run layers 2 and 3 on the BF16 matrix cores
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation):
+//   H1 = bf16(relu(phi W1 + b1)),  H2 = bf16(relu(H1 W2 + b2)),  F = H2 W3 + b3.
+// Width 256, out a multiple of 32 up to 256.  A workgroup of 512 threads owns
+// 128 rows: layer 1 on the vector ALU, H1 and H2 kept in LDS (BF16, rows
+// padded by 8 elements), W2 and W3 streamed through LDS in chunks of 4 k-steps
+// in MFMA B-fragment order (packed once per call by k_pack_wfrag), so every
+// layer reads its activations from LDS and writes nothing but F to memory.
+constexpr int IW = 256;          // hidden width of the BF16 inference kernel
+constexpr int IROWS = 128;       // rows per workgroup
+constexpr int IHS = IW + 8;      // LDS row stride of H (BF16 elements)
+constexpr int IKC = 4;           // k-steps (of 16) per weight chunk
+constexpr int ICHUNK = IKC * 8 * 1024;  // bytes of one chunk: IKC k-steps x 8 column tiles
+
+typedef __bf16 ibf16x8 __attribute__((ext_vector_type(8)));
+
+// W (K x N, row-major BF16, K = 256, N <= 256, N % 32 == 0) -> fragments
+// out[((ks * 8) + jt) * 64 + lane] = W[16ks + 8(lane/32) + e][32jt + lane%32], e < 8
+// (zero for jt >= N/32)
+__global__ void k_pack_wfrag(int N, const uint16_t* __restrict__ W, uint4* __restrict__ out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // (ks, jt, lane)
+  if (idx >= 16 * 8 * 64) return;
+  const int lane = idx & 63, jt = (idx >> 6) & 7, ks = idx >> 9;
+  const int j = 32 * jt + (lane & 31);
+  const int k0 = 16 * ks + 8 * (lane >> 5);
+  uint16_t v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = j < N ? W[(int64_t)(k0 + e) * N + j] : (uint16_t)0;
+  out[idx] = make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16), v[4] | ((uint32_t)v[5] << 16),
+                        v[6] | ((uint32_t)v[7] << 16));
+}
+
+struct InferArgs {
+  int64_t n; int out;
+  const float* phi;            // n x FEAT
+  const uint16_t* W1;          // FEAT x IW
+  const uint16_t* b1;          // IW
+  const uint4* W2f;            // packed fragments of W2 (IW x IW)
+  const uint16_t* b2;          // IW
+  const uint4* W3f;            // packed fragments of W3 (IW x out)
+  const uint16_t* b3;          // out
+  float* F; int64_t ldf;
+};
+
+__global__ __launch_bounds__(512, 2) void k_mlp_infer(InferArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  uint16_t* Hs = reinterpret_cast<uint16_t*>(lds_raw);                      // IROWS x IHS
+  char* Wc = lds_raw + (size_t)IROWS * IHS * 2;                               // 2 chunks
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rt = wave & 3, cg = wave >> 2;  // 32-row tile, 128-column half
+  const int64_t row0 = (int64_t)blockIdx.x * IROWS;
+
+  // layer 1 (vector ALU): thread -> row tid/4, columns 64*(tid%4) .. +63
+  {
+    const int r = tid >> 2, c0 = (tid & 3) * 64;
+    const int64_t gr = row0 + r;
+    float x[FEAT];
+#pragma unroll
+    for (int f = 0; f < FEAT; ++f) x[f] = gr < a.n ? a.phi[gr * FEAT + f] : 0.f;
+    for (int c = c0; c < c0 + 64; c += 2) {
+      float v0 = bf16_val(a.b1[c]), v1 = bf16_val(a.b1[c + 1]);
+#pragma unroll
+      for (int f = 0; f < FEAT; ++f) {
+        v0 = fmaf(x[f], bf16_val(a.W1[f * IW + c]), v0);
+        v1 = fmaf(x[f], bf16_val(a.W1[f * IW + c + 1]), v1);
+      }
+      const uint32_t pk = (uint32_t)bf16_rne(fmaxf(v0, 0.f)) | ((uint32_t)bf16_rne(fmaxf(v1, 0.f)) << 16);
+      *reinterpret_cast<uint32_t*>(Hs + r * IHS + c) = pk;
+    }
+  }
+
+  // one layer: acc[t] = H (rows 32rt..) x W (columns 128cg + 32t ..), weights from Wf
+  floatx16 acc[4];
+  auto layer = [&](const uint4* Wf) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
+    static_assert(ICHUNK / 16 / 512 == 4, "four 16-byte vectors per thread per chunk");
+    uint4 p0 = Wf[tid], p1 = Wf[tid + 512], p2 = Wf[tid + 1024], p3 = Wf[tid + 1536];
+    {
+      uint4* d = reinterpret_cast<uint4*>(Wc);
+      d[tid] = p0; d[tid + 512] = p1; d[tid + 1024] = p2; d[tid + 1536] = p3;
+    }
+    __syncthreads();
+    for (int ch = 0; ch < 16 / IKC; ++ch) {
+      const int buf = ch & 1;
+      const bool more = ch + 1 < 16 / IKC;
+      if (more) {
+        const uint4* src = Wf + (size_t)(ch + 1) * (ICHUNK / 16);
+        p0 = src[tid]; p1 = src[tid + 512]; p2 = src[tid + 1024]; p3 = src[tid + 1536];
+      }
+      const ibf16x8* Wl = reinterpret_cast<const ibf16x8*>(Wc + buf * ICHUNK);
+#pragma unroll
+      for (int kk = 0; kk < IKC; ++kk) {
+        const int ks = ch * IKC + kk;
+        const ibf16x8 av = *reinterpret_cast<const ibf16x8*>(Hs + (32 * rt + (lane & 31)) * IHS + 16 * ks +
+                                                              8 * (lane >> 5));
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const ibf16x8 bv = Wl[(kk * 8 + 4 * cg + t) * 64 + lane];
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[t], 0, 0, 0);
+        }
+      }
+      if (more) {
+        uint4* d = reinterpret_cast<uint4*>(Wc + (buf ^ 1) * ICHUNK);
+        d[tid] = p0; d[tid + 512] = p1; d[tid + 1024] = p2; d[tid + 1536] = p3;
+      }
+      __syncthreads();
+    }
+  };
+
+  __syncthreads();  // H1 complete
+  layer(a.W2f);
+  // H2 = bf16(relu(acc + b2)) over H1 (every wave has finished reading H1)
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int col = 128 * cg + 32 * t + (lane & 31);
+    const float bj = bf16_val(a.b2[col]);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int row = 32 * rt + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+      Hs[row * IHS + col] = bf16_rne(fmaxf(acc[t][e] + bj, 0.f));
+    }
+  }
+  __syncthreads();
+  layer(a.W3f);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int col = 128 * cg + 32 * t + (lane & 31);
+    if (col >= a.out) continue;
+    const float bj = bf16_val(a.b3[col]);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int64_t row = row0 + 32 * rt + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+      if (row < a.n) a.F[row * a.ldf + col] = acc[t][e] + bj;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- A^T B over row ranges
 // part[p](i, j) = sum_{r in range p} A(r, i) B(r, j), i < K1, j < K2.
 // Grid: (ceil(K1/64) * ceil(K2/64), parts).  Rows run in chunks of 32 via LDS.
@@ -641,6 +783,39 @@ sketchne_status ws_forward(sketchne_ctx* c, const sketchne_mlp* net, int64_t n, 
   SK_TRY(dense<uint16_t>(c, n, FEAT, w, phi, FEAT, Wb + f.W1, w, 1, Wb + f.b1, nullptr, 0, H1, w, true, false));
   SK_TRY(dense<uint16_t>(c, n, w, w, H1, w, Wb + f.W2, w, 1, Wb + f.b2, nullptr, 0, H2, w, true, false));
   return dense<uint16_t>(c, n, w, o, H2, w, Wb + f.W3, o, 1, Wb + f.b3, nullptr, 0, F, ldf, false, false);
+}
+
+bool ws_infer_supported(const sketchne_mlp* net) {
+  return net->width == IW && net->out >= 32 && net->out <= IW && net->out % 32 == 0;
+}
+
+size_t ws_infer_bytes() { return 2 * align_up((size_t)16 * 8 * 64 * 16); }
+
+sketchne_status ws_infer(sketchne_ctx* c, const sketchne_mlp* net, int64_t n, const float* phi, float* F, int64_t ldf,
+                         void* ws, size_t ws_bytes) {
+  if (!ws_infer_supported(net)) return SKETCHNE_E_UNSUPPORTED;
+  const int w = net->width, o = net->out;
+  const Off f = offsets(w, o);
+  Arena ar(ws, ws_bytes);
+  uint4* W2f = ar.take<uint4>(16 * 8 * 64);
+  uint4* W3f = ar.take<uint4>(16 * 8 * 64);
+  if (ar.overflow) return SKETCHNE_E_WORKSPACE;
+  if (n == 0) return SKETCHNE_OK;
+  ProfScope ps(c, SKETCHNE_PROF_PREP);
+  const uint16_t* Wb = net->bf16;
+  hipLaunchKernelGGL(k_pack_wfrag, dim3(32), dim3(256), 0, c->stream, w, Wb + f.W2, W2f);
+  hipLaunchKernelGGL(k_pack_wfrag, dim3(32), dim3(256), 0, c->stream, o, Wb + f.W3, W3f);
+  InferArgs a;
+  a.n = n; a.out = o; a.phi = phi;
+  a.W1 = Wb + f.W1; a.b1 = Wb + f.b1;
+  a.W2f = W2f; a.b2 = Wb + f.b2;
+  a.W3f = W3f; a.b3 = Wb + f.b3;
+  a.F = F; a.ldf = ldf;
+  const size_t shmem = (size_t)IROWS * IHS * 2 + 2 * (size_t)ICHUNK;
+  hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp_infer), hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)shmem);
+  hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + IROWS - 1) / IROWS)), dim3(512), shmem, c->stream, a);
+  return launch_status();
 }
 
 sketchne_status ws_grad(sketchne_ctx* c, const sketchne_mlp* net, int64_t n, const float* phi, const float* U,

@@ -111,9 +111,10 @@ def test_warm_start_null_arguments_rejected(lib):
     p = B.SketchParams(k=8, s_eig=8, d=4, h=8, l=16, z=4).c()
     assert L.sketchne_ws_init(None, C.byref(net), 1) == B.E_ARG
     assert L.sketchne_ws_forward(None, C.byref(net), 10, None, None, 64, None, 0) == B.E_ARG
+    assert L.sketchne_ws_infer(None, C.byref(net), 10, None, None, 64, None, 0) == B.E_ARG
     assert L.sketchne_ws_grad(None, C.byref(net), 10, None, None, 64, 0.1, None, None, None, 0) == B.E_ARG
     assert L.sketchne_ws_adam(None, C.byref(net), None, 1e-3, 1) == B.E_ARG
     assert L.sketchne_ritz_residual(None, C.byref(g), 0.5, 8, None, None, None, None, 0) == B.E_ARG
     fb = C.c_int32(0)
     assert L.sketchne_eig_learned(None, C.byref(g), C.byref(p), C.byref(net), 1, 1.0, None, None, C.byref(fb),
-                                  None, 0) == B.E_ARG
+                                  None, None, 0) == B.E_ARG

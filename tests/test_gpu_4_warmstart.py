@@ -91,6 +91,24 @@ def test_forward_and_gradient_parity(lib, n, width, out):
     assert eg <= 1e-5 and max(blocks.values()) <= 1e-4
 
 
+@pytest.mark.parametrize("n,out", [(1000, 256), (4099, 64), (70, 32)])
+def test_bf16_inference_parity(lib, n, out):
+    """The inference pass (BF16 hidden activations on the BF16 matrix cores)
+    against the oracle's BF16-inference semantics on the same BF16 weights, and
+    against the exact forward pass within the activation-rounding bound."""
+    net, phi, U, phi_d, U_d = _net_and_inputs(lib, n, 256, out, 300 + n)
+    p = om.unflatten(net.bf16_values(), 256, out)
+    F = lib.ws_infer(net, phi_d).cpu().numpy().astype(np.float64)
+    ref = om.forward_bf16(p, phi.astype(np.float64))
+    _, _, exact = om.forward(p, phi.astype(np.float64))
+    e_inf, e_exact = rel(F, ref), rel(F, exact)
+    say(f"n={n} out={out}: BF16 inference vs oracle BF16 semantics {e_inf:.2e}, vs exact forward {e_exact:.2e}")
+    # FP32 sums against FP64 sums can move an activation across a BF16
+    # rounding boundary (one BF16 unit, 2^-8 relative) in a few entries
+    assert e_inf <= 1e-3
+    assert e_exact <= 2e-2
+
+
 def test_adam_parity_and_bf16_copy(lib):
     net, phi, U, phi_d, U_d = _net_and_inputs(lib, 777, 128, 32, 5)
 
@@ -160,8 +178,13 @@ def test_training_gain_and_fallback(lib):
         row = []
         for q in (0, 1, 2):
             Up, lp = lib.eig(G, P(q, 11))
-            Uw, lw, fb = lib.eig_learned(G, P(q, 11), net, q, float("inf"))
+            Uw, lw, fb, worst = lib.eig_learned(G, P(q, 11), net, q, float("inf"), with_residual=True)
             assert not fb
+            # the decision residual (from the Rayleigh-Ritz Gram) equals the
+            # largest ||X u_j - lambda_j u_j|| formed with a further SpMM
+            direct = float(lib.ritz_residual(G, 0.5, Uw, lw).max())
+            say(f"  q={q}: worst Ritz residual {worst:.6e} (Gram form) vs {direct:.6e} (SpMM form)")
+            assert abs(worst - direct) <= 1e-4 * direct + 1e-6
             row.append((q, _sin_theta(Up, Uref), _sin_theta(Uw, Uref)))
         say(f"held-out graph {i}: " + "  ".join(f"q={q}: plain {a:.4f} learned {b:.4f}" for q, a, b in row))
         gains.append(row)

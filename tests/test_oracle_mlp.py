@@ -118,3 +118,31 @@ def test_bf16_round_ties_to_even():
     assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2 ** -6 and r[3] == 1.0 + 2 ** -7
     assert r[4] == -2.5
     assert abs(mlp.bf16_round(np.pi) - np.pi) <= 2 ** -8 * np.pi
+
+
+def test_bf16_inference_exact_on_representable_activations():
+    # small integer weights and inputs: every pre-activation is an integer of
+    # magnitude < 256, exactly representable in bfloat16, so the BF16 inference
+    # pass must equal the exact forward pass bit for bit
+    rng = np.random.default_rng(7)
+    width, out, n = 16, 8, 40
+    p = {"W1": rng.integers(-1, 2, (mlp.FEAT, width)).astype(float), "b1": rng.integers(-2, 3, width).astype(float),
+         "W2": rng.integers(-1, 2, (width, width)).astype(float), "b2": rng.integers(-2, 3, width).astype(float),
+         "W3": rng.integers(-1, 2, (width, out)).astype(float) * 0.5, "b3": rng.integers(-2, 3, out).astype(float)}
+    phi = rng.integers(-2, 3, (n, mlp.FEAT)).astype(float)
+    _, H2, F = mlp.forward(p, phi)
+    assert np.abs(H2).max() < 256
+    assert np.array_equal(mlp.forward_bf16(p, phi), F)
+
+
+def test_bf16_inference_within_rounding_bound():
+    # each hidden activation is rounded with relative error <= 2^-9, so F moves
+    # by at most the rounding of H1 propagated through |W2|, |W3| plus that of H2
+    phi, theta, U, width, out = _small_problem(seed=3)
+    p = mlp.unflatten(theta, width, out)
+    H1, H2, F = mlp.forward(p, phi)
+    Fb = mlp.forward_bf16(p, phi)
+    u = 2.0 ** -9
+    bound = (u * H1) @ np.abs(p["W2"]) @ np.abs(p["W3"]) + u * (H2 + (u * H1) @ np.abs(p["W2"])) @ np.abs(p["W3"])
+    assert np.all(np.abs(Fb - F) <= bound + 1e-12)
+    assert np.abs(Fb - F).max() > 0  # the rounding is not vacuous here
