@@ -205,23 +205,29 @@ def main():
     print(json.dumps(line))
 
 
+TRAIN_GRAPHS, TRAIN_LOGN, TRAIN_STEPS = 16, 17, 2000
+
+
 def learned_form(lib, g, p, ws, plain_form):
-    """Learned warm start of Alg. 5: train the network on eight seeded graphs
-    (n = 2^16, SBM and Chung-Lu, exponent 2.0-2.5, mean degree 8-32) against
-    their own converged eigenvectors (q = 16), then compare the Gaussian and
-    learned starts on the bench graph (held out) at q = 0, 1, 2: subspace
-    error of U_k against a q = 16 reference and eigensolver time."""
+    """Learned warm start of Alg. 5: train the network on sixteen seeded
+    graphs (n = 2^17, SBM and Chung-Lu, exponent 2.0-2.5, mean degree 8-32)
+    against their own converged eigenvectors (q = 16), then compare the
+    Gaussian and learned starts on the bench graph (held out) at q = 0, 1, 2:
+    subspace error of U_k against a q = 16 reference and eigensolver time."""
     import torch
     import synth
     from paper_2110_12782_amd.binding import DeviceGraph, MLP, SketchParams
     t0 = time.time()
     sets = []
     calib = []
-    for i in range(8):
+    nt = 1 << TRAIN_LOGN
+    for i in range(TRAIN_GRAPHS):
         if i % 2 == 0:
-            rp, ci = synth.sbm([4096] * 16, 0.0035 + 0.001 * (i % 4), 0.0001, 6000 + i)
+            # 16 blocks; edge probabilities scaled with n to keep the degrees of the n = 2^16 family
+            f = (1 << 16) / nt
+            rp, ci = synth.sbm([nt // 16] * 16, 0.0035 * f * (1 + 0.3 * (i % 4)), 0.0001 * f, 6000 + i)
         else:
-            rp, ci = synth.chung_lu(1 << 16, 2.0 + 0.125 * (i % 5), 8 + 8 * (i % 4), 2, 6000 + i)
+            rp, ci = synth.chung_lu(nt, 2.0 + 0.125 * (i % 5), 8 + 8 * (i % 4), 2, 6000 + i)
         G = DeviceGraph(rp, ci)
         pr = SketchParams(k=p.k, s_eig=p.s_eig, q=16, d=p.d, h=p.h, l=p.l, z=p.z, seed=100 + i)
         Uref, _ = lib.eig(G, pr)
@@ -235,7 +241,7 @@ def learned_form(lib, g, p, ws, plain_form):
     t_data = time.time() - t0
     net = MLP(lib, 256, p.k)
     lib.ws_init(net, 11)
-    steps = 480
+    steps = TRAIN_STEPS
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     losses = lib.ws_train(net, sets, steps, 1e-3, 0.1)
@@ -295,7 +301,7 @@ def learned_form(lib, g, p, ws, plain_form):
             f"({v['learned_eig_ms']:.1f} ms)" for k, v in rows.items()) + f"; iterations saved {saved}; "
         f"whole step with the learned start at q={qw}: {lstep_ms:.2f} ms (plain q=2: {plain_form['ms_per_step']:.2f} ms), "
         f"fallback threshold {threshold:.3f}, fallback used {sum(fbs)}/3")
-    return {"training": {"graphs": 8, "n": 1 << 16, "steps": steps, "seconds": t_train,
+    return {"training": {"graphs": TRAIN_GRAPHS, "n": nt, "steps": steps, "seconds": t_train,
                          "loss_first16": float(losses[:16].mean()), "loss_last16": float(losses[-16:].mean())},
             "held_out": "the bench graph (reference: q = 16)", "by_q": rows, "iterations_saved": saved,
             "step": {"q_warm": qw, "ms_per_step": lstep_ms, "plain_q2_ms_per_step": plain_form["ms_per_step"],
