@@ -31,7 +31,7 @@ def _params(prec, split):
                         precision=prec, split_r=split)
 
 
-@pytest.mark.parametrize("prec,split,tol", [(1, 32, 1e-2), (0, 0, 1e-4)])
+@pytest.mark.parametrize("prec,split,tol", [(1, 32, 1e-2), (2, 32, 1e-2), (0, 0, 1e-4)])
 def test_fullsize_sketch_sampled_rows(lib, big, prec, split, tol):
     import torch
     rowptr, colidx, A, G = big
