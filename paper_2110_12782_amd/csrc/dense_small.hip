@@ -2,7 +2,8 @@
 //
 // Cholesky: G = R^T R for an SPD m x m matrix (m <= 512), right-looking and
 // blocked by 32 inside one 512-thread workgroup (diagonal blocks factored by
-// one wavefront in registers, trailing updates on the FP64 matrix cores).  The same row operations are
+// one wavefront in registers, row panels and trailing updates on the FP64
+// matrix cores).  The same row operations are
 // applied to an appended identity, so the right half ends up holding R^-T
 // (block row J of [R | R^-T] is R_JJ^-T times the updated block row J of
 // [G | I]).  A pivot that is not positive restarts the factorization once with
@@ -16,6 +17,8 @@ namespace skne {
 namespace {
 
 constexpr int NB = 32;
+constexpr int CH_MAXM = 512;            // largest order
+constexpr int CH_CHUNKS = CH_MAXM / 64;  // 64-column chunks of a row
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
@@ -25,53 +28,92 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// Cholesky of the jb x jb diagonal block held in D (LDS, upper triangle, row
-// stride NB + 1) by one wavefront: lane b keeps column b in registers (the
-// block is padded with the identity beyond jb), row t of the factor is
-// exchanged with readlane, so no workgroup barrier is needed.  Sets *fail
-// when a pivot is not positive.
-__device__ void chol_diag_wave(double* D, int jb, int lane, int* fail) {
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Factorization of the jb x jb diagonal block by one wavefront.  Lanes 0..31
+// hold the columns of the block (upper triangle, read from D: LDS, row stride
+// NB + 1; padded with the identity beyond jb), lanes 32..63 the columns of an
+// identity, and the row operations of the factorization turn the pair into
+// [R_JJ | R_JJ^-T].  Row t is passed between lanes through LDS (xrow; LDS
+// operations of one wavefront complete in order).  On return the left lanes
+// have written R_JJ to W (and added the column sums of |R_JJ| to colsum when
+// it is non-null), and D holds R_JJ^-T, padded with the identity.  Sets
+// *fail when a pivot is not positive.
+__device__ void chol_diag_wave(double* D, double* xrow, double* W, int64_t m2, int j0, int jb, int lane,
+                               double* colsum, int* fail) {
+  const int b = lane & (NB - 1);
+  const bool right = lane >= NB;
   double c[NB];
 #pragma unroll
   for (int a = 0; a < NB; ++a) {
-    double v = 0.0;
-    if (lane < jb && a < jb) v = a <= lane ? D[a * (NB + 1) + lane] : 0.0;
-    else if (a == lane) v = 1.0;
+    double v = a == b ? 1.0 : 0.0;
+    if (!right && b < jb && a < jb) v = a <= b ? D[a * (NB + 1) + b] : 0.0;
     c[a] = v;
   }
   bool bad = false;
 #pragma unroll
   for (int t = 0; t < NB; ++t) {
-    double d = readlane_d(c[t], t);
-    if (!(d > 0.0) || !isfinite(d)) { bad = true; d = 1.0; }
-    d = sqrt(d);
-    if (lane == t) c[t] = d;
-    else if (lane > t) c[t] /= d;
+    double piv = readlane_d(c[t], t);
+    if (!(piv > 0.0) || !isfinite(piv)) { bad = true; piv = 1.0; }
+    const double d = sqrt(piv);
+    const double rd = 1.0 / d;
+    // (entries below the diagonal of a left column are never read, so they
+    // take the same unconditional operations as the rest)
+    c[t] = (!right && b == t) ? d : c[t] * rd;
+    xrow[lane] = c[t];  // row t of [R_JJ | R_JJ^-T]
 #pragma unroll
-    for (int a = t + 1; a < NB; ++a) {
-      const double rta = readlane_d(c[t], a);  // R(t, a)
-      if (a <= lane) c[a] = fma(-rta, c[t], c[a]);
-    }
+    for (int a = t + 1; a < NB; ++a) c[a] = fma(-xrow[a], c[t], c[a]);  // xrow[a] = R(t, a)
   }
-  if (lane < jb) {
+  if (!right) {
+    if (b < jb) {
+      double cs = 0.0;
 #pragma unroll
-    for (int a = 0; a < NB; ++a)
-      if (a <= lane) D[a * (NB + 1) + lane] = c[a];
+      for (int a = 0; a < NB; ++a)
+        if (a <= b) {
+          W[(int64_t)(j0 + a) * m2 + j0 + b] = c[a];
+          cs += fabs(c[a]);
+        }
+      if (colsum) colsum[j0 + b] += cs;
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < NB; ++a) D[a * (NB + 1) + b] = c[a];
   }
   if (bad && lane == 0) *fail = 1;
 }
 
+// W (m x 2m, row-major) holds [Gs | I] and is reduced in place to [Rs | Rs^-T].
+// Only the parts the factorization reads are ever written or read: the left
+// half on and above the diagonal, the right half below the diagonal and in
+// the diagonal blocks.  Every loop over W keeps many loads in flight (a row
+// per wavefront, its 64-column chunks over the lanes, several rows at once),
+// since one workgroup is bound by the latency of its loads, not by their
+// bandwidth.
 __global__ __launch_bounds__(512) void k_chol_inv(int m, const double* __restrict__ G, double* __restrict__ W,
-                                                   double* __restrict__ RinvT, uint32_t* __restrict__ flags,
-                                                   int* __restrict__ need_more, const int* __restrict__ run_if) {
+                                                  double* __restrict__ RinvT, uint32_t* __restrict__ flags,
+                                                  int* __restrict__ need_more, const int* __restrict__ run_if) {
   if (run_if && *run_if == 0) return;
   extern __shared__ double smem[];
-  double* D = smem;               // NB x (NB+1)
+  double* D = smem;                  // NB x (NB+1)
   double* P = smem + NB * (NB + 1);  // NB x m panel
-  __shared__ double dsc[512];     // column scales sqrt(G_ii) (1 for a zero column)
+  __shared__ double rsc[CH_MAXM];     // 1 / sqrt(G_ii) (1 for a zero or invalid diagonal)
+  __shared__ double colsum[CH_MAXM];  // column sums of |Rs|, added as block rows of Rs are finished
+  __shared__ double xrow[64];         // row exchange of the diagonal-block factorization
+  __shared__ double s_red[2][8];
   __shared__ int s_fail;
   __shared__ int s_shifted;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), nw = nt >> 6;
   const int64_t m2 = 2 * (int64_t)m;
 
   // The scaled matrix Gs = S^-1 G S^-1 (S = diag(sqrt(G_ii))) is factored:
@@ -79,102 +121,135 @@ __global__ __launch_bounds__(512) void k_chol_inv(int m, const double* __restric
   // Cholesky-QR basis does not depend on the scaling, and the condition
   // number that decides a second pass is the scaled one (power iterates
   // differ mostly in column scale).
+  double trp = 0.0;
   for (int i = tid; i < m; i += nt) {
     const double g = G[(int64_t)i * m + i];
-    dsc[i] = (g > 0.0 && isfinite(g)) ? sqrt(g) : 1.0;
+    const double r = (g > 0.0 && isfinite(g)) ? 1.0 / sqrt(g) : 1.0;
+    rsc[i] = r;
+    trp += fabs(g) * r * r;
   }
+  trp = wave_sum(trp);
+  if (lane == 0) s_red[0][wv] = trp;
+  if (tid == 0) s_shifted = 0;
   __syncthreads();
-  if (tid == 0) {
-    double tr = 0.0;
-    for (int i = 0; i < m; ++i) tr += fabs(G[(int64_t)i * m + i]) / (dsc[i] * dsc[i]);
-    s_fail = 0;
-    s_shifted = 0;
-    // shifted retry: s = 11 (m^2 + m) u trace(Gs)  (shifted Cholesky-QR)
-    D[0] = 11.0 * ((double)m * m + m) * 1.1102230246251565e-16 * (tr > 0 ? tr : 1.0);
-  }
-  __syncthreads();
-  const double retry_shift = D[0];
-  __syncthreads();
+  double tr = 0.0;
+  for (int w = 0; w < nw; ++w) tr += s_red[0][w];
+  // shifted retry: s = 11 (m^2 + m) u trace(Gs)  (shifted Cholesky-QR)
+  const double retry_shift = 11.0 * ((double)m * m + m) * 1.1102230246251565e-16 * (tr > 0 ? tr : 1.0);
 
   for (int attempt = 0; attempt < 2; ++attempt) {
     const double shift = attempt == 0 ? 0.0 : retry_shift;
-    for (int64_t idx = tid; idx < (int64_t)m * m2; idx += nt) {
-      int64_t r = idx / m2, c = idx - r * m2;
-      double v;
-      if (c < m) {
-        int64_t a = r < c ? r : c, b = r < c ? c : r;  // symmetric: read the upper triangle
-        v = G[a * m + b] / (dsc[a] * dsc[b]) + (r == c ? shift : 0.0);
-      } else {
-        v = (c - m == r) ? 1.0 : 0.0;
+    for (int r0 = 4 * wv; r0 < m; r0 += 4 * nw) {
+      double v[4][CH_CHUNKS];
+#pragma unroll
+      for (int h = 0; h < 4; ++h)
+#pragma unroll
+        for (int cc = 0; cc < CH_CHUNKS; ++cc) {
+          const int r = r0 + h, c = lane + 64 * cc;
+          v[h][cc] = (r < m && c < m && c >= r) ? G[(int64_t)r * m + c] : 0.0;
+        }
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int r = r0 + h;
+        if (r >= m) break;
+        double* row = W + (int64_t)r * m2;
+        const int rend = min(m, (r / NB + 1) * NB);  // right half: up to the end of the diagonal block
+        const double rr = rsc[r];
+#pragma unroll
+        for (int cc = 0; cc < CH_CHUNKS; ++cc) {
+          const int c = lane + 64 * cc;
+          if (c < m && c >= r) row[c] = v[h][cc] * rr * rsc[c] + (c == r ? shift : 0.0);
+          if (c < rend) row[m + c] = c == r ? 1.0 : 0.0;
+        }
       }
-      W[idx] = v;
     }
+    for (int j = tid; j < m; j += nt) colsum[j] = 0.0;
     if (tid == 0) s_fail = 0;
     __syncthreads();
 
     for (int j0 = 0; j0 < m; j0 += NB) {
       const int jb = min(NB, m - j0);
       // 1. factor the diagonal block in LDS (one wavefront)
-      for (int idx = tid; idx < jb * jb; idx += nt) {
-        int a = idx / jb, b = idx % jb;
-        D[a * (NB + 1) + b] = (b >= a) ? W[(int64_t)(j0 + a) * m2 + j0 + b] : 0.0;
+      for (int idx = tid; idx < NB * NB; idx += nt) {
+        const int a = idx / NB, b = idx % NB;
+        D[a * (NB + 1) + b] = (b < jb && a <= b) ? W[(int64_t)(j0 + a) * m2 + j0 + b] : 0.0;
       }
       __syncthreads();
-      if (tid < 64) chol_diag_wave(D, jb, tid, &s_fail);
+      if (tid < 64) chol_diag_wave(D, xrow, W, m2, j0, jb, tid, need_more ? colsum : nullptr, &s_fail);
       __syncthreads();
       if (s_fail) break;
-      for (int idx = tid; idx < jb * jb; idx += nt) {
-        int a = idx / jb, b = idx % jb;
-        if (b >= a) W[(int64_t)(j0 + a) * m2 + j0 + b] = D[a * (NB + 1) + b];
-      }
-      // 2. row panel: W[J, c] <- R_JJ^-T W[J, c] for the left columns right of
-      //    the block and the right columns that can be non-zero (< j0 + jb)
+      // 2. row panel X = R_JJ^-T W[J, c] for the left columns right of the
+      //    block and the right columns that can be non-zero (< j0 + jb), on
+      //    the FP64 matrix cores: 16 x 16 tiles of X (rows i, columns pc),
+      //    A(i, k) = R_JJ^-T(i, k) from D, B(k, j) = W[j0 + k, col(pc0 + j)].
+      //    X goes back to W and, zero-padded to NB rows, to the panel P.
       const int nleft = m - j0 - jb;
-      for (int pc = tid; pc < m; pc += nt) {
-        int64_t col = pc < nleft ? (int64_t)(j0 + jb + pc) : (int64_t)m + (pc - nleft);
-        double x[NB];
-        // all loads first (the solve writes the same column back)
+      for (int ct = wv; ct < (m + 15) / 16; ct += nw) {
+        const int pc = 16 * ct + (lane & 15);
+        const bool okc = pc < m;
+        const int64_t col = pc < nleft ? (int64_t)(j0 + jb + pc) : (int64_t)m + (pc - nleft);
+        double bv[NB / 4];
 #pragma unroll
-        for (int t = 0; t < NB; ++t) x[t] = t < jb ? W[(int64_t)(j0 + t) * m2 + col] : 0.0;
-#pragma unroll
-        for (int t = 0; t < NB; ++t) {
-          if (t < jb) {
-            double v = x[t];
-            for (int s2 = 0; s2 < t; ++s2) v -= D[s2 * (NB + 1) + t] * x[s2];
-            x[t] = v / D[t * (NB + 1) + t];
-          }
+        for (int kk = 0; kk < NB / 4; ++kk) {
+          const int k = 4 * kk + (lane >> 4);
+          bv[kk] = (okc && k < jb) ? W[(int64_t)(j0 + k) * m2 + col] : 0.0;
         }
+        doublex4 x0 = {0.0, 0.0, 0.0, 0.0}, x1 = x0;
 #pragma unroll
-        for (int t = 0; t < NB; ++t) {
-          if (t < jb) W[(int64_t)(j0 + t) * m2 + col] = x[t];
-          P[t * m + pc] = t < jb ? x[t] : 0.0;  // zero padding rows of a partial last block
+        for (int kk = 0; kk < NB / 4; ++kk) {
+          const int k = 4 * kk + (lane >> 4);
+          x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(D[(lane & 15) * (NB + 1) + k], bv[kk], x0, 0, 0, 0);
+          x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(D[(16 + (lane & 15)) * (NB + 1) + k], bv[kk], x1, 0, 0, 0);
+        }
+        double cs = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i0 = (lane >> 4) + 4 * q, i1 = i0 + 16;
+          if (okc) {
+            if (i0 < jb) W[(int64_t)(j0 + i0) * m2 + col] = x0[q];
+            if (i1 < jb) W[(int64_t)(j0 + i1) * m2 + col] = x1[q];
+            P[i0 * m + pc] = x0[q];
+            P[i1 * m + pc] = x1[q];
+          }
+          cs += fabs(x0[q]) + fabs(x1[q]);
+        }
+        if (need_more) {
+          cs += __shfl_xor(cs, 16, 64);
+          cs += __shfl_xor(cs, 32, 64);
+          if (lane < 16 && pc < nleft) colsum[col] += cs;
         }
       }
       __syncthreads();
       // 3. trailing update of the rows below the block on the FP64 matrix
       //    cores: W[r, col(pc)] -= sum_t P[t][pr] P[t][pc] in 16 x 16 tiles
       //    (v_mfma_f64_16x16x4f64; A(i, k) = -P[k][pr0 + i], B(k, j) = P[k][pc0 + j];
-      //    output lane l, register q: row (l / 16) + 4 q, column l % 16).  Tiles
-      //    wholly below the diagonal of the left part are skipped; only the
-      //    upper triangle of the left part is written.
+      //    output lane l, register q: row (l / 16) + 4 q, column l % 16).
+      //    Only live tiles are enumerated: tile row tr of the left part starts
+      //    at the diagonal (tiles wholly below it are never read), and only
+      //    the upper triangle of the left part is written.
       {
         const int nrows = nleft;
         const int tr_n = (nrows + 15) / 16, tc_n = (m + 15) / 16;
-        const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-        // two tiles per pass so that their loads overlap
-        for (int tix0 = 2 * wv; tix0 < tr_n * tc_n; tix0 += 2 * nw) {
-          doublex4 acc[2];
-          int64_t gofs[2][4];
-          bool ok[2][4];
-          bool live[2];
-          int trs[2], pcs[2];
+        const int FL = nleft / 16;  // tiles tc < FL lie wholly in the left part
+        int nlive = 0;
+        for (int tr = 0; tr < tr_n; ++tr) nlive += tc_n - min(tr, FL);
+        // four tiles per pass, so that their 16 loads per lane overlap
+        constexpr int UT = 4;
+        for (int base = UT * wv; base < nlive; base += UT * nw) {
+          doublex4 acc[UT];
+          int64_t gofs[UT][4];
+          bool ok[UT][4];
+          bool live[UT];
+          int pras[UT], pcs[UT];
 #pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const int tix = tix0 + u;
-            const int tr = tix / tc_n, tc = tix - tr * tc_n;
-            // outside the grid, or strictly below the diagonal of the left part
-            live[u] = tix < tr_n * tc_n && !(16 * tc + 15 < nleft && tc < tr);
-            trs[u] = tr;
+          for (int u = 0; u < UT; ++u) {
+            int li = base + u;
+            live[u] = li < nlive;
+            if (!live[u]) li = 0;
+            int tr = 0, len = tc_n;
+            while (li >= len) { li -= len; ++tr; len = tc_n - min(tr, FL); }
+            const int tc = min(tr, FL) + li;
+            pras[u] = 16 * tr + (lane & 15);
             const int pc = 16 * tc + (lane & 15);
             pcs[u] = pc;
 #pragma unroll
@@ -186,21 +261,19 @@ __global__ __launch_bounds__(512) void k_chol_inv(int m, const double* __restric
               acc[u][q] = ok[u][q] ? W[gofs[u][q]] : 0.0;
             }
           }
+          // k outer, tiles inner: the UT accumulation chains interleave
 #pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            if (!live[u]) continue;
-            const int pra = 16 * trs[u] + (lane & 15);
-            const int pc = pcs[u];
+          for (int k0 = 0; k0 < NB; k0 += 4) {
+            const int t = k0 + (lane >> 4);
 #pragma unroll
-            for (int k0 = 0; k0 < NB; k0 += 4) {
-              const int t = k0 + (lane >> 4);
-              const double av = pra < nrows ? -P[t * m + pra] : 0.0;
-              const double bv = pc < m ? P[t * m + pc] : 0.0;
+            for (int u = 0; u < UT; ++u) {
+              const double av = (live[u] && pras[u] < nrows) ? -P[t * m + pras[u]] : 0.0;
+              const double bv = (live[u] && pcs[u] < m) ? P[t * m + pcs[u]] : 0.0;
               acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
             }
           }
 #pragma unroll
-          for (int u = 0; u < 2; ++u)
+          for (int u = 0; u < UT; ++u)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
               if (ok[u][q]) W[gofs[u][q]] = acc[u][q];
@@ -216,32 +289,43 @@ __global__ __launch_bounds__(512) void k_chol_inv(int m, const double* __restric
     }
     __syncthreads();
   }
-  for (int64_t idx = tid; idx < (int64_t)m * m; idx += nt) {
-    int64_t r = idx / m, c = idx - r * m;
-    RinvT[idx] = c <= r ? W[r * m2 + m + c] / dsc[c] : 0.0;
+  // R^-T = Rs^-T S^-1 from the lower triangle of the right half (zeros above
+  // it), and the row sums of |Rs^-T| for the condition number
+  double rmax = 0.0;
+  for (int r0 = 4 * wv; r0 < m; r0 += 4 * nw) {
+    double x[4][CH_CHUNKS];
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int cc = 0; cc < CH_CHUNKS; ++cc) {
+        const int r = r0 + h, c = lane + 64 * cc;
+        x[h][cc] = (r < m && c <= r) ? W[(int64_t)r * m2 + m + c] : 0.0;
+      }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int r = r0 + h;
+      if (r >= m) break;
+      double rs = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < CH_CHUNKS; ++cc) {
+        const int c = lane + 64 * cc;
+        if (c < m) RinvT[(int64_t)r * m + c] = x[h][cc] * rsc[c];
+        rs += fabs(x[h][cc]);
+      }
+      rmax = fmax(rmax, wave_sum(rs));
+    }
   }
   if (need_more) {
-    // kappa_1(Rs) = ||Rs||_1 ||Rs^-1||_1 from the two halves of W: column sums
-    // of the upper triangle of Rs and row sums of Rs^-T
-    __shared__ double s_red[2][16];
-    double cmax = 0.0, rmax = 0.0;
-    for (int j = tid; j < m; j += nt) {
-      double cs = 0.0, rs = 0.0;
-      for (int i = 0; i <= j; ++i) cs += fabs(W[(int64_t)i * m2 + j]);
-      for (int c2 = 0; c2 <= j; ++c2) rs += fabs(W[(int64_t)j * m2 + m + c2]);
-      cmax = fmax(cmax, cs);
-      rmax = fmax(rmax, rs);
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      cmax = fmax(cmax, __shfl_xor(cmax, off, 64));
-      rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
-    }
-    if ((tid & 63) == 0) { s_red[0][tid >> 6] = cmax; s_red[1][tid >> 6] = rmax; }
+    // kappa_1(Rs) = ||Rs||_1 ||Rs^-1||_1: the largest column sum of Rs and
+    // the largest row sum of Rs^-T
+    double cmax = 0.0;
+    for (int j = tid; j < m; j += nt) cmax = fmax(cmax, colsum[j]);
+    cmax = wave_max(cmax);
+    if (lane == 0) { s_red[0][wv] = cmax; s_red[1][wv] = rmax; }
     __syncthreads();
     if (tid == 0) {
       double a = 0.0, b = 0.0;
-      for (int w = 0; w < nt / 64; ++w) { a = fmax(a, s_red[0][w]); b = fmax(b, s_red[1][w]); }
+      for (int w = 0; w < nw; ++w) { a = fmax(a, s_red[0][w]); b = fmax(b, s_red[1][w]); }
       double kappa = a * b;
       *need_more = (s_shifted || !(kappa <= kCholQRRepeat)) ? 1 : 0;
     }
@@ -295,12 +379,6 @@ __device__ __forceinline__ void pair_of(int s, int pi, int mp, int& p, int& q) {
   else { a = (s + pi) % ring; b = (s - pi + ring) % ring; }
   p = a < b ? a : b;
   q = a < b ? b : a;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
 }
 
 // one DPP move of a double (two 32-bit halves)
@@ -619,7 +697,7 @@ sketchne_status copy_if(sketchne_ctx* c, int64_t count, const float* src, float*
 sketchne_status chol_inv(sketchne_ctx* c, int m, const double* G, double* RinvT, double* work, int* need_more,
                          const int* run_if) {
   if (m <= 0) return SKETCHNE_OK;
-  if (m > 512) return SKETCHNE_E_UNSUPPORTED;
+  if (m > CH_MAXM) return SKETCHNE_E_UNSUPPORTED;
   ProfScope ps(c, SKETCHNE_PROF_SMALL);
   size_t shmem = sizeof(double) * (NB * (NB + 1) + (size_t)NB * m);
   hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_inv), hipFuncAttributeMaxDynamicSharedMemorySize,
