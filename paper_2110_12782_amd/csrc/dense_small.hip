@@ -357,8 +357,9 @@ __global__ void k_copy_if(int64_t count, const float* __restrict__ src, float* _
 // blocks by the round-robin (circle) schedule.  In a cross launch one
 // workgroup takes a block pair (P, Q); group g of 16 lanes keeps column g of P
 // in registers for all 16 rounds and meets column (g + round) mod 16 of Q,
-// which is the only data that moves (through LDS).  Rows are strided by 16
-// over the lanes of a group and the three inner products are reduced by DPP.
+// which is the only data that moves (through LDS).  Columns are stored with
+// 288 rows (zero below m), a lane holds pairs of adjacent rows strided by 32,
+// and the three inner products are reduced by DPP.
 // Every sweep counts its rotations and its "large" rotations (|g| above
 // OJ_BIG sqrt(ab)).  A sweep without a large rotation ends the iteration:
 // the off-diagonal it leaves is of the order of the square of that bound
@@ -367,6 +368,7 @@ __global__ void k_copy_if(int64_t count, const float* __restrict__ src, float* _
 constexpr int NBJ = 16;           // columns per block
 constexpr int OJ_GL = 16;         // lanes per column (one DPP row)
 constexpr int OJ_MAXR = 18;       // rows per lane: m <= OJ_GL * OJ_MAXR = 288
+constexpr int OJ_ROWS = OJ_GL * OJ_MAXR;  // stored column length; rows m.. are zero
 constexpr int OJ_THREADS = NBJ * OJ_GL;
 constexpr double OJ_SHIFT = 1.5;  // c = OJ_SHIFT * ||A||_F
 constexpr double OJ_BIG = 1e-8;   // a rotation with |g| > OJ_BIG sqrt(ab) is large
@@ -425,15 +427,17 @@ __global__ __launch_bounds__(1024) void k_oj_norm(int m, const double* __restric
   }
 }
 
-// G (column-major, mp columns of m rows) = A + c I (zero padding columns), counters = 0
+// G (column-major, mp columns of OJ_ROWS rows) = A + c I, zero-padded in both
+// directions (zero rows stay zero under rotations, so the kernels below need
+// no row bounds), counters = 0
 __global__ void k_oj_init(int m, int mp, const double* __restrict__ A, const double* __restrict__ shift,
                           double* __restrict__ G, int* __restrict__ counters, int max_sweeps) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < max_sweeps) counters[idx] = 0;
-  if (idx >= mp * m) return;
-  int c = idx / m, r = idx - c * m;
+  if (idx >= mp * OJ_ROWS) return;
+  int c = idx / OJ_ROWS, r = idx - c * OJ_ROWS;
   double g = 0.0;
-  if (c < m) {
+  if (c < m && r < m) {
     g = r <= c ? A[r * m + c] : A[c * m + r];
     if (r == c) g += *shift;
   }
@@ -459,18 +463,24 @@ __device__ __forceinline__ bool oj_angle(double a, double b, double g, double& c
   return true;
 }
 
-// orthogonalise columns p and q of sG (LDS, column-major, m rows) by the
-// lanes of one column group; returns whether a rotation was applied
-__device__ __forceinline__ bool oj_rotate_lds(double* __restrict__ sG, int m, int p, int q, int sub, bool& big) {
-  double* gp = sG + p * m;
-  double* gq = sG + q * m;
+// Lane sub of a column group holds rows 2 sub + 2 OJ_GL i and the row after
+// it (i < OJ_MAXR / 2): one 16-byte access per pair, and the 16 lanes of a
+// group cover 256 contiguous bytes.
+__device__ __forceinline__ int oj_row(int sub, int i) { return 2 * sub + 2 * OJ_GL * i; }
+
+// orthogonalise columns p and q of sG (LDS, column-major, OJ_ROWS rows) by
+// the lanes of one column group; returns whether a rotation was applied
+__device__ __forceinline__ bool oj_rotate_lds(double* __restrict__ sG, int p, int q, int sub, bool& big) {
+  double* gp = sG + p * OJ_ROWS;
+  double* gq = sG + q * OJ_ROWS;
   double x[OJ_MAXR], y[OJ_MAXR];
   double a = 0.0, b = 0.0, g = 0.0;
 #pragma unroll
-  for (int i = 0; i < OJ_MAXR; ++i) {
-    const int r = sub + OJ_GL * i;
-    x[i] = r < m ? gp[r] : 0.0;
-    y[i] = r < m ? gq[r] : 0.0;
+  for (int i = 0; i < OJ_MAXR / 2; ++i) {
+    const double2 u = *reinterpret_cast<const double2*>(gp + oj_row(sub, i));
+    const double2 v = *reinterpret_cast<const double2*>(gq + oj_row(sub, i));
+    x[2 * i] = u.x; x[2 * i + 1] = u.y;
+    y[2 * i] = v.x; y[2 * i + 1] = v.y;
   }
 #pragma unroll
   for (int i = 0; i < OJ_MAXR; ++i) {
@@ -484,17 +494,16 @@ __device__ __forceinline__ bool oj_rotate_lds(double* __restrict__ sG, int m, in
   double c, sn;
   if (!oj_angle(a, b, g, c, sn, big)) return false;
 #pragma unroll
-  for (int i = 0; i < OJ_MAXR; ++i) {
-    const int r = sub + OJ_GL * i;
-    if (r < m) {
-      gp[r] = c * x[i] - sn * y[i];
-      gq[r] = sn * x[i] + c * y[i];
-    }
+  for (int i = 0; i < OJ_MAXR / 2; ++i) {
+    *reinterpret_cast<double2*>(gp + oj_row(sub, i)) =
+        make_double2(c * x[2 * i] - sn * y[2 * i], c * x[2 * i + 1] - sn * y[2 * i + 1]);
+    *reinterpret_cast<double2*>(gq + oj_row(sub, i)) =
+        make_double2(sn * x[2 * i] + c * y[2 * i], sn * x[2 * i + 1] + c * y[2 * i + 1]);
   }
   return true;
 }
 
-// load / store NBJ contiguous columns of m doubles (a block) with double2,
+// load / store contiguous columns of OJ_ROWS doubles with double2,
 // `batch` transfers in flight per thread
 __device__ __forceinline__ void oj_block_load(const double* __restrict__ src, double* __restrict__ dst, int count) {
   constexpr int BATCH = 6;
@@ -516,12 +525,12 @@ __device__ __forceinline__ void oj_block_load(const double* __restrict__ src, do
 // workgroup w orthogonalises the pairs inside blocks 2w and 2w+1 (both in LDS)
 __global__ __launch_bounds__(OJ_THREADS) void k_oj_intra(int m, int sweep, double* __restrict__ G, int* __restrict__ counters) {
   if (sweep > 0 && counters[kMaxSweeps + sweep - 1] == 0) return;
-  extern __shared__ double lds[];
-  double* sG = lds;  // 2 NBJ columns x m rows
+  extern __shared__ __attribute__((aligned(16))) double lds[];
+  double* sG = lds;  // 2 NBJ columns x OJ_ROWS rows
   __shared__ int s_rot, s_big;
   const int tid = threadIdx.x;
   if (tid == 0) s_rot = s_big = 0;
-  const int blk = NBJ * m;
+  const int blk = NBJ * OJ_ROWS;
   double* g0 = G + (int64_t)(2 * blockIdx.x) * blk;  // blocks 2w, 2w+1 are contiguous
   oj_block_load(g0, sG, 2 * blk);
   __syncthreads();
@@ -532,7 +541,7 @@ __global__ __launch_bounds__(OJ_THREADS) void k_oj_intra(int m, int sweep, doubl
     int p, q;
     pair_of(rnd, grp & 7, NBJ, p, q);
     bool big;
-    if (oj_rotate_lds(sG, m, p + half * NBJ, q + half * NBJ, sub, big) && sub == 0) {
+    if (oj_rotate_lds(sG, p + half * NBJ, q + half * NBJ, sub, big) && sub == 0) {
       ++my_rot;
       my_big += big;
     }
@@ -551,33 +560,35 @@ __global__ __launch_bounds__(OJ_THREADS) void k_oj_intra(int m, int sweep, doubl
 __global__ __launch_bounds__(OJ_THREADS) void k_oj_cross(int m, int nb, int s, int sweep, double* __restrict__ G,
                                                   int* __restrict__ counters) {
   if (sweep > 0 && counters[kMaxSweeps + sweep - 1] == 0) return;
-  extern __shared__ double lds[];
-  double* sQ = lds;  // NBJ columns x m rows
+  extern __shared__ __attribute__((aligned(16))) double lds[];
+  double* sQ = lds;  // NBJ columns x OJ_ROWS rows
   __shared__ int s_rot, s_big;
   int P, Q;
   pair_of(s, blockIdx.x, nb, P, Q);
   const int tid = threadIdx.x, grp = tid / OJ_GL, sub = tid % OJ_GL;
   if (tid == 0) s_rot = s_big = 0;
-  const int blk = NBJ * m;
-  double* gpcol = G + (int64_t)P * blk + (int64_t)grp * m;
+  const int blk = NBJ * OJ_ROWS;
+  double* gpcol = G + (int64_t)P * blk + (int64_t)grp * OJ_ROWS;
   double* gQ = G + (int64_t)Q * blk;
   double x[OJ_MAXR];
 #pragma unroll
-  for (int i = 0; i < OJ_MAXR; ++i) {
-    const int r = sub + OJ_GL * i;
-    x[i] = r < m ? gpcol[r] : 0.0;
+  for (int i = 0; i < OJ_MAXR / 2; ++i) {
+    const double2 u = *reinterpret_cast<const double2*>(gpcol + oj_row(sub, i));
+    x[2 * i] = u.x;
+    x[2 * i + 1] = u.y;
   }
   oj_block_load(gQ, sQ, blk);
   __syncthreads();
   int my_rot = 0, my_big = 0;
   for (int rnd = 0; rnd < NBJ; ++rnd) {
-    double* gq = sQ + ((grp + rnd) & (NBJ - 1)) * m;
+    double* gq = sQ + ((grp + rnd) & (NBJ - 1)) * OJ_ROWS;
     double y[OJ_MAXR];
     double a = 0.0, b = 0.0, g = 0.0;
 #pragma unroll
-    for (int i = 0; i < OJ_MAXR; ++i) {
-      const int r = sub + OJ_GL * i;
-      y[i] = r < m ? gq[r] : 0.0;
+    for (int i = 0; i < OJ_MAXR / 2; ++i) {
+      const double2 v = *reinterpret_cast<const double2*>(gq + oj_row(sub, i));
+      y[2 * i] = v.x;
+      y[2 * i + 1] = v.y;
     }
 #pragma unroll
     for (int i = 0; i < OJ_MAXR; ++i) {
@@ -592,11 +603,12 @@ __global__ __launch_bounds__(OJ_THREADS) void k_oj_cross(int m, int nb, int s, i
     bool big;
     if (oj_angle(a, b, g, c, sn, big)) {
 #pragma unroll
-      for (int i = 0; i < OJ_MAXR; ++i) {
-        const int r = sub + OJ_GL * i;
-        const double xi = x[i];
-        x[i] = c * xi - sn * y[i];
-        if (r < m) gq[r] = sn * xi + c * y[i];
+      for (int i = 0; i < OJ_MAXR / 2; ++i) {
+        const double x0 = x[2 * i], x1 = x[2 * i + 1];
+        x[2 * i] = c * x0 - sn * y[2 * i];
+        x[2 * i + 1] = c * x1 - sn * y[2 * i + 1];
+        *reinterpret_cast<double2*>(gq + oj_row(sub, i)) =
+            make_double2(sn * x0 + c * y[2 * i], sn * x1 + c * y[2 * i + 1]);
       }
       if (sub == 0) {
         ++my_rot;
@@ -606,10 +618,8 @@ __global__ __launch_bounds__(OJ_THREADS) void k_oj_cross(int m, int nb, int s, i
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < OJ_MAXR; ++i) {
-    const int r = sub + OJ_GL * i;
-    if (r < m) gpcol[r] = x[i];
-  }
+  for (int i = 0; i < OJ_MAXR / 2; ++i)
+    *reinterpret_cast<double2*>(gpcol + oj_row(sub, i)) = make_double2(x[2 * i], x[2 * i + 1]);
   if (sub == 0 && my_rot) atomicAdd(&s_rot, my_rot);
   if (sub == 0 && my_big) atomicAdd(&s_big, my_big);
   oj_block_load(sQ, gQ, blk);
@@ -642,7 +652,7 @@ __global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restr
     for (int i = 0; i < (OJ_GL * OJ_MAXR + 63) / 64; ++i) {
       const int r = lane + 64 * i;
       if (r < m) {
-        const double v = G[(int64_t)j * m + r];
+        const double v = G[(int64_t)j * OJ_ROWS + r];
         d = fma(v, v, d);
       }
     }
@@ -670,7 +680,7 @@ __global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restr
   for (int64_t idx = tid; idx < (int64_t)m * m; idx += blockDim.x) {
     const int j = (int)(idx / m), r = (int)(idx % m);
     // a zero matrix (c = 0) has G = 0: its eigenvectors are the unit vectors
-    const double v = inv[j] > 0.0 ? G[idx] * inv[j] : (r == j ? 1.0 : 0.0);
+    const double v = inv[j] > 0.0 ? G[(int64_t)j * OJ_ROWS + r] * inv[j] : (r == j ? 1.0 : 0.0);
     Vout[(int64_t)r * m + rank[j]] = v;
   }
 }
@@ -741,7 +751,7 @@ sketchne_status ritz_from_gram(sketchne_ctx* c, int m, int k, const double* G, c
 
 size_t symeig_ws_bytes(int m) {
   int mp = oj_nblocks(m) * NBJ;
-  size_t mat = align_up(sizeof(double) * (size_t)mp * m);
+  size_t mat = align_up(sizeof(double) * (size_t)mp * OJ_ROWS);
   return mat + align_up(sizeof(int) * 2 * kMaxSweeps) + align_up(sizeof(double));
 }
 
@@ -750,16 +760,16 @@ sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* Vout, do
   if (m > OJ_GL * OJ_MAXR) return SKETCHNE_E_UNSUPPORTED;
   const int nb = oj_nblocks(m), mp = nb * NBJ;
   Arena ar(ws, symeig_ws_bytes(m));
-  double* G = ar.take<double>((size_t)mp * m);
+  double* G = ar.take<double>((size_t)mp * OJ_ROWS);
   int* counters = ar.take<int>(2 * kMaxSweeps);  // rotations, then large rotations, per sweep
   double* shift = ar.take<double>(1);
   ProfScope ps(c, SKETCHNE_PROF_SMALL);
   hipLaunchKernelGGL(k_oj_norm, dim3(1), dim3(1024), 0, c->stream, m, A, shift);
-  int tot = mp * m;
+  int tot = mp * OJ_ROWS;
   hipLaunchKernelGGL(k_oj_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, m, mp, A, shift, G,
                      counters, 2 * kMaxSweeps);
-  const size_t sh_intra = sizeof(double) * (size_t)(2 * NBJ) * m;
-  const size_t sh_cross = sizeof(double) * (size_t)NBJ * m;
+  const size_t sh_intra = sizeof(double) * (size_t)(2 * NBJ) * OJ_ROWS;
+  const size_t sh_cross = sizeof(double) * (size_t)NBJ * OJ_ROWS;
   hipFuncSetAttribute(reinterpret_cast<const void*>(k_oj_intra), hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)sh_intra);
   hipFuncSetAttribute(reinterpret_cast<const void*>(k_oj_cross), hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
   const int grp = q % GR_GROUPS;
   const int range = (q / GR_GROUPS) * 8 + (L & 7);
   if (range >= g.nranges) return;
-  extern __shared__ float lds[];
+  extern __shared__ __attribute__((aligned(16))) float lds[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int S = g.stride;
   const int CH = GR_CHUNK * S;
