@@ -446,9 +446,12 @@ __global__ void k_oj_init(int m, int mp, const double* __restrict__ A, const dou
 
 // Jacobi rotation that orthogonalises the pair (x, y) given a = x.x, b = y.y,
 // g = x.y; returns false when the pair is already orthogonal to 1e-14; `big`
-// reports |g| > OJ_BIG sqrt(ab).  With d = b - a and r = sqrt(d^2 + 4 g^2),
-// t = tan(theta) = sgn(d) 2g / (|d| + r) is the smaller root of
-// t^2 + (d/g) t - 1 = 0, c = 1 / sqrt(1 + t^2), s = c t.
+// reports |g| > OJ_BIG sqrt(ab).  The angle is the smaller one,
+// |theta| <= pi / 4: with d = b - a and h = sqrt(d^2 + 4 g^2),
+// cos(2 theta) = |d| / h and sin(2 theta) = sgn(d) 2 g / h, so
+// c^2 = (1 + |d| / h) / 2 and s = sgn(d) g / (h c) (tan(theta) =
+// sgn(d) 2g / (|d| + h)); two reciprocal square roots and no division keep
+// the dependent chain short.
 __device__ __forceinline__ bool oj_angle(double a, double b, double g, double& c, double& sn, bool& big) {
   const double tol = 1e-14;
   const double g2 = g * g, ab = a * b;
@@ -456,10 +459,11 @@ __device__ __forceinline__ bool oj_angle(double a, double b, double g, double& c
   if (!(a > 0.0 && b > 0.0 && g2 > (tol * tol) * ab)) return false;
   big = g2 > (OJ_BIG * OJ_BIG) * ab;
   const double d = b - a;
-  const double r = sqrt(fma(d, d, 4.0 * g2));
-  const double t = (d >= 0.0 ? 2.0 * g : -2.0 * g) / (fabs(d) + r);
-  c = rsqrt(fma(t, t, 1.0));
-  sn = c * t;
+  const double rh = rsqrt(fma(d, d, 4.0 * g2));  // 1 / h
+  const double c2 = fma(fabs(d), 0.5 * rh, 0.5);  // c^2
+  const double rc = rsqrt(c2);
+  c = c2 * rc;
+  sn = (d >= 0.0 ? g : -g) * rh * rc;
   return true;
 }
 
