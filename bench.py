@@ -43,7 +43,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32"])
-    ap.add_argument("--split-r", type=int, default=32)
+    ap.add_argument("--split-r", type=int, default=16)
     ap.add_argument("--scale", type=int, default=20, help="n = 2^scale")
     ap.add_argument("--mean-degree", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

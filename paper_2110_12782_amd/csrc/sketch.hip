@@ -529,11 +529,10 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
     float sa[16], sb[16];
     load_signs(t >= 1 ? tb + t - 1 : -1, sa, sb);
     __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int v = 0; v < VT; ++v)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) cur[v][e] = 0.0f;
     const frag* Al = reinterpret_cast<const frag*>(lds_raw + buf * TB);
+    // the first k-step takes a zero accumulator operand, so the tile's
+    // accumulators need no clearing
+    const floatx16 zero = {};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const frag a = Al[ks * 64 + lane];
@@ -543,7 +542,7 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
         if (ks < KSM) b = bfr[v][ks];
         else if (ks < KB) b = Blo[(v * KSS + ks - KSM) * 64 + lane];
         else b = bfr[v][ks - KB];
-        cur[v] = Op::mma(a, b, cur[v]);
+        cur[v] = Op::mma(a, b, ks == 0 ? zero : cur[v]);
       }
     }
     epilogue(prev, sa, sb);
