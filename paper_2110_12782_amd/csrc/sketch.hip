@@ -214,24 +214,33 @@ __global__ void k_pack_B(int64_t n, int64_t nrows, int64_t nvt, int KSM, int KSS
     if (row >= 0 && kb < k) val = (float)(d1[row] * (double)U[row * ldu + kb]);
     static_cast<float*>(out)[idx] = val;
   } else {
-    uint16_t vv[8];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      vv[e] = 0;
-      const int kappa = kb + e;
-      int comp = -1;
-      bool want_lo = false;
-      if (kappa < 16 * KSM) {
-        comp = kappa < k ? kappa : -1;
+    // the E = 8 summation indices kb .. kb+7 of this lane lie in one section
+    // (sections are whole 16-wide k-steps): components comp0 .. comp0+7 of
+    // the main part (hi, below k) or of the split part (lo, below r)
+    const bool want_lo = kb >= 16 * KSM;
+    const int comp0 = want_lo ? kb - 16 * KSM : kb;
+    const int lim = want_lo ? r : k;
+    uint16_t vv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (row >= 0 && comp0 < lim) {
+      const double s = d1[row];
+      const float* src = U + row * ldu + comp0;
+      float u[8];
+      if (comp0 + 8 <= lim && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+        const float4 a = *reinterpret_cast<const float4*>(src);
+        const float4 b = *reinterpret_cast<const float4*>(src + 4);
+        u[0] = a.x; u[1] = a.y; u[2] = a.z; u[3] = a.w;
+        u[4] = b.x; u[5] = b.y; u[6] = b.z; u[7] = b.w;
       } else {
-        comp = kappa - 16 * KSM;
-        comp = comp < r ? comp : -1;
-        want_lo = true;
+#pragma unroll
+        for (int e = 0; e < E; ++e) u[e] = comp0 + e < lim ? src[e] : 0.0f;
       }
-      if (row >= 0 && comp >= 0) {
-        uint16_t hi, lo;
-        split2(d1[row] * (double)U[row * ldu + comp], PREC, hi, lo);
-        vv[e] = want_lo ? lo : hi;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (comp0 + e < lim) {
+          uint16_t hi, lo;
+          split2(s * (double)u[e], PREC, hi, lo);
+          vv[e] = want_lo ? lo : hi;
+        }
       }
     }
     uint4 w;
