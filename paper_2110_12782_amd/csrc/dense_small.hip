@@ -681,11 +681,15 @@ __global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restr
   }
   __syncthreads();
   for (int i = tid; i < m; i += blockDim.x) wout[rank[i]] = w[i];
-  for (int64_t idx = tid; idx < (int64_t)m * m; idx += blockDim.x) {
-    const int j = (int)(idx / m), r = (int)(idx % m);
-    // a zero matrix (c = 0) has G = 0: its eigenvectors are the unit vectors
-    const double v = inv[j] > 0.0 ? G[(int64_t)j * OJ_ROWS + r] * inv[j] : (r == j ? 1.0 : 0.0);
-    Vout[(int64_t)r * m + rank[j]] = v;
+  // one wavefront per column of G, its rows over the lanes
+  for (int j = wave; j < m; j += 16) {
+    const double s = inv[j];
+    const int rj = rank[j];
+    for (int r = lane; r < m; r += 64) {
+      // a zero matrix (c = 0) has G = 0: its eigenvectors are the unit vectors
+      const double v = s > 0.0 ? G[(int64_t)j * OJ_ROWS + r] * s : (r == j ? 1.0 : 0.0);
+      Vout[(int64_t)r * m + rj] = v;
+    }
   }
 }
 

@@ -231,8 +231,17 @@ __global__ void k_gram_reduce(int m, int nbk, int nblk, int nwg, const double* _
   blk_coords(b, nbk, I, J);
   int i = I * 16 + (lane >> 4) + 4 * r, j = J * 16 + (lane & 15);
   if (i >= m || j >= m) return;
+  // eight partials in flight per step, added in workgroup order
   double s = 0.0;
-  for (int w = 0; w < nwg; ++w) s += partial[((int64_t)w * nblk + b) * 256 + e];
+  int w = 0;
+  for (; w + 8 <= nwg; w += 8) {
+    double p[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) p[u] = partial[((int64_t)(w + u) * nblk + b) * 256 + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += p[u];
+  }
+  for (; w < nwg; ++w) s += partial[((int64_t)w * nblk + b) * 256 + e];
   G[(int64_t)i * m + j] = s;
   if (I != J) G[(int64_t)j * m + i] = s;
 }

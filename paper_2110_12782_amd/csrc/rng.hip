@@ -24,7 +24,7 @@ __device__ __forceinline__ uint64_t draw(uint64_t seed, uint64_t ctr) {
 
 // Box-Muller in FP32: one pair of uniforms gives two normals, written to
 // consecutive elements 2e and 2e+1 of the row-major block.
-__global__ void k_gauss(int64_t n, int cols, int64_t ld, uint64_t seed, float* __restrict__ out) {
+__global__ void k_gauss(int64_t n, int cols, int64_t ld, uint64_t seed, double inv_cols, float* __restrict__ out) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t total = n * cols;
   int64_t i0 = 2 * e;
@@ -34,17 +34,20 @@ __global__ void k_gauss(int64_t n, int cols, int64_t ld, uint64_t seed, float* _
   // two 32-bit uniforms in (0, 1]
   float u1 = ((float)((uint32_t)(r >> 40)) + 1.0f) * (1.0f / 16777216.0f);
   float u2 = (float)((uint32_t)(r >> 8) & 0xffffffu) * (1.0f / 16777216.0f);
-  float rad = sqrtf(-2.0f * logf(u1));
-  float sn, cs;
-  sincosf(6.28318530717958647692f * u2, &sn, &cs);
-  int64_t a = i0 / cols;
+  // Box-Muller on the hardware transcendentals: log2, and sin / cos of an
+  // angle given in revolutions (u2 in [0, 1))
+  const float rad = __builtin_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u1));  // -2 ln 2 log2(u1)
+  const float sn = __builtin_amdgcn_sinf(u2), cs = __builtin_amdgcn_cosf(u2);
+  // row a = i0 / cols from an FP64 quotient (exact below 2^53) corrected by
+  // one step either way, instead of a 64-bit integer division
+  int64_t a = (int64_t)((double)i0 * inv_cols);
+  if (a * cols > i0) --a;
+  else if ((a + 1) * cols <= i0) ++a;
   int b = (int)(i0 - a * cols);
   out[a * ld + b] = rad * cs;
-  int64_t i1 = i0 + 1;
-  if (i1 < total) {
-    int64_t a1 = i1 / cols;
-    int b1 = (int)(i1 - a1 * cols);
-    out[a1 * ld + b1] = rad * sn;
+  if (i0 + 1 < total) {
+    if (++b == cols) { b = 0; ++a; }
+    out[a * ld + b] = rad * sn;
   }
 }
 
@@ -100,7 +103,7 @@ sketchne_status gen_gauss(sketchne_ctx* c, int64_t n, int cols, int64_t ld, uint
   if (total == 0) return SKETCHNE_OK;
   ProfScope ps(c, SKETCHNE_PROF_PREP);
   int64_t blocks = ((total + 1) / 2 + 255) / 256;
-  hipLaunchKernelGGL(k_gauss, dim3((unsigned)blocks), dim3(256), 0, c->stream, n, cols, ld, seed, out);
+  hipLaunchKernelGGL(k_gauss, dim3((unsigned)blocks), dim3(256), 0, c->stream, n, cols, ld, seed, 1.0 / cols, out);
   return launch_status();
 }
 

@@ -215,7 +215,20 @@ __global__ __launch_bounds__(256) void k_spmm_fixup(int64_t n, int64_t nnz, cons
   const int nc4 = cols >> 2;
   for (int c4 = lane; c4 < nc4; c4 += 64) {
     float4 acc = *reinterpret_cast<const float4*>(partial + (2 * ws + 1) * (int64_t)cols + 4 * c4);
-    for (int64_t wv = ws + 1; wv <= we; ++wv) {
+    // a hub row spans many slices: eight partial loads in flight per step,
+    // added in slice order
+    int64_t wv = ws + 1;
+    for (; wv + 8 <= we + 1; wv += 8) {
+      float4 p[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        p[u] = *reinterpret_cast<const float4*>(partial + (2 * (wv + u)) * (int64_t)cols + 4 * c4);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        acc.x += p[u].x; acc.y += p[u].y; acc.z += p[u].z; acc.w += p[u].w;
+      }
+    }
+    for (; wv <= we; ++wv) {
       float4 p = *reinterpret_cast<const float4*>(partial + (2 * wv) * (int64_t)cols + 4 * c4);
       acc.x += p.x; acc.y += p.y; acc.z += p.z; acc.w += p.w;
     }

@@ -42,6 +42,9 @@ def test_gen_gauss(lib, torch):
     g = lib.gen_gauss(200000, 8, 5).cpu().numpy().astype(np.float64)
     assert abs(g.mean()) < 0.01 and abs(g.std() - 1) < 0.01
     assert abs((np.abs(g) < 1).mean() - 0.6827) < 0.005
+    # tails: P(|g| > 2) = 0.0455, P(|g| > 3) = 0.0027 (1.6M draws: sd 1.6e-4 and 4e-5)
+    assert abs((np.abs(g) > 2).mean() - 0.0455) < 0.0015
+    assert abs((np.abs(g) > 3).mean() - 0.0027) < 0.0004
     assert np.array_equal(g, lib.gen_gauss(200000, 8, 5).cpu().numpy())
 
 
