@@ -206,6 +206,7 @@ def main():
 
 
 TRAIN_GRAPHS, TRAIN_LOGN, TRAIN_STEPS = 16, 17, 2000
+TRAIN_MU = 2.0  # weight of the orthogonality term of the loss
 
 
 def learned_form(lib, g, p, ws, plain_form):
@@ -244,7 +245,7 @@ def learned_form(lib, g, p, ws, plain_form):
     steps = TRAIN_STEPS
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    losses = lib.ws_train(net, sets, steps, 1e-3, 0.1)
+    losses = lib.ws_train(net, sets, steps, 1e-3, TRAIN_MU)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     losses = losses.cpu().numpy()
@@ -277,6 +278,19 @@ def learned_form(lib, g, p, ws, plain_form):
     target = rows["q2"]["plain_sin_theta"]
     reach = [q for q in (0, 1, 2) if rows[f"q{q}"]["learned_sin_theta"] <= target]
     saved = 2 - min(reach) if reach else 0
+    # the converse at equal error: plain iterations needed to reach the error
+    # of the learned start at q = 2
+    target_w = rows["q2"]["learned_sin_theta"]
+    plain_err = {q: rows[f"q{q}"]["plain_sin_theta"] for q in (0, 1, 2)}
+    for q in (3, 4, 5):
+        if min(plain_err.values()) <= target_w:
+            break
+        pq = SketchParams(k=p.k, s_eig=p.s_eig, q=q, d=p.d, h=p.h, l=p.l, z=p.z, seed=p.seed)
+        (Up, _), tp = timed(lambda: lib.eig(g, pq, ws=ws))
+        plain_err[q] = err(Up)
+        rows[f"q{q}"] = {"plain_sin_theta": plain_err[q], "plain_eig_ms": tp}
+    need = [q for q in sorted(plain_err) if plain_err[q] <= target_w]
+    q_plain_eq = need[0] if need else None
     # whole step with the learned start at the smallest q that reaches the
     # plain q = 2 error, the fallback armed with the calibrated threshold
     qw = min(reach) if reach else 2
@@ -295,17 +309,54 @@ def learned_form(lib, g, p, ws, plain_form):
     fbs = [lstep() for _ in range(3)]
     torch.cuda.synchronize()
     lstep_ms = (time.perf_counter() - t) / 3 * 1e3
+
+    def whole_step_ms(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / 3 * 1e3
+
+    # whole steps at equal error: learned start at q = 2 against the plain
+    # start at the q that first reaches the same error
+    eq = None
+    if q_plain_eq is not None:
+        pl = SketchParams(k=p.k, s_eig=p.s_eig, q=2, d=p.d, h=p.h, l=p.l, z=p.z, seed=p.seed,
+                          precision=p.precision, split_r=p.split_r)
+        pp = SketchParams(k=p.k, s_eig=p.s_eig, q=q_plain_eq, d=p.d, h=p.h, l=p.l, z=p.z, seed=p.seed,
+                          precision=p.precision, split_r=p.split_r)
+
+        def lstep2():
+            U, lam, _ = lib.eig_learned(g, pl, net, 2, threshold, ws=None)
+            Yt, Z, S, O = lib.sketch(g, pl, U, lam, ws=ws)
+            lib.embed(g.n, pl, Yt, Z, O, ws=ws)
+
+        def pstep():
+            U, lam = lib.eig(g, pp, ws=ws)
+            Yt, Z, S, O = lib.sketch(g, pp, U, lam, ws=ws)
+            lib.embed(g.n, pp, Yt, Z, O, ws=ws)
+
+        eq = {"error": target_w, "learned_q": 2, "learned_ms_per_step": whole_step_ms(lstep2),
+              "plain_q": q_plain_eq, "plain_error": plain_err[q_plain_eq], "plain_ms_per_step": whole_step_ms(pstep),
+              "iterations_saved": q_plain_eq - 2}
     log(f"learned form: data {t_data:.1f}s, {steps} training steps in {t_train:.2f}s, loss {losses[:16].mean():.3f} -> "
         f"{losses[-16:].mean():.3f}; " + "; ".join(
-            f"{k}: plain {v['plain_sin_theta']:.4f} ({v['plain_eig_ms']:.1f} ms) learned {v['learned_sin_theta']:.4f} "
-            f"({v['learned_eig_ms']:.1f} ms)" for k, v in rows.items()) + f"; iterations saved {saved}; "
+            f"{k}: plain {v['plain_sin_theta']:.4f} ({v['plain_eig_ms']:.1f} ms)" + (
+                f" learned {v['learned_sin_theta']:.4f} ({v['learned_eig_ms']:.1f} ms)" if "learned_sin_theta" in v else "")
+            for k, v in rows.items()) + f"; iterations saved {saved}; "
         f"whole step with the learned start at q={qw}: {lstep_ms:.2f} ms (plain q=2: {plain_form['ms_per_step']:.2f} ms), "
-        f"fallback threshold {threshold:.3f}, fallback used {sum(fbs)}/3")
+        f"fallback threshold {threshold:.3f}, fallback used {sum(fbs)}/3; " + (
+            f"at the learned q=2 error {target_w:.4f}: plain needs q={eq['plain_q']} ({eq['plain_error']:.4f}), "
+            f"whole step {eq['plain_ms_per_step']:.2f} ms against {eq['learned_ms_per_step']:.2f} ms learned"
+            if eq else f"plain does not reach the learned q=2 error {target_w:.4f} by q=5"))
     return {"training": {"graphs": TRAIN_GRAPHS, "n": nt, "steps": steps, "seconds": t_train,
                          "loss_first16": float(losses[:16].mean()), "loss_last16": float(losses[-16:].mean())},
             "held_out": "the bench graph (reference: q = 16)", "by_q": rows, "iterations_saved": saved,
             "step": {"q_warm": qw, "ms_per_step": lstep_ms, "plain_q2_ms_per_step": plain_form["ms_per_step"],
-                     "fallback_threshold": threshold, "fallback_used": int(sum(fbs)), "steps": 3}}
+                     "fallback_threshold": threshold, "fallback_used": int(sum(fbs)), "steps": 3},
+            "equal_error_at_learned_q2": eq}
 
 
 def sin_theta(A, B) -> float:

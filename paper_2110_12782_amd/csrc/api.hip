@@ -111,21 +111,22 @@ sketchne_status apply_rinv(sketchne_ctx* c, int64_t n, int m, const float* src, 
 // One Cholesky-QR pass src -> dst.  need_more: set by the Cholesky when a
 // second pass is needed; run_if: the pass runs only when it points to 1.
 sketchne_status orth_pass(sketchne_ctx* c, int64_t n, int m, const float* src, float* dst, int64_t ld,
-                          bool transposed, const OrthWs& w, int* need_more, const int* run_if) {
+                          bool transposed, const OrthWs& w, int* need_more, const int* run_if,
+                          double repeat_kappa = kCholQRRepeat) {
   if (!transposed) SK_TRY(gram_tall(c, n, m, src, ld, 1, nullptr, 0, 0, nullptr, w.G, w.partial, w.partial_cap, run_if));
   else SK_TRY(gram_tall(c, n, m, src, 1, ld, nullptr, 0, 0, nullptr, w.G, w.partial, w.partial_cap, run_if));
-  SK_TRY(chol_inv(c, m, w.G, w.RinvT, w.cwork, need_more, run_if));
+  SK_TRY(chol_inv(c, m, w.G, w.RinvT, w.cwork, need_more, run_if, repeat_kappa));
   return apply_rinv(c, n, m, src, ld, transposed, w.RinvT, dst, w, run_if);
 }
 
 // Cholesky-QR with FP64 Gram and Cholesky: src -> dst, and a second pass
 // (dst -> tmp -> dst) only when the first factor's 1-norm condition number
-// (Gram scaled to unit diagonal) exceeds kCholQRRepeat or its Cholesky needed
-// a shift.  Below that bound one
-// FP64 pass already leaves dst orthonormal to the FP32 rounding of its storage.
+// (Gram scaled to unit diagonal) exceeds repeat_kappa or its Cholesky needed
+// a shift (kCholQRRepeat for a basis used as orthonormal, kCholQRRepeatInner
+// for a power-iteration basis).
 sketchne_status orth2(sketchne_ctx* c, int64_t n, int m, const float* src, float* tmp, float* dst, int64_t ld,
-                      bool transposed, const OrthWs& w) {
-  SK_TRY(orth_pass(c, n, m, src, dst, ld, transposed, w, w.need2, nullptr));
+                      bool transposed, const OrthWs& w, double repeat_kappa = kCholQRRepeat) {
+  SK_TRY(orth_pass(c, n, m, src, dst, ld, transposed, w, w.need2, nullptr, repeat_kappa));
   SK_TRY(orth_pass(c, n, m, dst, tmp, ld, transposed, w, nullptr, w.need2));
   int64_t count = transposed ? (int64_t)m * ld : n * ld;
   return copy_if(c, count, tmp, dst, w.need2);
@@ -463,14 +464,15 @@ static sketchne_status eig_impl(sketchne_ctx* c, const sketchne_graph* A, const 
     SK_TRY(gen_gauss(c, n, K, K, p->seed, w.Q));
     start = w.Q;
   }
-  // line 4-5: Y = X Omega, Q = orth(Y)
+  // line 4-5: Y = X Omega, Q = orth(Y).  Every basis but the last one only
+  // feeds the next X (X Q), so it takes the relaxed second-pass bound.
   SK_TRY(spmm(c, n, A->nnz, A->rowptr, A->colidx, w.dscale, start, K, K, w.P1, K, w.spmm_part));
-  SK_TRY(orth2(c, n, K, w.P1, w.P2, w.Q, K, false, w.ow));
+  SK_TRY(orth2(c, n, K, w.P1, w.P2, w.Q, K, false, w.ow, p->q > 0 ? kCholQRRepeatInner : kCholQRRepeat));
   // lines 6-8: q times Q = orth(X (X Q))
   for (int it = 0; it < p->q; ++it) {
     SK_TRY(spmm(c, n, A->nnz, A->rowptr, A->colidx, w.dscale, w.Q, K, K, w.P1, K, w.spmm_part));
     SK_TRY(spmm(c, n, A->nnz, A->rowptr, A->colidx, w.dscale, w.P1, K, K, w.P2, K, w.spmm_part));
-    SK_TRY(orth2(c, n, K, w.P2, w.P1, w.Q, K, false, w.ow));
+    SK_TRY(orth2(c, n, K, w.P2, w.P1, w.Q, K, false, w.ow, it + 1 < p->q ? kCholQRRepeatInner : kCholQRRepeat));
   }
   // line 9: H = Q^T X Q
   SK_TRY(spmm(c, n, A->nnz, A->rowptr, A->colidx, w.dscale, w.Q, K, K, w.P1, K, w.spmm_part));

@@ -101,7 +101,8 @@ __device__ void chol_diag_wave(double* D, double* xrow, double* W, int64_t m2, i
 // bandwidth.
 __global__ __launch_bounds__(512) void k_chol_inv(int m, const double* __restrict__ G, double* __restrict__ W,
                                                   double* __restrict__ RinvT, uint32_t* __restrict__ flags,
-                                                  int* __restrict__ need_more, const int* __restrict__ run_if) {
+                                                  int* __restrict__ need_more, const int* __restrict__ run_if,
+                                                  double repeat_kappa) {
   if (run_if && *run_if == 0) return;
   extern __shared__ double smem[];
   double* D = smem;                  // NB x (NB+1)
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(512) void k_chol_inv(int m, const double* __restric
       double a = 0.0, b = 0.0;
       for (int w = 0; w < nw; ++w) { a = fmax(a, s_red[0][w]); b = fmax(b, s_red[1][w]); }
       double kappa = a * b;
-      *need_more = (s_shifted || !(kappa <= kCholQRRepeat)) ? 1 : 0;
+      *need_more = (s_shifted || !(kappa <= repeat_kappa)) ? 1 : 0;
     }
   }
 }
@@ -713,7 +714,7 @@ sketchne_status copy_if(sketchne_ctx* c, int64_t count, const float* src, float*
 }
 
 sketchne_status chol_inv(sketchne_ctx* c, int m, const double* G, double* RinvT, double* work, int* need_more,
-                         const int* run_if) {
+                         const int* run_if, double repeat_kappa) {
   if (m <= 0) return SKETCHNE_OK;
   if (m > CH_MAXM) return SKETCHNE_E_UNSUPPORTED;
   ProfScope ps(c, SKETCHNE_PROF_SMALL);
@@ -721,7 +722,7 @@ sketchne_status chol_inv(sketchne_ctx* c, int m, const double* G, double* RinvT,
   hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_inv), hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)shmem);
   hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(512), shmem, c->stream, m, G, work, RinvT, c->d_flags, need_more,
-                     run_if);
+                     run_if, repeat_kappa);
   return launch_status();
 }
 

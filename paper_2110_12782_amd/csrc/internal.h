@@ -142,12 +142,22 @@ sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int
 // inverse factor; writes RinvT (= R^-T, lower triangular, row-major m x m).
 // The Gram matrix is first scaled to unit diagonal.  need_more (nullable):
 // set to 1 when the scaled factor's 1-norm condition number exceeds
-// kCholQRRepeat (or a shift was needed), else 0.  run_if (nullable):
+// repeat_kappa (or a shift was needed), else 0.  run_if (nullable):
 // when it points to 0 the launch does nothing.
+//   kCholQRRepeat: a basis that is used as an orthonormal basis (Rayleigh-
+//     Ritz, the embedding); one FP64 pass below it leaves the FP32 basis
+//     orthonormal to its storage rounding.
+//   kCholQRRepeatInner: a power-iteration basis that only feeds the next
+//     X (X Q).  Any invertible R keeps the span, which is all the next step
+//     uses, and the next orthonormalisation restores orthogonality, so a
+//     second pass is spent only when the Cholesky needed a shift (or the
+//     estimate is not finite).
 constexpr double kCholQRRepeat = 1e5;
+constexpr double kCholQRRepeatInner = __builtin_inf();
 size_t chol_ws_bytes(int m);
 sketchne_status chol_inv(sketchne_ctx* c, int m, const double* G, double* RinvT, double* work,
-                         int* need_more = nullptr, const int* run_if = nullptr);
+                         int* need_more = nullptr, const int* run_if = nullptr,
+                         double repeat_kappa = kCholQRRepeat);
 sketchne_status copy_if(sketchne_ctx* c, int64_t count, const float* src, float* dst, const int* run_if);
 constexpr int kSymeigMax = 288;  // largest order of the Jacobi eigensolver
 size_t symeig_ws_bytes(int m);
