@@ -127,30 +127,45 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, int64_t nnz, const int6
   }
 }
 
-// Narrow variant for blocks of at most 32 columns (8 float4): lane l takes
-// neighbour slot l >> 3 (8 neighbours in flight per wavefront) and column quad
-// l & 7, and the 8 slots are summed with three xor shuffles, so a narrow block
-// does not leave most lanes idle as k_spmm would.  (Splitting a wide block
-// into 32-column launches was measured slower than k_spmm: 5.6 TB/s of
-// 128-byte gathers against 7.3 TB/s of whole-row gathers.)  Rows that cross a
-// slice boundary use the same head/tail partial slots as k_spmm.
-__global__ __launch_bounds__(256) void k_spmm_c32(int64_t n, int64_t nnz, const int64_t* __restrict__ rowptr,
-                                                  const int32_t* __restrict__ colidx,
-                                                  const float* __restrict__ dscale,
-                                                  const float* __restrict__ B, int64_t ldb, int cw,
-                                                  float* __restrict__ C, int64_t ldc,
-                                                  float* __restrict__ partial, const int64_t* __restrict__ brow,
-                                                  int64_t nwaves) {
+// Narrow variant for blocks of at most 32 columns (CWP <= 8 float4 column
+// quads, a power of two).  A row is taken by a group of 8 * CWP lanes: lane
+// slot (sub / CWP) walks every 8th neighbour and column quad sub % CWP, and
+// the 8 slots are summed with xor shuffles inside the group.  A wavefront
+// runs 8 / CWP row groups side by side over the rows of its slice, so a
+// 4-column block (the warm-start probes) has eight rows' dependent load
+// chains in flight instead of one.  (Splitting a wide block into 32-column
+// launches was measured slower than k_spmm: 5.6 TB/s of 128-byte gathers
+// against 7.3 TB/s of whole-row gathers.)  Rows that cross a slice boundary
+// use the same head/tail partial slots as k_spmm.
+template <int CWP>
+__global__ __launch_bounds__(256) void k_spmm_narrow(int64_t n, int64_t nnz, const int64_t* __restrict__ rowptr,
+                                                     const int32_t* __restrict__ colidx,
+                                                     const float* __restrict__ dscale,
+                                                     const float* __restrict__ B, int64_t ldb, int cw,
+                                                     float* __restrict__ C, int64_t ldc,
+                                                     float* __restrict__ partial, const int64_t* __restrict__ brow,
+                                                     int64_t nwaves) {
+  constexpr int GL = 8 * CWP;  // lanes per row group
+  constexpr int NG = 64 / GL;  // row groups per wavefront
   const int lane = threadIdx.x & 63;
   int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   w = __builtin_amdgcn_readfirstlane((int)w);
   if (w >= nwaves) return;
-  const int slot = lane >> 3, c4 = lane & 7;
+  const int grp = lane / GL, sub = lane % GL, slot = sub / CWP, c4 = sub % CWP;
   const bool colok = c4 < cw;
   const int64_t e0 = w * kP;
   const int64_t e1 = min(e0 + (int64_t)kP, nnz);
-  int64_t r = brow[w];
-  while (true) {
+  // rows [rfirst, rend) hold this slice's entries (empty rows among them are
+  // skipped; k_zero_empty writes them)
+  const int64_t rfirst = brow[w];
+  int64_t rend;
+  if (w + 1 < nwaves) {
+    const int64_t rb = brow[w + 1];
+    rend = rowptr[rb] < e1 ? rb + 1 : rb;
+  } else {
+    rend = row_of(rowptr, n, e1 - 1) + 1;
+  }
+  for (int64_t r = rfirst + grp; r < rend; r += NG) {
     const int64_t rs = rowptr[r], re = rowptr[r + 1];
     const int64_t a = max(rs, e0), bnd = min(re, e1);
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -177,22 +192,20 @@ __global__ __launch_bounds__(256) void k_spmm_c32(int64_t n, int64_t nnz, const 
         acc.z = fmaf(s0, v0.z, acc.z); acc.w = fmaf(s0, v0.w, acc.w);
       }
     }
+    // the xor partners stay inside the group, which shares r
 #pragma unroll
-    for (int off = 8; off < 64; off <<= 1) {
+    for (int off = CWP; off < GL; off <<= 1) {
       acc.x += __shfl_xor(acc.x, off, 64);
       acc.y += __shfl_xor(acc.y, off, 64);
       acc.z += __shfl_xor(acc.z, off, 64);
       acc.w += __shfl_xor(acc.w, off, 64);
     }
-    if (slot == 0 && colok) {
+    if (slot == 0 && colok && a < bnd) {
       const float sr = dscale[r];
       const bool whole = (rs >= e0) && (re <= e1);
       float* dst = whole ? (C + r * ldc) : (partial + (2 * w + (rs < e0 ? 0 : 1)) * (int64_t)(4 * cw));
       *reinterpret_cast<float4*>(dst + 4 * c4) = make_float4(sr * acc.x, sr * acc.y, sr * acc.z, sr * acc.w);
     }
-    if (re >= e1) break;
-    ++r;
-    while (rowptr[r + 1] == rowptr[r]) ++r;  // skip empty rows (written by k_zero_empty)
   }
 }
 
@@ -288,10 +301,16 @@ sketchne_status spmm(sketchne_ctx* c, int64_t n, int64_t nnz, const int64_t* row
                          rowptr, cols, C, ldc, partial, brow, nwaves);
     return launch_status();
   }
-  // narrow blocks (<= 32 columns): eight neighbours per wavefront at once
+  // narrow blocks (<= 32 columns): 8 / CWP rows per wavefront at once
   const int cw = cols / 4;
-  hipLaunchKernelGGL(k_spmm_c32, dim3(blocks), dim3(256), 0, c->stream, n, nnz, rowptr, colidx, dscale, B, ldb, cw,
-                     C, ldc, partial, brow, nwaves);
+#define SKNE_NARROW(CWP)                                                                                         \
+  hipLaunchKernelGGL(k_spmm_narrow<CWP>, dim3(blocks), dim3(256), 0, c->stream, n, nnz, rowptr, colidx, dscale, B, \
+                     ldb, cw, C, ldc, partial, brow, nwaves)
+  if (cw <= 1) SKNE_NARROW(1);
+  else if (cw <= 2) SKNE_NARROW(2);
+  else if (cw <= 4) SKNE_NARROW(4);
+  else SKNE_NARROW(8);
+#undef SKNE_NARROW
   if (nwaves > 1)
     hipLaunchKernelGGL(k_spmm_fixup, dim3((unsigned)((nwaves - 1 + 3) / 4)), dim3(256), 0, c->stream, n, nnz,
                        rowptr, cols, C, ldc, partial, brow, nwaves);

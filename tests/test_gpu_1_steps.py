@@ -62,7 +62,9 @@ def _spmm_case(lib, torch, rowptr, colidx, cols, alpha, seed):
     return err, rowerr
 
 
-@pytest.mark.parametrize("cols", [4, 64, 288])
+# 4, 8, 16, 28 and 32 columns take the narrow kernel with 1, 2, 4, 8 and 8
+# column quads per row group (28: one quad of each group masked)
+@pytest.mark.parametrize("cols", [4, 8, 16, 28, 32, 64, 288])
 def test_spmm_sbm(lib, torch, cols):
     say(f"spmm SBM n=4096 cols={cols}")
     rowptr, colidx = c1_graph()
@@ -70,15 +72,16 @@ def test_spmm_sbm(lib, torch, cols):
     assert err < 1e-6 and rowerr < 1e-5
 
 
-def test_spmm_hubs_and_isolated(lib, torch):
+@pytest.mark.parametrize("cols", [288, 4, 12])
+def test_spmm_hubs_and_isolated(lib, torch, cols):
     # Chung-Lu with hubs (rows far longer than one wavefront slice) plus
     # isolated vertices and an empty trailing row
-    say("spmm Chung-Lu n=20000 + isolated, cols=288, alpha=0.4")
+    say(f"spmm Chung-Lu n=20000 + isolated, cols={cols}, alpha=0.4")
     rowptr, colidx = synth.chung_lu(20000, 2.1, 16, 2, 5)
     rowptr = np.concatenate([rowptr[:1], rowptr[1:5001], np.full(3, rowptr[5000]), rowptr[5001:],
                              np.full(2, rowptr[-1])])
     colidx = np.where(colidx >= 5000, colidx + 3, colidx).astype(np.int32)
-    err, rowerr = _spmm_case(lib, torch, rowptr, colidx, 288, 0.4, 1)
+    err, rowerr = _spmm_case(lib, torch, rowptr, colidx, cols, 0.4, 1)
     assert err < 1e-6 and rowerr < 1e-5
 
 
