@@ -97,6 +97,40 @@ def test_orth(lib, torch):
         assert s.max() < 1e-5
 
 
+@pytest.mark.parametrize("kappa", [1e6, 1e12])
+def test_orth_ill_conditioned(lib, torch, kappa):
+    # correlated columns, so the condition number survives the scaling of the
+    # Gram to unit diagonal: 1e6 takes the second Cholesky-QR pass; at 1e12
+    # the FP32 rounding of B leaves an effective condition number near the
+    # limit of the FP64 Gram, so the first Cholesky may take the shifted
+    # retry (flag 1) before the second pass
+    n, K = 20000, 96
+    say(f"orth ill-conditioned n={n} K={K} kappa={kappa:g}")
+    rng = np.random.default_rng(int(np.log10(kappa)))
+    Ua, _ = np.linalg.qr(rng.standard_normal((n, K)))
+    Va, _ = np.linalg.qr(rng.standard_normal((K, K)))
+    B = ((Ua * np.logspace(0, -np.log10(kappa), K)) @ Va.T).astype(np.float32)
+    assert lib.sync() == 0
+    Qd = torch.from_numpy(B.copy()).cuda()
+    Q = lib.orth(Qd).cpu().numpy().astype(np.float64)
+    flags = lib.sync()
+    assert np.isfinite(Q).all()
+    assert np.abs(Q.T @ Q - np.eye(K)).max() < 1e-5
+    if kappa < 1e8:
+        assert flags == 0
+        # the FP32 input itself fixes its span to about kappa * 6e-8
+        s = metrics.sin_principal_angles(Q, B.astype(np.float64))
+        assert s.max() < 0.2
+        # the leading directions (singular values above 1e-3) are exact to FP32 level
+        lead = Ua[:, :K // 2]
+        assert metrics.sin_principal_angles(Q, lead).max() < 5e-4
+    else:
+        assert flags & ~1 == 0  # at most SKETCHNE_FLAG_CHOL_SHIFT
+        say(f"  flags {flags}")
+        lead = Ua[:, :K // 4]
+        assert metrics.sin_principal_angles(Q, lead).max() < 1e-3
+
+
 @pytest.mark.parametrize("m", [2, 7, 64, 288])
 def test_symeig_random(lib, torch, m):
     say(f"symeig random m={m}")
