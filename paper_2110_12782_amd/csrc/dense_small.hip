@@ -65,8 +65,10 @@ __device__ void chol_diag_wave(double* D, double* xrow, double* W, int64_t m2, i
   for (int t = 0; t < NB; ++t) {
     double piv = readlane_d(c[t], t);
     if (!(piv > 0.0) || !isfinite(piv)) { bad = true; piv = 1.0; }
-    const double d = sqrt(piv);
-    const double rd = 1.0 / d;
+    // 1 / R(t, t) from one reciprocal square root and R(t, t) = piv / R(t, t):
+    // a shorter dependent chain than a square root followed by a division
+    const double rd = rsqrt(piv);
+    const double d = piv * rd;
     // (entries below the diagonal of a left column are never read, so they
     // take the same unconditional operations as the rest)
     c[t] = (!right && b == t) ? d : c[t] * rd;
