@@ -114,16 +114,24 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
         int64_t r = c0 + 4 * qq;
         if (i < g.m) {
           const float* px0 = g.X + (int64_t)i * g.xc + r;
-          a.x = r < r1 ? px0[0] : 0.f;
-          a.y = r + 1 < r1 ? px0[1] : 0.f;
-          a.z = r + 2 < r1 ? px0[2] : 0.f;
-          a.w = r + 3 < r1 ? px0[3] : 0.f;
+          if (r + 3 < r1 && (reinterpret_cast<uintptr_t>(px0) & 15) == 0) {
+            a = *reinterpret_cast<const float4*>(px0);
+          } else {
+            a.x = r < r1 ? px0[0] : 0.f;
+            a.y = r + 1 < r1 ? px0[1] : 0.f;
+            a.z = r + 2 < r1 ? px0[2] : 0.f;
+            a.w = r + 3 < r1 ? px0[3] : 0.f;
+          }
           if (TWO) {
             const float* py0 = g.Y + (int64_t)i * g.yc + r;
-            b.x = r < r1 ? py0[0] : 0.f;
-            b.y = r + 1 < r1 ? py0[1] : 0.f;
-            b.z = r + 2 < r1 ? py0[2] : 0.f;
-            b.w = r + 3 < r1 ? py0[3] : 0.f;
+            if (r + 3 < r1 && (reinterpret_cast<uintptr_t>(py0) & 15) == 0) {
+              b = *reinterpret_cast<const float4*>(py0);
+            } else {
+              b.x = r < r1 ? py0[0] : 0.f;
+              b.y = r + 1 < r1 ? py0[1] : 0.f;
+              b.z = r + 2 < r1 ? py0[2] : 0.f;
+              b.w = r + 3 < r1 ? py0[3] : 0.f;
+            }
           }
         }
       }
