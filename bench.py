@@ -206,7 +206,7 @@ def main():
 
 
 TRAIN_GRAPHS, TRAIN_LOGN, TRAIN_STEPS = 16, 17, 2000
-TRAIN_MU = 2.0  # weight of the orthogonality term of the loss
+TRAIN_MU = 10.0  # weight of the orthogonality term of the loss (chosen on held-out graphs)
 
 
 def learned_form(lib, g, p, ws, plain_form):
