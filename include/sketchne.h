@@ -200,12 +200,16 @@ sketchne_status sketchne_gen_sparse_sign(sketchne_ctx* ctx, int64_t n, uint64_t 
  * a 3-layer ReLU network maps per-vertex features to the first out <= k
  * columns of Omega; the other columns stay Gaussian, and the plain Gaussian
  * start remains the fallback.
- *   features   phi_i = [log max(deg_i,1), (Xg)_i, (X^2 g)_i, (X^3 g)_i, (X^4 g)_i]
- *              with X = D^-a A D^-a and g a Rademacher vector, each column
+ *   features   phi_i = [log max(deg_i,1), (X^3 G)_i1 .. (X^3 G)_i4,
+ *                       (X^4 G)_i1 .. (X^4 G)_i3]
+ *              with X = D^-a A D^-a and G an n x SKETCHNE_WS_PROBES block of
+ *              Rademacher vectors (powers of independent probes are random
+ *              combinations of the leading eigenvectors), each column
  *              standardised over the vertices to mean 0 and standard deviation
  *              1 (a column whose standard deviation is at most 1e-6 times its
- *              root mean square is set to 0), padded with zeros to
- *              SKETCHNE_WS_FEAT columns; phi is n x SKETCHNE_WS_FEAT FP32.
+ *              root mean square is set to 0); SKETCHNE_WS_RAW of the
+ *              SKETCHNE_WS_FEAT columns are used (the rest are 0); phi is
+ *              n x SKETCHNE_WS_FEAT FP32.
  *   network    F = relu(relu(phi W1 + b1) W2 + b2) W3 + b3   (n x out FP32)
  *   loss       L = ||(I - U U^T) F||_F^2 / ||F||_F^2
  *                  + mu || (out / ||F||_F^2) F^T F - I ||_F^2
@@ -217,7 +221,8 @@ sketchne_status sketchne_gen_sparse_sign(sketchne_ctx* ctx, int64_t n, uint64_t 
  * copy (round to nearest even).  Products run on the FP32 matrix cores with
  * FP32 accumulation; reductions over vertices use a fixed order. */
 #define SKETCHNE_WS_FEAT 8
-#define SKETCHNE_WS_RAW 5
+#define SKETCHNE_WS_RAW 8
+#define SKETCHNE_WS_PROBES 4
 
 typedef struct {
   int32_t width;     /* hidden width, >= 1                                    */
@@ -243,8 +248,9 @@ sketchne_status sketchne_ws_workspace_size(const sketchne_params* p, int32_t wid
 /* He initialisation N(0, 2/fan_in) of the weights from seed (the padded rows
  * of W1 are 0), zero biases and moments, BF16 copy. */
 sketchne_status sketchne_ws_init(sketchne_ctx* ctx, const sketchne_mlp* net, uint64_t seed);
-/* phi (n x SKETCHNE_WS_FEAT) for the graph; g (n, +-1) is the probe vector,
- * or NULL to draw it on the device from seed. */
+/* phi (n x SKETCHNE_WS_FEAT) for the graph; g (n x SKETCHNE_WS_PROBES
+ * row-major, +-1) is the probe block, or NULL to draw it on the device from
+ * seed. */
 sketchne_status sketchne_ws_features(sketchne_ctx* ctx, const sketchne_graph* A, double alpha, const float* g,
                                      uint64_t seed, float* phi, void* ws, size_t ws_bytes);
 /* F = network(phi): n x out written with leading dimension ldf >= out. */

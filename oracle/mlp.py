@@ -8,12 +8,14 @@ This module defines the learned start used as a replacement for the first k
 columns of that block:
 
 * features (per vertex i, before standardisation)
-      phi_i = [ log max(deg_i, 1), (X g)_i, (X^2 g)_i, (X^3 g)_i, (X^4 g)_i ]
-  with X = D^-a A D^-a (the matrix of Alg. 5) and g a Rademacher vector; each
-  column is then standardised to mean 0 and (population) standard deviation 1
-  over the vertices; a column whose standard deviation is at most 1e-6 times
-  its root mean square is constant up to rounding and is set to 0.  The
-  feature block is padded with zero columns to ``FEAT`` columns.
+      phi_i = [ log max(deg_i, 1), (X^3 g)_i1 .. (X^3 g)_i4, (X^4 g)_i1 .. (X^4 g)_i3 ]
+  with X = D^-a A D^-a (the matrix of Alg. 5) and g an n x 4 block of
+  Rademacher vectors: powers of independent probes are random combinations
+  of the leading eigenvectors of X.  Each column is then standardised to
+  mean 0 and (population) standard deviation 1 over the vertices; a column
+  whose standard deviation is at most 1e-6 times its root mean square is
+  constant up to rounding and is set to 0.  ``N_RAW`` of the ``FEAT`` columns
+  are used (the rest are 0).
 * network  F = relu(relu(phi W1 + b1) W2 + b2) W3 + b3   (n x k)
 * loss     L(F) = ||(I - U U^T) F||_F^2 / ||F||_F^2
                   + mu * || (k / ||F||_F^2) F^T F - I ||_F^2
@@ -34,12 +36,15 @@ import numpy as np
 import scipy.sparse as sp
 
 FEAT = 8  # padded feature width
-N_RAW = 5  # features actually used
+N_RAW = 8  # features used: log-degree, X^3 G (4 columns), X^4 G (first 3 columns)
+N_PROBE = 4  # Rademacher probe vectors
 SPREAD_TOL = 1e-6  # a column with std <= SPREAD_TOL * rms is constant: set to 0
 
 
 def features(rowptr, colidx, alpha: float, g) -> np.ndarray:
-    """phi (n x FEAT), FP64: log-degree and four random-walk probes X^t g."""
+    """phi (n x FEAT), FP64: log-degree and random-walk probes of a block g of
+    N_PROBE Rademacher vectors (n x N_PROBE): all columns of X^3 g and the
+    first three of X^4 g, each column standardised."""
     rowptr = np.asarray(rowptr, dtype=np.int64)
     colidx = np.asarray(colidx, dtype=np.int64)
     n = len(rowptr) - 1
@@ -50,10 +55,13 @@ def features(rowptr, colidx, alpha: float, g) -> np.ndarray:
     X = sp.diags(dp) @ A @ sp.diags(dp)
     raw = np.zeros((n, N_RAW))
     raw[:, 0] = np.log(np.maximum(deg, 1.0))
-    v = np.asarray(g, dtype=np.float64)
-    for t in range(1, N_RAW):
+    v = np.asarray(g, dtype=np.float64).reshape(n, N_PROBE)
+    for t in range(1, 5):
         v = X @ v
-        raw[:, t] = v
+        if t == 3:
+            raw[:, 1:1 + N_PROBE] = v
+        elif t == 4:
+            raw[:, 1 + N_PROBE:N_RAW] = v[:, :N_RAW - 1 - N_PROBE]
     phi = np.zeros((n, FEAT))
     mean = raw.mean(axis=0)
     std = raw.std(axis=0)

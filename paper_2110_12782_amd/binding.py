@@ -317,7 +317,8 @@ class Library:
         self.check(self.lib.sketchne_ws_init(self.ctx(), C.byref(s), seed), "ws_init")
 
     def ws_features(self, g: "DeviceGraph", alpha: float, probe=None, seed: int = 0, ws=None):
-        """phi (n x 8 float32); probe: n float32 (+-1) or None to draw from seed."""
+        """phi (n x 8 float32); probe: n x 4 float32 (+-1, row-major) or None to
+        draw it from seed."""
         import torch
         phi = torch.empty((g.n, WS_FEAT), dtype=torch.float32, device="cuda")
         nb = self.ws_workspace_size(1, 1, g.n, g.nnz, WS_OP_FEATURES)

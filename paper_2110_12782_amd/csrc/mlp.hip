@@ -487,24 +487,24 @@ __global__ void k_to_bf16(int64_t count, const float* __restrict__ x, uint16_t* 
 
 // ---------------------------------------------------------------- features
 // raw(i, 0) = log max(deg_i, 1); T0 = [g, 0, 0, 0] (n x 4)
+// raw column 0 = log max(deg, 1); T0 = the probe block G (n x 4)
 __global__ void k_feat_seed(int64_t n, const int64_t* __restrict__ rowptr, const float* __restrict__ g,
                             float* __restrict__ raw, float* __restrict__ T0) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double deg = (double)(rowptr[i + 1] - rowptr[i]);
   raw[i * FEAT] = (float)log(deg > 1.0 ? deg : 1.0);
-  T0[i * 4 + 0] = g[i];
-  T0[i * 4 + 1] = 0.f;
-  T0[i * 4 + 2] = 0.f;
-  T0[i * 4 + 3] = 0.f;
+  for (int j = 0; j < 4; ++j) T0[i * 4 + j] = g[i * 4 + j];
 }
-__global__ void k_feat_take(int64_t n, int col, const float* __restrict__ T, float* __restrict__ raw) {
+// raw columns col0 .. col0 + ncols - 1 = the first ncols columns of T (n x 4)
+__global__ void k_feat_take(int64_t n, int col0, int ncols, const float* __restrict__ T, float* __restrict__ raw) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) raw[i * FEAT + col] = T[i * 4];
+  if (i >= n) return;
+  for (int j = 0; j < ncols; ++j) raw[i * FEAT + col0 + j] = T[i * 4 + j];
 }
 // Column moments of the raw features in two passes over fixed row ranges
 // (FP64, fixed order): pass 0 sums x, pass 1 sums (x - mean)^2 and x^2.
-// part[(b * 5 + j) * 2 + {0, 1}] for block b.
+// part[(b * SKETCHNE_WS_RAW + j) * 2 + {0, 1}] for block b.
 constexpr int FS_BLOCKS = 256;
 __global__ __launch_bounds__(256) void k_feat_moments(int64_t n, int pass, const float* __restrict__ raw,
                                                       const double* __restrict__ stat, double* __restrict__ part) {
@@ -695,7 +695,7 @@ size_t ws_grad_bytes(int64_t n, int width, int out) {
 }
 
 size_t ws_features_bytes(int64_t n, int64_t nnz) {
-  return 2 * align_up(sizeof(float) * (size_t)n * 4) + align_up(sizeof(float) * (size_t)n) +
+  return 2 * align_up(sizeof(float) * (size_t)n * 4) + align_up(sizeof(float) * (size_t)n * SKETCHNE_WS_PROBES) +
          align_up(sizeof(double) * 2 * FEAT) + align_up(sizeof(double) * FS_BLOCKS * SKETCHNE_WS_RAW * 2) +
          align_up(sizeof(float) * (size_t)n) + spmm_ws_bytes(nnz, 4);
 }
@@ -716,8 +716,9 @@ sketchne_status ws_init(sketchne_ctx* c, const sketchne_mlp* net, uint64_t seed)
   SK_TRY(gen_gauss(c, w, o, o, seed ^ 0x3333, net->master + f.W3));
   hipLaunchKernelGGL(k_scale_f, dim3(nblk((int64_t)SKETCHNE_WS_RAW * w)), dim3(256), 0, c->stream,
                      (int64_t)SKETCHNE_WS_RAW * w, sqrtf(2.f / SKETCHNE_WS_RAW), net->master + f.W1);
-  hipLaunchKernelGGL(k_fill_f, dim3(nblk((int64_t)(FEAT - SKETCHNE_WS_RAW) * w)), dim3(256), 0, c->stream,
-                     (int64_t)(FEAT - SKETCHNE_WS_RAW) * w, 0.f, net->master + f.W1 + (int64_t)SKETCHNE_WS_RAW * w);
+  if (FEAT > SKETCHNE_WS_RAW)
+    hipLaunchKernelGGL(k_fill_f, dim3(nblk((int64_t)(FEAT - SKETCHNE_WS_RAW) * w)), dim3(256), 0, c->stream,
+                       (int64_t)(FEAT - SKETCHNE_WS_RAW) * w, 0.f, net->master + f.W1 + (int64_t)SKETCHNE_WS_RAW * w);
   hipLaunchKernelGGL(k_scale_f, dim3(nblk((int64_t)w * w)), dim3(256), 0, c->stream, (int64_t)w * w,
                      sqrtf(2.f / w), net->master + f.W2);
   hipLaunchKernelGGL(k_scale_f, dim3(nblk((int64_t)w * o)), dim3(256), 0, c->stream, (int64_t)w * o,
@@ -738,7 +739,7 @@ sketchne_status ws_features(sketchne_ctx* c, int64_t n, int64_t nnz, const int64
   Arena ar(ws, ws_bytes);
   float* T0 = ar.take<float>((size_t)n * 4);
   float* T1 = ar.take<float>((size_t)n * 4);
-  float* gdraw = ar.take<float>((size_t)n);
+  float* gdraw = ar.take<float>((size_t)n * SKETCHNE_WS_PROBES);
   double* stat = ar.take<double>(2 * FEAT);
   double* mom = ar.take<double>((size_t)FS_BLOCKS * SKETCHNE_WS_RAW * 2);
   float* dscale = ar.take<float>((size_t)n);
@@ -746,7 +747,7 @@ sketchne_status ws_features(sketchne_ctx* c, int64_t n, int64_t nnz, const int64
   if (ar.overflow) return SKETCHNE_E_WORKSPACE;
   ProfScope ps(c, SKETCHNE_PROF_PREP);
   if (!g) {
-    SK_TRY(gen_rademacher(c, n, seed, gdraw));
+    SK_TRY(gen_rademacher(c, n * SKETCHNE_WS_PROBES, seed, gdraw));
     g = gdraw;
   }
   SK_TRY(degree_scale(c, n, rowptr, alpha, dscale));
@@ -754,9 +755,14 @@ sketchne_status ws_features(sketchne_ctx* c, int64_t n, int64_t nnz, const int64
   SK_TRY(launch_status());
   float* src = T0;
   float* dst = T1;
-  for (int t = 1; t < SKETCHNE_WS_RAW; ++t) {
+  // X^t G for t = 1 .. 4; X^3 G fills raw columns 1-4, X^4 G columns 5-7
+  static_assert(SKETCHNE_WS_PROBES == 4 && SKETCHNE_WS_RAW == 8, "feature layout");
+  for (int t = 1; t <= 4; ++t) {
     SK_TRY(spmm(c, n, nnz, rowptr, colidx, dscale, src, 4, 4, dst, 4, part));
-    hipLaunchKernelGGL(k_feat_take, dim3(nblk(n)), dim3(256), 0, c->stream, n, t, dst, phi);
+    if (t == 3)
+      hipLaunchKernelGGL(k_feat_take, dim3(nblk(n)), dim3(256), 0, c->stream, n, 1, 4, dst, phi);
+    else if (t == 4)
+      hipLaunchKernelGGL(k_feat_take, dim3(nblk(n)), dim3(256), 0, c->stream, n, 5, 3, dst, phi);
     float* tmp = src;
     src = dst;
     dst = tmp;

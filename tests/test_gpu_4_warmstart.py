@@ -27,9 +27,9 @@ def test_features_parity(lib):
     from paper_2110_12782_amd.binding import DeviceGraph
     for rowptr, colidx in (synth.sbm([512] * 8, 0.02, 0.001, 1001), _graph_with_isolated()):
         n = len(rowptr) - 1
-        g = synth.rademacher(n, 21)
+        g = synth.rademacher(n * om.N_PROBE, 21).reshape(n, om.N_PROBE)
         G = DeviceGraph(rowptr, colidx)
-        phi = lib.ws_features(G, 0.5, probe=torch.from_numpy(g).cuda()).cpu().numpy()
+        phi = lib.ws_features(G, 0.5, probe=torch.from_numpy(np.ascontiguousarray(g)).cuda()).cpu().numpy()
         ref = om.features(rowptr, colidx, 0.5, g.astype(np.float64))
         e = rel(phi, ref)
         say(f"n={n} features rel {e:.3e}")

@@ -83,27 +83,30 @@ def test_adam_first_step_closed_form():
 def test_features_on_cycle_closed_form():
     n = 64
     rowptr, colidx = synth.cycle(n)
-    g = synth.rademacher(n, 11).astype(np.float64)
+    g = synth.rademacher(n * mlp.N_PROBE, 11).astype(np.float64).reshape(n, mlp.N_PROBE)
     phi = mlp.features(rowptr, colidx, 0.5, g)
-    # 2-regular: X = A / 2, so X g is the average of the two ring neighbours
-    raw = np.zeros((n, 4))
+    # 2-regular: X = A / 2, so X v is the average of the two ring neighbours
     v = g.copy()
+    powers = []
     for t in range(4):
-        v = 0.5 * (np.roll(v, 1) + np.roll(v, -1))
-        raw[:, t] = v
-    for t in range(4):
-        expect = (raw[:, t] - raw[:, t].mean()) / raw[:, t].std()
-        assert np.allclose(phi[:, 1 + t], expect, atol=1e-12)
+        v = 0.5 * (np.roll(v, 1, axis=0) + np.roll(v, -1, axis=0))
+        powers.append(v)
+    # columns 1-4: X^3 g (all probes); columns 5-7: X^4 g (first three)
+    expect_raw = np.concatenate([powers[2], powers[3][:, :3]], axis=1)
+    for j in range(expect_raw.shape[1]):
+        c = expect_raw[:, j]
+        assert np.allclose(phi[:, 1 + j], (c - c.mean()) / c.std(), atol=1e-12)
     # constant degree: the log-degree column has no spread and is set to 0
     assert np.all(phi[:, 0] == 0.0)
-    assert np.all(phi[:, mlp.N_RAW:] == 0.0)
+    assert mlp.N_RAW == 1 + mlp.N_PROBE + 3 == mlp.FEAT
 
 
 def test_features_standardised_and_isolated_vertices():
     rowptr, colidx = synth.chung_lu(3000, 2.3, 6, 1, 77)
     # append three isolated vertices
     rowptr = np.concatenate([rowptr, [rowptr[-1]] * 3])
-    g = synth.rademacher(len(rowptr) - 1, 12).astype(np.float64)
+    n = len(rowptr) - 1
+    g = synth.rademacher(n * mlp.N_PROBE, 12).astype(np.float64).reshape(n, mlp.N_PROBE)
     phi = mlp.features(rowptr, colidx, 0.5, g)
     assert np.allclose(phi[:, :mlp.N_RAW].mean(axis=0), 0, atol=1e-12)
     assert np.allclose(phi[:, :mlp.N_RAW].std(axis=0), 1, atol=1e-12)
