@@ -194,16 +194,17 @@ __global__ __launch_bounds__(512) void k_dense_wide(WideArgs a) {
 // hidden activations to BF16 and run layers 2 and 3 on the BF16 matrix cores
 // (v_mfma_f32_32x32x16_bf16, FP32 accumulation):
 //   H1 = bf16(relu(phi W1 + b1)),  H2 = bf16(relu(H1 W2 + b2)),  F = H2 W3 + b3.
-// Width 256, out a multiple of 32 up to 256.  A workgroup of 512 threads owns
-// 128 rows: layer 1 on the vector ALU, H1 and H2 kept in LDS (BF16, rows
-// padded by 8 elements), W2 and W3 streamed through LDS in chunks of 4 k-steps
-// in MFMA B-fragment order (packed once per call by k_pack_wfrag), so every
-// layer reads its activations from LDS and writes nothing but F to memory.
+// Width 256, out a multiple of 32 up to 256.  Persistent workgroups of 512
+// threads walk blocks of 128 rows.  Wave w keeps the MFMA B fragments of
+// column tile w of W2 and W3 (packed once per call by k_pack_wfrag) in
+// registers for the whole launch, so no weight moves after the start.  Per
+// row block: layer 1 on the vector ALU, H1 and then H2 in LDS (BF16, rows
+// padded by 8 elements), each wave multiplying all four 32-row tiles of H by
+// its column tile; nothing but F is written to memory.
 constexpr int IW = 256;          // hidden width of the BF16 inference kernel
-constexpr int IROWS = 128;       // rows per workgroup
+constexpr int IROWS = 128;       // rows per row block
 constexpr int IHS = IW + 8;      // LDS row stride of H (BF16 elements)
-constexpr int IKC = 4;           // k-steps (of 16) per weight chunk
-constexpr int ICHUNK = IKC * 8 * 1024;  // bytes of one chunk: IKC k-steps x 8 column tiles
+constexpr int IPERSIST = 256;    // persistent workgroups (one per CU of the MI355X)
 
 typedef __bf16 ibf16x8 __attribute__((ext_vector_type(8)));
 
@@ -235,98 +236,88 @@ struct InferArgs {
   float* F; int64_t ldf;
 };
 
-__global__ __launch_bounds__(512, 2) void k_mlp_infer(InferArgs a) {
+__global__ __launch_bounds__(512, 1) void k_mlp_infer(InferArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds_raw[];
-  uint16_t* Hs = reinterpret_cast<uint16_t*>(lds_raw);                      // IROWS x IHS
-  char* Wc = lds_raw + (size_t)IROWS * IHS * 2;                               // 2 chunks
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int rt = wave & 3, cg = wave >> 2;  // 32-row tile, 128-column half
-  const int64_t row0 = (int64_t)blockIdx.x * IROWS;
-
-  // layer 1 (vector ALU): thread -> row tid/4, columns 64*(tid%4) .. +63
-  {
-    const int r = tid >> 2, c0 = (tid & 3) * 64;
-    const int64_t gr = row0 + r;
-    float x[FEAT];
+  uint16_t* Hs = reinterpret_cast<uint16_t*>(lds_raw);                     // IROWS x IHS
+  float* W1s = reinterpret_cast<float*>(lds_raw + (size_t)IROWS * IHS * 2);  // FEAT x IW
+  float* b1s = W1s + FEAT * IW;                                             // IW
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int ct = __builtin_amdgcn_readfirstlane(tid >> 6);  // this wave's 32-column tile
+  for (int i = tid; i < FEAT * IW; i += 512) W1s[i] = bf16_val(a.W1[i]);
+  for (int i = tid; i < IW; i += 512) b1s[i] = bf16_val(a.b1[i]);
+  // the B fragments of column tile ct of W2 and W3, all 16 k-steps, stay in
+  // registers for every row block of the workgroup
+  ibf16x8 w2[16], w3[16];
+  const ibf16x8* W2f = reinterpret_cast<const ibf16x8*>(a.W2f);
+  const ibf16x8* W3f = reinterpret_cast<const ibf16x8*>(a.W3f);
 #pragma unroll
-    for (int f = 0; f < FEAT; ++f) x[f] = gr < a.n ? a.phi[gr * FEAT + f] : 0.f;
-    for (int c = c0; c < c0 + 64; c += 2) {
-      float v0 = bf16_val(a.b1[c]), v1 = bf16_val(a.b1[c + 1]);
-#pragma unroll
-      for (int f = 0; f < FEAT; ++f) {
-        v0 = fmaf(x[f], bf16_val(a.W1[f * IW + c]), v0);
-        v1 = fmaf(x[f], bf16_val(a.W1[f * IW + c + 1]), v1);
-      }
-      const uint32_t pk = (uint32_t)bf16_rne(fmaxf(v0, 0.f)) | ((uint32_t)bf16_rne(fmaxf(v1, 0.f)) << 16);
-      *reinterpret_cast<uint32_t*>(Hs + r * IHS + c) = pk;
-    }
+  for (int ks = 0; ks < 16; ++ks) {
+    w2[ks] = W2f[(ks * 8 + ct) * 64 + lane];
+    w3[ks] = W3f[(ks * 8 + ct) * 64 + lane];
   }
-
-  // one layer: acc[t] = H (rows 32rt..) x W (columns 128cg + 32t ..), weights from Wf
+  const int col = 32 * ct + (lane & 31);
+  const bool has3 = 32 * ct < a.out;
+  const float bias2 = bf16_val(a.b2[col]);
+  const float bias3 = has3 ? bf16_val(a.b3[col]) : 0.f;
+  const int64_t nblocks = (a.n + IROWS - 1) / IROWS;
   floatx16 acc[4];
-  auto layer = [&](const uint4* Wf) {
+  // one wavefront's product of the four 32-row tiles of Hs with its column
+  // tile, k-steps in order
+  auto layer = [&](const ibf16x8 (&w)[16]) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int rt = 0; rt < 4; ++rt) {
+      floatx16 c = {};
 #pragma unroll
-      for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
-    static_assert(ICHUNK / 16 / 512 == 4, "four 16-byte vectors per thread per chunk");
-    uint4 p0 = Wf[tid], p1 = Wf[tid + 512], p2 = Wf[tid + 1024], p3 = Wf[tid + 1536];
-    {
-      uint4* d = reinterpret_cast<uint4*>(Wc);
-      d[tid] = p0; d[tid + 512] = p1; d[tid + 1024] = p2; d[tid + 1536] = p3;
-    }
-    __syncthreads();
-    for (int ch = 0; ch < 16 / IKC; ++ch) {
-      const int buf = ch & 1;
-      const bool more = ch + 1 < 16 / IKC;
-      if (more) {
-        const uint4* src = Wf + (size_t)(ch + 1) * (ICHUNK / 16);
-        p0 = src[tid]; p1 = src[tid + 512]; p2 = src[tid + 1024]; p3 = src[tid + 1536];
-      }
-      const ibf16x8* Wl = reinterpret_cast<const ibf16x8*>(Wc + buf * ICHUNK);
-#pragma unroll
-      for (int kk = 0; kk < IKC; ++kk) {
-        const int ks = ch * IKC + kk;
+      for (int ks = 0; ks < 16; ++ks) {
         const ibf16x8 av = *reinterpret_cast<const ibf16x8*>(Hs + (32 * rt + (lane & 31)) * IHS + 16 * ks +
                                                               8 * (lane >> 5));
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const ibf16x8 bv = Wl[(kk * 8 + 4 * cg + t) * 64 + lane];
-          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[t], 0, 0, 0);
-        }
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, w[ks], c, 0, 0, 0);
       }
-      if (more) {
-        uint4* d = reinterpret_cast<uint4*>(Wc + (buf ^ 1) * ICHUNK);
-        d[tid] = p0; d[tid + 512] = p1; d[tid + 1024] = p2; d[tid + 1536] = p3;
-      }
-      __syncthreads();
+      acc[rt] = c;
     }
   };
-
-  __syncthreads();  // H1 complete
-  layer(a.W2f);
-  // H2 = bf16(relu(acc + b2)) over H1 (every wave has finished reading H1)
+  for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    const int64_t row0 = blk * IROWS;
+    __syncthreads();  // Hs is free (and W1s, b1s are written on the first pass)
+    // layer 1 (vector ALU): thread -> row tid/4, columns 64*(tid%4) .. +63
+    {
+      const int r = tid >> 2, c0 = (tid & 3) * 64;
+      const int64_t gr = row0 + r;
+      float x[FEAT];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int col = 128 * cg + 32 * t + (lane & 31);
-    const float bj = bf16_val(a.b2[col]);
+      for (int f = 0; f < FEAT; ++f) x[f] = gr < a.n ? a.phi[gr * FEAT + f] : 0.f;
+      for (int c = c0; c < c0 + 64; c += 2) {
+        float v0 = b1s[c], v1 = b1s[c + 1];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int row = 32 * rt + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-      Hs[row * IHS + col] = bf16_rne(fmaxf(acc[t][e] + bj, 0.f));
+        for (int f = 0; f < FEAT; ++f) {
+          v0 = fmaf(x[f], W1s[f * IW + c], v0);
+          v1 = fmaf(x[f], W1s[f * IW + c + 1], v1);
+        }
+        const uint32_t pk = (uint32_t)bf16_rne(fmaxf(v0, 0.f)) | ((uint32_t)bf16_rne(fmaxf(v1, 0.f)) << 16);
+        *reinterpret_cast<uint32_t*>(Hs + r * IHS + c) = pk;
+      }
     }
-  }
-  __syncthreads();
-  layer(a.W3f);
+    __syncthreads();  // H1 complete
+    layer(w2);
+    __syncthreads();  // every wave has finished reading H1
+    // H2 = bf16(relu(acc + b2)) over H1
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int col = 128 * cg + 32 * t + (lane & 31);
-    if (col >= a.out) continue;
-    const float bj = bf16_val(a.b3[col]);
+    for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int64_t row = row0 + 32 * rt + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-      if (row < a.n) a.F[row * a.ldf + col] = acc[t][e] + bj;
+      for (int e = 0; e < 16; ++e) {
+        const int row = 32 * rt + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        Hs[row * IHS + col] = bf16_rne(fmaxf(acc[rt][e] + bias2, 0.f));
+      }
+    __syncthreads();  // H2 complete
+    if (has3) {
+      layer(w3);
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int64_t row = row0 + 32 * rt + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+          if (row < a.n) a.F[row * a.ldf + col] = acc[rt][e] + bias3;
+        }
     }
   }
 }
@@ -817,10 +808,14 @@ sketchne_status ws_infer(sketchne_ctx* c, const sketchne_mlp* net, int64_t n, co
   a.W2f = W2f; a.b2 = Wb + f.b2;
   a.W3f = W3f; a.b3 = Wb + f.b3;
   a.F = F; a.ldf = ldf;
-  const size_t shmem = (size_t)IROWS * IHS * 2 + 2 * (size_t)ICHUNK;
+  const size_t shmem = (size_t)IROWS * IHS * 2 + sizeof(float) * (size_t)(FEAT + 1) * IW;
   hipFuncSetAttribute(reinterpret_cast<const void*>(k_mlp_infer), hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)shmem);
-  hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + IROWS - 1) / IROWS)), dim3(512), shmem, c->stream, a);
+  // persistent workgroups, one per CU: each loads the weights once and walks
+  // row blocks blockIdx.x, blockIdx.x + gridDim.x, ...
+  const int64_t nblocks = (n + IROWS - 1) / IROWS;
+  const unsigned grid = (unsigned)(nblocks < IPERSIST ? nblocks : IPERSIST);
+  hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(512), shmem, c->stream, a);
   return launch_status();
 }
 
