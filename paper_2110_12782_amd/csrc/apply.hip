@@ -33,6 +33,33 @@ struct ApplyArgs {
   const int* run_if;
 };
 
+// One chunk's products for the wave's column blocks 2t + ch, t = T0 .. NBH-1,
+// k-steps in order, as straight-line code.
+template <int T0, int NBH>
+__device__ __forceinline__ void chunk_mfma(const double (*As)[AR + 2], const double (*Bs)[32 * NBH + 2], int rg,
+                                           int ch, int lane, doublex4 (&acc)[2][NBH]) {
+#pragma unroll
+  for (int kk = 0; kk < ABK / 4; ++kk) {
+    const int kr = kk * 4 + (lane >> 4);
+    const double a0 = As[kr][32 * rg + (lane & 15)];
+    const double a1 = As[kr][32 * rg + 16 + (lane & 15)];
+#pragma unroll
+    for (int t = T0; t < NBH; ++t) {
+      const double b = Bs[kr][16 * (2 * t + ch) + (lane & 15)];
+      acc[0][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][t], 0, 0, 0);
+      acc[1][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][t], 0, 0, 0);
+    }
+  }
+}
+
+template <int C, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (C < N) {
+    f(std::integral_constant<int, C>{});
+    static_for<C + 1, N>(f);
+  }
+}
+
 // ACOL: A(i,k) = A[k*lda + i] (else A[i*lda + k]); BCOL: B(k,j) = B[j*ldb + k]
 // (else B[k*ldb + j]); CCOL: C(i,j) = C[j*ldc + i] (else C[i*ldc + j]);
 // TRI: B(k,j) = 0 for k > j.
@@ -47,7 +74,7 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
   __shared__ double Bs[ABK][NC + 2];
   if (g.run_if && *g.run_if == 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int rg = wave & 3, ch = wave >> 2;
+  const int rg = wave & 3, ch = __builtin_amdgcn_readfirstlane(wave >> 2);
   const int64_t i0 = (int64_t)blockIdx.x * AR;
   const int kend = TRI ? min(g.K, g.N) : g.K;
 
@@ -153,26 +180,31 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
   }
   __syncthreads();
   if (nchunk > 1) fetch(ABK);
-  for (int c = 0; c < nchunk; ++c) {
-#pragma unroll
-    for (int kk = 0; kk < ABK / 4; ++kk) {
-      const int kr = kk * 4 + (lane >> 4);
-      const double a0 = As[kr][32 * rg + (lane & 15)];
-      const double a1 = As[kr][32 * rg + 16 + (lane & 15)];
-#pragma unroll
-      for (int t = 0; t < NBH; ++t) {
-        const int jb = 2 * t + ch;              // column blocks interleaved over the two halves
-        if (TRI && 16 * jb + 15 < ABK * c) continue;  // B(k, j) = 0 for the whole block
-        const double b = Bs[kr][16 * jb + (lane & 15)];
-        acc[0][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][t], 0, 0, 0);
-        acc[1][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][t], 0, 0, 0);
-      }
-    }
+  auto advance = [&](int c) {
     __syncthreads();
     if (c + 1 < nchunk) {
       stash();
       __syncthreads();
       if (c + 2 < nchunk) fetch((c + 2) * ABK);
+    }
+  };
+  // column blocks are interleaved over the two halves: block 2t + ch
+  if constexpr (TRI) {
+    // Chunk c (indices 32c .. 32c+31) meets block 2t + ch only if its last
+    // column 32t + 16ch + 15 >= 32c, i.e. t >= c on both halves.  N = K <=
+    // 32 NBH, so there are at most NBH chunks: the loop is unrolled and each
+    // chunk gets a branch-free body over its blocks.
+    static_for<0, NBH>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      if (c < nchunk) {
+        chunk_mfma<c, NBH>(As, Bs, rg, ch, lane, acc);
+        advance(c);
+      }
+    });
+  } else {
+    for (int c = 0; c < nchunk; ++c) {
+      chunk_mfma<0, NBH>(As, Bs, rg, ch, lane, acc);
+      advance(c);
     }
   }
 
