@@ -5,8 +5,10 @@
 // (R^-1 upper triangular), U = Q U^(:, 1:k) after Rayleigh-Ritz, and
 // E = Y (R^-1 U^ Sigma^1/2) in the embedding.  A workgroup owns 128 rows and
 // every output column, so each row of A is read from HBM once and written
-// once; B streams from L2 in chunks of 32 summation indices through LDS, the
-// registers holding the next chunk during the MFMAs.  With a triangular B a
+// once.  A and B stream in chunks of 16 summation indices through two LDS
+// buffers: chunk c + 1 is stored into one while chunk c is multiplied out of
+// the other (one barrier per chunk), and the registers already hold chunk
+// c + 2, fetched from HBM (A) and L2 (B).  With a triangular B a
 // chunk only meets the column blocks at or right of its diagonal, which
 // halves the work of the Cholesky-QR apply; entries below the diagonal are
 // masked on load, whatever the buffer holds there.
@@ -23,7 +25,7 @@ namespace {
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int AR = 128;   // rows per workgroup
-constexpr int ABK = 32;   // summation chunk
+constexpr int ABK = 16;   // summation chunk
 
 struct ApplyArgs {
   int64_t n; int K, N;
@@ -70,8 +72,8 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
   constexpr int APER = AVEC / 512;
   constexpr int BVEC = ABK * NC / 2;                  // double2 per B chunk
   constexpr int BPER = (BVEC + 511) / 512;
-  __shared__ double As[ABK][AR + 2];
-  __shared__ double Bs[ABK][NC + 2];
+  __shared__ double As[2][ABK][AR + 2];
+  __shared__ double Bs[2][ABK][NC + 2];
   if (g.run_if && *g.run_if == 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rg = wave & 3, ch = __builtin_amdgcn_readfirstlane(wave >> 2);
@@ -129,22 +131,22 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
       rb[p] = v;
     }
   };
-  auto stash = [&]() {
+  auto stash = [&](int buf) {
 #pragma unroll
     for (int p = 0; p < APER; ++p) {
       const int e = tid + 512 * p;
       if (!ACOL) {
         const int r = e % AR, q = (e / AR) * 4;
-        As[q + 0][r] = ra[p].x;
-        As[q + 1][r] = ra[p].y;
-        As[q + 2][r] = ra[p].z;
-        As[q + 3][r] = ra[p].w;
+        As[buf][q + 0][r] = ra[p].x;
+        As[buf][q + 1][r] = ra[p].y;
+        As[buf][q + 2][r] = ra[p].z;
+        As[buf][q + 3][r] = ra[p].w;
       } else {
         const int kk = e / (AR / 4), q = (e % (AR / 4)) * 4;
-        As[kk][q + 0] = ra[p].x;
-        As[kk][q + 1] = ra[p].y;
-        As[kk][q + 2] = ra[p].z;
-        As[kk][q + 3] = ra[p].w;
+        As[buf][kk][q + 0] = ra[p].x;
+        As[buf][kk][q + 1] = ra[p].y;
+        As[buf][kk][q + 2] = ra[p].z;
+        As[buf][kk][q + 3] = ra[p].w;
       }
     }
 #pragma unroll
@@ -153,12 +155,12 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
       if (e < BVEC) {
         if (BCOL) {
           const int j = e % NC, kk = (e / NC) * 2;
-          Bs[kk][j] = rb[p].x;
-          Bs[kk + 1][j] = rb[p].y;
+          Bs[buf][kk][j] = rb[p].x;
+          Bs[buf][kk + 1][j] = rb[p].y;
         } else {
           const int kk = e / (NC / 2), j = (e % (NC / 2)) * 2;
-          Bs[kk][j] = rb[p].x;
-          Bs[kk][j + 1] = rb[p].y;
+          Bs[buf][kk][j] = rb[p].x;
+          Bs[buf][kk][j + 1] = rb[p].y;
         }
       }
     }
@@ -170,40 +172,41 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
 #pragma unroll
     for (int t = 0; t < NBH; ++t) acc[m][t] = doublex4{0.0, 0.0, 0.0, 0.0};
 
-  // one LDS buffer; the registers run two chunks ahead: chunk c + 1 is
-  // stored once every wave has finished with chunk c, and chunk c + 2 is
-  // fetched while chunk c + 1 is being multiplied
+  // two LDS buffers; the registers run two chunks ahead
   const int nchunk = (kend + ABK - 1) / ABK;
   if (nchunk > 0) {
     fetch(0);
-    stash();
+    stash(0);
   }
-  __syncthreads();
   if (nchunk > 1) fetch(ABK);
+  __syncthreads();
+  // after chunk c's MFMAs are issued: chunk c + 1 into the other buffer (last
+  // read by chunk c - 1, before the previous barrier), then fetch chunk c + 2
   auto advance = [&](int c) {
-    __syncthreads();
     if (c + 1 < nchunk) {
-      stash();
-      __syncthreads();
+      stash((c + 1) & 1);
       if (c + 2 < nchunk) fetch((c + 2) * ABK);
     }
+    __syncthreads();
   };
   // column blocks are interleaved over the two halves: block 2t + ch
   if constexpr (TRI) {
-    // Chunk c (indices 32c .. 32c+31) meets block 2t + ch only if its last
-    // column 32t + 16ch + 15 >= 32c, i.e. t >= c on both halves.  N = K <=
-    // 32 NBH, so there are at most NBH chunks: the loop is unrolled and each
-    // chunk gets a branch-free body over its blocks.
-    static_for<0, NBH>([&](auto cc) {
+    // Chunk c (indices 16c .. 16c+15) meets block 2t + ch only if its last
+    // column 32t + 16ch + 15 >= 16c.  Both halves start at t = c / 2 (for odd
+    // c the even half's first block lies left of the diagonal; B was zeroed
+    // there on load, so it adds zeros).  N = K <= 32 NBH, so there are at
+    // most 2 NBH chunks: the loop is unrolled and each chunk gets a
+    // branch-free body over its blocks.
+    static_for<0, 2 * NBH>([&](auto cc) {
       constexpr int c = decltype(cc)::value;
       if (c < nchunk) {
-        chunk_mfma<c, NBH>(As, Bs, rg, ch, lane, acc);
+        chunk_mfma<c / 2, NBH>(As[c & 1], Bs[c & 1], rg, ch, lane, acc);
         advance(c);
       }
     });
   } else {
     for (int c = 0; c < nchunk; ++c) {
-      chunk_mfma<0, NBH>(As, Bs, rg, ch, lane, acc);
+      chunk_mfma<0, NBH>(As[c & 1], Bs[c & 1], rg, ch, lane, acc);
       advance(c);
     }
   }
