@@ -86,7 +86,9 @@ def test_spmm_hubs_and_isolated(lib, torch, cols):
 
 
 def test_orth(lib, torch):
-    for n, K in [(20000, 64), (50000, 288), (4100, 160)]:
+    # K = 100 and 20: an odd number of 16-index apply chunks, the last one
+    # partial; n = 777 and 4100 leave a ragged last row block
+    for n, K in [(20000, 64), (50000, 288), (4100, 160), (3000, 100), (777, 20)]:
         say(f"orth n={n} K={K}")
         rng = np.random.default_rng(K)
         B = (rng.standard_normal((n, K)) @ np.diag(np.logspace(0, 3, K))).astype(np.float32)
