@@ -115,7 +115,8 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
       double2 v = make_double2(0.0, 0.0);
       if (e < BVEC) {
         int j, k;
-        if (BCOL) { j = e % NC; k = k0 + (e / NC) * 2; }
+        // BCOL: eight consecutive lanes read one column's 16 indices (128 B)
+        if (BCOL) { j = e / (ABK / 2); k = k0 + (e % (ABK / 2)) * 2; }
         else { k = k0 + e / (NC / 2); j = (e % (NC / 2)) * 2; }
         // with a triangular B, whole columns j < k0 are zero in this chunk
         if (j < g.N && k < kend && !(TRI && j < k0)) {
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
       const int e = tid + 512 * p;
       if (e < BVEC) {
         if (BCOL) {
-          const int j = e % NC, kk = (e / NC) * 2;
+          const int j = e / (ABK / 2), kk = (e % (ABK / 2)) * 2;
           Bs[buf][kk][j] = rb[p].x;
           Bs[buf][kk + 1][j] = rb[p].y;
         } else {
