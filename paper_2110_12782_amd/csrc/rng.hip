@@ -51,6 +51,43 @@ __global__ void k_gauss(int64_t n, int cols, int64_t ld, uint64_t seed, double i
   }
 }
 
+// Even column counts: pair e = a cols / 2 + b / 2 lies in row a, so one thread
+// takes four pairs of a row (columns 8q .. 8q+7) with the same counters and
+// positions as k_gauss, the row found once and the SplitMix64 states stepped
+// by gamma instead of multiplied.
+__global__ void k_gauss_row8(int64_t n, int cols, int64_t ld, uint64_t seed, int chunks, double inv_chunks,
+                             float* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * chunks) return;
+  int64_t a = (int64_t)((double)t * inv_chunks);
+  if (a * chunks > t) --a;
+  else if ((a + 1) * chunks <= t) ++a;
+  const int b0 = 8 * (int)(t - a * chunks);
+  const uint64_t s = mix64(seed ^ 0x6a09e667f3bcc909ULL);
+  const uint64_t e0 = (uint64_t)a * (uint64_t)(cols / 2) + (uint64_t)(b0 / 2);
+  uint64_t state = s + kGamma * (e0 + 1);
+  float v[8];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const uint64_t r = mix64(state);
+    state += kGamma;
+    const float u1 = ((float)((uint32_t)(r >> 40)) + 1.0f) * (1.0f / 16777216.0f);
+    const float u2 = (float)((uint32_t)(r >> 8) & 0xffffffu) * (1.0f / 16777216.0f);
+    const float rad = __builtin_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u1));
+    v[2 * p] = rad * __builtin_amdgcn_cosf(u2);
+    v[2 * p + 1] = rad * __builtin_amdgcn_sinf(u2);
+  }
+  float* o = out + a * ld + b0;
+  if (b0 + 8 <= cols && (reinterpret_cast<uintptr_t>(o) & 15) == 0) {
+    reinterpret_cast<float4*>(o)[0] = make_float4(v[0], v[1], v[2], v[3]);
+    reinterpret_cast<float4*>(o)[1] = make_float4(v[4], v[5], v[6], v[7]);
+  } else {
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (b0 + u < cols) o[u] = v[u];
+  }
+}
+
 // One thread per column: z distinct rows uniformly from [0, n), independent
 // fair signs.  A duplicate is redrawn with a fresh counter; after a bounded
 // number of redraws the next free row (cyclically) is taken, which keeps the
@@ -102,6 +139,13 @@ sketchne_status gen_gauss(sketchne_ctx* c, int64_t n, int cols, int64_t ld, uint
   int64_t total = n * cols;
   if (total == 0) return SKETCHNE_OK;
   ProfScope ps(c, SKETCHNE_PROF_PREP);
+  if (cols % 2 == 0) {
+    const int chunks = (cols + 7) / 8;
+    const int64_t blocks = (n * chunks + 255) / 256;
+    hipLaunchKernelGGL(k_gauss_row8, dim3((unsigned)blocks), dim3(256), 0, c->stream, n, cols, ld, seed, chunks,
+                       1.0 / chunks, out);
+    return launch_status();
+  }
   int64_t blocks = ((total + 1) / 2 + 255) / 256;
   hipLaunchKernelGGL(k_gauss, dim3((unsigned)blocks), dim3(256), 0, c->stream, n, cols, ld, seed, 1.0 / cols, out);
   return launch_status();

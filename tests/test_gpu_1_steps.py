@@ -37,6 +37,43 @@ def test_gen_sparse_sign(lib, torch):
     assert chi2 < 180  # 99 dof
 
 
+def _splitmix_gauss(n, cols, seed):
+    # the device generator written out from its definition: SplitMix64's
+    # output function of seed' + gamma (e + 1) for pair e of the row-major
+    # block (seed' = mix(seed ^ stream constant)), Box-Muller on the two
+    # 24-bit uniforms: element 2e = r cos(2 pi u2), 2e + 1 = r sin(2 pi u2)
+    M = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+    def mix(z):
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xbf58476d1ce4e5b9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94d049bb133111eb)
+        return z ^ (z >> np.uint64(31))
+
+    with np.errstate(over="ignore"):
+        s = mix(np.array([seed], dtype=np.uint64) ^ np.uint64(0x6a09e667f3bcc909))[0]
+        e = np.arange((n * cols + 1) // 2, dtype=np.uint64)
+        r = mix(s + np.uint64(0x9e3779b97f4a7c15) * (e + np.uint64(1)))
+    u1 = ((r >> np.uint64(40)).astype(np.float64) + 1.0) / 2.0 ** 24
+    u2 = ((r >> np.uint64(8)) & np.uint64(0xFFFFFF)).astype(np.float64) / 2.0 ** 24
+    rad = np.sqrt(-2.0 * np.log(u1))
+    out = np.empty(2 * len(e))
+    out[0::2] = rad * np.cos(2 * np.pi * u2)
+    out[1::2] = rad * np.sin(2 * np.pi * u2)
+    return out[:n * cols].reshape(n, cols)
+
+
+@pytest.mark.parametrize("n,cols", [(37, 18), (5, 7), (3, 288)])
+def test_gen_gauss_values(lib, torch, n, cols):
+    # every value and its place against the generator's definition: 18 and
+    # 288 columns take the eight-per-thread form (18: a ragged last chunk of
+    # each row), 7 the pair-per-thread form whose pairs straddle rows; FP32
+    # hardware log / sin / cos against FP64
+    say(f"gen_gauss values n={n} cols={cols}")
+    g = lib.gen_gauss(n, cols, 99).cpu().numpy().astype(np.float64)
+    ref = _splitmix_gauss(n, cols, 99)
+    assert np.abs(g - ref).max() < 1e-4 * (1 + np.abs(ref).max())
+
+
 def test_gen_gauss(lib, torch):
     say("gen_gauss 200000 x 8")
     g = lib.gen_gauss(200000, 8, 5).cpu().numpy().astype(np.float64)
