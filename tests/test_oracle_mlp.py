@@ -149,3 +149,17 @@ def test_bf16_inference_within_rounding_bound():
     bound = (u * H1) @ np.abs(p["W2"]) @ np.abs(p["W3"]) + u * (H2 + (u * H1) @ np.abs(p["W2"])) @ np.abs(p["W3"])
     assert np.all(np.abs(Fb - F) <= bound + 1e-12)
     assert np.abs(Fb - F).max() > 0  # the rounding is not vacuous here
+
+
+def test_adam_two_steps_constant_gradient_closed_form():
+    # with the same gradient g at steps 1 and 2 the bias-corrected moments are
+    # exactly g and g^2 at both steps (m2 = 0.19 g, 1 - 0.9^2 = 0.19;
+    # v2 = 0.001999 g^2, 1 - 0.999^2 = 0.001999), so each step moves every
+    # parameter by -lr g / (|g| + eps)
+    g = np.array([3.0, -2.0, 0.5, -1e-3])
+    lr = 0.01
+    th, m, v = mlp.adam(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, lr=lr)
+    th, m, v = mlp.adam(th, g, m, v, 2, lr=lr)
+    step = lr * g / (np.abs(g) + 1e-8)
+    assert np.allclose(th, -2 * step, rtol=1e-12, atol=0)
+    assert np.allclose(m, 0.19 * g, rtol=1e-14) and np.allclose(v, 0.001999 * g * g, rtol=1e-12)

@@ -339,3 +339,62 @@ def test_eq11_row_subset_forms_match_full_factors():
     Z1 = sk.sketch_z_sampled(Lp, Rp, rows, signs)
     Z2 = sk.sketch_z_parts(Lp[p], Rp[:, p], 3000, rows, signs)
     assert np.allclose(Z1, Z2, rtol=1e-13, atol=1e-15)
+
+
+# ---------------------------------------------------------------- eigenpair order (Alg. 5, Lemma 4)
+
+def test_sort_by_abs_desc_hand_permutation():
+    # |lambda| descending (the order of Lemma 4), ties by lambda descending,
+    # then by index; the expected permutation is written out by hand
+    lam = np.array([0.5, -2.0, 2.0, -0.5, 1.0, -1.0, 0.0, 1.0])
+    assert list(fr.sort_by_abs_desc(lam)) == [2, 1, 4, 7, 5, 0, 3, 6]
+    # a spectrum dominated by negative values: signed order would differ everywhere
+    lam = np.array([-0.9, 0.1, -0.7, 0.3, -0.99])
+    assert list(fr.sort_by_abs_desc(lam)) == [4, 0, 2, 3, 1]
+
+
+def test_freigs_orders_bipartite_spectrum_by_magnitude():
+    # Even cycle C_10 at alpha = 1/2: D^-1/2 A D^-1/2 = A/2 has the eigenvalues
+    # cos(2 pi j / 10): 1, -1 and +-cos(pi/5), +-cos(2 pi/5) twice each, none
+    # zero.  With k + s = n the start block spans everything, so Alg. 5
+    # returns the exact pairs; by magnitude the order is +-1, then the four
+    # of modulus cos(pi/5), then the four of cos(2 pi/5) (a signed order
+    # would put every negative value last).
+    A = A_of(synth.cycle(10))
+    X = netmf.modified_laplacian(A, 0.5)
+    Om = synth.gaussian_block(10, 10, 3).astype(np.float64)
+    U, lam = fr.freigs(X, Om, 10, 1)
+    a, b = np.cos(np.pi / 5), np.cos(2 * np.pi / 5)
+    # equal moduli are equal only up to rounding, so the tie rule (lambda
+    # descending) is not checked here: each group of equal modulus must hold
+    # exactly its signed values
+    assert np.allclose(np.abs(lam), [1, 1, a, a, a, a, b, b, b, b], atol=1e-12)
+    for lo, hi, vals in [(0, 2, [-1, 1]), (2, 6, [-a, -a, a, a]), (6, 10, [-b, -b, b, b])]:
+        assert np.allclose(np.sort(lam[lo:hi]), vals, atol=1e-12)
+    # the pair of eigenvalue -1 (one of the first two) is the alternating vector
+    alt = np.array([1, -1] * 5) / np.sqrt(10)
+    j = int(np.argmin(lam[:2]))
+    assert abs(abs(U[:, j] @ alt) - 1) < 1e-12
+
+
+# ---------------------------------------------------------------- Alg. 6 line 5 through embed_step
+
+def test_embed_step_scales_by_sqrt_sigma():
+    # Alg. 4 on a symmetric X = V diag(mu) V^T of exact rank r: its SVD is
+    # U = V (columns sorted by |mu|), Sigma = |mu|.  Alg. 6 line 5 gives
+    # E = U_d Sigma_d^(1/2), so E E^T = V_d |mu_d| V_d^T whatever the signs
+    # of the singular vectors (E = U_d Sigma_d would give V_d mu_d^2 V_d^T).
+    rng = np.random.default_rng(12)
+    n, r, h, l, d = 300, 10, 24, 80, 6
+    V = np.linalg.qr(rng.standard_normal((n, r)))[0]
+    mu = np.array([6.0, -5.0, 4.0, -3.5, 3.0, 2.5, -2.0, 1.5, 1.0, 0.5])
+    X = V @ np.diag(mu) @ V.T
+    rS, sS = synth.sparse_sign(n, h, 8, 5)
+    rO, sO = synth.sparse_sign(n, l, 8, 6)
+    S = sk.sparse_sign_dense(n, rS, sS)
+    O = sk.sparse_sign_dense(n, rO, sO)
+    E, sig = pipeline.embed_step(X @ S, O.T @ X @ O, rO, sO, d)
+    order = np.argsort(-np.abs(mu))[:d]
+    expect = V[:, order] @ np.diag(np.abs(mu[order])) @ V[:, order].T
+    assert np.allclose(sig, np.abs(mu[order]), rtol=1e-10)
+    assert np.abs(E @ E.T - expect).max() < 1e-10
