@@ -18,8 +18,11 @@ in the order and notation of the paper (SketchNE, TKDE 2023, arXiv
                   two sketches Y and Z of Alg. 4, and the reduced matrix W /
                   SVD of Alg. 4 (Section 3.1).
 * ``pipeline`` -- Alg. 6 lines 1-5 and Alg. 1 (exact NetMF, for context).
+* ``propagation`` -- Alg. 6 line 6, spectral propagation by a Chebyshev
+                  polynomial of the random-walk Laplacian (coefficients read
+                  from ProNE's band-pass filter; see that module).
 * ``metrics``  -- relative Frobenius error and principal angles.
 * ``mlp``      -- the warm-start MLP (not from the paper: parity unpinned
                   against the paper, pinned by finite differences).
 """
-from . import netmf, freigs, sketch, pipeline, metrics, mlp  # noqa: F401
+from . import netmf, freigs, sketch, pipeline, metrics, mlp, propagation  # noqa: F401
