@@ -155,6 +155,42 @@ sketchne_status sketchne_embed(sketchne_ctx* ctx, const sketchne_params* p, int6
                                const float* Yt, const float* Z, const sketchne_sparse_sign* O,
                                float* E, double* sigma, void* ws, size_t ws_bytes);
 
+/* ---- General single pass (Eqs. 5-10) ---------------------------------- */
+/* The single-pass SVD of a target f(LR) that need not be symmetric (for
+ * instance the matrix of a directed graph), f = trunc_log, with four
+ * sparse-sign test matrices C, S (n x h) and H, O (n x l), Eq. (5):
+ *   K = f(LR)^T C   (n x h, written TRANSPOSED: Kt[c*n + i] = K[i][c])
+ *   Y = f(LR) S     (n x h, written transposed: Yt)
+ *   Z = H^T f(LR) O (l x l row-major)
+ * visiting only the entries of f(LR) the test matrices touch.
+ *   L:  n x k row-major FP32 (the left factor); Rt: n x k row-major FP32,
+ *       the TRANSPOSE of the right factor R (k x n).
+ *   p:  h, l, z, precision (FP32 or BF16; FP16 is SKETCHNE_E_UNSUPPORTED
+ *       here: the factors carry no range bound) and split_r are read; k is
+ *       the argument.  C, S have h columns, H, O have l, all with p->z
+ *       nonzeros per column (z <= 8).
+ * sketchne_embed_general then forms, Eqs. (6)-(10), P = orth(K), Q = orth(Y)
+ * (Cholesky-QR, kept implicit), W = (H^T Q)^+ Z (P^T O)^+ by two FP64
+ * least-squares solves, the SVD W = U^ Sigma V^^T (one-sided Jacobi, h <= 288)
+ * and the two d-dimensional embeddings
+ *   E  = Q U^(:, 1:d) Sigma_d^1/2      (n x d FP32, the column side)
+ *   Ed = P V^(:, 1:d) Sigma_d^1/2      (n x d FP32, the row side)
+ * with sigma (d FP64) descending.  For a symmetric target with C = S and
+ * H = O this is the single pass of Alg. 4.
+ * Workspace: sketchne_general_workspace_size(p, n, k, SKETCHNE_OP_SKETCH |
+ * SKETCHNE_OP_EMBED); the embed step reads k = h. */
+sketchne_status sketchne_general_workspace_size(const sketchne_params* p, int64_t n, int32_t k, int op_mask,
+                                                size_t* bytes);
+sketchne_status sketchne_sketch_general(sketchne_ctx* ctx, int64_t n, int32_t k, const float* L, const float* Rt,
+                                        const sketchne_params* p, const sketchne_sparse_sign* C,
+                                        const sketchne_sparse_sign* S, const sketchne_sparse_sign* H,
+                                        const sketchne_sparse_sign* O, float* Kt, float* Yt, float* Z, void* ws,
+                                        size_t ws_bytes);
+sketchne_status sketchne_embed_general(sketchne_ctx* ctx, const sketchne_params* p, int64_t n, const float* Kt,
+                                       const float* Yt, const float* Z, const sketchne_sparse_sign* H,
+                                       const sketchne_sparse_sign* O, float* E, float* Ed, double* sigma, void* ws,
+                                       size_t ws_bytes);
+
 /* Wait for the context's stream; *flags (host, nullable) receives the OR of
  * the numeric flag bits raised since the previous sync.  Returns
  * SKETCHNE_E_NUMERIC if CHOL_FAIL, EIG_NOCONV or NONFINITE was raised, and
@@ -186,6 +222,30 @@ sketchne_status sketchne_orth(sketchne_ctx* ctx, int64_t n, int32_t cols, float*
 sketchne_status sketchne_symeig_workspace_size(int32_t m, size_t* bytes);
 sketchne_status sketchne_symeig(sketchne_ctx* ctx, int32_t m, const double* A, double* V, double* w,
                                 void* ws, size_t ws_bytes);
+
+/* ---- Spectral propagation (Alg. 6 line 6) ------------------------------ */
+/* E_out = sum_{r=0..p} c_r T_r(L - I) E with L = I - D^-1 A the random-walk
+ * Laplacian of Alg. 6 and T_r the Chebyshev polynomials of the first kind
+ * (T_0 = I, T_1(M) = M, T_{r+1}(M) = 2 M T_r(M) - T_{r-1}(M)); L - I = -D^-1 A
+ * has its spectrum in [-1, 1], where this recurrence is stable.  The paper
+ * names the Chebyshev coefficients c_r and the degree p (10 by default) and
+ * takes the step from ProNE; sketchne_propagate_coeffs() gives the reading
+ * used here: c_r interpolate ProNE's band-pass filter
+ *     g(lambda) = exp(-theta/2 ((lambda - mu)^2 - 1))
+ * on the Laplacian spectrum lambda in [0, 2] at the p + 1 Chebyshev nodes
+ * lambda_j = 1 + cos(pi (j + 1/2) / (p + 1)) (theta = 0.5, mu = 0.2 in the
+ * paper's ProNE settings).  An isolated vertex has a zero row in D^-1 A.
+ *   E:    n x d FP32 (ld lde), read only; out: n x d FP32 (ld ldo), written;
+ *         they must not overlap; both 16-byte aligned, d % 4 == 0, d <= 256,
+ *         lde and ldo multiples of 4.
+ *   coef: host, p + 1 doubles (c_0 .. c_p), 0 <= p <= 64.
+ * Every step is one fused SpMM (neighbour sum, recurrence and running sum);
+ * T_r lives in the workspace (two n x d blocks).  Arithmetic is FP32. */
+sketchne_status sketchne_propagate_coeffs(int32_t p, double theta, double mu, double* coef /* host, p+1 */);
+sketchne_status sketchne_propagate_workspace_size(int64_t n, int64_t nnz, int32_t d, size_t* bytes);
+sketchne_status sketchne_propagate(sketchne_ctx* ctx, const sketchne_graph* A, int32_t d, const float* E,
+                                   int64_t lde, int32_t p, const double* coef, float* out, int64_t ldo, void* ws,
+                                   size_t ws_bytes);
 
 /* Device generators (counter-based SplitMix64, Steele, Lea & Flood 2014).
  * gauss: n x cols standard normal block (Box-Muller in FP32).
@@ -311,7 +371,8 @@ sketchne_status sketchne_eig_learned(sketchne_ctx* ctx, const sketchne_graph* A,
 #define SKETCHNE_PROF_GEMM64    3
 #define SKETCHNE_PROF_SMALL     4
 #define SKETCHNE_PROF_PREP      5
-#define SKETCHNE_PROF_CLASSES   6
+#define SKETCHNE_PROF_PROPAGATE 6
+#define SKETCHNE_PROF_CLASSES   7
 sketchne_status sketchne_profile_enable(sketchne_ctx* ctx, int on);
 sketchne_status sketchne_profile_read(sketchne_ctx* ctx, double* ms, int64_t* launches);
 

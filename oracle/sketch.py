@@ -98,3 +98,55 @@ def sketch_z_parts(L_rows_p, R_cols_p, n: int, rows, signs):
     p = unique_rows(rows)
     O = sparse_sign_matrix(n, rows, signs)[p, :].toarray()
     return O.T @ trunc_log(np.asarray(L_rows_p) @ np.asarray(R_cols_p)) @ O
+
+
+# ---------------------------------------------------------------------------
+# The general (non-symmetric) single pass, Eqs. (5)-(10): four sparse-sign
+# test matrices C, S (n x h) and H, O (n x l) for a target f(LR) that need
+# not be symmetric (L: n x k, R: k x n given).
+
+def sketch_general_dense(L, R, C, S, H, O):
+    """Eq. (5) by its definition on a dense F = f(LR) (small n only):
+    K = F^T C, Y = F S, Z = H^T F O."""
+    F = trunc_log(np.asarray(L) @ np.asarray(R))
+    return F.T @ C, F @ S, H.T @ F @ O
+
+
+def sketch_general_sampled(L, R, c_rs, s_rs, h_rs, o_rs):
+    """Eq. (5) visiting only the entries of f(LR) the test matrices touch (the
+    column sampling of Eq. (4) applied to each product); each *_rs is a
+    (rows, signs) pair of a test matrix.
+      K = f(L(p_C, :) R)^T C(p_C, :)
+      Y = f(L R(:, p_S)) S(p_S, :)
+      Z = H(p_H, :)^T f(L(p_H, :) R(:, p_O)) O(p_O, :)"""
+    L = np.asarray(L, np.float64)
+    R = np.asarray(R, np.float64)
+    n = L.shape[0]
+
+    def dense_rows(rs):
+        p = unique_rows(rs[0])
+        return p, sparse_sign_matrix(n, rs[0], rs[1])[p, :].toarray()
+
+    pC, Cp = dense_rows(c_rs)
+    pS, Sp = dense_rows(s_rs)
+    pH, Hp = dense_rows(h_rs)
+    pO, Op = dense_rows(o_rs)
+    K = trunc_log(L[pC, :] @ R).T @ Cp
+    Y = trunc_log(L @ R[:, pS]) @ Sp
+    Z = Hp.T @ trunc_log(L[pH, :] @ R[:, pO]) @ Op
+    return K, Y, Z
+
+
+def single_pass_svd_general(K, Y, Z, H, O, d: int):
+    """Eqs. (6)-(10) given the sketches: P = orth(K), Q = orth(Y);
+    W = (H^T Q)^+ Z (P^T O)^+ by two least-squares solves; [U^, Sigma, V^] =
+    svd(W); U_d = Q U^(:, 1:d), V_d = P V^(:, 1:d), Sigma_d.  H and O may be
+    sparse."""
+    P, _ = np.linalg.qr(K, mode="reduced")
+    Q, _ = np.linalg.qr(Y, mode="reduced")
+    B1 = np.asarray(H.T @ Q)           # l x h
+    B2 = np.asarray(O.T @ P)           # l x h, (P^T O)^T
+    Tm = np.linalg.lstsq(B1, Z, rcond=None)[0]           # (H^T Q) T = Z        (h x l)
+    W = np.linalg.lstsq(B2, Tm.T, rcond=None)[0].T        # W (P^T O) = T        (h x h)
+    Uh, sig, Vh = np.linalg.svd(W)
+    return Q @ Uh[:, :d], sig[:d], P @ Vh.T[:, :d], W

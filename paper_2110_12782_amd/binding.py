@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libsketchne.so")
 OK, E_ARG, E_WORKSPACE, E_DEVICE, E_NUMERIC, E_UNSUPPORTED = range(6)
 FP32, BF16, FP16 = 0, 1, 2
 OP_EIG, OP_SKETCH, OP_EMBED, OP_SPMM = 1, 2, 4, 8
-PROF_NAMES = ["spmm", "sketch_y", "sketch_z", "gemm64", "small", "prep"]
+PROF_NAMES = ["spmm", "sketch_y", "sketch_z", "gemm64", "small", "prep", "propagate"]
 
 EXPORTED = [
     "sketchne_status_str", "sketchne_create", "sketchne_destroy", "sketchne_set_stream",
@@ -28,6 +28,9 @@ EXPORTED = [
     "sketchne_profile_read", "sketchne_ws_param_count", "sketchne_ws_workspace_size", "sketchne_ws_init",
     "sketchne_ws_features", "sketchne_ws_forward", "sketchne_ws_grad", "sketchne_ws_adam",
     "sketchne_ritz_residual", "sketchne_eig_learned", "sketchne_ws_train", "sketchne_ws_infer",
+    "sketchne_propagate_coeffs", "sketchne_propagate_workspace_size", "sketchne_propagate",
+    "sketchne_general_workspace_size", "sketchne_sketch_general",
+    "sketchne_embed_general",
 ]
 WS_FEAT = 8
 WS_OP_FEATURES, WS_OP_FORWARD, WS_OP_GRAD, WS_OP_RESIDUAL, WS_OP_EIG = 1, 2, 4, 8, 16
@@ -150,6 +153,19 @@ class Library:
         L.sketchne_eig_learned.argtypes = [C.c_void_p, C.POINTER(Graph), C.POINTER(Params), C.POINTER(MLPStruct),
                                            C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
                                            C.POINTER(C.c_double), C.c_void_p, C.c_size_t]
+        L.sketchne_general_workspace_size.argtypes = [C.POINTER(Params), C.c_int64, C.c_int32, C.c_int,
+                                                      C.POINTER(C.c_size_t)]
+        L.sketchne_sketch_general.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p,
+                                              C.POINTER(Params), C.POINTER(SparseSign), C.POINTER(SparseSign),
+                                              C.POINTER(SparseSign), C.POINTER(SparseSign), C.c_void_p, C.c_void_p,
+                                              C.c_void_p, C.c_void_p, C.c_size_t]
+        L.sketchne_embed_general.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p,
+                                             C.c_void_p, C.POINTER(SparseSign), C.POINTER(SparseSign), C.c_void_p,
+                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]
+        L.sketchne_propagate_coeffs.argtypes = [C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_double)]
+        L.sketchne_propagate_workspace_size.argtypes = [C.c_int64, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
+        L.sketchne_propagate.argtypes = [C.c_void_p, C.POINTER(Graph), C.c_int32, C.c_void_p, C.c_int64, C.c_int32,
+                                         C.POINTER(C.c_double), C.c_void_p, C.c_int64, C.c_void_p, C.c_size_t]
         self._ctx = None
 
     # ---------------------------------------------------------------- helpers
@@ -249,6 +265,55 @@ class Library:
                                            C.c_void_p(sig.data_ptr()), C.c_void_p(self._aligned(ws)), nb), "embed")
         return E, sig
 
+    # ---------------------------------------------------------------- general single pass
+    def general_workspace_size(self, p: SketchParams, n: int, k: int, ops: int) -> int:
+        out = C.c_size_t(0)
+        pc = p.c()
+        self.check(self.lib.sketchne_general_workspace_size(C.byref(pc), n, k, ops, C.byref(out)),
+                   "general_workspace_size")
+        return out.value
+
+    def sketch_general(self, L, Rt, p: SketchParams, Cm, S, H, O, ws=None):
+        """Eq. (5) for f(L R) with R given transposed (Rt, n x k): returns Kt, Yt
+        (h x n) and Z (l x l).  Cm, S, H, O: (rows, signs) device tensors."""
+        import torch
+        n, k = L.shape
+        assert Rt.shape == (n, k) and L.dtype == torch.float32 and Rt.dtype == torch.float32
+        assert L.is_contiguous() and Rt.is_contiguous()
+        ss = [SparseSign(cols, p.z, t[0].data_ptr(), t[1].data_ptr())
+              for cols, t in ((p.h, Cm), (p.h, S), (p.l, H), (p.l, O))]
+        Kt = torch.empty((p.h, n), dtype=torch.float32, device="cuda")
+        Yt = torch.empty((p.h, n), dtype=torch.float32, device="cuda")
+        Z = torch.empty((p.l, p.l), dtype=torch.float32, device="cuda")
+        nb = self.general_workspace_size(p, n, k, OP_SKETCH)
+        ws = ws if ws is not None else self.workspace(nb)
+        pc = p.c()
+        self.check(self.lib.sketchne_sketch_general(self.ctx(), n, k, C.c_void_p(L.data_ptr()),
+                                                    C.c_void_p(Rt.data_ptr()), C.byref(pc), C.byref(ss[0]),
+                                                    C.byref(ss[1]), C.byref(ss[2]), C.byref(ss[3]),
+                                                    C.c_void_p(Kt.data_ptr()), C.c_void_p(Yt.data_ptr()),
+                                                    C.c_void_p(Z.data_ptr()), C.c_void_p(self._aligned(ws)), nb),
+                   "sketch_general")
+        return Kt, Yt, Z
+
+    def embed_general(self, n: int, p: SketchParams, Kt, Yt, Z, H, O, ws=None):
+        """Eqs. (6)-(10): E (column side), Ed (row side), both n x d, and sigma."""
+        import torch
+        E = torch.empty((n, p.d), dtype=torch.float32, device="cuda")
+        Ed = torch.empty((n, p.d), dtype=torch.float32, device="cuda")
+        sig = torch.empty(p.d, dtype=torch.float64, device="cuda")
+        Hs = SparseSign(p.l, p.z, H[0].data_ptr(), H[1].data_ptr())
+        Os = SparseSign(p.l, p.z, O[0].data_ptr(), O[1].data_ptr())
+        nb = self.general_workspace_size(p, n, p.h, OP_EMBED)
+        ws = ws if ws is not None else self.workspace(nb)
+        pc = p.c()
+        self.check(self.lib.sketchne_embed_general(self.ctx(), C.byref(pc), n, C.c_void_p(Kt.data_ptr()),
+                                                   C.c_void_p(Yt.data_ptr()), C.c_void_p(Z.data_ptr()), C.byref(Hs),
+                                                   C.byref(Os), C.c_void_p(E.data_ptr()), C.c_void_p(Ed.data_ptr()),
+                                                   C.c_void_p(sig.data_ptr()), C.c_void_p(self._aligned(ws)), nb),
+                   "embed_general")
+        return E, Ed, sig
+
     # ---------------------------------------------------------------- steps
     def spmm(self, g: "DeviceGraph", alpha: float, B, out=None):
         import torch
@@ -284,6 +349,31 @@ class Library:
                                             C.c_void_p(w.data_ptr()), C.c_void_p(self._aligned(ws)), nb.value),
                    "symeig")
         return V, w
+
+    def propagate_coeffs(self, p: int = 10, theta: float = 0.5, mu: float = 0.2) -> np.ndarray:
+        """Chebyshev coefficients c_0..c_p of the band-pass filter (host)."""
+        out = (C.c_double * (p + 1))()
+        self.check(self.lib.sketchne_propagate_coeffs(p, theta, mu, out), "propagate_coeffs")
+        return np.array(out[:], dtype=np.float64)
+
+    def propagate(self, g: "DeviceGraph", E, coef, out=None, ws=None):
+        """Alg. 6 line 6: sum_r coef[r] T_r(L - I) E for an n x d float32 block E."""
+        import torch
+        assert E.dtype == torch.float32 and E.dim() == 2 and E.is_contiguous()
+        n, d = E.shape
+        if out is None:
+            out = torch.empty_like(E)
+        coef = np.ascontiguousarray(coef, dtype=np.float64)
+        nb = C.c_size_t(0)
+        self.check(self.lib.sketchne_propagate_workspace_size(n, g.nnz, d, C.byref(nb)), "propagate_workspace_size")
+        if ws is None or ws.numel() < nb.value + 256:
+            ws = self.workspace(nb.value)
+        gc = g.c()
+        cp = (C.c_double * len(coef))(*coef)
+        self.check(self.lib.sketchne_propagate(self.ctx(), C.byref(gc), d, C.c_void_p(E.data_ptr()), d,
+                                               len(coef) - 1, cp, C.c_void_p(out.data_ptr()), out.stride(0),
+                                               C.c_void_p(self._aligned(ws)), nb.value), "propagate")
+        return out
 
     def gen_gauss(self, n: int, cols: int, seed: int):
         import torch
@@ -429,10 +519,10 @@ class Library:
         self.check(self.lib.sketchne_profile_enable(self.ctx(), int(on)), "profile_enable")
 
     def profile_read(self) -> dict:
-        ms = (C.c_double * 6)()
-        n = (C.c_int64 * 6)()
+        ms = (C.c_double * len(PROF_NAMES))()
+        n = (C.c_int64 * len(PROF_NAMES))()
         self.check(self.lib.sketchne_profile_read(self.ctx(), ms, n), "profile_read")
-        return {PROF_NAMES[i]: (ms[i], n[i]) for i in range(6)}
+        return {PROF_NAMES[i]: (ms[i], n[i]) for i in range(len(PROF_NAMES))}
 
 
 class DeviceGraph:

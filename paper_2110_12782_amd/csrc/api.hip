@@ -231,6 +231,7 @@ struct SketchWs {
   float* sgnO;
   void* Bp;
   float* T1t;
+  double* pscale;
 };
 
 SketchWs carve_sketch(Arena& ar, const sketchne_params* p, int64_t n) {
@@ -257,6 +258,7 @@ SketchWs carve_sketch(Arena& ar, const sketchne_params* p, int64_t n) {
   int64_t nvtmax = g.nvt_pad > g.nvtO_pad ? g.nvt_pad : g.nvtO_pad;
   w.Bp = ar.take<char>((size_t)nvtmax * (g.KSM + g.KSS) * 64 * g.FB);
   w.T1t = ar.take<float>((size_t)p->l * g.zl);
+  w.pscale = ar.take<double>(2);
   return w;
 }
 
@@ -566,18 +568,19 @@ sketchne_status sketchne_sketch(sketchne_ctx* c, const sketchne_graph* A, const 
     gd.B = w.Cc; gd.tb = Ty::F64; gd.sbk = 1; gd.sbj = k;
     gd.C = w.RtT; gd.tc = Ty::F64; gd.sci = k; gd.scj = 1;
     SK_TRY(gemm64(c, gd, w.k_partial, w.k_cap));
-    SK_TRY(pack_A(c, g.prec, ntiles, g.KSM, g.KSS, k, g.r, w.RtT, Ap));
+    SK_TRY(balance(c, g.prec, (int64_t)ntiles * 32 * k, w.RtT, w.pscale));
+    SK_TRY(pack_A(c, g.prec, ntiles, g.KSM, g.KSS, k, g.r, w.RtT, w.pscale, Ap));
     return pack_signs(c, ntiles, groups, p->z, T->signs, sgn);
   };
 
   // Alg. 4 line 4: Y = f(L' R'(:, p)) S(p, :)
   SK_TRY(build_A(S, g.ntS, p->h, w.ApS, w.sgnS));
-  SK_TRY(pack_B(c, g.prec, n, n, g.nvt_pad, g.KSM, g.KSS, k, g.r, nullptr, U, k, w.d1, w.Bp));
+  SK_TRY(pack_B(c, g.prec, n, n, g.nvt_pad, g.KSM, g.KSS, k, g.r, nullptr, U, k, w.d1, w.pscale, w.Bp));
   SK_TRY(fused_sketch(c, SKETCHNE_PROF_SKETCH_Y, g.prec, n, p->h, g.ntS, g.KSM, g.KSS, w.Bp, w.ApS, w.sgnS, Yt, n,
                       ln2 * inv_sqrt_z));
   // Alg. 4 line 7: Z = O(p,:)^T f(L'(p,:) R'(:, p)) O(p,:)
   SK_TRY(build_A(O, g.ntO, p->l, w.ApO, w.sgnO));
-  SK_TRY(pack_B(c, g.prec, n, g.zl, g.nvtO_pad, g.KSM, g.KSS, k, g.r, O->rows, U, k, w.d1, w.Bp));
+  SK_TRY(pack_B(c, g.prec, n, g.zl, g.nvtO_pad, g.KSM, g.KSS, k, g.r, O->rows, U, k, w.d1, w.pscale, w.Bp));
   SK_TRY(fused_sketch(c, SKETCHNE_PROF_SKETCH_Z, g.prec, g.zl, p->l, g.ntO, g.KSM, g.KSS, w.Bp, w.ApO, w.sgnO, w.T1t,
                       g.zl,
                       ln2 * inv_sqrt_z));
@@ -664,6 +667,296 @@ sketchne_status sketchne_embed(sketchne_ctx* c, const sketchne_params* p, int64_
   return gemm64(c, gd, w.s_partial, w.s_cap);
 }
 
+// ===================================================== general single pass
+// Eqs. (5)-(10): four test matrices for a target f(LR) that need not be
+// symmetric.  The three sketches reuse the fused kernel: Y with the rows of
+// L against the columns of R at S, K = f(LR)^T C as f(R^T L^T) C with the
+// roles of the factors exchanged, and Z with the rows of L at H's
+// coordinates against the columns of R at O.
+}  // extern "C"
+
+namespace {
+
+// k_general_map: Map_v(:, j) = W^T u_j / sqrt(sigma_j)  (zero when sigma_j = 0),
+// from WtU = W^T U^_d (h x d); V^_d Sigma_d^(1/2) = W^T U^_d Sigma_d^(-1/2)
+__global__ void k_scale_inv_sqrt(int h, int d, const double* __restrict__ WtU, const double* __restrict__ sigma,
+                                 double* __restrict__ out) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= h * d) return;
+  const double s = sigma[idx % d];
+  out[idx] = s > 0.0 ? WtU[idx] / sqrt(s) : 0.0;
+}
+
+struct GenSketchWs {
+  double* Gsel;
+  void* Ap;
+  float* sgn;
+  void* Bp;
+  float* T1t;
+  double* pscale;
+};
+
+sketchne_params general_params(const sketchne_params* p, int k) {
+  sketchne_params q = *p;
+  q.k = k;
+  return q;
+}
+
+GenSketchWs carve_gen_sketch(Arena& ar, const sketchne_params* q, int64_t n) {
+  SketchGeo g = sketch_geo(q, n);
+  GenSketchWs w;
+  const int ntmax = g.ntS > g.ntO ? g.ntS : g.ntO;
+  w.Gsel = ar.take<double>((size_t)ntmax * 32 * q->k);
+  w.Ap = ar.take<char>((size_t)ntmax * (g.KSM + 2 * g.KSS) * 64 * g.FB);
+  w.sgn = ar.take<float>((size_t)ntmax * 32);
+  int64_t nvtmax = g.nvt_pad > g.nvtO_pad ? g.nvt_pad : g.nvtO_pad;
+  w.Bp = ar.take<char>((size_t)nvtmax * (g.KSM + g.KSS) * 64 * g.FB);
+  w.T1t = ar.take<float>((size_t)q->l * g.zl);
+  w.pscale = ar.take<double>(2);
+  return w;
+}
+
+struct GenEmbedWs {
+  float* Q1;
+  OrthWs ow;
+  double* RT2;
+  double* RciY;
+  double* RciK;
+  double* T;      // H^T Y, then O^T K (l x h)
+  double* B1;
+  double* B2;
+  double* Bq1;
+  double* Bq2;
+  double* Bqt;
+  double* Gb;
+  double* Rb1;
+  double* Rb2;
+  double* cwork;
+  double* Rinv1;
+  double* Rinv2;
+  double* M1;
+  double* M2;
+  double* M3;
+  double* W;
+  double* Vw;
+  double* ww;
+  double* Mu;
+  double* Mv;
+  double* WtU;
+  double* Map2;
+  double* s_partial;
+  size_t s_cap;
+  void* symws;
+};
+
+GenEmbedWs carve_gen_embed(Arena& ar, const sketchne_params* p, int64_t n) {
+  const int h = p->h, l = p->l, d = p->d;
+  GenEmbedWs w;
+  w.Q1 = ar.take<float>((size_t)h * n);
+  w.ow = carve_orth(ar, n, h, true);
+  w.RT2 = ar.take<double>((size_t)h * h);
+  w.RciY = ar.take<double>((size_t)h * h);
+  w.RciK = ar.take<double>((size_t)h * h);
+  w.T = ar.take<double>((size_t)l * h);
+  w.B1 = ar.take<double>((size_t)l * h);
+  w.B2 = ar.take<double>((size_t)l * h);
+  w.Bq1 = ar.take<double>((size_t)l * h);
+  w.Bq2 = ar.take<double>((size_t)l * h);
+  w.Bqt = ar.take<double>((size_t)l * h);
+  w.Gb = ar.take<double>((size_t)h * h);
+  w.Rb1 = ar.take<double>((size_t)h * h);
+  w.Rb2 = ar.take<double>((size_t)h * h);
+  w.cwork = ar.take<double>(chol_ws_bytes(h) / sizeof(double) + 1);
+  w.Rinv1 = ar.take<double>((size_t)h * h);
+  w.Rinv2 = ar.take<double>((size_t)h * h);
+  w.M1 = ar.take<double>((size_t)h * l);
+  w.M2 = ar.take<double>((size_t)h * h);
+  w.M3 = ar.take<double>((size_t)h * h);
+  w.W = ar.take<double>((size_t)h * h);
+  w.Vw = ar.take<double>((size_t)h * h);
+  w.ww = ar.take<double>(h);
+  w.Mu = ar.take<double>((size_t)h * d);
+  w.Mv = ar.take<double>((size_t)h * d);
+  w.WtU = ar.take<double>((size_t)h * d);
+  w.Map2 = ar.take<double>((size_t)h * d);
+  w.s_cap = max_bytes({gemm64_partial_bytes(h, h, l, true), gemm64_partial_bytes(l, h, h, false),
+                       gemm64_partial_bytes(h, h, h, false), gemm64_partial_bytes(h, l, l, false),
+                       gemm64_partial_bytes(h, h, l, false), gemm64_partial_bytes(h, d, h, false),
+                       gemm64_partial_bytes(n, d, h, false)});
+  w.s_partial = ar.take<double>(w.s_cap / sizeof(double) + 1);
+  w.symws = ar.take<char>(symeig_ws_bytes(h));
+  return w;
+}
+
+sketchne_status check_general(const sketchne_params* p, int64_t n, int k) {
+  if (!p || n < 1 || k < 1 || k > n) return SKETCHNE_E_ARG;
+  if (p->d < 1 || p->h < p->d || p->l < p->h || p->h > n) return SKETCHNE_E_ARG;
+  if (p->z < 1 || p->z > n) return SKETCHNE_E_ARG;
+  if (p->precision < 0 || p->precision > 2 || p->split_r < 0 || p->split_r > k) return SKETCHNE_E_ARG;
+  if (n >= ((int64_t)1 << 31)) return SKETCHNE_E_UNSUPPORTED;
+  return SKETCHNE_OK;
+}
+
+bool test_matrix_ok(const sketchne_sparse_sign* T, int cols, int z) {
+  return T && T->cols == cols && T->z == z && T->rows && T->signs;
+}
+
+}  // namespace
+
+extern "C" {
+
+sketchne_status sketchne_general_workspace_size(const sketchne_params* p, int64_t n, int32_t k, int op_mask,
+                                                size_t* bytes) {
+  if (!bytes) return SKETCHNE_E_ARG;
+  SK_TRY(check_general(p, n, k));
+  sketchne_params q = general_params(p, k);
+  size_t best = 0;
+  if (op_mask & SKETCHNE_OP_SKETCH) { Arena a(nullptr, 0); carve_gen_sketch(a, &q, n); best = a.off > best ? a.off : best; }
+  if (op_mask & SKETCHNE_OP_EMBED) { Arena a(nullptr, 0); carve_gen_embed(a, &q, n); best = a.off > best ? a.off : best; }
+  *bytes = best;
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_sketch_general(sketchne_ctx* c, int64_t n, int32_t k, const float* L, const float* Rt,
+                                        const sketchne_params* p, const sketchne_sparse_sign* C,
+                                        const sketchne_sparse_sign* S, const sketchne_sparse_sign* H,
+                                        const sketchne_sparse_sign* O, float* Kt, float* Yt, float* Z, void* ws,
+                                        size_t ws_bytes) {
+  if (!c || !L || !Rt || !Kt || !Yt || !Z) return SKETCHNE_E_ARG;
+  SK_TRY(check_general(p, n, k));
+  if (!test_matrix_ok(C, p->h, p->z) || !test_matrix_ok(S, p->h, p->z) || !test_matrix_ok(H, p->l, p->z) ||
+      !test_matrix_ok(O, p->l, p->z))
+    return SKETCHNE_E_ARG;
+  if (p->z > 8 || p->precision == SKETCHNE_FP16) return SKETCHNE_E_UNSUPPORTED;
+  sketchne_params q = general_params(p, k);
+  SketchGeo g = sketch_geo(&q, n);
+  if (!g.ok || g.zl >= ((int64_t)1 << 31)) return SKETCHNE_E_UNSUPPORTED;
+  size_t need = 0;
+  SK_TRY(sketchne_general_workspace_size(p, n, k, SKETCHNE_OP_SKETCH, &need));
+  SK_TRY(check_ws(ws, ws_bytes, need));
+  Arena ar(ws, ws_bytes);
+  GenSketchWs w = carve_gen_sketch(ar, &q, n);
+  if (ar.overflow) return SKETCHNE_E_WORKSPACE;
+  const float ln2 = 0.69314718055994530942f;
+  const float inv_sqrt_z = (float)(1.0 / sqrt((double)p->z));
+  // one product f(B_rows A_cols^T) T of the fused kernel: the expanded columns
+  // are rows of `acols` (n x k) at T's coordinates, the vertex rows are rows
+  // of `brows` (n x k), gathered at `gather` when given
+  auto pass = [&](int cls, const sketchne_sparse_sign* T, int ntiles, int groups, const float* acols,
+                  const float* brows, const int32_t* gather, int64_t nrows, int64_t nvt_pad, float* out,
+                  int64_t ld_out) -> sketchne_status {
+    SK_TRY(gather_expanded(c, n, ntiles, groups, p->z, T->rows, acols, k, k, nullptr, 1.0, w.Gsel));
+    SK_TRY(balance(c, g.prec, (int64_t)ntiles * 32 * k, w.Gsel, w.pscale));
+    SK_TRY(pack_A(c, g.prec, ntiles, g.KSM, g.KSS, k, g.r, w.Gsel, w.pscale, w.Ap));
+    SK_TRY(pack_signs(c, ntiles, groups, p->z, T->signs, w.sgn));
+    SK_TRY(pack_B(c, g.prec, n, nrows, nvt_pad, g.KSM, g.KSS, k, g.r, gather, brows, k, nullptr, w.pscale, w.Bp));
+    return fused_sketch(c, cls, g.prec, nrows, groups, ntiles, g.KSM, g.KSS, w.Bp, w.Ap, w.sgn, out, ld_out,
+                        ln2 * inv_sqrt_z);
+  };
+  // Eq. (5): Y = f(LR) S
+  SK_TRY(pass(SKETCHNE_PROF_SKETCH_Y, S, g.ntS, p->h, Rt, L, nullptr, n, g.nvt_pad, Yt, n));
+  // K = f(LR)^T C = f(R^T L^T) C
+  SK_TRY(pass(SKETCHNE_PROF_SKETCH_Y, C, g.ntS, p->h, L, Rt, nullptr, n, g.nvt_pad, Kt, n));
+  // Z = H^T f(LR) O: rows of L at H's coordinates against the columns of R at O
+  SK_TRY(pass(SKETCHNE_PROF_SKETCH_Z, O, g.ntO, p->l, Rt, L, H->rows, g.zl, g.nvtO_pad, w.T1t, g.zl));
+  return z_reduce(c, p->l, p->z, H->signs, w.T1t, g.zl, inv_sqrt_z, Z);
+}
+
+sketchne_status sketchne_embed_general(sketchne_ctx* c, const sketchne_params* p, int64_t n, const float* Kt,
+                                       const float* Yt, const float* Z, const sketchne_sparse_sign* H,
+                                       const sketchne_sparse_sign* O, float* E, float* Ed, double* sigma, void* ws,
+                                       size_t ws_bytes) {
+  if (!c || !Kt || !Yt || !Z || !E || !Ed || !sigma) return SKETCHNE_E_ARG;
+  SK_TRY(check_general(p, n, p ? p->h : 1));
+  if (!test_matrix_ok(H, p->l, p->z) || !test_matrix_ok(O, p->l, p->z)) return SKETCHNE_E_ARG;
+  if (p->h > kSymeigMax) return SKETCHNE_E_UNSUPPORTED;
+  size_t need = 0;
+  SK_TRY(sketchne_general_workspace_size(p, n, p->h, SKETCHNE_OP_EMBED, &need));
+  SK_TRY(check_ws(ws, ws_bytes, need));
+  const int h = p->h, l = p->l, d = p->d;
+  Arena ar(ws, ws_bytes);
+  GenEmbedWs w = carve_gen_embed(ar, p, n);
+  if (ar.overflow) return SKETCHNE_E_WORKSPACE;
+  auto small = [&](int64_t M, int64_t N, int64_t K, const void* Ap, Ty ta, int64_t sai, int64_t sak, const void* Bp,
+                   Ty tb, int64_t sbk, int64_t sbj, double* C, bool upper, const int* run_if) -> sketchne_status {
+    GemmDesc gd;
+    gd.M = M; gd.N = N; gd.K = K;
+    gd.A = Ap; gd.ta = ta; gd.sai = sai; gd.sak = sak;
+    gd.B = Bp; gd.tb = tb; gd.sbk = sbk; gd.sbj = sbj;
+    gd.C = C; gd.tc = Ty::F64; gd.sci = N; gd.scj = 1;
+    gd.upper_only = upper;
+    gd.run_if = run_if;
+    return gemm64(c, gd, w.s_partial, w.s_cap);
+  };
+  const OrthWs& ow = w.ow;
+  // Eq. (6) kept implicit: X = orth(X) Rc for X = Y, K (both held transposed,
+  // h x n); Rci = Rc^-1, with a second Cholesky-QR pass when X is
+  // ill-conditioned
+  auto implicit_orth = [&](const float* Xt, double* Rci) -> sketchne_status {
+    SK_TRY(gram_tall(c, n, h, Xt, 1, n, nullptr, 0, 0, nullptr, ow.G, ow.partial, ow.partial_cap, nullptr));
+    SK_TRY(chol_inv(c, h, ow.G, ow.RinvT, ow.cwork, ow.need2, nullptr));
+    hipLaunchKernelGGL(k_transpose, dim3((h * h + 255) / 256), dim3(256), 0, c->stream, h, ow.RinvT, Rci);
+    SK_TRY(launch_status());
+    SK_TRY(apply_rinv(c, n, h, Xt, n, true, ow.RinvT, w.Q1, ow, ow.need2));
+    SK_TRY(gram_tall(c, n, h, w.Q1, 1, n, nullptr, 0, 0, nullptr, ow.G, ow.partial, ow.partial_cap, ow.need2));
+    SK_TRY(chol_inv(c, h, ow.G, w.RT2, ow.cwork, nullptr, ow.need2));
+    return small(h, h, h, ow.RinvT, Ty::F64, 1, h, w.RT2, Ty::F64, 1, h, Rci, false, ow.need2);
+  };
+  // B = Bq R by Cholesky-QR twice in FP64; Rinv = R^-1 (row-major)
+  auto small_qr = [&](const double* Bm, double* Bq, double* Rinv) -> sketchne_status {
+    SK_TRY(small(h, h, l, Bm, Ty::F64, 1, h, Bm, Ty::F64, h, 1, w.Gb, true, nullptr));
+    SK_TRY(chol_inv(c, h, w.Gb, w.Rb1, w.cwork));
+    SK_TRY(small(l, h, h, Bm, Ty::F64, h, 1, w.Rb1, Ty::F64, 1, h, w.Bqt, false, nullptr));
+    SK_TRY(small(h, h, l, w.Bqt, Ty::F64, 1, h, w.Bqt, Ty::F64, h, 1, w.Gb, true, nullptr));
+    SK_TRY(chol_inv(c, h, w.Gb, w.Rb2, w.cwork));
+    SK_TRY(small(l, h, h, w.Bqt, Ty::F64, h, 1, w.Rb2, Ty::F64, 1, h, Bq, false, nullptr));
+    return small(h, h, h, w.Rb1, Ty::F64, 1, h, w.Rb2, Ty::F64, 1, h, Rinv, false, nullptr);
+  };
+  const double isz = 1.0 / sqrt((double)p->z);
+  SK_TRY(implicit_orth(Yt, w.RciY));
+  SK_TRY(implicit_orth(Kt, w.RciK));
+  // H^T Q = (H^T Y) Rq^-1 and O^T P = (O^T K) Rp^-1   (l x h)
+  SK_TRY(ot_q(c, l, p->z, h, H->rows, H->signs, Yt, n, isz, w.T));
+  SK_TRY(small(l, h, h, w.T, Ty::F64, h, 1, w.RciY, Ty::F64, h, 1, w.B1, false, nullptr));
+  SK_TRY(ot_q(c, l, p->z, h, O->rows, O->signs, Kt, n, isz, w.T));
+  SK_TRY(small(l, h, h, w.T, Ty::F64, h, 1, w.RciK, Ty::F64, h, 1, w.B2, false, nullptr));
+  // Eq. (9): W = (H^T Q)^+ Z (P^T O)^+ = R1^-1 Bq1^T Z Bq2 R2^-T
+  SK_TRY(small_qr(w.B1, w.Bq1, w.Rinv1));
+  SK_TRY(small_qr(w.B2, w.Bq2, w.Rinv2));
+  SK_TRY(small(h, l, l, w.Bq1, Ty::F64, 1, h, Z, Ty::F32, l, 1, w.M1, false, nullptr));
+  SK_TRY(small(h, h, l, w.M1, Ty::F64, l, 1, w.Bq2, Ty::F64, h, 1, w.M2, false, nullptr));
+  SK_TRY(small(h, h, h, w.Rinv1, Ty::F64, h, 1, w.M2, Ty::F64, h, 1, w.M3, false, nullptr));
+  SK_TRY(small(h, h, h, w.M3, Ty::F64, h, 1, w.Rinv2, Ty::F64, 1, h, w.W, false, nullptr));
+  // Eq. (10): SVD of W (general) by one-sided Jacobi: W J = U^ Sigma
+  SK_TRY(symeig(c, h, w.W, w.Vw, w.ww, w.symws, true));
+  hipLaunchKernelGGL(k_embed_map, dim3((h * d + 255) / 256), dim3(256), 0, c->stream, h, d, w.Vw, w.ww, w.Mu,
+                     sigma);
+  SK_TRY(launch_status());
+  // V^_d Sigma_d^(1/2) = W^T U^_d Sigma_d^(-1/2)
+  SK_TRY(small(h, d, h, w.W, Ty::F64, 1, h, w.Vw, Ty::F64, h, 1, w.WtU, false, nullptr));
+  hipLaunchKernelGGL(k_scale_inv_sqrt, dim3((h * d + 255) / 256), dim3(256), 0, c->stream, h, d, w.WtU, sigma, w.Mv);
+  SK_TRY(launch_status());
+  // E = Q U^_d Sigma_d^(1/2) = Y (Rq^-1 Mu);  Ed = P V^_d Sigma_d^(1/2) = K (Rp^-1 Mv)
+  auto tall = [&](const float* Xt, const double* Map, float* out) -> sketchne_status {
+    ApplyDesc ad;
+    ad.n = n; ad.K = h; ad.N = d;
+    ad.A = Xt; ad.lda = n; ad.acol = true;
+    ad.B = Map; ad.ldb = d;
+    ad.C = out; ad.ldc = d;
+    if (apply_tall_supported(ad)) return apply_tall(c, ad);
+    GemmDesc gd;
+    gd.M = n; gd.N = d; gd.K = h;
+    gd.A = Xt; gd.ta = Ty::F32; gd.sai = 1; gd.sak = n;
+    gd.B = Map; gd.tb = Ty::F64; gd.sbk = d; gd.sbj = 1;
+    gd.C = out; gd.tc = Ty::F32; gd.sci = d; gd.scj = 1;
+    return gemm64(c, gd, w.s_partial, w.s_cap);
+  };
+  SK_TRY(small(h, d, h, w.RciY, Ty::F64, h, 1, w.Mu, Ty::F64, d, 1, w.Map2, false, nullptr));
+  SK_TRY(tall(Yt, w.Map2, E));
+  SK_TRY(small(h, d, h, w.RciK, Ty::F64, h, 1, w.Mv, Ty::F64, d, 1, w.Map2, false, nullptr));
+  return tall(Kt, w.Map2, Ed);
+}
+
 sketchne_status sketchne_sync(sketchne_ctx* c, uint32_t* flags) {
   if (!c) return SKETCHNE_E_ARG;
   if (hipMemcpyAsync(c->h_flags, c->d_flags, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
@@ -732,6 +1025,45 @@ sketchne_status sketchne_symeig(sketchne_ctx* c, int32_t m, const double* A, dou
   if (m > kSymeigMax) return SKETCHNE_E_UNSUPPORTED;
   SK_TRY(check_ws(ws, ws_bytes, symeig_ws_bytes(m)));
   return symeig(c, m, A, V, w, ws);
+}
+
+sketchne_status sketchne_propagate_coeffs(int32_t p, double theta, double mu, double* coef) {
+  if (!coef || p < 0 || p > kPropagateMaxDegree || !(theta >= 0.0) || !isfinite(mu)) return SKETCHNE_E_ARG;
+  // interpolation at the p + 1 Chebyshev nodes x_j = cos(phi_j) of [-1, 1],
+  // lambda_j = 1 + x_j: c_r = (2 - [r == 0]) / (p + 1) sum_j g(lambda_j) cos(r phi_j)
+  const double pi = 3.14159265358979323846;
+  double gv[kPropagateMaxDegree + 1];
+  for (int j = 0; j <= p; ++j) {
+    const double phi = pi * (j + 0.5) / (p + 1);
+    const double lam = 1.0 + cos(phi) - mu;
+    gv[j] = exp(-0.5 * theta * (lam * lam - 1.0));
+  }
+  for (int r = 0; r <= p; ++r) {
+    double acc = 0.0;
+    for (int j = 0; j <= p; ++j) acc += gv[j] * cos(r * pi * (j + 0.5) / (p + 1));
+    coef[r] = acc * (r == 0 ? 1.0 : 2.0) / (p + 1);
+  }
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_propagate_workspace_size(int64_t n, int64_t nnz, int32_t d, size_t* bytes) {
+  if (!bytes || n < 1 || nnz < 0 || d < 1) return SKETCHNE_E_ARG;
+  *bytes = propagate_ws_bytes(n, nnz, d);
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_propagate(sketchne_ctx* c, const sketchne_graph* A, int32_t d, const float* E, int64_t lde,
+                                   int32_t p, const double* coef, float* out, int64_t ldo, void* ws,
+                                   size_t ws_bytes) {
+  if (!c || !E || !out || !coef) return SKETCHNE_E_ARG;
+  SK_TRY(check_graph(A));
+  if (d < 1 || d % 4 || lde < d || ldo < d || lde % 4 || ldo % 4 || p < 0) return SKETCHNE_E_ARG;
+  if (d > 256 || p > kPropagateMaxDegree) return SKETCHNE_E_UNSUPPORTED;
+  if (reinterpret_cast<uintptr_t>(E) % 16 || reinterpret_cast<uintptr_t>(out) % 16) return SKETCHNE_E_ARG;
+  for (int r = 0; r <= p; ++r)
+    if (!isfinite(coef[r])) return SKETCHNE_E_ARG;
+  SK_TRY(check_ws(ws, ws_bytes, propagate_ws_bytes(A->n, A->nnz, d)));
+  return propagate(c, A->n, A->nnz, A->rowptr, A->colidx, d, E, lde, p, coef, out, ldo, ws);
 }
 
 sketchne_status sketchne_gen_gauss(sketchne_ctx* c, int64_t n, int32_t cols, uint64_t seed, float* out) {

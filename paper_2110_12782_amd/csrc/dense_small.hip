@@ -10,7 +10,9 @@
 // a small diagonal shift (shifted Cholesky-QR) and raises a flag; a second
 // failure raises CHOL_FAIL.
 //
-// Eigensolver: one-sided block Jacobi (see the comment above k_oj_cross).
+// Eigensolver: one-sided block Jacobi (see the comment above oj_cross_round).
+#include <hip/hip_cooperative_groups.h>
+
 #include "internal.h"
 
 namespace skne {
@@ -353,11 +355,15 @@ __global__ void k_copy_if(int64_t count, const float* __restrict__ src, float* _
 // convergence the columns of G = B V are (lambda_j + c) v_j.  The
 // eigenvectors are therefore the normalised columns of G (accurate to a few
 // units of rounding because B is well conditioned) and lambda_j =
-// ||g_j|| - c; V itself is never formed.
+// ||g_j|| - c; V itself is never formed.  The same sweeps on a general
+// (non-symmetric) matrix A with c = 0 give its singular value decomposition:
+// at convergence G = A J has orthogonal columns sigma_j u_j, so the
+// normalised columns are the left singular vectors and the norms the
+// singular values (J, the right singular vectors, is not formed).
 //
-// Columns are grouped in blocks of NBJ = 16.  A sweep is one "intra" launch
-// (the pairs inside each block) and nb - 1 "cross" launches that pair the
-// blocks by the round-robin (circle) schedule.  In a cross launch one
+// Columns are grouped in blocks of NBJ = 16.  A sweep is one "intra" round
+// (the pairs inside each block) and nb - 1 "cross" rounds that pair the
+// blocks by the round-robin (circle) schedule.  In a cross round one
 // workgroup takes a block pair (P, Q); group g of 16 lanes keeps column g of P
 // in registers for all 16 rounds and meets column (g + round) mod 16 of Q,
 // which is the only data that moves (through LDS).  Columns are stored with
@@ -367,7 +373,7 @@ __global__ void k_copy_if(int64_t count, const float* __restrict__ src, float* _
 // OJ_BIG sqrt(ab)).  A sweep without a large rotation ends the iteration:
 // the off-diagonal it leaves is of the order of the square of that bound
 // (cyclic Jacobi converges quadratically), so a further sweep would only
-// confirm it.  Launches of later sweeps return at once.
+// confirm it.
 constexpr int NBJ = 16;           // columns per block
 constexpr int OJ_GL = 16;         // lanes per column (one DPP row)
 constexpr int OJ_MAXR = 18;       // rows per lane: m <= OJ_GL * OJ_MAXR = 288
@@ -411,8 +417,14 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
-// c = OJ_SHIFT * ||A||_F over the symmetric matrix given by its upper triangle
-__global__ __launch_bounds__(1024) void k_oj_norm(int m, const double* __restrict__ A, double* __restrict__ shift) {
+// c = OJ_SHIFT * ||A||_F over the symmetric matrix given by its upper
+// triangle; c = 0 for a general matrix (its singular value decomposition)
+__global__ __launch_bounds__(1024) void k_oj_norm(int m, const double* __restrict__ A, int general,
+                                                  double* __restrict__ shift) {
+  if (general) {
+    if (threadIdx.x == 0) *shift = 0.0;
+    return;
+  }
   __shared__ double part[16];
   double s = 0.0;
   for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
@@ -433,7 +445,7 @@ __global__ __launch_bounds__(1024) void k_oj_norm(int m, const double* __restric
 // G (column-major, mp columns of OJ_ROWS rows) = A + c I, zero-padded in both
 // directions (zero rows stay zero under rotations, so the kernels below need
 // no row bounds), counters = 0
-__global__ void k_oj_init(int m, int mp, const double* __restrict__ A, const double* __restrict__ shift,
+__global__ void k_oj_init(int m, int mp, const double* __restrict__ A, int general, const double* __restrict__ shift,
                           double* __restrict__ G, int* __restrict__ counters, int max_sweeps) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < max_sweeps) counters[idx] = 0;
@@ -441,8 +453,12 @@ __global__ void k_oj_init(int m, int mp, const double* __restrict__ A, const dou
   int c = idx / OJ_ROWS, r = idx - c * OJ_ROWS;
   double g = 0.0;
   if (c < m && r < m) {
-    g = r <= c ? A[r * m + c] : A[c * m + r];
-    if (r == c) g += *shift;
+    if (general) {
+      g = A[r * m + c];
+    } else {
+      g = r <= c ? A[r * m + c] : A[c * m + r];
+      if (r == c) g += *shift;
+    }
   }
   G[idx] = g;
 }
@@ -530,15 +546,12 @@ __device__ __forceinline__ void oj_block_load(const double* __restrict__ src, do
 }
 
 // workgroup w orthogonalises the pairs inside blocks 2w and 2w+1 (both in LDS)
-__global__ __launch_bounds__(OJ_THREADS) void k_oj_intra(int m, int sweep, double* __restrict__ G, int* __restrict__ counters) {
-  if (sweep > 0 && counters[kMaxSweeps + sweep - 1] == 0) return;
-  extern __shared__ __attribute__((aligned(16))) double lds[];
-  double* sG = lds;  // 2 NBJ columns x OJ_ROWS rows
-  __shared__ int s_rot, s_big;
+__device__ __forceinline__ void oj_intra_round(int w, int sweep, double* __restrict__ G, int* __restrict__ counters,
+                                               double* __restrict__ sG, int* s_cnt) {
   const int tid = threadIdx.x;
-  if (tid == 0) s_rot = s_big = 0;
+  if (tid == 0) s_cnt[0] = s_cnt[1] = 0;
   const int blk = NBJ * OJ_ROWS;
-  double* g0 = G + (int64_t)(2 * blockIdx.x) * blk;  // blocks 2w, 2w+1 are contiguous
+  double* g0 = G + (int64_t)(2 * w) * blk;  // blocks 2w, 2w+1 are contiguous
   oj_block_load(g0, sG, 2 * blk);
   __syncthreads();
   const int grp = tid / OJ_GL, sub = tid % OJ_GL;
@@ -554,26 +567,22 @@ __global__ __launch_bounds__(OJ_THREADS) void k_oj_intra(int m, int sweep, doubl
     }
     __syncthreads();
   }
-  if (sub == 0 && my_rot) atomicAdd(&s_rot, my_rot);
-  if (sub == 0 && my_big) atomicAdd(&s_big, my_big);
+  if (sub == 0 && my_rot) atomicAdd(&s_cnt[0], my_rot);
+  if (sub == 0 && my_big) atomicAdd(&s_cnt[1], my_big);
   oj_block_load(sG, g0, 2 * blk);
   __syncthreads();
-  if (tid == 0 && s_rot) atomicAdd(&counters[sweep], s_rot);
-  if (tid == 0 && s_big) atomicAdd(&counters[kMaxSweeps + sweep], s_big);
+  if (tid == 0 && s_cnt[0]) atomicAdd(&counters[sweep], s_cnt[0]);
+  if (tid == 0 && s_cnt[1]) atomicAdd(&counters[kMaxSweeps + sweep], s_cnt[1]);
 }
 
 // workgroup w takes the block pair w of round s: column g of block P stays
 // in the registers of lane group g, the 16 columns of block Q rotate past it
-__global__ __launch_bounds__(OJ_THREADS) void k_oj_cross(int m, int nb, int s, int sweep, double* __restrict__ G,
-                                                  int* __restrict__ counters) {
-  if (sweep > 0 && counters[kMaxSweeps + sweep - 1] == 0) return;
-  extern __shared__ __attribute__((aligned(16))) double lds[];
-  double* sQ = lds;  // NBJ columns x OJ_ROWS rows
-  __shared__ int s_rot, s_big;
+__device__ __forceinline__ void oj_cross_round(int w, int nb, int s, int sweep, double* __restrict__ G,
+                                               int* __restrict__ counters, double* __restrict__ sQ, int* s_cnt) {
   int P, Q;
-  pair_of(s, blockIdx.x, nb, P, Q);
+  pair_of(s, w, nb, P, Q);
   const int tid = threadIdx.x, grp = tid / OJ_GL, sub = tid % OJ_GL;
-  if (tid == 0) s_rot = s_big = 0;
+  if (tid == 0) s_cnt[0] = s_cnt[1] = 0;
   const int blk = NBJ * OJ_ROWS;
   double* gpcol = G + (int64_t)P * blk + (int64_t)grp * OJ_ROWS;
   double* gQ = G + (int64_t)Q * blk;
@@ -627,12 +636,40 @@ __global__ __launch_bounds__(OJ_THREADS) void k_oj_cross(int m, int nb, int s, i
 #pragma unroll
   for (int i = 0; i < OJ_MAXR / 2; ++i)
     *reinterpret_cast<double2*>(gpcol + oj_row(sub, i)) = make_double2(x[2 * i], x[2 * i + 1]);
-  if (sub == 0 && my_rot) atomicAdd(&s_rot, my_rot);
-  if (sub == 0 && my_big) atomicAdd(&s_big, my_big);
+  if (sub == 0 && my_rot) atomicAdd(&s_cnt[0], my_rot);
+  if (sub == 0 && my_big) atomicAdd(&s_cnt[1], my_big);
   oj_block_load(sQ, gQ, blk);
   __syncthreads();
-  if (tid == 0 && s_rot) atomicAdd(&counters[sweep], s_rot);
-  if (tid == 0 && s_big) atomicAdd(&counters[kMaxSweeps + sweep], s_big);
+  if (tid == 0 && s_cnt[0]) atomicAdd(&counters[sweep], s_cnt[0]);
+  if (tid == 0 && s_cnt[1]) atomicAdd(&counters[kMaxSweeps + sweep], s_cnt[1]);
+}
+
+// All sweeps in one cooperative launch of nb / 2 workgroups (one per block
+// pair of a round): a grid barrier separates the rounds, and after the last
+// round of a sweep every workgroup reads that sweep's count of large
+// rotations (final once the barrier has passed) and leaves the loop when it is
+// zero, so the stopping rule needs no host round trip.  The rounds and their
+// arithmetic are those of a sweep-per-launch schedule, so the results do not
+// depend on the launch shape.
+__global__ __launch_bounds__(OJ_THREADS) void k_oj_sweeps(int nb, double* __restrict__ G, int* __restrict__ counters) {
+  extern __shared__ __attribute__((aligned(16))) double lds[];
+  __shared__ int s_cnt[2];
+  __shared__ int s_stop;
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const int w = blockIdx.x;
+  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+    oj_intra_round(w, sweep, G, counters, lds, s_cnt);
+    grid.sync();
+    for (int s = 0; s < nb - 1; ++s) {
+      oj_cross_round(w, nb, s, sweep, G, counters, lds, s_cnt);
+      grid.sync();
+    }
+    if (threadIdx.x == 0)
+      s_stop = __hip_atomic_load(&counters[kMaxSweeps + sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    __syncthreads();
+    if (s_stop) break;
+    __syncthreads();  // s_stop is rewritten only after every thread has read it
+  }
 }
 
 // lambda_j = ||g_j|| - c and v_j = g_j / ||g_j|| (one wavefront per column);
@@ -696,10 +733,19 @@ __global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restr
   }
 }
 
-int oj_nblocks(int m) {
-  int nb = (m + NBJ - 1) / NBJ;
-  return nb + (nb & 1);
+constexpr int oj_nblocks(int m) {
+  return (m + NBJ - 1) / NBJ + (((m + NBJ - 1) / NBJ) & 1);
 }
+
+constexpr size_t oj_align(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// workspace of the eigensolver of order m: the padded column block, the
+// per-sweep rotation counts and the shift
+constexpr size_t oj_ws_bytes(int m) {
+  return oj_align(sizeof(double) * (size_t)(oj_nblocks(m) * NBJ) * OJ_ROWS) + oj_align(sizeof(int) * 2 * kMaxSweeps) +
+         oj_align(sizeof(double));
+}
+
 
 }  // namespace
 
@@ -760,13 +806,10 @@ sketchne_status ritz_from_gram(sketchne_ctx* c, int m, int k, const double* G, c
   return launch_status();
 }
 
-size_t symeig_ws_bytes(int m) {
-  int mp = oj_nblocks(m) * NBJ;
-  size_t mat = align_up(sizeof(double) * (size_t)mp * OJ_ROWS);
-  return mat + align_up(sizeof(int) * 2 * kMaxSweeps) + align_up(sizeof(double));
-}
+size_t symeig_ws_bytes(int m) { return oj_ws_bytes(m); }
 
-sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* Vout, double* wout, void* ws) {
+
+sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* Vout, double* wout, void* ws, bool general) {
   if (m <= 0) return SKETCHNE_OK;
   if (m > OJ_GL * OJ_MAXR) return SKETCHNE_E_UNSUPPORTED;
   const int nb = oj_nblocks(m), mp = nb * NBJ;
@@ -775,29 +818,22 @@ sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* Vout, do
   int* counters = ar.take<int>(2 * kMaxSweeps);  // rotations, then large rotations, per sweep
   double* shift = ar.take<double>(1);
   ProfScope ps(c, SKETCHNE_PROF_SMALL);
-  hipLaunchKernelGGL(k_oj_norm, dim3(1), dim3(1024), 0, c->stream, m, A, shift);
+  hipLaunchKernelGGL(k_oj_norm, dim3(1), dim3(1024), 0, c->stream, m, A, (int)general, shift);
   int tot = mp * OJ_ROWS;
-  hipLaunchKernelGGL(k_oj_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, m, mp, A, shift, G,
-                     counters, 2 * kMaxSweeps);
-  const size_t sh_intra = sizeof(double) * (size_t)(2 * NBJ) * OJ_ROWS;
-  const size_t sh_cross = sizeof(double) * (size_t)NBJ * OJ_ROWS;
-  hipFuncSetAttribute(reinterpret_cast<const void*>(k_oj_intra), hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)sh_intra);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(k_oj_cross), hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)sh_cross);
-  int run = 0;
-  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-    hipLaunchKernelGGL(k_oj_intra, dim3(nb / 2), dim3(OJ_THREADS), sh_intra, c->stream, m, sweep, G, counters);
-    for (int s = 0; s < nb - 1; ++s)
-      hipLaunchKernelGGL(k_oj_cross, dim3(nb / 2), dim3(OJ_THREADS), sh_cross, c->stream, m, nb, s, sweep, G,
-                         counters);
-    run = sweep + 1;
-    if (sweep >= 4) {  // one small host read per sweep from the fifth on
-      hipMemcpyAsync(c->h_counter, counters + kMaxSweeps + sweep, sizeof(int), hipMemcpyDeviceToHost, c->stream);
-      if (hipStreamSynchronize(c->stream) != hipSuccess) return SKETCHNE_E_DEVICE;
-      if (*c->h_counter == 0) break;
-    }
-  }
+  hipLaunchKernelGGL(k_oj_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, m, mp, A, (int)general,
+                     shift, G, counters, 2 * kMaxSweeps);
+  const size_t sh_intra = sizeof(double) * (size_t)(2 * NBJ) * OJ_ROWS;  // the larger of the two rounds
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_oj_sweeps), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)sh_intra) != hipSuccess)
+    return SKETCHNE_E_DEVICE;
+  int nb_arg = nb;
+  void* args[] = {&nb_arg, &G, &counters};
+  if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_oj_sweeps), dim3(nb / 2), dim3(OJ_THREADS), args,
+                                 (unsigned)sh_intra, c->stream) != hipSuccess)
+    return SKETCHNE_E_DEVICE;
+  // every sweep slot not reached keeps its zero count, so the finish kernel's
+  // convergence test may scan them all
+  const int run = kMaxSweeps;
   hipLaunchKernelGGL(k_oj_finish, dim3(1), dim3(1024), 0, c->stream, m, G, shift, counters, run, Vout, wout,
                      c->d_flags);
   return launch_status();

@@ -161,7 +161,18 @@ sketchne_status chol_inv(sketchne_ctx* c, int m, const double* G, double* RinvT,
 sketchne_status copy_if(sketchne_ctx* c, int64_t count, const float* src, float* dst, const int* run_if);
 constexpr int kSymeigMax = 288;  // largest order of the Jacobi eigensolver
 size_t symeig_ws_bytes(int m);
-sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* V, double* w, void* ws);
+// general = false: eigendecomposition of the symmetric A (upper triangle
+// read), pairs by |w| descending.  general = true: singular values w >= 0
+// (descending) and left singular vectors V of the general row-major A, by
+// the same one-sided Jacobi on A itself (A J = V diag(w)).
+sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* V, double* w, void* ws, bool general = false);
+
+// propagate.hip (spectral propagation, Alg. 6 line 6)
+constexpr int kPropagateMaxDegree = 64;
+size_t propagate_ws_bytes(int64_t n, int64_t nnz, int d);
+sketchne_status propagate(sketchne_ctx* c, int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colidx,
+                          int d, const float* E, int64_t lde, int p, const double* coef, float* out, int64_t ldo,
+                          void* ws);
 
 // mlp.hip (learned warm start)
 int64_t ws_param_count(int width, int out);

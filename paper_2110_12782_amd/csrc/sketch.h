@@ -16,10 +16,14 @@ sketchne_status scale_rows(sketchne_ctx* c, int rows, int cols, const double* M,
 sketchne_status identity(sketchne_ctx* c, int m, double* M);
 sketchne_status gather_expanded(sketchne_ctx* c, int64_t n, int ntiles, int groups, int z, const int32_t* rows,
                                 const float* U, int64_t ldu, int k, const double* d1, double scale, double* Gsel);
+// pscale = {2^-e, 2^e}: the power-of-two range balance of the FP16 operands
+// (e = 0 for BF16 and FP32), chosen on the device from max |R'|
+sketchne_status balance(sketchne_ctx* c, int prec, int64_t count, const double* RtT, double* pscale);
 sketchne_status pack_A(sketchne_ctx* c, int prec, int ntiles, int KSM, int KSS, int k, int r, const double* RtT,
-                       void* out);
+                       const double* pscale, void* out);
 sketchne_status pack_B(sketchne_ctx* c, int prec, int64_t n, int64_t nrows, int64_t nvt, int KSM, int KSS, int k,
-                       int r, const int32_t* gather, const float* U, int64_t ldu, const double* d1, void* out);
+                       int r, const int32_t* gather, const float* U, int64_t ldu, const double* d1, const double* pscale,
+                       void* out);
 sketchne_status pack_signs(sketchne_ctx* c, int ntiles, int groups, int z, const int8_t* signs, float* sgn);
 sketchne_status fused_sketch(sketchne_ctx* c, int cls, int prec, int64_t nrows, int groups, int ntiles, int KSM,
                              int KSS, const void* Bpack, const void* Apack, const float* sgn, float* out,

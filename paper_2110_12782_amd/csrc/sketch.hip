@@ -33,6 +33,8 @@
 // and A's third section meets B's first KSS k-steps (hi(0..r)) again, so the
 // GEMM forms hi.hi + hi.lo + lo.hi on the dominant components in one pass
 // while B stores only KSM + KSS fragments per vertex.
+#include <type_traits>
+
 #include "internal.h"
 
 #include "sketch.h"
@@ -76,8 +78,8 @@ __device__ __forceinline__ void split2(double x, int prec, uint16_t& hi, uint16_
 // value at summation index kappa of an operand row in the sectioned layout
 // (16*KSM main entries, then 16*KSS split entries, then, A side only, 16*KSS
 // more); zero in the padding
-__device__ __forceinline__ uint16_t sect_val(const double* row, int k, int r, int KSM, int KSS, int kappa, int prec,
-                                             bool a_side) {
+__device__ __forceinline__ uint16_t sect_val(const double* row, double scale, int k, int r, int KSM, int KSS, int kappa,
+                                             int prec, bool a_side) {
   int comp;
   bool want_lo;
   if (kappa < 16 * KSM) {
@@ -94,7 +96,7 @@ __device__ __forceinline__ uint16_t sect_val(const double* row, int k, int r, in
   }
   if (comp < 0) return 0;
   uint16_t hi, lo;
-  split2(row[comp], prec, hi, lo);
+  split2(row[comp] * scale, prec, hi, lo);
   return want_lo ? lo : hi;
 }
 
@@ -134,7 +136,8 @@ __global__ void k_identity(int m, double* __restrict__ M) {
 
 // Rows of the expanded column matrix before the core product:
 //   Gsel[rho][:] = scale * d1[p] * U[p][:], p = coordinate of expanded column rho
-// (zero for padding).  rho runs over ntiles*32 rows in tile order.
+// (zero for padding; d1 == nullptr reads as 1).  rho runs over ntiles*32 rows
+// in tile order.
 __global__ void k_gather_expanded(int64_t n, int ntiles, int groups, int z, const int32_t* __restrict__ rows,
                                   const float* __restrict__ U, int64_t ldu, int k, const double* __restrict__ d1,
                                   double scale, double* __restrict__ Gsel, uint32_t* __restrict__ flags) {
@@ -147,10 +150,21 @@ __global__ void k_gather_expanded(int64_t n, int ntiles, int groups, int z, cons
   double v = 0.0;
   if (g < groups && t < z) {
     int64_t p = rows[(int64_t)g * z + t];
-    if (p >= 0 && p < n) v = scale * d1[p] * (double)U[p * ldu + col];
+    if (p >= 0 && p < n) v = scale * (d1 ? d1[p] : 1.0) * (double)U[p * ldu + col];
     else atomicOr(flags, SKETCHNE_FLAG_BAD_INDEX);
   }
   Gsel[idx] = v;
+}
+
+// whether eight packed 16-bit values are finite (an FP16 conversion that
+// overflowed gives +-inf; BF16 keeps the FP32 exponent range)
+template <int PREC>
+__device__ __forceinline__ bool packed_finite(const uint16_t (&v)[8]) {
+  const uint16_t expmask = PREC == SKETCHNE_FP16 ? 0x7c00 : 0x7f80;
+  bool ok = true;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) ok &= (v[e] & expmask) != expmask;
+  return ok;
 }
 
 // A operand (expanded columns of R'), MFMA fragment order, KS = KSM + 2*KSS
@@ -158,7 +172,7 @@ __global__ void k_gather_expanded(int64_t n, int ntiles, int groups, int z, cons
 //   RtT: (ntiles*32) x k FP64, row rho in tile order.
 template <int PREC>
 __global__ void k_pack_A(int ntiles, int KSM, int KSS, int k, int r, const double* __restrict__ RtT,
-                         void* __restrict__ out) {
+                         const double* __restrict__ pscale, void* __restrict__ out, uint32_t* __restrict__ flags) {
   constexpr int KSTEP = (PREC == SKETCHNE_FP32) ? 2 : 16;
   constexpr int E = (PREC == SKETCHNE_FP32) ? 1 : 8;
   const int KS = KSM + 2 * KSS;
@@ -175,9 +189,11 @@ __global__ void k_pack_A(int ntiles, int KSM, int KSS, int k, int r, const doubl
   if (PREC == SKETCHNE_FP32) {
     static_cast<float*>(out)[idx] = kb < k ? (float)row[kb] : 0.0f;
   } else {
+    const double sa = pscale[0];
     uint16_t v[8];
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = sect_val(row, k, r, KSM, KSS, kb + e, PREC, true);
+    for (int e = 0; e < E; ++e) v[e] = sect_val(row, sa, k, r, KSM, KSS, kb + e, PREC, true);
+    if (!packed_finite<PREC>(v)) atomicOr(flags, SKETCHNE_FLAG_NONFINITE);
     uint4 w;
     w.x = v[0] | ((uint32_t)v[1] << 16);
     w.y = v[2] | ((uint32_t)v[3] << 16);
@@ -187,12 +203,14 @@ __global__ void k_pack_A(int ntiles, int KSM, int KSS, int k, int r, const doubl
   }
 }
 
-// B operand (rows of L' = D^(-1+a) U, optionally gathered), fragment order,
-// KB = KSM + KSS k-steps per vertex tile (FP32: KSS = 0).
+// B operand (rows of L' = D^(-1+a) U, optionally gathered; d1 == nullptr
+// reads as 1, giving the rows of U itself), fragment order, KB = KSM + KSS
+// k-steps per vertex tile (FP32: KSS = 0).
 template <int PREC>
 __global__ void k_pack_B(int64_t n, int64_t nrows, int64_t nvt, int KSM, int KSS, int k, int r,
                          const int32_t* __restrict__ gather, const float* __restrict__ U, int64_t ldu,
-                         const double* __restrict__ d1, void* __restrict__ out, uint32_t* __restrict__ flags) {
+                         const double* __restrict__ d1, const double* __restrict__ pscale, void* __restrict__ out,
+                         uint32_t* __restrict__ flags) {
   constexpr int KSTEP = (PREC == SKETCHNE_FP32) ? 2 : 16;
   constexpr int E = (PREC == SKETCHNE_FP32) ? 1 : 8;
   const int KS = KSM + KSS;
@@ -211,7 +229,7 @@ __global__ void k_pack_B(int64_t n, int64_t nrows, int64_t nvt, int KSM, int KSS
   if (v < nrows && row < 0 && (lane >> 5) == 0 && ks == 0) atomicOr(flags, SKETCHNE_FLAG_BAD_INDEX);
   if (PREC == SKETCHNE_FP32) {
     float val = 0.0f;
-    if (row >= 0 && kb < k) val = (float)(d1[row] * (double)U[row * ldu + kb]);
+    if (row >= 0 && kb < k) val = (float)((d1 ? d1[row] : 1.0) * (double)U[row * ldu + kb]);
     static_cast<float*>(out)[idx] = val;
   } else {
     // the E = 8 summation indices kb .. kb+7 of this lane lie in one section
@@ -222,7 +240,7 @@ __global__ void k_pack_B(int64_t n, int64_t nrows, int64_t nvt, int KSM, int KSS
     const int lim = want_lo ? r : k;
     uint16_t vv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (row >= 0 && comp0 < lim) {
-      const double s = d1[row];
+      const double s = (d1 ? d1[row] : 1.0) * pscale[1];
       const float* src = U + row * ldu + comp0;
       float u[8];
       if (comp0 + 8 <= lim && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
@@ -243,12 +261,44 @@ __global__ void k_pack_B(int64_t n, int64_t nrows, int64_t nvt, int KSM, int KSS
         }
       }
     }
+    if (!packed_finite<PREC>(vv)) atomicOr(flags, SKETCHNE_FLAG_NONFINITE);
     uint4 w;
     w.x = vv[0] | ((uint32_t)vv[1] << 16);
     w.y = vv[2] | ((uint32_t)vv[3] << 16);
     w.z = vv[4] | ((uint32_t)vv[5] << 16);
     w.w = vv[6] | ((uint32_t)vv[7] << 16);
     static_cast<uint4*>(out)[idx] = w;
+  }
+}
+
+// Range balancing of the FP16 operands.  The product L'_i . R'(:, j) does not
+// change when L' is multiplied by 2^e and R' by 2^-e, and power-of-two
+// scaling is exact, but FP16 holds only |x| < 65504: R' carries the factor
+// vol / (bT) (Eq. 11) and reaches about 3e5 on a graph of 2^20 vertices,
+// while |L'_it| = d_i^(-1+a) |U_it| <= 1 (U has orthonormal columns and
+// degrees are at least 1).  With M = max |R'| over the expanded columns,
+// e = floor(log2(sqrt(M))) (clamped to [0, 15]) leaves both operands below
+// sqrt(M) <= 65504 for M up to 4e9, and lifts the small entries of L' out of
+// the FP16 subnormal range.  pscale = {2^-e (R' side), 2^e (L' side)}; BF16
+// and FP32 take e = 0.  One workgroup.
+__global__ __launch_bounds__(1024) void k_balance(int64_t count, const double* __restrict__ RtT, int prec,
+                                                  double* __restrict__ pscale) {
+  __shared__ double part[16];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += blockDim.x) m = fmax(m, fabs(RtT[i]));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = fmax(t, part[w]);
+    int e = 0;
+    if (prec == SKETCHNE_FP16 && t > 1.0 && isfinite(t)) {
+      e = (int)floor(0.5 * log2(t));
+      e = e < 0 ? 0 : (e > 15 ? 15 : e);
+    }
+    pscale[0] = ldexp(1.0, -e);
+    pscale[1] = ldexp(1.0, e);
   }
 }
 
@@ -405,15 +455,19 @@ __global__ __launch_bounds__(512) void k_fused_sketch(int64_t nrows, int groups,
 //   owns vertex tiles 2w, 2w+1 of the workgroup's 8 (256 vertices).  The
 //   vertex fragments of the main section stay in registers for the whole
 //   launch; the split-section (lo) fragments sit in the wave's LDS region.
-//   All waves walk the same sequence of expanded-column tiles: tile t+1 is
-//   copied global -> LDS by the LDS-DMA path (no registers) while tile t is
-//   multiplied, and the trunc_log / signed group sums of tile t-1 run on the
-//   vector ALU interleaved with tile t's MFMAs (two accumulator sets, whose
-//   roles alternate, so every LDS buffer index is static).  Signs are read
-//   through scalar loads: the sign of accumulator register e depends only on
-//   the lane half.  Results leave through buffer stores whose descriptor
-//   covers exactly the tile's output rows, so rows past `groups` and
-//   vertices past `nrows` are dropped by the hardware range check.
+//   All waves walk the same sequence of expanded-column tiles through three
+//   LDS buffers: tile t+1 is copied global -> LDS by the LDS-DMA path (no
+//   registers) while tile t is multiplied, and the trunc_log / signed group
+//   sums of tile t-1 run on the vector ALU interleaved with tile t's MFMAs
+//   (two accumulator sets, whose roles alternate).  A buffer holds a tile's
+//   fragments and its 32 signs (register e of lane half hf), so the signs of
+//   tile t-1 are read from LDS while tile t+1 lands in the third buffer.  The
+//   loop is unrolled over the period 6 of (buffer, accumulator set), so every
+//   LDS offset is a compile-time constant and the reads of the current
+//   buffers never wait on the copy into the next one.  Results leave through
+//   buffer stores whose descriptor covers exactly the tile's output rows, so
+//   rows past `groups` and vertices past `nrows` are dropped by the hardware
+//   range check.
 //   out[g * ld_out + v] = out_scale * sum_t s_gt log2(max(x_{v, (g,t)}, 1))
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -427,6 +481,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(const float* base, ui
   return __builtin_amdgcn_make_buffer_rsrc(ptr, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
 }
 
+template <int N>
+using cint = std::integral_constant<int, N>;
+
+
 template <int PREC, int KSM, int KSS>
 __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups, int ntiles, int tiles_per_block,
                                                        const void* __restrict__ Bpack, const void* Apack,
@@ -438,7 +496,12 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
   constexpr int KS = KSM + 2 * KSS;  // A k-steps per tile
   constexpr int KB = KSM + KSS;      // B k-steps per vertex tile
   constexpr int TB = KS * 1024;      // bytes of one A tile
+  // dynamic LDS: the three fragment buffers; separate static arrays hold each
+  // buffer's signs and the split-section B fragments, so that the compiler
+  // sees them as objects apart from the buffer being filled
   extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  __shared__ __attribute__((aligned(16))) float sg0[32], sg1[32], sg2[32];
+  __shared__ __attribute__((aligned(16))) char blo_all[4 * VT * KSS * 1024 + 16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t vt0 = (int64_t)blockIdx.x * (4 * VT) + wave * VT;
   // this workgroup's expanded-column tiles: tb .. tb + nt - 1 (blockIdx.y splits
@@ -453,7 +516,7 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
   for (int v = 0; v < VT; ++v)
 #pragma unroll
     for (int ks = 0; ks < KSM; ++ks) bfr[v][ks] = Bp[((vt0 + v) * KB + ks) * 64 + lane];
-  char* blo = lds_raw + 2 * TB + wave * (VT * KSS * 1024);
+  char* blo = blo_all + wave * (VT * KSS * 1024);
 #pragma unroll
   for (int v = 0; v < VT; ++v)
 #pragma unroll
@@ -462,15 +525,26 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
                                        (lds_void*)(blo + (v * KSS + j) * 1024), 16, 0, 0);
   const frag* Blo = reinterpret_cast<const frag*>(blo);
   const char* Ag = static_cast<const char*>(Apack);
-  // tile t -> LDS buffer buf: fragment c of the tile is one 1 KiB DMA by wave c % 4
-  auto dma = [&](int t, int buf) {
+  auto signs_of = [&](auto Bc) -> float* {
+    constexpr int B = decltype(Bc)::value;
+    if constexpr (B == 0) return sg0;
+    else if constexpr (B == 1) return sg1;
+    else return sg2;
+  };
+  // tile t -> LDS buffer B: fragment c of the tile is one 1 KiB DMA by wave
+  // c % 4, the 128 bytes of signs one DMA by eight lanes of wave 3
+  auto dma = [&](int t, auto Bc) {
+    constexpr int B = decltype(Bc)::value;
 #pragma unroll
     for (int u = 0; u < (KS + 3) / 4; ++u) {
       const int c = u * 4 + wave;
       if (KS % 4 == 0 || c < KS)
         __builtin_amdgcn_global_load_lds((const void*)(Ag + (int64_t)t * TB + c * 1024 + lane * 16),
-                                         (lds_void*)(lds_raw + buf * TB + c * 1024), 16, 0, 0);
+                                         (lds_void*)(lds_raw + B * TB + c * 1024), 16, 0, 0);
     }
+    if (wave == 3 && lane < 8)
+      __builtin_amdgcn_global_load_lds((const void*)(sgn + (int64_t)t * 32 + lane * 4),
+                                       (lds_void*)signs_of(Bc), 16, 0, 0);
   };
   const int64_t vbase = vt0 * 32 + (lane & 31);
   floatx16 accP[VT], accC[VT];
@@ -492,35 +566,33 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
       __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(yv[v][1]), rs, o1, 0, 0);
     }
   };
-  // signs of tile tt: sgn[tt*32 + hf*16 + e] for lane half hf, register e
-  auto load_signs = [&](int tt, float (&sa)[16], float (&sb)[16]) {
-    const float* st = sgn + (int64_t)(tt < 0 ? 0 : tt) * 32;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      sa[e] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, st[e])));
-      sb[e] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, st[16 + e])));
-    }
-  };
   // trunc_log and signed group sums: registers 0..7 form group 4tt + hf,
-  // registers 8..15 group 4tt + 2 + hf
-  auto epilogue = [&](floatx16 (&acc)[VT], const float (&sa)[16], const float (&sb)[16]) {
-    const bool hi = lane >= 32;
-    float sv[16];
+  // registers 8..15 group 4tt + 2 + hf; the signs of register e of this
+  // lane half are entry hf * 16 + e of the tile's sign block, read four at a
+  // time (all lanes of a half read the same 16 bytes)
+  auto epilogue = [&](floatx16 (&acc)[VT], const float* signs) {
+    const float4* sl = reinterpret_cast<const float4*>(signs + (lane >> 5) * 16);
+    float y[VT][2];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) sv[e] = hi ? sb[e] : sa[e];
+    for (int v = 0; v < VT; ++v) y[v][0] = y[v][1] = 0.0f;
+#pragma unroll
+    for (int c4 = 0; c4 < 4; ++c4) {
+      const float4 s4 = sl[c4];
+      const float sv[4] = {s4.x, s4.y, s4.z, s4.w};
+#pragma unroll
+      for (int v = 0; v < VT; ++v)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          y[v][c4 >> 1] = fmaf(sv[u], fmaxf(__builtin_amdgcn_logf(acc[v][4 * c4 + u]), 0.0f), y[v][c4 >> 1]);
+    }
 #pragma unroll
     for (int v = 0; v < VT; ++v) {
-      float y0 = 0.0f, y1 = 0.0f;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) y0 = fmaf(sv[e], fmaxf(__builtin_amdgcn_logf(acc[v][e]), 0.0f), y0);
-#pragma unroll
-      for (int e = 8; e < 16; ++e) y1 = fmaf(sv[e], fmaxf(__builtin_amdgcn_logf(acc[v][e]), 0.0f), y1);
-      yv[v][0] = out_scale * y0;
-      yv[v][1] = out_scale * y1;
+      yv[v][0] = out_scale * y[v][0];
+      yv[v][1] = out_scale * y[v][1];
     }
   };
 
-  dma(tb, 0);
+  dma(tb, cint<0>());
 #pragma unroll
   for (int v = 0; v < VT; ++v)
 #pragma unroll
@@ -529,16 +601,18 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
   for (int v = 0; v < VT; ++v) yv[v][0] = yv[v][1] = 0.0f;
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  // one step: stores of tile t-2, DMA of tile t+1, MFMAs of tile t into cur
-  // with the epilogue of tile t-1 (from prev) spread over them
-  auto step = [&](int t, floatx16 (&cur)[VT], floatx16 (&prev)[VT]) {
-    const int buf = t & 1;
+  // step J of the period: stores of tile t-2, DMA of tile t+1 into buffer
+  // (J+1) % 3, MFMAs of tile t (buffer J % 3) into one accumulator set, and
+  // the epilogue of tile t-1 (the other set, signs in buffer (J+2) % 3)
+  // spread over them
+  auto step = [&](auto Jc, int t) {
+    constexpr int J = decltype(Jc)::value;
+    floatx16(&cur)[VT] = (J % 2 == 0) ? accC : accP;
+    floatx16(&prev)[VT] = (J % 2 == 0) ? accP : accC;
     store_tile(t >= 2 ? tb + t - 2 : -1);
-    dma(tb + (t + 1 < nt ? t + 1 : nt - 1), buf ^ 1);
-    float sa[16], sb[16];
-    load_signs(t >= 1 ? tb + t - 1 : -1, sa, sb);
+    dma(tb + (t + 1 < nt ? t + 1 : nt - 1), cint<(J + 1) % 3>());
     __builtin_amdgcn_sched_barrier(0);
-    const frag* Al = reinterpret_cast<const frag*>(lds_raw + buf * TB);
+    const frag* Al = reinterpret_cast<const frag*>(lds_raw + (J % 3) * TB);
     // the first k-step takes a zero accumulator operand, so the tile's
     // accumulators need no clearing
     const floatx16 zero = {};
@@ -554,7 +628,8 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
         cur[v] = Op::mma(a, b, ks == 0 ? zero : cur[v]);
       }
     }
-    epilogue(prev, sa, sb);
+    // tile t - 1 (at t = 0 its result is discarded: nothing is stored for tile -1)
+    epilogue(prev, signs_of(cint<(J + 2) % 3>()));
     // A fragments three ahead of their MFMAs; epilogue ALU work spread over the MFMA stream
     __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
 #pragma unroll
@@ -563,26 +638,31 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
       __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
       __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
-    // the DMA into the other buffer has landed for every wave before anyone reads it
+    // the DMA into the next buffer has landed for every wave before anyone reads it
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   };
   int t = 0;
-  for (; t + 1 < nt; t += 2) {
-    step(t, accC, accP);
-    step(t + 1, accP, accC);
+  for (; t + 6 <= nt; t += 6) {
+    step(cint<0>(), t);
+    step(cint<1>(), t + 1);
+    step(cint<2>(), t + 2);
+    step(cint<3>(), t + 3);
+    step(cint<4>(), t + 4);
+    step(cint<5>(), t + 5);
   }
-  if (t < nt) {
-    step(t, accC, accP);
-#pragma unroll
-    for (int v = 0; v < VT; ++v) accP[v] = accC[v];
-  }
+  const int rem = nt - t;
+  if (rem > 0) step(cint<0>(), t);
+  if (rem > 1) step(cint<1>(), t + 1);
+  if (rem > 2) step(cint<2>(), t + 2);
+  if (rem > 3) step(cint<3>(), t + 3);
+  if (rem > 4) step(cint<4>(), t + 4);
   store_tile(nt >= 2 ? tb + nt - 2 : -1);
-  {
-    float sa[16], sb[16];
-    load_signs(tb + nt - 1, sa, sb);
-    epilogue(accP, sa, sb);
-  }
+  // the last tile: accumulator set and buffer of period index (nt - 1) % 6
+  const int lb = (nt - 1) % 3;
+  const float* last_signs = lb == 0 ? sg0 : (lb == 1 ? sg1 : sg2);
+  if ((nt - 1) % 2 == 0) epilogue(accC, last_signs);
+  else epilogue(accP, last_signs);
   store_tile(tb + nt - 1);
 }
 
@@ -632,7 +712,7 @@ template <int PREC, int KSM, int KSS>
 sketchne_status launch_lowp(sketchne_ctx* c, int cls, int64_t nrows, int groups, int ntiles, const void* Bpack,
                             const void* Apack, const float* sgn, float* out, int64_t ld_out, float out_scale) {
   constexpr int KS = KSM + 2 * KSS;
-  const size_t shmem = (size_t)2 * KS * 1024 + (size_t)4 * 2 * KSS * 1024;
+  const size_t shmem = (size_t)3 * KS * 1024;  // plus the kernel's static signs and split fragments
   const int64_t nvt = (nrows + 31) / 32;
   const int64_t blocks = (nvt + 7) / 8;
   // few vertex blocks (the Z pass): split the tile range so that about 1024
@@ -723,37 +803,44 @@ sketchne_status gather_expanded(sketchne_ctx* c, int64_t n, int ntiles, int grou
   return launch_status();
 }
 
+sketchne_status balance(sketchne_ctx* c, int prec, int64_t count, const double* RtT, double* pscale) {
+  ProfScope ps(c, SKETCHNE_PROF_PREP);
+  hipLaunchKernelGGL(k_balance, dim3(1), dim3(1024), 0, c->stream, count, RtT, prec, pscale);
+  return launch_status();
+}
+
 sketchne_status pack_A(sketchne_ctx* c, int prec, int ntiles, int KSM, int KSS, int k, int r, const double* RtT,
-                       void* out) {
+                       const double* pscale, void* out) {
   int64_t tot = (int64_t)ntiles * (KSM + 2 * KSS) * 64;
   unsigned blocks = (unsigned)((tot + 255) / 256);
   ProfScope ps(c, SKETCHNE_PROF_PREP);
   if (prec == SKETCHNE_FP32)
     hipLaunchKernelGGL(k_pack_A<SKETCHNE_FP32>, dim3(blocks), dim3(256), 0, c->stream, ntiles, KSM, KSS, k, r, RtT,
-                       out);
+                       pscale, out, c->d_flags);
   else if (prec == SKETCHNE_BF16)
     hipLaunchKernelGGL(k_pack_A<SKETCHNE_BF16>, dim3(blocks), dim3(256), 0, c->stream, ntiles, KSM, KSS, k, r, RtT,
-                       out);
+                       pscale, out, c->d_flags);
   else
     hipLaunchKernelGGL(k_pack_A<SKETCHNE_FP16>, dim3(blocks), dim3(256), 0, c->stream, ntiles, KSM, KSS, k, r, RtT,
-                       out);
+                       pscale, out, c->d_flags);
   return launch_status();
 }
 
 sketchne_status pack_B(sketchne_ctx* c, int prec, int64_t n, int64_t nrows, int64_t nvt, int KSM, int KSS, int k,
-                       int r, const int32_t* gather, const float* U, int64_t ldu, const double* d1, void* out) {
+                       int r, const int32_t* gather, const float* U, int64_t ldu, const double* d1, const double* pscale,
+                       void* out) {
   int64_t tot = nvt * (KSM + KSS) * 64;
   unsigned blocks = (unsigned)((tot + 255) / 256);
   ProfScope ps(c, SKETCHNE_PROF_PREP);
   if (prec == SKETCHNE_FP32)
     hipLaunchKernelGGL(k_pack_B<SKETCHNE_FP32>, dim3(blocks), dim3(256), 0, c->stream, n, nrows, nvt, KSM, KSS, k, r,
-                       gather, U, ldu, d1, out, c->d_flags);
+                       gather, U, ldu, d1, pscale, out, c->d_flags);
   else if (prec == SKETCHNE_BF16)
     hipLaunchKernelGGL(k_pack_B<SKETCHNE_BF16>, dim3(blocks), dim3(256), 0, c->stream, n, nrows, nvt, KSM, KSS, k, r,
-                       gather, U, ldu, d1, out, c->d_flags);
+                       gather, U, ldu, d1, pscale, out, c->d_flags);
   else
     hipLaunchKernelGGL(k_pack_B<SKETCHNE_FP16>, dim3(blocks), dim3(256), 0, c->stream, n, nrows, nvt, KSM, KSS, k, r,
-                       gather, U, ldu, d1, out, c->d_flags);
+                       gather, U, ldu, d1, pscale, out, c->d_flags);
   return launch_status();
 }
 

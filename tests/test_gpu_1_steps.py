@@ -187,6 +187,21 @@ def test_symeig_random(lib, torch, m):
     assert np.abs(V @ np.diag(w) @ V.T - A).max() < 1e-12 * scale * max(1, m / 16)
 
 
+def test_symeig_deterministic(lib, torch):
+    # the sweeps run as one cooperative launch whose rounds exchange columns
+    # through global memory between grid barriers: two calls on the same input
+    # must agree bit for bit (a stale read would change the rotation path)
+    say("symeig m=288 twice, bitwise")
+    rng = np.random.default_rng(12)
+    for m in (288, 200, 40):
+        M = rng.standard_normal((m, m))
+        A = torch.from_numpy(M + M.T).cuda()
+        V1, w1 = lib.symeig(A)
+        V2, w2 = lib.symeig(A)
+        assert lib.sync() == 0
+        assert torch.equal(V1, V2) and torch.equal(w1, w2)
+
+
 def test_symeig_degenerate(lib, torch):
     say("symeig degenerate spectra")
     m = 40
