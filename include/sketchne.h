@@ -247,6 +247,21 @@ sketchne_status sketchne_propagate(sketchne_ctx* ctx, const sketchne_graph* A, i
                                    int64_t lde, int32_t p, const double* coef, float* out, int64_t ldo, void* ws,
                                    size_t ws_bytes);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): sketchne_symeig
+ * without a workspace argument.  Its scratch (the padded column block,
+ * rotation counts and shift of the eigensolver, 664,064 bytes, enough for
+ * m <= 288) is a device array inside the library, one per device, held until
+ * the process ends; its address is looked up once per device by
+ * sketchne_create.  m > 288 returns SKETCHNE_E_UNSUPPORTED; SKETCHNE_E_DEVICE
+ * if the scratch could not be located.  The call allocates nothing (the
+ * eigensolver is one ordinary and one cooperative launch plus two small
+ * ones).  Every call on a device shares that device's scratch, which keeps
+ * the last call's contents (each call initialises what it reads): calls that
+ * overlap on one device -- from two streams or two contexts -- race and must
+ * be serialised by the caller.  Results equal sketchne_symeig's. */
+sketchne_status sketchne_symeig_noalloc(sketchne_ctx* ctx, int32_t m, const double* A, double* V, double* w);
+
 /* Device generators (counter-based SplitMix64, Steele, Lea & Flood 2014).
  * gauss: n x cols standard normal block (Box-Muller in FP32).
  * sparse_sign: fills out->rows/signs for an n-row test matrix (Alg. 3). */

@@ -29,7 +29,7 @@ EXPORTED = [
     "sketchne_ws_features", "sketchne_ws_forward", "sketchne_ws_grad", "sketchne_ws_adam",
     "sketchne_ritz_residual", "sketchne_eig_learned", "sketchne_ws_train", "sketchne_ws_infer",
     "sketchne_propagate_coeffs", "sketchne_propagate_workspace_size", "sketchne_propagate",
-    "sketchne_general_workspace_size", "sketchne_sketch_general",
+    "sketchne_symeig_noalloc", "sketchne_general_workspace_size", "sketchne_sketch_general",
     "sketchne_embed_general",
 ]
 WS_FEAT = 8
@@ -162,6 +162,7 @@ class Library:
         L.sketchne_embed_general.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p,
                                              C.c_void_p, C.POINTER(SparseSign), C.POINTER(SparseSign), C.c_void_p,
                                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]
+        L.sketchne_symeig_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
         L.sketchne_propagate_coeffs.argtypes = [C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_double)]
         L.sketchne_propagate_workspace_size.argtypes = [C.c_int64, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
         L.sketchne_propagate.argtypes = [C.c_void_p, C.POINTER(Graph), C.c_int32, C.c_void_p, C.c_int64, C.c_int32,
@@ -348,6 +349,17 @@ class Library:
         self.check(self.lib.sketchne_symeig(self.ctx(), m, C.c_void_p(A.data_ptr()), C.c_void_p(V.data_ptr()),
                                             C.c_void_p(w.data_ptr()), C.c_void_p(self._aligned(ws)), nb.value),
                    "symeig")
+        return V, w
+
+    def symeig_noalloc(self, A, V=None, w=None):
+        """sketchne_symeig without a workspace (the library's own device scratch);
+        V (m x m float64) and w (m float64) are allocated here unless given."""
+        import torch
+        m = A.shape[0]
+        V = V if V is not None else torch.empty((m, m), dtype=torch.float64, device="cuda")
+        w = w if w is not None else torch.empty(m, dtype=torch.float64, device="cuda")
+        self.check(self.lib.sketchne_symeig_noalloc(self.ctx(), m, C.c_void_p(A.data_ptr()), C.c_void_p(V.data_ptr()),
+                                                    C.c_void_p(w.data_ptr())), "symeig_noalloc")
         return V, w
 
     def propagate_coeffs(self, p: int = 10, theta: float = 0.5, mu: float = 0.2) -> np.ndarray:

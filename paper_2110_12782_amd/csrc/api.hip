@@ -402,6 +402,9 @@ sketchne_status sketchne_create(sketchne_ctx** out, int device, void* stream) {
   }
   c->h_counter = reinterpret_cast<int*>(c->h_flags + 1);
   hipMemset(c->d_flags, 0, sizeof(uint32_t));
+  // address of this device's eigensolver scratch (sketchne_symeig_noalloc);
+  // a failure here only disables that entry point, which then reports it
+  symeig_scratch_init(device);
   for (int i = 0; i < sketchne_ctx::kMaxEvents; ++i) hipEventCreate(&c->ev[i]);
   *out = c;
   return SKETCHNE_OK;
@@ -1024,6 +1027,19 @@ sketchne_status sketchne_symeig(sketchne_ctx* c, int32_t m, const double* A, dou
   if (!c || !A || !V || !w || m < 1) return SKETCHNE_E_ARG;
   if (m > kSymeigMax) return SKETCHNE_E_UNSUPPORTED;
   SK_TRY(check_ws(ws, ws_bytes, symeig_ws_bytes(m)));
+  return symeig(c, m, A, V, w, ws);
+}
+
+sketchne_status sketchne_symeig_noalloc(sketchne_ctx* c, int32_t m, const double* A, double* V, double* w) {
+  if (!c || !A || !V || !w || m < 1) return SKETCHNE_E_ARG;
+  if (m > kSymeigMax) return SKETCHNE_E_UNSUPPORTED;
+  void* ws = symeig_scratch(c->device);
+  if (!ws) {
+    // first call on a device whose lookup failed at create: try once more
+    SK_TRY(symeig_scratch_init(c->device));
+    ws = symeig_scratch(c->device);
+  }
+  if (!ws || symeig_ws_bytes(m) > symeig_scratch_bytes()) return SKETCHNE_E_DEVICE;
   return symeig(c, m, A, V, w, ws);
 }
 

@@ -13,6 +13,8 @@
 // Eigensolver: one-sided block Jacobi (see the comment above oj_cross_round).
 #include <hip/hip_cooperative_groups.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace skne {
@@ -746,6 +748,17 @@ constexpr size_t oj_ws_bytes(int m) {
          oj_align(sizeof(double));
 }
 
+// The no-allocation variant's scratch: the workspace of the largest order, in
+// a file-scope device array.  Every device that loads the library holds its
+// own copy until the process ends.  On the host the name `scratch` is only a
+// stand-in for the symbol, never a device address: host code uses the
+// address hipGetSymbolAddress returns for the current device.
+constexpr size_t kSymeigScratchBytes = oj_ws_bytes(kSymeigMax);
+static __device__ __align__(256) char scratch[kSymeigScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
 
 }  // namespace
 
@@ -808,6 +821,28 @@ sketchne_status ritz_from_gram(sketchne_ctx* c, int m, int k, const double* G, c
 
 size_t symeig_ws_bytes(int m) { return oj_ws_bytes(m); }
 
+size_t symeig_scratch_bytes() { return kSymeigScratchBytes; }
+
+sketchne_status symeig_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return SKETCHNE_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return SKETCHNE_OK;
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) return SKETCHNE_E_DEVICE;
+  if (prev != device && hipSetDevice(device) != hipSuccess) return SKETCHNE_E_DEVICE;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (prev != device) hipSetDevice(prev);
+  if (e != hipSuccess || !ptr) return SKETCHNE_E_DEVICE;
+  g_scratch_ptr[device] = ptr;
+  return SKETCHNE_OK;
+}
+
+void* symeig_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* Vout, double* wout, void* ws, bool general) {
   if (m <= 0) return SKETCHNE_OK;

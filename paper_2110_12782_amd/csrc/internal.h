@@ -166,6 +166,13 @@ size_t symeig_ws_bytes(int m);
 // (descending) and left singular vectors V of the general row-major A, by
 // the same one-sided Jacobi on A itself (A J = V diag(w)).
 sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* V, double* w, void* ws, bool general = false);
+// The eigensolver's scratch for orders up to kSymeigMax in a device array of
+// the library (one per device, held until the process ends).  init looks up
+// its address on `device` (once; called by sketchne_create); scratch returns
+// it, or nullptr when init has not succeeded on that device.
+size_t symeig_scratch_bytes();
+sketchne_status symeig_scratch_init(int device);
+void* symeig_scratch(int device);
 
 // propagate.hip (spectral propagation, Alg. 6 line 6)
 constexpr int kPropagateMaxDegree = 64;
