@@ -28,6 +28,16 @@ def csr_from_edges(n: int, u: np.ndarray, v: np.ndarray):
     return rowptr, cols
 
 
+def degree_exponent_mle(deg: np.ndarray, d_min: int = 10) -> float:
+    """Discrete power-law exponent of the degree tail d >= d_min by the
+    standard continuous approximation of the maximum-likelihood estimate
+    (Clauset, Shalizi and Newman 2009): 1 + N / sum ln(d / (d_min - 1/2))."""
+    tail = deg[deg >= d_min].astype(np.float64)
+    if len(tail) == 0:
+        return float("nan")
+    return float(1.0 + len(tail) / np.sum(np.log(tail / (d_min - 0.5))))
+
+
 def graph_stats(rowptr: np.ndarray, colidx: np.ndarray) -> dict:
     deg = np.diff(rowptr)
     n = len(deg)
@@ -39,6 +49,7 @@ def graph_stats(rowptr: np.ndarray, colidx: np.ndarray) -> dict:
         "max_degree": int(deg.max()) if n else 0,
         "min_degree": int(deg.min()) if n else 0,
         "isolated": int((deg == 0).sum()),
+        "gamma_hat_d10": degree_exponent_mle(deg, 10) if n else float("nan"),
     }
 
 
@@ -92,8 +103,14 @@ def sbm(block_sizes, p_in: float, p_out: float, seed: int):
 
 
 def _chung_lu_weights(n: int, gamma: float, mean_deg: float, min_w: float):
-    """Power-law expected degrees w_i = c (i + i0)^(-1/(gamma-1)), min w = min_w, mean w = mean_deg,
-    capped at sqrt(sum w) so every pair probability w_i w_j / sum(w) stays <= 1."""
+    """Power-law expected degrees w_i = c (i + i0)^(-1/(gamma-1)) with min w =
+    min_w, solved for the mean.  Each of eight refinement passes clips the
+    weights at the square root of that pass's unclipped sum and rescales the
+    target mean; the clip is therefore loose (on the n = 2^20, mean 20 graph
+    the largest returned weight is about 19,000 and the mean about 14), and no
+    bound w_i w_j / sum(w) <= 1 is claimed: the generator draws edge endpoints
+    independently in proportion to w (Norros-Reittu form), which needs no
+    such bound, and tops the edge count up to the target mean degree."""
     beta = 1.0 / (gamma - 1.0)
     i = np.arange(n, dtype=np.float64)
     target = mean_deg

@@ -51,3 +51,14 @@ def test_sparse_sign_draw():
     # n == z: every column is a permutation of all rows
     r3, _ = synth.sparse_sign(8, 20, 8, 6)
     assert all(sorted(r) == list(range(8)) for r in r3)
+
+
+def test_degree_exponent_mle():
+    # integer samples of a power law with exponent 2.4 above d_min = 10 (a
+    # Pareto draw rounded to the nearest integer): the estimate recovers it
+    rng = np.random.default_rng(3)
+    d = np.rint(9.5 * rng.random(200000) ** (-1.0 / 1.4)).astype(np.int64)
+    assert abs(synth.graphs.degree_exponent_mle(d, 10) - 2.4) < 0.05
+    # the bench-shaped Chung-Lu graph has the exponent it was built for
+    rowptr, colidx = synth.chung_lu(1 << 15, 2.1, 16, 2, 9)
+    assert abs(synth.graph_stats(rowptr, colidx)["gamma_hat_d10"] - 2.1) < 0.2
