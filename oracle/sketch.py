@@ -150,3 +150,33 @@ def single_pass_svd_general(K, Y, Z, H, O, d: int):
     W = np.linalg.lstsq(B2, Tm.T, rcond=None)[0].T        # W (P^T O) = T        (h x h)
     Uh, sig, Vh = np.linalg.svd(W)
     return Q @ Uh[:, :d], sig[:d], P @ Vh.T[:, :d], W
+
+
+# ---------------------------------------------------------------------------
+# The full-visit reading of Alg. 3: the z nonzeros of a test matrix in every
+# ROW (one set per vertex), so every entry of f(L'R') enters the sketches.
+
+def sparse_sign_rows_matrix(n: int, width: int, cols_idx: np.ndarray, signs: np.ndarray) -> sp.csr_matrix:
+    """The n x width test matrix with z nonzeros per row, entries +-1/sqrt(z)."""
+    n_, z = cols_idx.shape
+    r_idx = np.repeat(np.arange(n_), z)
+    vals = signs.ravel().astype(np.float64) / np.sqrt(z)
+    return sp.csr_matrix((vals, (r_idx, cols_idx.ravel().astype(np.int64))), shape=(n, width))
+
+
+def sketch_fullvisit(Lp, Rp, s_cols, s_signs, o_cols, o_signs, h: int, l: int, row_block: int = 2048):
+    """Y = f(L'R') S and Z = O^T f(L'R') O by their definitions, every entry of
+    f(L'R') formed (row blocks of it at a time, so that no n x n array is
+    held): Y[blk] = f(L'[blk] R') S, Z = sum_blk O[blk]^T (f(L'[blk] R') O)."""
+    Lp = np.asarray(Lp, np.float64)
+    Rp = np.asarray(Rp, np.float64)
+    n = Lp.shape[0]
+    S = sparse_sign_rows_matrix(n, h, s_cols, s_signs)
+    O = sparse_sign_rows_matrix(n, l, o_cols, o_signs)
+    Y = np.zeros((n, h))
+    Z = np.zeros((l, l))
+    for r0 in range(0, n, row_block):
+        F = trunc_log(Lp[r0:r0 + row_block] @ Rp)
+        Y[r0:r0 + row_block] = np.asarray(S.T @ F.T).T
+        Z += np.asarray(O[r0:r0 + row_block].T @ np.asarray(O.T @ F.T).T)
+    return Y, Z

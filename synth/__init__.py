@@ -17,4 +17,4 @@ from .graphs import (  # noqa: F401
     disjoint_union,
     graph_stats,
 )
-from .draws import gaussian_block, sparse_sign, rademacher  # noqa: F401
+from .draws import gaussian_block, sparse_sign, sparse_sign_rows, rademacher  # noqa: F401

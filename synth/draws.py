@@ -49,3 +49,25 @@ def sparse_sign(n: int, cols: int, z: int, seed: int):
                 rows[c] = rng.permutation(r)[:z]
     signs = (rng.integers(0, 2, size=(cols, z)) * 2 - 1).astype(np.int8)
     return rows.astype(np.int32), signs
+
+
+def sparse_sign_rows(n: int, cols: int, z: int, seed: int):
+    """Coordinates and signs of an n x cols sparse-sign matrix with z nonzeros
+    per ROW (one per vertex): row i has ``z`` distinct column coordinates in
+    [0, cols), in random order, and ``z`` fair signs.  Returns ``cols_idx``
+    int32 (n, z) and ``signs`` int8 (n, z); the numeric value of an entry is
+    signs/sqrt(z)."""
+    if not (1 <= z <= cols):
+        raise ValueError("need 1 <= z <= cols")
+    rng = np.random.default_rng(seed)
+    idx = np.empty((n, z), dtype=np.int32)
+    for r0 in range(0, n, 16384):
+        r1 = min(n, r0 + 16384)
+        # the z smallest of cols uniform keys: a uniformly random z-subset,
+        # in the random order of their keys
+        keys = rng.random((r1 - r0, cols))
+        part = np.argpartition(keys, z - 1, axis=1)[:, :z] if z < cols else np.tile(np.arange(cols), (r1 - r0, 1))
+        order = np.argsort(np.take_along_axis(keys, part, axis=1), axis=1)
+        idx[r0:r1] = np.take_along_axis(part, order, axis=1)
+    signs = (rng.integers(0, 2, size=(n, z)) * 2 - 1).astype(np.int8)
+    return idx, signs
