@@ -457,17 +457,20 @@ __global__ __launch_bounds__(512) void k_fused_sketch(int64_t nrows, int groups,
 //   launch; the split-section (lo) fragments sit in the wave's LDS region.
 //   All waves walk the same sequence of expanded-column tiles through three
 //   LDS buffers: tile t+1 is copied global -> LDS by the LDS-DMA path (no
-//   registers) while tile t is multiplied, and the trunc_log / signed group
-//   sums of tile t-1 run on the vector ALU interleaved with tile t's MFMAs
-//   (two accumulator sets, whose roles alternate).  A buffer holds a tile's
-//   fragments and its 32 signs (register e of lane half hf), so the signs of
-//   tile t-1 are read from LDS while tile t+1 lands in the third buffer.  The
-//   loop is unrolled over the period 6 of (buffer, accumulator set), so every
-//   LDS offset is a compile-time constant and the reads of the current
-//   buffers never wait on the copy into the next one.  Results leave through
-//   buffer stores whose descriptor covers exactly the tile's output rows, so
-//   rows past `groups` and vertices past `nrows` are dropped by the hardware
-//   range check.
+//   registers) while tile t is multiplied, then the trunc_log / signed group
+//   sums of tile t run on the vector ALU; the two workgroups that share a CU
+//   keep the matrix cores busy during each other's vector phases.  (A second
+//   accumulator set that overlapped tile t-1's vector work with tile t's
+//   MFMAs inside one wave left too few registers for reading the A
+//   fragments ahead, and measured slower; so did two wave groups per
+//   workgroup alternating the phases under barriers, and split-K chains.)
+//   A buffer holds a tile's fragments and its 32 signs (register e of lane
+//   half hf).  The loop is unrolled over the period 3 of the buffers, so every
+//   LDS offset is a compile-time constant and the reads of the current buffer
+//   never wait on the copy into the next one.  Results leave through buffer
+//   stores whose descriptor covers exactly the tile's output rows, so rows
+//   past `groups` and vertices past `nrows` are dropped by the hardware range
+//   check.
 //   out[g * ld_out + v] = out_scale * sum_t s_gt log2(max(x_{v, (g,t)}, 1))
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -547,7 +550,7 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
                                        (lds_void*)signs_of(Bc), 16, 0, 0);
   };
   const int64_t vbase = vt0 * 32 + (lane & 31);
-  floatx16 accP[VT], accC[VT];
+  floatx16 accC[VT];
   float yv[VT][2];
   // stores of finished tile tt (nothing for tt < 0): output rows 4tt .. 4tt+3
   auto store_tile = [&](int tt) {
@@ -594,27 +597,18 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
 
   dma(tb, cint<0>());
 #pragma unroll
-  for (int v = 0; v < VT; ++v)
-#pragma unroll
-    for (int e = 0; e < 16; ++e) accP[v][e] = 0.0f;
-#pragma unroll
   for (int v = 0; v < VT; ++v) yv[v][0] = yv[v][1] = 0.0f;
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  // step J of the period: stores of tile t-2, DMA of tile t+1 into buffer
-  // (J+1) % 3, MFMAs of tile t (buffer J % 3) into one accumulator set, and
-  // the epilogue of tile t-1 (the other set, signs in buffer (J+2) % 3)
-  // spread over them
+  // step J of the period: stores of tile t-1, DMA of tile t+1 into buffer
+  // (J+1) % 3, MFMAs of tile t (buffer J % 3), four A fragments read ahead,
+  // then the epilogue of tile t (its signs in the same buffer)
   auto step = [&](auto Jc, int t) {
     constexpr int J = decltype(Jc)::value;
-    floatx16(&cur)[VT] = (J % 2 == 0) ? accC : accP;
-    floatx16(&prev)[VT] = (J % 2 == 0) ? accP : accC;
-    store_tile(t >= 2 ? tb + t - 2 : -1);
+    store_tile(t >= 1 ? tb + t - 1 : -1);
     dma(tb + (t + 1 < nt ? t + 1 : nt - 1), cint<(J + 1) % 3>());
     __builtin_amdgcn_sched_barrier(0);
     const frag* Al = reinterpret_cast<const frag*>(lds_raw + (J % 3) * TB);
-    // the first k-step takes a zero accumulator operand, so the tile's
-    // accumulators need no clearing
     const floatx16 zero = {};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
@@ -625,44 +619,29 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
         if (ks < KSM) b = bfr[v][ks];
         else if (ks < KB) b = Blo[(v * KSS + ks - KSM) * 64 + lane];
         else b = bfr[v][ks - KB];
-        cur[v] = Op::mma(a, b, ks == 0 ? zero : cur[v]);
+        accC[v] = Op::mma(a, b, ks == 0 ? zero : accC[v]);
       }
     }
-    // tile t - 1 (at t = 0 its result is discarded: nothing is stored for tile -1)
-    epilogue(prev, signs_of(cint<(J + 2) % 3>()));
-    // A fragments three ahead of their MFMAs; epilogue ALU work spread over the MFMA stream
-    __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
 #pragma unroll
     for (int g = 0; g < KS; ++g) {
       __builtin_amdgcn_sched_group_barrier(0x008, VT, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
       __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
-    // the DMA into the next buffer has landed for every wave before anyone reads it
+    __builtin_amdgcn_sched_barrier(0);
+    epilogue(accC, signs_of(cint<J % 3>()));
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   };
   int t = 0;
-  for (; t + 6 <= nt; t += 6) {
+  for (; t + 3 <= nt; t += 3) {
     step(cint<0>(), t);
     step(cint<1>(), t + 1);
     step(cint<2>(), t + 2);
-    step(cint<3>(), t + 3);
-    step(cint<4>(), t + 4);
-    step(cint<5>(), t + 5);
   }
   const int rem = nt - t;
   if (rem > 0) step(cint<0>(), t);
   if (rem > 1) step(cint<1>(), t + 1);
-  if (rem > 2) step(cint<2>(), t + 2);
-  if (rem > 3) step(cint<3>(), t + 3);
-  if (rem > 4) step(cint<4>(), t + 4);
-  store_tile(nt >= 2 ? tb + nt - 2 : -1);
-  // the last tile: accumulator set and buffer of period index (nt - 1) % 6
-  const int lb = (nt - 1) % 3;
-  const float* last_signs = lb == 0 ? sg0 : (lb == 1 ? sg1 : sg2);
-  if ((nt - 1) % 2 == 0) epilogue(accC, last_signs);
-  else epilogue(accP, last_signs);
   store_tile(tb + nt - 1);
 }
 
