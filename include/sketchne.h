@@ -155,6 +155,35 @@ sketchne_status sketchne_embed(sketchne_ctx* ctx, const sketchne_params* p, int6
                                const float* Yt, const float* Z, const sketchne_sparse_sign* O,
                                float* E, double* sigma, void* ws, size_t ws_bytes);
 
+/* ---- Full-visit variant ------------------------------------------------ */
+/* The sparse-sign test matrices of Alg. 3 with their z nonzeros placed in
+ * every ROW (one set per vertex) instead of every column:
+ *   Y = f(L'R') S (n x h, written transposed: Yt),  Z = O^T f(L'R') O (l x l),
+ * with S (n x h) and O (n x l) holding z nonzeros +-1/sqrt(z) per row, so
+ * every one of the n^2 entries of f(L'R') is formed (nothing is sampled).
+ * Each tile of f(L'R') is formed on the matrix cores and multiplied by the
+ * matching rows of S (or O) on the matrix cores, never leaving registers.
+ * L', R' as in sketchne_sketch (Eq. 11); precision FP32 or BF16 (FP16 is
+ * SKETCHNE_E_UNSUPPORTED); S->width = h, O->width = l, both z = p->z <= h.
+ * sketchne_embed_fullvisit is sketchne_embed (Alg. 4 lines 5, 8-10) with that
+ * O.  Workspace: sketchne_fullvisit_workspace_size (it holds f(L'R') O, l x n,
+ * and O as a dense l-column matrix). */
+typedef struct {
+  int32_t width;   /* columns of the test matrix                               */
+  int32_t z;       /* nonzeros per row                                          */
+  int32_t* cols;   /* device, n*z: row i owns cols[i*z .. i*z+z-1], distinct in [0, width) */
+  int8_t* signs;   /* device, n*z: +-1 (value sign / sqrt(z))                  */
+} sketchne_row_sign;
+
+sketchne_status sketchne_fullvisit_workspace_size(const sketchne_params* p, int64_t n, int op_mask, size_t* bytes);
+sketchne_status sketchne_sketch_fullvisit(sketchne_ctx* ctx, const sketchne_graph* A, const sketchne_params* p,
+                                          const float* U, const double* lambda, sketchne_row_sign* S,
+                                          sketchne_row_sign* O, int generate, float* Yt, float* Z, void* ws,
+                                          size_t ws_bytes);
+sketchne_status sketchne_embed_fullvisit(sketchne_ctx* ctx, const sketchne_params* p, int64_t n, const float* Yt,
+                                         const float* Z, const sketchne_row_sign* O, float* E, double* sigma,
+                                         void* ws, size_t ws_bytes);
+
 /* ---- General single pass (Eqs. 5-10) ---------------------------------- */
 /* The single-pass SVD of a target f(LR) that need not be symmetric (for
  * instance the matrix of a directed graph), f = trunc_log, with four

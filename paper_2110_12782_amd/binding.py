@@ -30,7 +30,8 @@ EXPORTED = [
     "sketchne_ritz_residual", "sketchne_eig_learned", "sketchne_ws_train", "sketchne_ws_infer",
     "sketchne_propagate_coeffs", "sketchne_propagate_workspace_size", "sketchne_propagate",
     "sketchne_symeig_noalloc", "sketchne_general_workspace_size", "sketchne_sketch_general",
-    "sketchne_embed_general",
+    "sketchne_embed_general", "sketchne_fullvisit_workspace_size", "sketchne_sketch_fullvisit",
+    "sketchne_embed_fullvisit",
 ]
 WS_FEAT = 8
 WS_OP_FEATURES, WS_OP_FORWARD, WS_OP_GRAD, WS_OP_RESIDUAL, WS_OP_EIG = 1, 2, 4, 8, 16
@@ -62,6 +63,10 @@ class MLPStruct(C.Structure):
 
 class SparseSign(C.Structure):
     _fields_ = [("cols", C.c_int32), ("z", C.c_int32), ("rows", C.c_void_p), ("signs", C.c_void_p)]
+
+
+class RowSign(C.Structure):
+    _fields_ = [("width", C.c_int32), ("z", C.c_int32), ("cols", C.c_void_p), ("signs", C.c_void_p)]
 
 
 @dataclass
@@ -162,6 +167,12 @@ class Library:
         L.sketchne_embed_general.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p,
                                              C.c_void_p, C.POINTER(SparseSign), C.POINTER(SparseSign), C.c_void_p,
                                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]
+        L.sketchne_fullvisit_workspace_size.argtypes = [C.POINTER(Params), C.c_int64, C.c_int, C.POINTER(C.c_size_t)]
+        L.sketchne_sketch_fullvisit.argtypes = [C.c_void_p, C.POINTER(Graph), C.POINTER(Params), C.c_void_p,
+                                                C.c_void_p, C.POINTER(RowSign), C.POINTER(RowSign), C.c_int,
+                                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]
+        L.sketchne_embed_fullvisit.argtypes = [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p,
+                                               C.POINTER(RowSign), C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]
         L.sketchne_symeig_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
         L.sketchne_propagate_coeffs.argtypes = [C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_double)]
         L.sketchne_propagate_workspace_size.argtypes = [C.c_int64, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
@@ -314,6 +325,53 @@ class Library:
                                                    C.c_void_p(sig.data_ptr()), C.c_void_p(self._aligned(ws)), nb),
                    "embed_general")
         return E, Ed, sig
+
+    # ---------------------------------------------------------------- full-visit variant
+    def fullvisit_workspace_size(self, p: SketchParams, n: int, ops: int) -> int:
+        out = C.c_size_t(0)
+        pc = p.c()
+        self.check(self.lib.sketchne_fullvisit_workspace_size(C.byref(pc), n, ops, C.byref(out)),
+                   "fullvisit_workspace_size")
+        return out.value
+
+    def sketch_fullvisit(self, g: "DeviceGraph", p: SketchParams, U, lam, S=None, O=None, ws=None):
+        """Y (transposed, h x n) and Z (l x l) with z nonzeros per row of S and O.
+        S, O: (cols, signs) device tensors of shape (n, z), or None to draw on
+        the device (then returned)."""
+        import torch
+        generate = S is None or O is None
+        if generate:
+            S = (torch.empty((g.n, p.z), dtype=torch.int32, device="cuda"),
+                 torch.empty((g.n, p.z), dtype=torch.int8, device="cuda"))
+            O = (torch.empty((g.n, p.z), dtype=torch.int32, device="cuda"),
+                 torch.empty((g.n, p.z), dtype=torch.int8, device="cuda"))
+        Ss = RowSign(p.h, p.z, S[0].data_ptr(), S[1].data_ptr())
+        Os = RowSign(p.l, p.z, O[0].data_ptr(), O[1].data_ptr())
+        Yt = torch.empty((p.h, g.n), dtype=torch.float32, device="cuda")
+        Z = torch.empty((p.l, p.l), dtype=torch.float32, device="cuda")
+        nb = self.fullvisit_workspace_size(p, g.n, OP_SKETCH)
+        ws = ws if ws is not None else self.workspace(nb)
+        pc, gs = p.c(), g.c()
+        self.check(self.lib.sketchne_sketch_fullvisit(self.ctx(), C.byref(gs), C.byref(pc), C.c_void_p(U.data_ptr()),
+                                                      C.c_void_p(lam.data_ptr()), C.byref(Ss), C.byref(Os),
+                                                      int(generate), C.c_void_p(Yt.data_ptr()),
+                                                      C.c_void_p(Z.data_ptr()), C.c_void_p(self._aligned(ws)), nb),
+                   "sketch_fullvisit")
+        return Yt, Z, S, O
+
+    def embed_fullvisit(self, n: int, p: SketchParams, Yt, Z, O, ws=None):
+        import torch
+        E = torch.empty((n, p.d), dtype=torch.float32, device="cuda")
+        sig = torch.empty(p.d, dtype=torch.float64, device="cuda")
+        Os = RowSign(p.l, p.z, O[0].data_ptr(), O[1].data_ptr())
+        nb = self.fullvisit_workspace_size(p, n, OP_EMBED)
+        ws = ws if ws is not None else self.workspace(nb)
+        pc = p.c()
+        self.check(self.lib.sketchne_embed_fullvisit(self.ctx(), C.byref(pc), n, C.c_void_p(Yt.data_ptr()),
+                                                     C.c_void_p(Z.data_ptr()), C.byref(Os), C.c_void_p(E.data_ptr()),
+                                                     C.c_void_p(sig.data_ptr()), C.c_void_p(self._aligned(ws)), nb),
+                   "embed_fullvisit")
+        return E, sig
 
     # ---------------------------------------------------------------- steps
     def spmm(self, g: "DeviceGraph", alpha: float, B, out=None):

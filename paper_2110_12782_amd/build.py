@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsketchne.so")
-SOURCES = ["api.hip", "rng.hip", "spmm.hip", "gemm64.hip", "gram.hip", "dense_small.hip", "sketch.hip", "mlp.hip", "apply.hip", "propagate.hip"]
+SOURCES = ["api.hip", "rng.hip", "spmm.hip", "gemm64.hip", "gram.hip", "dense_small.hip", "sketch.hip", "mlp.hip", "apply.hip", "propagate.hip", "fullvisit.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

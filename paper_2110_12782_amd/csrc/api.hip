@@ -290,7 +290,7 @@ struct EmbedWs {
   void* symws;
 };
 
-EmbedWs carve_embed(Arena& ar, const sketchne_params* p, int64_t n) {
+EmbedWs carve_embed(Arena& ar, const sketchne_params* p, int64_t n, bool dense_o = false) {
   const int h = p->h, l = p->l, d = p->d;
   EmbedWs w;
   w.Q1 = ar.take<float>((size_t)h * n);
@@ -318,7 +318,8 @@ EmbedWs carve_embed(Arena& ar, const sketchne_params* p, int64_t n) {
   w.s_cap = max_bytes({gemm64_partial_bytes(h, h, l, true), gemm64_partial_bytes(l, h, h, false),
                        gemm64_partial_bytes(h, h, h, false), gemm64_partial_bytes(h, l, l, false),
                        gemm64_partial_bytes(h, h, l, false), gemm64_partial_bytes(h, d, h, false),
-                       gemm64_partial_bytes(n, d, h, false)});
+                       gemm64_partial_bytes(n, d, h, false),
+                       dense_o ? gemm64_partial_bytes(l, h, n, false) : (size_t)0});
   w.s_partial = ar.take<double>(w.s_cap / sizeof(double) + 1);
   w.symws = ar.take<char>(symeig_ws_bytes(h));
   return w;
@@ -340,6 +341,30 @@ sketchne_status check_ws(void* ws, size_t ws_bytes, size_t need) {
   if (need == 0) return SKETCHNE_OK;
   if (!ws || ws_bytes < need || !aligned(ws)) return SKETCHNE_E_WORKSPACE;
   return SKETCHNE_OK;
+}
+
+// Alg. 6 lines 2-3 (Eq. 11): Kmat = U^T D^(-1+2a) U Lambda, then
+// C = Lambda sum_{r=1..T} Kmat^(r-1) by Horner (Sa, Sb: k x k scratch)
+sketchne_status eq11_core(sketchne_ctx* c, int64_t n, int k, int T, const float* U, const double* lambda,
+                          const double* d2, double* Kmat, double* Sa, double* Sb, double* Cc, double* k_partial,
+                          size_t k_cap) {
+  // U^T D U is symmetric (upper blocks, mirrored); Lambda is applied after
+  SK_TRY(gram_tall(c, n, k, U, k, 1, nullptr, 0, 0, d2, Kmat, k_partial, k_cap, nullptr));
+  SK_TRY(scale_cols(c, k, k, Kmat, lambda));
+  SK_TRY(identity(c, k, Sa));
+  double* cur = Sa;
+  double* nxt = Sb;
+  for (int r = 1; r < T; ++r) {
+    GemmDesc gd;
+    gd.M = k; gd.N = k; gd.K = k;
+    gd.A = Kmat; gd.ta = Ty::F64; gd.sai = k; gd.sak = 1;
+    gd.B = cur; gd.tb = Ty::F64; gd.sbk = k; gd.sbj = 1;
+    gd.C = nxt; gd.tc = Ty::F64; gd.sci = k; gd.scj = 1;
+    gd.diag_add = 1.0;
+    SK_TRY(gemm64(c, gd, k_partial, k_cap));
+    double* t = cur; cur = nxt; nxt = t;
+  }
+  return scale_rows(c, k, k, cur, lambda, Cc);
 }
 
 // ------------------------------------------------------------- learned warm start
@@ -537,25 +562,7 @@ sketchne_status sketchne_sketch(sketchne_ctx* c, const sketchne_graph* A, const 
     SK_TRY(gen_sparse_sign(c, n, p->l, p->z, p->seed ^ 0xaaaaaaaaaaaaaaaaULL, O->rows, O->signs));
   }
   SK_TRY(degree_powers(c, n, A->rowptr, p->alpha, w.d1, w.d2));
-  // Alg. 6 line 2: K = U^T D^(-1+2a) U Lambda
-  // U^T D U is symmetric (upper blocks, mirrored); Lambda is applied after
-  SK_TRY(gram_tall(c, n, k, U, k, 1, nullptr, 0, 0, w.d2, w.Kmat, w.k_partial, w.k_cap, nullptr));
-  SK_TRY(scale_cols(c, k, k, w.Kmat, lambda));
-  // Alg. 6 line 3: sum_{r=1..T} K^(r-1) by Horner, C = Lambda * sum
-  SK_TRY(identity(c, k, w.Sa));
-  double* cur = w.Sa;
-  double* nxt = w.Sb;
-  for (int r = 1; r < p->T; ++r) {
-    GemmDesc gd;
-    gd.M = k; gd.N = k; gd.K = k;
-    gd.A = w.Kmat; gd.ta = Ty::F64; gd.sai = k; gd.sak = 1;
-    gd.B = cur; gd.tb = Ty::F64; gd.sbk = k; gd.sbj = 1;
-    gd.C = nxt; gd.tc = Ty::F64; gd.sci = k; gd.scj = 1;
-    gd.diag_add = 1.0;
-    SK_TRY(gemm64(c, gd, w.k_partial, w.k_cap));
-    double* t = cur; cur = nxt; nxt = t;
-  }
-  SK_TRY(scale_rows(c, k, k, cur, lambda, w.Cc));
+  SK_TRY(eq11_core(c, n, k, p->T, U, lambda, w.d2, w.Kmat, w.Sa, w.Sb, w.Cc, w.k_partial, w.k_cap));
 
   const double vol = (double)A->nnz;
   const double scale = vol / (p->b * p->T);
@@ -591,6 +598,10 @@ sketchne_status sketchne_sketch(sketchne_ctx* c, const sketchne_graph* A, const 
   return SKETCHNE_OK;
 }
 
+static sketchne_status embed_impl(sketchne_ctx* c, const sketchne_params* p, int64_t n, const float* Yt,
+                                  const float* Z, const sketchne_sparse_sign* O, const float* Odense, float* E,
+                                  double* sigma, void* ws, size_t ws_bytes);
+
 sketchne_status sketchne_embed(sketchne_ctx* c, const sketchne_params* p, int64_t n, const float* Yt,
                                const float* Z, const sketchne_sparse_sign* O, float* E, double* sigma, void* ws,
                                size_t ws_bytes) {
@@ -600,9 +611,17 @@ sketchne_status sketchne_embed(sketchne_ctx* c, const sketchne_params* p, int64_
   if (p->h > kSymeigMax) return SKETCHNE_E_UNSUPPORTED;
   if (p->h > n) return SKETCHNE_E_ARG;
   SK_TRY(check_ws(ws, ws_bytes, op_bytes(p, n, 0, SKETCHNE_OP_EMBED)));
+  return embed_impl(c, p, n, Yt, Z, O, nullptr, E, sigma, ws, ws_bytes);
+}
+
+// Alg. 4 lines 5, 8-10 with O given by its columns' coordinates (O) or, for
+// the full-visit variant, as a dense n x l matrix (Odense)
+static sketchne_status embed_impl(sketchne_ctx* c, const sketchne_params* p, int64_t n, const float* Yt,
+                                  const float* Z, const sketchne_sparse_sign* O, const float* Odense, float* E,
+                                  double* sigma, void* ws, size_t ws_bytes) {
   const int h = p->h, l = p->l, d = p->d;
   Arena ar(ws, ws_bytes);
-  EmbedWs w = carve_embed(ar, p, n);
+  EmbedWs w = carve_embed(ar, p, n, Odense != nullptr);
   if (ar.overflow) return SKETCHNE_E_WORKSPACE;
 
   auto small = [&](int64_t M, int64_t N, int64_t K, const void* Ap, Ty ta, int64_t sai, int64_t sak, const void* Bp,
@@ -631,7 +650,16 @@ sketchne_status sketchne_embed(sketchne_ctx* c, const sketchne_params* p, int64_
     SK_TRY(small(h, h, h, ow.RinvT, Ty::F64, 1, h, w.RT2, Ty::F64, 1, h, w.Rci, false, ow.need2));
   }
   // B = O^T Q = (O^T Y) Rc^-1   (l x h)
-  SK_TRY(ot_q(c, l, p->z, h, O->rows, O->signs, Yt, n, 1.0 / sqrt((double)p->z), w.OY));
+  if (Odense) {
+    GemmDesc gd;  // O^T Y: O(k, i) = Odense[k l + i], Y(k, j) = Yt[j n + k]
+    gd.M = l; gd.N = h; gd.K = n;
+    gd.A = Odense; gd.ta = Ty::F32; gd.sai = 1; gd.sak = l;
+    gd.B = Yt; gd.tb = Ty::F32; gd.sbk = 1; gd.sbj = n;
+    gd.C = w.OY; gd.tc = Ty::F64; gd.sci = h; gd.scj = 1;
+    SK_TRY(gemm64(c, gd, w.s_partial, w.s_cap));
+  } else {
+    SK_TRY(ot_q(c, l, p->z, h, O->rows, O->signs, Yt, n, 1.0 / sqrt((double)p->z), w.OY));
+  }
   SK_TRY(small(l, h, h, w.OY, Ty::F64, h, 1, w.Rci, Ty::F64, h, 1, w.Bm, false, nullptr));
   // QR of B by Cholesky-QR twice in FP64: B = Bq R, R^-1 = R1^-1 R2^-1
   SK_TRY(small(h, h, l, w.Bm, Ty::F64, 1, h, w.Bm, Ty::F64, h, 1, w.Gb, true, nullptr));
@@ -958,6 +986,185 @@ sketchne_status sketchne_embed_general(sketchne_ctx* c, const sketchne_params* p
   SK_TRY(tall(Yt, w.Map2, E));
   SK_TRY(small(h, d, h, w.RciK, Ty::F64, h, 1, w.Mv, Ty::F64, d, 1, w.Map2, false, nullptr));
   return tall(Kt, w.Map2, Ed);
+}
+
+// ===================================================== full-visit variant
+// Test matrices with z nonzeros per ROW: every entry of f(L'R') is formed,
+// by two chained matrix-core products per tile (fullvisit.hip).
+}  // extern "C"
+
+namespace {
+
+struct FvGeo {
+  int prec, KSM, KSS;
+  int64_t npad, njt, nvt_pad;
+  int nct_h, nct_l;
+  int fb;   // bytes per lane of one fragment
+  int ks2;  // k-steps of the second product per 32 columns
+};
+
+FvGeo fv_geo(const sketchne_params* p, int64_t n) {
+  FvGeo g;
+  g.prec = p->precision;
+  g.KSM = g.KSS = 0;
+  sketch_sections(g.prec, p->k, 0, &g.KSM, &g.KSS);
+  g.npad = (n + 31) / 32 * 32;
+  g.njt = g.npad / 32;
+  g.nvt_pad = (g.njt + 3) / 4 * 4;
+  g.nct_h = (p->h + 31) / 32;
+  g.nct_l = (p->l + 31) / 32;
+  g.fb = g.prec == SKETCHNE_FP32 ? 4 : 16;
+  g.ks2 = g.prec == SKETCHNE_FP32 ? 16 : 2;
+  return g;
+}
+
+struct FvWs {
+  double* d1;
+  double* d2;
+  double* Kmat;
+  double* Sa;
+  double* Sb;
+  double* Cc;
+  double* k_partial;
+  size_t k_cap;
+  double* Gsel;
+  double* RtT;
+  void* A1;
+  void* Bp;
+  void* A2;
+  float* T;
+  float* Od;
+  double* z_partial;
+  size_t z_cap;
+  double* pscale;
+};
+
+FvWs carve_fv(Arena& ar, const sketchne_params* p, int64_t n) {
+  FvGeo g = fv_geo(p, n);
+  const int k = p->k;
+  FvWs w;
+  w.d1 = ar.take<double>(n);
+  w.d2 = ar.take<double>(n);
+  w.Kmat = ar.take<double>((size_t)k * k);
+  w.Sa = ar.take<double>((size_t)k * k);
+  w.Sb = ar.take<double>((size_t)k * k);
+  w.Cc = ar.take<double>((size_t)k * k);
+  w.k_cap = max_bytes({gram_ws_bytes(n, k), gemm64_partial_bytes(k, k, k, false),
+                       gemm64_partial_bytes(g.npad, k, k, false)});
+  w.k_partial = ar.take<double>(w.k_cap / sizeof(double) + 1);
+  w.Gsel = ar.take<double>((size_t)g.npad * k);
+  w.RtT = ar.take<double>((size_t)g.npad * k);
+  w.A1 = ar.take<char>((size_t)g.njt * g.KSM * 64 * g.fb);
+  w.Bp = ar.take<char>((size_t)g.nvt_pad * g.KSM * 64 * g.fb);
+  const int nct = g.nct_h > g.nct_l ? g.nct_h : g.nct_l;
+  w.A2 = ar.take<char>((size_t)g.njt * nct * g.ks2 * 64 * g.fb);
+  w.T = ar.take<float>((size_t)p->l * n);
+  w.Od = ar.take<float>((size_t)n * p->l);
+  w.z_cap = gemm64_partial_bytes(p->l, p->l, n, false);
+  w.z_partial = ar.take<double>(w.z_cap / sizeof(double) + 1);
+  w.pscale = ar.take<double>(2);
+  return w;
+}
+
+bool row_sign_ok(const sketchne_row_sign* T, int width, int z) {
+  return T && T->width == width && T->z == z && T->cols && T->signs;
+}
+
+}  // namespace
+
+extern "C" {
+
+sketchne_status sketchne_fullvisit_workspace_size(const sketchne_params* p, int64_t n, int op_mask, size_t* bytes) {
+  if (!bytes || n < 1) return SKETCHNE_E_ARG;
+  SK_TRY(check_params(p, n));
+  size_t best = 0;
+  if (op_mask & SKETCHNE_OP_SKETCH) { Arena a(nullptr, 0); carve_fv(a, p, n); best = a.off > best ? a.off : best; }
+  if (op_mask & SKETCHNE_OP_EMBED) {
+    Arena a(nullptr, 0);
+    carve_embed(a, p, n, true);
+    a.take<float>((size_t)n * p->l);
+    best = a.off > best ? a.off : best;
+  }
+  *bytes = best;
+  return SKETCHNE_OK;
+}
+
+sketchne_status sketchne_sketch_fullvisit(sketchne_ctx* c, const sketchne_graph* A, const sketchne_params* p,
+                                          const float* U, const double* lambda, sketchne_row_sign* S,
+                                          sketchne_row_sign* O, int generate, float* Yt, float* Z, void* ws,
+                                          size_t ws_bytes) {
+  if (!c || !U || !lambda || !Yt || !Z) return SKETCHNE_E_ARG;
+  SK_TRY(check_graph(A));
+  SK_TRY(check_params(p, A->n));
+  if (!row_sign_ok(S, p->h, p->z) || !row_sign_ok(O, p->l, p->z) || p->z > p->h) return SKETCHNE_E_ARG;
+  if (p->precision == SKETCHNE_FP16 || p->k % 4) return SKETCHNE_E_UNSUPPORTED;
+  const int64_t n = A->n;
+  FvGeo g = fv_geo(p, n);
+  if (g.KSM == 0) return SKETCHNE_E_UNSUPPORTED;
+  size_t need = 0;
+  SK_TRY(sketchne_fullvisit_workspace_size(p, n, SKETCHNE_OP_SKETCH, &need));
+  SK_TRY(check_ws(ws, ws_bytes, need));
+  Arena ar(ws, ws_bytes);
+  FvWs w = carve_fv(ar, p, n);
+  if (ar.overflow) return SKETCHNE_E_WORKSPACE;
+  const int k = p->k;
+  if (generate) {  // z distinct columns per row: the column draw of Alg. 3 with the roles of n and width exchanged
+    SK_TRY(gen_sparse_sign(c, p->h, (int)n, p->z, p->seed ^ 0x1111111111111111ULL, S->cols, S->signs));
+    SK_TRY(gen_sparse_sign(c, p->l, (int)n, p->z, p->seed ^ 0x2222222222222222ULL, O->cols, O->signs));
+  }
+  SK_TRY(degree_powers(c, n, A->rowptr, p->alpha, w.d1, w.d2));
+  SK_TRY(eq11_core(c, n, k, p->T, U, lambda, w.d2, w.Kmat, w.Sa, w.Sb, w.Cc, w.k_partial, w.k_cap));
+  // R'^T rows for every vertex: RtT = scale D1 U C^T (Eq. 11)
+  const double scale = (double)A->nnz / (p->b * p->T);
+  SK_TRY(gather_rows(c, n, g.npad, k, U, k, w.d1, scale, w.Gsel));
+  {
+    GemmDesc gd;
+    gd.M = g.npad; gd.N = k; gd.K = k;
+    gd.A = w.Gsel; gd.ta = Ty::F64; gd.sai = k; gd.sak = 1;
+    gd.B = w.Cc; gd.tb = Ty::F64; gd.sbk = 1; gd.sbj = k;
+    gd.C = w.RtT; gd.tc = Ty::F64; gd.sci = k; gd.scj = 1;
+    SK_TRY(gemm64(c, gd, w.k_partial, w.k_cap));
+  }
+  SK_TRY(balance(c, g.prec, g.npad * k, w.RtT, w.pscale));
+  SK_TRY(pack_A(c, g.prec, (int)g.njt, g.KSM, 0, k, 0, w.RtT, w.pscale, w.A1));
+  SK_TRY(pack_B(c, g.prec, n, n, g.nvt_pad, g.KSM, 0, k, 0, nullptr, U, k, w.d1, w.pscale, w.Bp));
+  const float inv_sqrt_z = (float)(1.0 / sqrt((double)p->z));
+  const float out_scale = 0.69314718055994530942f * inv_sqrt_z;
+  // Y = f(L'R') S
+  SK_TRY(pack_s_full(c, g.prec, n, g.njt, g.nct_h, p->z, S->cols, S->signs, p->h, w.A2));
+  SK_TRY(fullvisit(c, SKETCHNE_PROF_SKETCH_Y, g.prec, g.KSM, n, g.njt, g.nct_h, p->h, w.Bp, w.A1, w.A2, Yt, n,
+                   out_scale));
+  // T = f(L'R') O, then Z = O^T T
+  SK_TRY(pack_s_full(c, g.prec, n, g.njt, g.nct_l, p->z, O->cols, O->signs, p->l, w.A2));
+  SK_TRY(fullvisit(c, SKETCHNE_PROF_SKETCH_Z, g.prec, g.KSM, n, g.njt, g.nct_l, p->l, w.Bp, w.A1, w.A2, w.T, n,
+                   out_scale));
+  SK_TRY(dense_rows(c, n, p->l, p->z, O->cols, O->signs, inv_sqrt_z, w.Od));
+  GemmDesc gd;  // Z = O^T T: O(k, i) = Od[k l + i], T(k, j) = Tt[j n + k]
+  gd.M = p->l; gd.N = p->l; gd.K = n;
+  gd.A = w.Od; gd.ta = Ty::F32; gd.sai = 1; gd.sak = p->l;
+  gd.B = w.T; gd.tb = Ty::F32; gd.sbk = 1; gd.sbj = n;
+  gd.C = Z; gd.tc = Ty::F32; gd.sci = p->l; gd.scj = 1;
+  return gemm64(c, gd, w.z_partial, w.z_cap);
+}
+
+sketchne_status sketchne_embed_fullvisit(sketchne_ctx* c, const sketchne_params* p, int64_t n, const float* Yt,
+                                         const float* Z, const sketchne_row_sign* O, float* E, double* sigma,
+                                         void* ws, size_t ws_bytes) {
+  if (!c || !Yt || !Z || !E || !sigma || n < 1) return SKETCHNE_E_ARG;
+  SK_TRY(check_params(p, n));
+  if (!row_sign_ok(O, p->l, p->z)) return SKETCHNE_E_ARG;
+  if (p->h > kSymeigMax) return SKETCHNE_E_UNSUPPORTED;
+  if (p->h > n) return SKETCHNE_E_ARG;
+  size_t need = 0;
+  SK_TRY(sketchne_fullvisit_workspace_size(p, n, SKETCHNE_OP_EMBED, &need));
+  SK_TRY(check_ws(ws, ws_bytes, need));
+  // the dense O goes after the embedding's own workspace
+  Arena ar(nullptr, 0);
+  carve_embed(ar, p, n, true);
+  const size_t off = ar.off;
+  float* Od = reinterpret_cast<float*>(static_cast<char*>(ws) + off);
+  SK_TRY(dense_rows(c, n, p->l, p->z, O->cols, O->signs, (float)(1.0 / sqrt((double)p->z)), Od));
+  return embed_impl(c, p, n, Yt, Z, nullptr, Od, E, sigma, ws, off);
 }
 
 sketchne_status sketchne_sync(sketchne_ctx* c, uint32_t* flags) {

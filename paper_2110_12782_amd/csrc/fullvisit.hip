@@ -1,0 +1,298 @@
+// The full-visit variant of the sparse-sign sketch: test matrices with z
+// nonzeros in every ROW (one set per vertex) instead of every column, so
+//     Y = f(L'R') S,   T = f(L'R') O,   Z = O^T T
+// touch every one of the n^2 entries of f(L'R') (Alg. 3 read with the
+// nonzeros of a test matrix spread over its rows).  Nothing is sampled, so
+// the product becomes two chained GEMMs, as in attention:
+//     X^T tile (32 columns j x 32 vertices i) = R'(:, j)^T L'(i, :)^T   (MFMA)
+//     F = trunc_log(X) in registers
+//     Y^T tile (32 outputs c x 32 vertices i) += S(j, c)^T F            (MFMA)
+// The accumulator layout of the first product is the B-operand layout of
+// the second once the summation index j of the second is taken in the order
+// the accumulators hold it, so F never leaves registers; S is packed in that
+// order (exact +-1 in BF16 or FP32, 1/sqrt(z) and ln 2 applied at the store).
+// A workgroup of four wavefronts takes 128 vertices (one 32-vertex tile per
+// wave, its L' fragments in registers) and streams the column tiles of R'
+// and the matching S blocks through two LDS buffers by LDS-DMA.  The output
+// columns are taken NCT tiles of 32 at a time (blockIdx.y), each launch chunk
+// recomputing the first product.
+#include <type_traits>
+
+#include "internal.h"
+
+#include "sketch.h"
+
+namespace skne {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <int PREC>
+struct FvOp;
+template <>
+struct FvOp<SKETCHNE_FP32> {
+  typedef float frag;
+  static constexpr int KS2 = 16;  // k-steps of the second product over 32 columns j
+  static __device__ __forceinline__ floatx16 mma(frag a, frag b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct FvOp<SKETCHNE_BF16> {
+  typedef bf16x8 frag;
+  static constexpr int KS2 = 2;
+  static __device__ __forceinline__ floatx16 mma(frag a, frag b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// column j (0..31) of a 32-column tile that k-step s, lane half hf, element u
+// of the second product's operands stands for: the order in which the first
+// product's accumulators hold the columns (register e of lane half hf holds
+// row 8 (e / 4) + 4 hf + e % 4 of the 32 x 32 output)
+__device__ __forceinline__ int fv_col(int prec, int s, int hf, int u) {
+  if (prec == SKETCHNE_FP32) return 8 * (s >> 2) + 4 * hf + (s & 3);
+  return 16 * s + (u < 4 ? 4 * hf + u : 8 + 4 * hf + (u - 4));
+}
+
+// S^T blocks in MFMA A-fragment order: [column tile jt][output tile ct][k-step s][lane]
+// (lane l: output c = 32 ct + l % 32, columns j of k-step s from fv_col)
+// value = sign if c is among the z columns of row j (of n rows), else 0
+template <int PREC>
+__global__ void k_pack_s_full(int64_t n, int64_t njt, int nct, int z, const int32_t* __restrict__ cols,
+                              const int8_t* __restrict__ signs, void* __restrict__ out, uint32_t* __restrict__ flags,
+                              int width) {
+  constexpr int KS2 = FvOp<PREC>::KS2;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = njt * nct * KS2 * 64;
+  if (idx >= total) return;
+  const int lane = (int)(idx & 63);
+  int64_t q = idx >> 6;
+  const int s = (int)(q % KS2);
+  q /= KS2;
+  const int ct = (int)(q % nct);
+  const int64_t jt = q / nct;
+  const int c = 32 * ct + (lane & 31), hf = lane >> 5;
+  auto value = [&](int u) -> float {
+    const int64_t j = 32 * jt + fv_col(PREC, s, hf, u);
+    if (j >= n) return 0.0f;
+    float v = 0.0f;
+    for (int t = 0; t < z; ++t) {
+      const int col = cols[j * z + t];
+      if (col < 0 || col >= width) atomicOr(flags, SKETCHNE_FLAG_BAD_INDEX);
+      if (col == c) v = (float)signs[j * z + t];
+    }
+    return v;
+  };
+  if (PREC == SKETCHNE_FP32) {
+    static_cast<float*>(out)[idx] = value(0);
+  } else {
+    uint16_t w[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) w[u] = bf16_rne(value(u));
+    static_cast<uint4*>(out)[idx] = make_uint4(w[0] | ((uint32_t)w[1] << 16), w[2] | ((uint32_t)w[3] << 16),
+                                               w[4] | ((uint32_t)w[5] << 16), w[6] | ((uint32_t)w[7] << 16));
+  }
+}
+
+// rows of R'^T before the core product: Gsel[j][:] = scale d1[j] U[j][:] (zero for j >= n)
+__global__ void k_gather_rows(int64_t n, int64_t npad, int k, const float* __restrict__ U, int64_t ldu,
+                              const double* __restrict__ d1, double scale, double* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= npad * k) return;
+  const int64_t j = idx / k;
+  const int col = (int)(idx - j * k);
+  out[idx] = j < n ? scale * d1[j] * (double)U[j * ldu + col] : 0.0;
+}
+
+// dense O (n x l, FP32) from the per-row coordinates: O[i][cols[i][t]] = signs[i][t] / sqrt(z)
+__global__ void k_dense_rows(int64_t n, int width, int z, const int32_t* __restrict__ cols,
+                             const int8_t* __restrict__ signs, float inv_sqrt_z, float* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * z) return;
+  const int64_t i = idx / z;
+  const int col = cols[idx];
+  if (col >= 0 && col < width) out[i * width + col] = inv_sqrt_z * (float)signs[idx];
+}
+
+__global__ void k_fill0(int64_t count, float* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < count) out[idx] = 0.0f;
+}
+
+template <int PREC, int KSM, int NCT>
+__global__ __launch_bounds__(256, 1) void k_fullvisit(int64_t nrows, int64_t njt, int nct_all, int width,
+                                                      const void* __restrict__ Bpack, const void* A1pack,
+                                                      const void* A2pack, float* __restrict__ out, int64_t ld_out,
+                                                      float out_scale) {
+  typedef FvOp<PREC> Op;
+  typedef typename Op::frag frag;
+  constexpr int FB = sizeof(frag) * 64;  // bytes of one fragment (64 lanes)
+  constexpr int KS2 = Op::KS2;
+  constexpr int NF = KSM + NCT * KS2;    // fragments per column tile in LDS
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t vt = (int64_t)blockIdx.x * 4 + wave;
+  const int ct0 = blockIdx.y * NCT;
+  const int nct = nct_all - ct0 < NCT ? nct_all - ct0 : NCT;
+
+  frag bfr[KSM];
+  const frag* Bp = static_cast<const frag*>(Bpack);
+#pragma unroll
+  for (int ks = 0; ks < KSM; ++ks) bfr[ks] = Bp[(vt * KSM + ks) * 64 + lane];
+  const char* A1 = static_cast<const char*>(A1pack);
+  const char* A2 = static_cast<const char*>(A2pack);
+  // column tile jt -> LDS buffer b: its KSM fragments of R'^T, then the S^T
+  // fragments of this launch's output tiles; fragment f is one DMA by wave f % 4
+  auto dma = [&](int64_t jt, int b) {
+    char* dst = lds_raw + (int64_t)b * NF * FB;
+    for (int f = wave; f < KSM + nct * KS2; f += 4) {
+      const char* src = f < KSM ? A1 + (jt * KSM + f) * FB
+                                : A2 + ((jt * nct_all + ct0) * KS2 + (f - KSM)) * FB;
+      if constexpr (sizeof(frag) == 16)
+        __builtin_amdgcn_global_load_lds((const void*)(src + lane * 16), (lds_void*)(dst + f * FB), 16, 0, 0);
+      else
+        __builtin_amdgcn_global_load_lds((const void*)(src + lane * 4), (lds_void*)(dst + f * FB), 4, 0, 0);
+    }
+  };
+  floatx16 accY[NCT];
+#pragma unroll
+  for (int q = 0; q < NCT; ++q)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) accY[q][e] = 0.0f;
+  dma(0, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int64_t jt = 0; jt < njt; ++jt) {
+    const int b = (int)(jt & 1);
+    if (jt + 1 < njt) dma(jt + 1, b ^ 1);
+    const frag* L = reinterpret_cast<const frag*>(lds_raw + (int64_t)b * NF * FB);
+    // first product: X^T (32 columns x 32 vertices)
+    floatx16 x = {};
+#pragma unroll
+    for (int ks = 0; ks < KSM; ++ks) x = Op::mma(L[ks * 64 + lane], bfr[ks], x);
+    // F = max(log2 x, 0) as the B operand of the second product
+    frag fb[KS2];
+    if constexpr (PREC == SKETCHNE_FP32) {
+#pragma unroll
+      for (int s = 0; s < KS2; ++s) fb[s] = fmaxf(__builtin_amdgcn_logf(x[s]), 0.0f);
+    } else {
+#pragma unroll
+      for (int s = 0; s < KS2; ++s) {
+        uint16_t w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) w[u] = bf16_rne(fmaxf(__builtin_amdgcn_logf(x[8 * s + u]), 0.0f));
+        uint4 pk = make_uint4(w[0] | ((uint32_t)w[1] << 16), w[2] | ((uint32_t)w[3] << 16),
+                              w[4] | ((uint32_t)w[5] << 16), w[6] | ((uint32_t)w[7] << 16));
+        fb[s] = __builtin_bit_cast(frag, pk);
+      }
+    }
+    // second product: Y^T tiles += S^T F
+#pragma unroll
+    for (int q = 0; q < NCT; ++q) {
+      if (q < nct) {
+#pragma unroll
+        for (int s = 0; s < KS2; ++s) accY[q] = Op::mma(L[(KSM + q * KS2 + s) * 64 + lane], fb[s], accY[q]);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  // Y^T[c][i], c = 32 (ct0 + q) + 8 (e / 4) + 4 hf + e % 4, i = 32 vt + lane % 32
+  const int64_t i = vt * 32 + (lane & 31);
+  if (i >= nrows) return;
+#pragma unroll
+  for (int q = 0; q < NCT; ++q) {
+    if (q < nct) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int c = 32 * (ct0 + q) + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        if (c < width) out[(int64_t)c * ld_out + i] = out_scale * accY[q][e];
+      }
+    }
+  }
+}
+
+template <int PREC, int KSM, int NCT>
+sketchne_status launch_fullvisit(sketchne_ctx* c, int cls, int64_t nrows, int64_t njt, int nct_all, int width,
+                                 const void* Bp, const void* A1, const void* A2, float* out, int64_t ld_out,
+                                 float out_scale) {
+  typedef typename FvOp<PREC>::frag frag;
+  constexpr int NF = KSM + NCT * FvOp<PREC>::KS2;
+  const size_t shmem = (size_t)2 * NF * 64 * sizeof(frag);
+  auto kern = k_fullvisit<PREC, KSM, NCT>;
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)shmem) != hipSuccess)
+    return SKETCHNE_E_DEVICE;
+  const int64_t nvt = (nrows + 31) / 32;
+  ProfScope ps(c, cls);
+  hipLaunchKernelGGL(kern, dim3((unsigned)((nvt + 3) / 4), (unsigned)((nct_all + NCT - 1) / NCT)), dim3(256), shmem,
+                     c->stream, nrows, njt, nct_all, width, Bp, A1, A2, out, ld_out, out_scale);
+  return launch_status();
+}
+
+}  // namespace
+
+// output tiles per launch chunk (accumulators held per lane: 16 per tile)
+int fullvisit_nct(int prec) { return prec == SKETCHNE_FP32 ? 3 : 9; }
+
+sketchne_status gather_rows(sketchne_ctx* c, int64_t n, int64_t npad, int k, const float* U, int64_t ldu,
+                            const double* d1, double scale, double* out) {
+  ProfScope ps(c, SKETCHNE_PROF_PREP);
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((npad * k + 255) / 256)), dim3(256), 0, c->stream, n, npad, k, U,
+                     ldu, d1, scale, out);
+  return launch_status();
+}
+
+sketchne_status pack_s_full(sketchne_ctx* c, int prec, int64_t n, int64_t njt, int nct, int z, const int32_t* cols,
+                            const int8_t* signs, int width, void* out) {
+  const int ks2 = prec == SKETCHNE_FP32 ? FvOp<SKETCHNE_FP32>::KS2 : FvOp<SKETCHNE_BF16>::KS2;
+  const int64_t tot = njt * nct * ks2 * 64;
+  ProfScope ps(c, SKETCHNE_PROF_PREP);
+  if (prec == SKETCHNE_FP32)
+    hipLaunchKernelGGL(k_pack_s_full<SKETCHNE_FP32>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, n,
+                       njt, nct, z, cols, signs, out, c->d_flags, width);
+  else
+    hipLaunchKernelGGL(k_pack_s_full<SKETCHNE_BF16>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, n,
+                       njt, nct, z, cols, signs, out, c->d_flags, width);
+  return launch_status();
+}
+
+sketchne_status dense_rows(sketchne_ctx* c, int64_t n, int width, int z, const int32_t* cols, const int8_t* signs,
+                           float inv_sqrt_z, float* out) {
+  ProfScope ps(c, SKETCHNE_PROF_PREP);
+  const int64_t cnt = n * width;
+  hipLaunchKernelGGL(k_fill0, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, c->stream, cnt, out);
+  hipLaunchKernelGGL(k_dense_rows, dim3((unsigned)((n * z + 255) / 256)), dim3(256), 0, c->stream, n, width, z, cols,
+                     signs, inv_sqrt_z, out);
+  return launch_status();
+}
+
+sketchne_status fullvisit(sketchne_ctx* c, int cls, int prec, int KSM, int64_t nrows, int64_t njt, int nct_all,
+                          int width, const void* Bp, const void* A1, const void* A2, float* out, int64_t ld_out,
+                          float out_scale) {
+  if (nrows == 0 || width == 0) return SKETCHNE_OK;
+  if (prec == SKETCHNE_FP32) {
+    switch (KSM) {
+      case 32: return launch_fullvisit<SKETCHNE_FP32, 32, 3>(c, cls, nrows, njt, nct_all, width, Bp, A1, A2, out, ld_out, out_scale);
+      case 64: return launch_fullvisit<SKETCHNE_FP32, 64, 3>(c, cls, nrows, njt, nct_all, width, Bp, A1, A2, out, ld_out, out_scale);
+      case 128: return launch_fullvisit<SKETCHNE_FP32, 128, 3>(c, cls, nrows, njt, nct_all, width, Bp, A1, A2, out, ld_out, out_scale);
+    }
+  } else if (prec == SKETCHNE_BF16) {
+    switch (KSM) {
+      case 8: return launch_fullvisit<SKETCHNE_BF16, 8, 9>(c, cls, nrows, njt, nct_all, width, Bp, A1, A2, out, ld_out, out_scale);
+      case 16: return launch_fullvisit<SKETCHNE_BF16, 16, 9>(c, cls, nrows, njt, nct_all, width, Bp, A1, A2, out, ld_out, out_scale);
+    }
+  }
+  return SKETCHNE_E_UNSUPPORTED;
+}
+
+}  // namespace skne

@@ -33,4 +33,16 @@ sketchne_status z_reduce(sketchne_ctx* c, int l, int z, const int8_t* signs, con
 sketchne_status ot_q(sketchne_ctx* c, int l, int z, int hcols, const int32_t* rows, const int8_t* signs,
                      const float* Qt, int64_t n, double inv_sqrt_z, double* Bm);
 
+// fullvisit.hip: the full-visit variant (z nonzeros per row of S and O)
+int fullvisit_nct(int prec);
+sketchne_status gather_rows(sketchne_ctx* c, int64_t n, int64_t npad, int k, const float* U, int64_t ldu,
+                            const double* d1, double scale, double* out);
+sketchne_status pack_s_full(sketchne_ctx* c, int prec, int64_t n, int64_t njt, int nct, int z, const int32_t* cols,
+                            const int8_t* signs, int width, void* out);
+sketchne_status dense_rows(sketchne_ctx* c, int64_t n, int width, int z, const int32_t* cols, const int8_t* signs,
+                           float inv_sqrt_z, float* out);
+sketchne_status fullvisit(sketchne_ctx* c, int cls, int prec, int KSM, int64_t nrows, int64_t njt, int nct_all,
+                          int width, const void* Bp, const void* A1, const void* A2, float* out, int64_t ld_out,
+                          float out_scale);
+
 }  // namespace skne
