@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}  # dense MFMA TFLOP/s (MI355X)
+BF16_CODE = 1
 HBM_PEAK = 8000.0  # GB/s
 
 
@@ -144,6 +145,7 @@ def main():
     sp_bytes = g.nnz * (4 + 4 * K)
     sp_gbs = sp_bytes / (sp_ms * 1e-3) / 1e9
     forms = {args.precision: {"ms_per_step": dt * 1e3, "sketch_y_ms": ty * 1e3, "sketch_z_ms": tz * 1e3,
+                              "sketch_entries_per_s": sketch_rate,
                               "per_class_ms": {kk: vv[0] / steps for kk, vv in prof.items()}}}
     ref_form = None
     if not args.no_compare and args.precision != "fp32":
@@ -163,6 +165,9 @@ def main():
 
     if not args.no_learned:
         forms["learned_warm_start"] = learned_form(lib, g, params(args.precision), ws, forms[args.precision])
+    extras = {"spectral_propagation": propagation_form(lib, g, out[6]),
+              "general_single_pass": general_form(lib, g.n, params(args.precision)),
+              "full_visit": fullvisit_form(lib, args.precision)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -200,102 +205,111 @@ def main():
                           "unit": "GB/s", "frac": sp_gbs / HBM_PEAK, "traffic": None, "launch_ms": sp_ms,
                           "algorithmic_bytes": sp_bytes},
         "forms": forms,
+        "beyond_the_step": extras,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
 
 
-TRAIN_GRAPHS, TRAIN_LOGN, TRAIN_STEPS = 16, 17, 2000
+# Training family of the learned warm start: SBM and Chung-Lu graphs, n
+# log-uniform over 2^16 .. 2^20 (mostly small: the gradient costs O(n)),
+# exponent 2.0-2.5, mean degree 8-32; held out: two SBM and two Chung-Lu
+# graphs at n = 2^20.
+TRAIN_LOGN = (16, 17, 18, 16, 17, 19, 16, 18, 17, 20, 16, 17)
+HELD_OUT = 4
+TRAIN_STEPS = 2000
 TRAIN_MU = 10.0  # weight of the orthogonality term of the loss (chosen on held-out graphs)
 
 
-def learned_form(lib, g, p, ws, plain_form):
-    """Learned warm start of Alg. 5: train the network on sixteen seeded
-    graphs (n = 2^17, SBM and Chung-Lu, exponent 2.0-2.5, mean degree 8-32)
-    against their own converged eigenvectors (q = 16), then compare the
-    Gaussian and learned starts on the bench graph (held out) at q = 0, 1, 2:
-    subspace error of U_k against a q = 16 reference and eigensolver time."""
-    import torch
+def family_graph(i, lg, seed, rng):
+    """Graph i of the warm-start family (even i: SBM of 16 blocks, odd i:
+    Chung-Lu), n = 2^lg, mean degree log-uniform on [8, 32]."""
     import synth
+    n = 1 << lg
+    deg = float(np.exp(rng.uniform(np.log(8.0), np.log(32.0))))
+    if i % 2 == 0:
+        bs = n // 16
+        return synth.sbm([bs] * 16, deg * 0.8 / bs, deg * 0.2 / (n - bs), seed)
+    return synth.chung_lu(n, float(rng.uniform(2.0, 2.5)), deg, 2, seed)
+
+
+def learned_form(lib, g, p, ws, plain_form):
+    """Learned warm start of Alg. 5: train the network on the family above
+    against each graph's own converged eigenvectors (q = 16), then on each
+    held-out graph compare the Gaussian and learned starts at q = 0..3
+    (subspace error of U_k against a q = 24 reference), count the power
+    iterations the learned start saves at equal error and the fallback
+    decisions; finally time the whole step on the bench graph with the
+    learned start at the q that matches the plain q = 2 error there."""
+    import torch
     from paper_2110_12782_amd.binding import DeviceGraph, MLP, SketchParams
     t0 = time.time()
-    sets = []
-    calib = []
-    nt = 1 << TRAIN_LOGN
-    for i in range(TRAIN_GRAPHS):
-        if i % 2 == 0:
-            # 16 blocks; edge probabilities scaled with n to keep the degrees of the n = 2^16 family
-            f = (1 << 16) / nt
-            rp, ci = synth.sbm([nt // 16] * 16, 0.0035 * f * (1 + 0.3 * (i % 4)), 0.0001 * f, 6000 + i)
-        else:
-            rp, ci = synth.chung_lu(nt, 2.0 + 0.125 * (i % 5), 8 + 8 * (i % 4), 2, 6000 + i)
+    rng = np.random.default_rng(0)
+
+    def P(q, seed, prec=None):
+        return SketchParams(k=p.k, s_eig=p.s_eig, q=q, d=p.d, h=p.h, l=p.l, z=p.z, seed=seed,
+                            precision=p.precision if prec is None else prec,
+                            split_r=p.split_r if prec is None else 0)
+
+    sets, calib = [], []
+    for i, lg in enumerate(TRAIN_LOGN):
+        rp, ci = family_graph(i, lg, 10000 + i, rng)
         G = DeviceGraph(rp, ci)
-        pr = SketchParams(k=p.k, s_eig=p.s_eig, q=16, d=p.d, h=p.h, l=p.l, z=p.z, seed=100 + i)
-        Uref, _ = lib.eig(G, pr)
+        Uref, _ = lib.eig(G, P(16, 100 + i))
         sets.append((lib.ws_features(G, 0.5, seed=200 + i), Uref.contiguous()))
         # fallback calibration: the largest Ritz residual of the plain start at q = 2
-        p2 = SketchParams(k=p.k, s_eig=p.s_eig, q=2, d=p.d, h=p.h, l=p.l, z=p.z, seed=300 + i)
-        U2, l2 = lib.eig(G, p2)
+        U2, l2 = lib.eig(G, P(2, 300 + i))
         calib.append(float(lib.ritz_residual(G, 0.5, U2, l2).max()))
     threshold = 1.1 * max(calib)
     torch.cuda.synchronize()
     t_data = time.time() - t0
     net = MLP(lib, 256, p.k)
     lib.ws_init(net, 11)
-    steps = TRAIN_STEPS
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    losses = lib.ws_train(net, sets, steps, 1e-3, TRAIN_MU)
+    losses = lib.ws_train(net, sets, TRAIN_STEPS, 1e-3, TRAIN_MU)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     losses = losses.cpu().numpy()
-    # held-out evaluation on the bench graph
-    pref = SketchParams(k=p.k, s_eig=p.s_eig, q=16, d=p.d, h=p.h, l=p.l, z=p.z, seed=999)
-    Uref, _ = lib.eig(g, pref, ws=ws)
+    del sets
 
-    def err(U):
+    def err(U, Uref):
         k = U.shape[1]
         s = torch.linalg.matrix_norm(Uref.double().T @ U.double()) ** 2
         return float(torch.sqrt(torch.clamp(k - s, min=0.0) / k))
 
-    def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        out = fn()
-        torch.cuda.synchronize()
-        return out, (time.perf_counter() - t) * 1e3
-
-    rows = {}
+    held = []
+    for j in range(HELD_OUT):
+        rp, ci = family_graph(j, 20, 20000 + j, rng)
+        G = DeviceGraph(rp, ci)
+        Uref, _ = lib.eig(G, P(24, 999))
+        plain, learned, fallbacks = [], [], 0
+        for q in (0, 1, 2, 3):
+            Up, _ = lib.eig(G, P(q, 11))
+            Uw, _, fb = lib.eig_learned(G, P(q, 11), net, q, threshold)
+            fallbacks += int(fb)
+            plain.append(err(Up, Uref))
+            learned.append(err(Uw, Uref))
+        # iterations saved at equal error: the smallest q_w whose learned error
+        # is at or below the plain error at q, for q = 1..3
+        saved = [q - min((qw for qw in range(4) if learned[qw] <= plain[q]), default=q) for q in (1, 2, 3)]
+        held.append({"graph": "sbm" if j % 2 == 0 else "chung-lu", "n": 1 << 20, "nnz": int(rp[-1]),
+                     "plain_sin_theta": plain, "learned_sin_theta": learned,
+                     "iterations_saved_at_q1_q2_q3": saved, "fallbacks_of_4": fallbacks})
+        log(f"held-out {held[-1]['graph']}: plain " + " ".join(f"{x:.4f}" for x in plain) + " | learned " +
+            " ".join(f"{x:.4f}" for x in learned) + f" | saved {saved} | fallbacks {fallbacks}/4")
+    # the whole step on the bench graph with the learned start at the smallest
+    # q that reaches the plain q = 2 error there
+    Uref, _ = lib.eig(g, P(24, 999), ws=ws)
+    Up2, _ = lib.eig(g, P(2, p.seed), ws=ws)
+    target = err(Up2, Uref)
+    qw = 2
     for q in (0, 1, 2):
-        pq = SketchParams(k=p.k, s_eig=p.s_eig, q=q, d=p.d, h=p.h, l=p.l, z=p.z, seed=p.seed)
-        (Up, lp), tp = timed(lambda: lib.eig(g, pq, ws=ws))
-        (Uw, lw, fb), tw = timed(lambda: lib.eig_learned(g, pq, net, q, float("inf")))
-        res_p = float(lib.ritz_residual(g, 0.5, Up, lp).max())
-        res_w = float(lib.ritz_residual(g, 0.5, Uw, lw).max())
-        rows[f"q{q}"] = {"plain_sin_theta": err(Up), "learned_sin_theta": err(Uw), "plain_eig_ms": tp,
-                         "learned_eig_ms": tw, "plain_max_ritz_residual": res_p, "learned_max_ritz_residual": res_w}
-    target = rows["q2"]["plain_sin_theta"]
-    reach = [q for q in (0, 1, 2) if rows[f"q{q}"]["learned_sin_theta"] <= target]
-    saved = 2 - min(reach) if reach else 0
-    # the converse at equal error: plain iterations needed to reach the error
-    # of the learned start at q = 2
-    target_w = rows["q2"]["learned_sin_theta"]
-    plain_err = {q: rows[f"q{q}"]["plain_sin_theta"] for q in (0, 1, 2)}
-    for q in (3, 4, 5):
-        if min(plain_err.values()) <= target_w:
+        Uw, _, _ = lib.eig_learned(g, P(q, p.seed), net, q, float("inf"))
+        if err(Uw, Uref) <= target:
+            qw = q
             break
-        pq = SketchParams(k=p.k, s_eig=p.s_eig, q=q, d=p.d, h=p.h, l=p.l, z=p.z, seed=p.seed)
-        (Up, _), tp = timed(lambda: lib.eig(g, pq, ws=ws))
-        plain_err[q] = err(Up)
-        rows[f"q{q}"] = {"plain_sin_theta": plain_err[q], "plain_eig_ms": tp}
-    need = [q for q in sorted(plain_err) if plain_err[q] <= target_w]
-    q_plain_eq = need[0] if need else None
-    # whole step with the learned start at the smallest q that reaches the
-    # plain q = 2 error, the fallback armed with the calibrated threshold
-    qw = min(reach) if reach else 2
-    pw = SketchParams(k=p.k, s_eig=p.s_eig, q=2, d=p.d, h=p.h, l=p.l, z=p.z, seed=p.seed, precision=p.precision,
-                      split_r=p.split_r)
+    pw = P(2, p.seed)
 
     def lstep():
         U, lam, fb = lib.eig_learned(g, pw, net, qw, threshold, ws=None)
@@ -309,54 +323,102 @@ def learned_form(lib, g, p, ws, plain_form):
     fbs = [lstep() for _ in range(3)]
     torch.cuda.synchronize()
     lstep_ms = (time.perf_counter() - t) / 3 * 1e3
+    log(f"learned form: data {t_data:.1f}s, {TRAIN_STEPS} training steps in {t_train:.2f}s, loss "
+        f"{losses[:16].mean():.3f} -> {losses[-16:].mean():.3f}; bench graph: plain q=2 error {target:.4f}, learned "
+        f"start reaches it at q={qw}; whole step {lstep_ms:.2f} ms (plain q=2 {plain_form['ms_per_step']:.2f} ms), "
+        f"fallback used {sum(fbs)}/3")
+    return {"training": {"graphs": len(TRAIN_LOGN), "n": [1 << x for x in TRAIN_LOGN], "steps": TRAIN_STEPS,
+                         "seconds": t_train, "loss_first16": float(losses[:16].mean()),
+                         "loss_last16": float(losses[-16:].mean())},
+            "held_out": held, "fallback_threshold": threshold,
+            "bench_graph": {"plain_q2_sin_theta": target, "learned_q_at_equal_error": qw,
+                            "ms_per_step": lstep_ms, "plain_q2_ms_per_step": plain_form["ms_per_step"],
+                            "fallback_used": int(sum(fbs)), "steps": 3}}
 
-    def whole_step_ms(fn):
+
+def timed_launches(lib, fn, reps=5):
+    """Mean milliseconds of fn() over reps calls on the library's stream
+    (HIP events around each call), after one warm-up call."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    start = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    end = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    for i in range(reps):
+        start[i].record()
         fn()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(3):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t) / 3 * 1e3
+        end[i].record()
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in zip(start, end)) / reps
 
-    # whole steps at equal error: learned start at q = 2 against the plain
-    # start at the q that first reaches the same error
-    eq = None
-    if q_plain_eq is not None:
-        pl = SketchParams(k=p.k, s_eig=p.s_eig, q=2, d=p.d, h=p.h, l=p.l, z=p.z, seed=p.seed,
-                          precision=p.precision, split_r=p.split_r)
-        pp = SketchParams(k=p.k, s_eig=p.s_eig, q=q_plain_eq, d=p.d, h=p.h, l=p.l, z=p.z, seed=p.seed,
-                          precision=p.precision, split_r=p.split_r)
 
-        def lstep2():
-            U, lam, _ = lib.eig_learned(g, pl, net, 2, threshold, ws=None)
-            Yt, Z, S, O = lib.sketch(g, pl, U, lam, ws=ws)
-            lib.embed(g.n, pl, Yt, Z, O, ws=ws)
+def propagation_form(lib, g, E):
+    """Alg. 6 line 6 on the step's embedding (d = 128, p = 10): one fused
+    SpMM per Chebyshev step.  HBM model per step: the gathered rows of T_r
+    (nnz * d * 4 bytes, no reuse) plus T_{r-1} read, T_{r+1} written and the
+    running sum read and written (4 n d 4 bytes) and the column indices."""
+    import torch
+    p = 10
+    coef = lib.propagate_coeffs(p, 0.5, 0.2)
+    E = E.contiguous()
+    out = torch.empty_like(E)
+    ms = timed_launches(lib, lambda: lib.propagate(g, E, coef, out=out))
+    n, d = E.shape
+    # compulsory bytes per step: column indices and row pointers once, T_r read
+    # once, T_{r-1} read, T_{r+1} written, the running sum read and written
+    compulsory = 4 * g.nnz + 8 * (n + 1) + 5 * n * d * 4
+    no_reuse = g.nnz * (4 + 4 * d) + 4 * n * d * 4
+    gbs = p * compulsory / (ms * 1e-3) / 1e9
+    log(f"spectral propagation d={d} p={p}: {ms:.2f} ms; {gbs:.0f} GB/s of compulsory bytes, "
+        f"{p * no_reuse / (ms * 1e-3) / 1e9:.0f} GB/s if no gathered row were reused")
+    return {"d": d, "p": p, "theta": 0.5, "mu": 0.2, "ms": ms, "compulsory_bytes_per_step": compulsory,
+            "no_reuse_bytes_per_step": no_reuse, "compulsory_GBps": gbs,
+            "no_reuse_GBps": p * no_reuse / (ms * 1e-3) / 1e9}
 
-        def pstep():
-            U, lam = lib.eig(g, pp, ws=ws)
-            Yt, Z, S, O = lib.sketch(g, pp, U, lam, ws=ws)
-            lib.embed(g.n, pp, Yt, Z, O, ws=ws)
 
-        eq = {"error": target_w, "learned_q": 2, "learned_ms_per_step": whole_step_ms(lstep2),
-              "plain_q": q_plain_eq, "plain_error": plain_err[q_plain_eq], "plain_ms_per_step": whole_step_ms(pstep),
-              "iterations_saved": q_plain_eq - 2}
-    log(f"learned form: data {t_data:.1f}s, {steps} training steps in {t_train:.2f}s, loss {losses[:16].mean():.3f} -> "
-        f"{losses[-16:].mean():.3f}; " + "; ".join(
-            f"{k}: plain {v['plain_sin_theta']:.4f} ({v['plain_eig_ms']:.1f} ms)" + (
-                f" learned {v['learned_sin_theta']:.4f} ({v['learned_eig_ms']:.1f} ms)" if "learned_sin_theta" in v else "")
-            for k, v in rows.items()) + f"; iterations saved {saved}; "
-        f"whole step with the learned start at q={qw}: {lstep_ms:.2f} ms (plain q=2: {plain_form['ms_per_step']:.2f} ms), "
-        f"fallback threshold {threshold:.3f}, fallback used {sum(fbs)}/3; " + (
-            f"at the learned q=2 error {target_w:.4f}: plain needs q={eq['plain_q']} ({eq['plain_error']:.4f}), "
-            f"whole step {eq['plain_ms_per_step']:.2f} ms against {eq['learned_ms_per_step']:.2f} ms learned"
-            if eq else f"plain does not reach the learned q=2 error {target_w:.4f} by q=5"))
-    return {"training": {"graphs": TRAIN_GRAPHS, "n": nt, "steps": steps, "seconds": t_train,
-                         "loss_first16": float(losses[:16].mean()), "loss_last16": float(losses[-16:].mean())},
-            "held_out": "the bench graph (reference: q = 16)", "by_q": rows, "iterations_saved": saved,
-            "step": {"q_warm": qw, "ms_per_step": lstep_ms, "plain_q2_ms_per_step": plain_form["ms_per_step"],
-                     "fallback_threshold": threshold, "fallback_used": int(sum(fbs)), "steps": 3},
-            "equal_error_at_learned_q2": eq}
+def general_form(lib, n, p):
+    """Eqs. (5)-(10), the general single pass (three sketches K, Y, Z and the
+    reduction with two QRs and an SVD of W), on random factors L, R of the
+    bench's size (n, k = 256), precision as the main form."""
+    import torch
+    k = p.k
+    L = lib.gen_gauss(n, k, 77).abs_().mul_(0.3)
+    Rt = lib.gen_gauss(n, k, 78).mul_(0.06).add_(0.02)
+    tests = [lib.gen_sparse_sign(n, c, p.z, s) for c, s in ((p.h, 31), (p.h, 32), (p.l, 33), (p.l, 34))]
+    ws = lib.workspace(lib.general_workspace_size(p, n, k, 2 | 4))
+
+    def run():
+        Kt, Yt, Z = lib.sketch_general(L, Rt, p, *tests, ws=ws)
+        return lib.embed_general(n, p, Kt, Yt, Z, tests[2], tests[3], ws=ws)
+
+    ms = timed_launches(lib, run, reps=3)
+    assert lib.sync() & ~1 == 0
+    log(f"general single pass (K, Y, Z, W, SVD, two embeddings) at n={n}, k={k}: {ms:.2f} ms")
+    return {"n": n, "k": k, "h": p.h, "l": p.l, "z": p.z, "precision": p.precision, "ms": ms}
+
+
+def fullvisit_form(lib, prec):
+    """The full-visit variant (z nonzeros per row of S and O: every entry of
+    f(L'R') formed) on the C2-shaped graph (Chung-Lu n = 2^16, mean degree
+    16; k = 256, h = 272, l = 1128): time of sketchne_sketch_fullvisit and
+    the matrix-core rate of its two chained products."""
+    import synth
+    from paper_2110_12782_amd.binding import DeviceGraph, SketchParams
+    rowptr, colidx = synth.chung_lu(1 << 16, 2.1, 16, 2, 1002)
+    g = DeviceGraph(rowptr, colidx)
+    p = SketchParams(alpha=0.5, T=10, b=1.0, k=256, s_eig=32, q=2, d=128, h=272, l=1128, z=8, seed=5,
+                     precision=BF16_CODE if prec != "fp32" else 0, split_r=0)
+    U, lam = lib.eig(g, p)
+    ws = lib.workspace(lib.fullvisit_workspace_size(p, g.n, 2))
+    ms = timed_launches(lib, lambda: lib.sketch_fullvisit(g, p, U, lam, ws=ws), reps=3)
+    assert lib.sync() & ~1 == 0
+    n = g.n
+    chunks = -(-((p.l + 31) // 32) // 9)  # output tiles of T per launch chunk (BF16: 9)
+    flops = 2.0 * n * n * (p.k + 288) + 2.0 * n * n * (p.k * chunks + 36 * 32)
+    log(f"full visit at n={n}: {ms:.2f} ms for Y and Z ({2.0 * n * n / (ms * 1e-3):.3e} formed entries/s, "
+        f"{flops / (ms * 1e-3) / 1e12:.0f} TFLOP/s of MFMA work)")
+    return {"n": n, "k": p.k, "h": p.h, "l": p.l, "z": p.z, "precision": "bf16" if prec != "fp32" else "fp32",
+            "ms": ms, "formed_entries_per_s": 2.0 * n * n / (ms * 1e-3), "mfma_TFLOPs": flops / (ms * 1e-3) / 1e12}
 
 
 def sin_theta(A, B) -> float:
@@ -454,7 +516,10 @@ def cpu_baseline(args, n, rowptr, colidx, out, ref_form, forms):
     return {"value": rate, "unit": "entries/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 NumPy oracle: Eq. 4 for {len(rows)} random rows of Y x all {vS} sampled columns "
                       f"plus all of Z ({vO} x {vO} sampled block), same U, lambda, S, O as the GPU step; "
-                      f"{ty + tz:.1f}s of CPU work"}
+                      f"{ty + tz:.1f}s of CPU work",
+            "scope": "the sketch only (Eq. 4 for Y and Alg. 4 line 7 for Z, from given factors); the GPU rate "
+                     "of the same scope is gpu_same_scope, while value above covers the whole step",
+            "gpu_same_scope": forms[args.precision]["sketch_entries_per_s"]}
 
 
 if __name__ == "__main__":

@@ -140,61 +140,73 @@ def _sin_theta(U, V):
 
 
 def test_training_gain_and_fallback(lib):
-    """Train on eight small graphs, evaluate on two held-out ones: subspace
-    error of U_k against a converged reference, Gaussian vs learned start, at
-    q = 0, 1, 2; then the fallback reproduces the plain result exactly."""
-    torch = _torch()
+    """The warm-start protocol at test scale: train on eight SBM and Chung-Lu
+    graphs (n = 2^13 and 2^14, exponent 2.0-2.5, mean degree 8-32) against
+    their own converged eigenvectors, evaluate on four held-out graphs (two
+    SBM, two Chung-Lu, n = 2^14): subspace error of U_k against a q = 24
+    reference for the Gaussian and learned starts at q = 0..3.  The learned
+    start is never worse at equal q, and on the Chung-Lu graphs it saves a
+    power iteration (learned at q - 1 at or below plain at q, q = 2, 3; on
+    the SBM graphs it gains less than one iteration, which is reported).
+    Then the decision residual equals the SpMM form and the fallback
+    reproduces the plain result exactly."""
+    import torch
     from paper_2110_12782_amd.binding import DeviceGraph, MLP, SketchParams
     k, s_eig, width = 64, 32, 256
+    rng = np.random.default_rng(0)
 
     def P(q, seed):
         return SketchParams(k=k, s_eig=s_eig, q=q, d=16, h=48, l=128, z=8, seed=seed)
 
-    def graph(i):
+    def graph(i, lg, seed):
+        n = 1 << lg
+        deg = float(np.exp(rng.uniform(np.log(8), np.log(32))))
         if i % 2 == 0:
-            return synth.sbm([512] * 16, 0.03, 0.0008, 5000 + i)
-        return synth.chung_lu(8192, 2.0 + 0.1 * (i % 5), 10 + 2 * (i % 4), 2, 5000 + i)
+            bs = n // 16
+            return synth.sbm([bs] * 16, deg * 0.8 / bs, deg * 0.2 / (n - bs), seed)
+        return synth.chung_lu(n, float(rng.uniform(2.0, 2.5)), deg, 2, seed)
 
-    sets = []
-    for i in range(8):
-        rowptr, colidx = graph(i)
+    sets, calib = [], []
+    for i, lg in enumerate((13, 13, 14, 14, 13, 14, 13, 14)):
+        rowptr, colidx = graph(i, lg, 10000 + i)
         G = DeviceGraph(rowptr, colidx)
-        Uref, _ = lib.eig(G, P(16, 70 + i))
-        sets.append((lib.ws_features(G, 0.5, seed=90 + i), Uref.contiguous()))
+        Uref, _ = lib.eig(G, P(16, 100 + i))
+        sets.append((lib.ws_features(G, 0.5, seed=200 + i), Uref.contiguous()))
+        U2, l2 = lib.eig(G, P(2, 300 + i))
+        calib.append(float(lib.ritz_residual(G, 0.5, U2, l2).max()))
     assert lib.sync() & ~1 == 0
     net = MLP(lib, width, k)
-    lib.ws_init(net, 3)
-    losses = lib.ws_train(net, sets, 480, 1e-3, 0.1).cpu().numpy()
+    lib.ws_init(net, 11)
+    losses = lib.ws_train(net, sets, 600, 1e-3, 0.1).cpu().numpy()
     first, last = losses[:16].mean(), losses[-16:].mean()
     say(f"training loss {first:.4f} -> {last:.4f}")
     assert np.all(np.isfinite(losses))
-    assert last < 0.95 * first
-
-    gains = []
-    for i in (100, 101):
-        rowptr, colidx = graph(i)
+    assert last < 0.5 * first
+    threshold = 1.1 * max(calib)
+    for j in range(4):
+        rowptr, colidx = graph(j, 14, 20000 + j)
         G = DeviceGraph(rowptr, colidx)
-        Uref, _ = lib.eig(G, P(24, 7))
-        row = []
-        for q in (0, 1, 2):
+        Uref, _ = lib.eig(G, P(24, 999))
+        plain, learned = [], []
+        for q in (0, 1, 2, 3):
             Up, lp = lib.eig(G, P(q, 11))
-            Uw, lw, fb, worst = lib.eig_learned(G, P(q, 11), net, q, float("inf"), with_residual=True)
-            assert not fb
+            Uw, lw, fb, worst = lib.eig_learned(G, P(q, 11), net, q, threshold, with_residual=True)
             # the decision residual (from the Rayleigh-Ritz Gram) equals the
             # largest ||X u_j - lambda_j u_j|| formed with a further SpMM
             direct = float(lib.ritz_residual(G, 0.5, Uw, lw).max())
-            say(f"  q={q}: worst Ritz residual {worst:.6e} (Gram form) vs {direct:.6e} (SpMM form)")
             assert abs(worst - direct) <= 1e-4 * direct + 1e-6
-            row.append((q, _sin_theta(Up, Uref), _sin_theta(Uw, Uref)))
-        say(f"held-out graph {i}: " + "  ".join(f"q={q}: plain {a:.4f} learned {b:.4f}" for q, a, b in row))
-        gains.append(row)
+            assert not fb or q == 0
+            plain.append(_sin_theta(Up, Uref))
+            learned.append(_sin_theta(Uw, Uref))
+        kind = "sbm" if j % 2 == 0 else "chung-lu"
+        say(f"held-out {kind}: plain " + " ".join(f"{x:.4f}" for x in plain) + "  learned " +
+            " ".join(f"{x:.4f}" for x in learned))
+        assert all(l_ <= p_ for l_, p_ in zip(learned, plain))
+        if kind == "chung-lu":
+            assert learned[1] <= plain[2] and learned[2] <= plain[3]
         # fallback: a zero threshold always rejects, and the plain start with p.q runs
         Uf, lf, fb = lib.eig_learned(G, P(2, 11), net, 0, 0.0)
         Up2, lp2 = lib.eig(G, P(2, 11))
         assert fb
         assert torch.equal(Uf, Up2) and torch.equal(lf, lp2)
-    # the learned start must not be worse than the Gaussian start without power iterations
-    for row in gains:
-        q0 = row[0]
-        assert q0[2] <= q0[1] * 1.05
     assert lib.sync() & ~1 == 0
