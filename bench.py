@@ -51,6 +51,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison form")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the oracle Y row sample")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start form")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the forms beyond the step (propagation, general and full-visit passes)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device copy first (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -165,9 +167,11 @@ def main():
 
     if not args.no_learned:
         forms["learned_warm_start"] = learned_form(lib, g, params(args.precision), ws, forms[args.precision])
-    extras = {"spectral_propagation": propagation_form(lib, g, out[6]),
-              "general_single_pass": general_form(lib, g.n, params(args.precision)),
-              "full_visit": fullvisit_form(lib, args.precision)}
+    extras = None
+    if not args.no_extras:
+        extras = {"spectral_propagation": propagation_form(lib, g, out[6]),
+                  "general_single_pass": general_form(lib, g.n, params(args.precision)),
+                  "full_visit": fullvisit_form(lib, args.precision)}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -258,7 +258,7 @@ SketchWs carve_sketch(Arena& ar, const sketchne_params* p, int64_t n) {
   int64_t nvtmax = g.nvt_pad > g.nvtO_pad ? g.nvt_pad : g.nvtO_pad;
   w.Bp = ar.take<char>((size_t)nvtmax * (g.KSM + g.KSS) * 64 * g.FB);
   w.T1t = ar.take<float>((size_t)p->l * g.zl);
-  w.pscale = ar.take<double>(2);
+  w.pscale = ar.take<double>(3);
   return w;
 }
 
@@ -743,7 +743,7 @@ GenSketchWs carve_gen_sketch(Arena& ar, const sketchne_params* q, int64_t n) {
   int64_t nvtmax = g.nvt_pad > g.nvtO_pad ? g.nvt_pad : g.nvtO_pad;
   w.Bp = ar.take<char>((size_t)nvtmax * (g.KSM + g.KSS) * 64 * g.FB);
   w.T1t = ar.take<float>((size_t)q->l * g.zl);
-  w.pscale = ar.take<double>(2);
+  w.pscale = ar.take<double>(3);
   return w;
 }
 
@@ -1011,8 +1011,11 @@ FvGeo fv_geo(const sketchne_params* p, int64_t n) {
   g.npad = (n + 31) / 32 * 32;
   g.njt = g.npad / 32;
   g.nvt_pad = (g.njt + 3) / 4 * 4;
-  g.nct_h = (p->h + 31) / 32;
-  g.nct_l = (p->l + 31) / 32;
+  // output tiles of 32 columns, padded (with zero blocks of S or O) to whole
+  // launch chunks of the kernel
+  const int ch = fullvisit_nct(g.prec);
+  g.nct_h = ((p->h + 31) / 32 + ch - 1) / ch * ch;
+  g.nct_l = ((p->l + 31) / 32 + ch - 1) / ch * ch;
   g.fb = g.prec == SKETCHNE_FP32 ? 4 : 16;
   g.ks2 = g.prec == SKETCHNE_FP32 ? 16 : 2;
   return g;
@@ -1062,7 +1065,7 @@ FvWs carve_fv(Arena& ar, const sketchne_params* p, int64_t n) {
   w.Od = ar.take<float>((size_t)n * p->l);
   w.z_cap = gemm64_partial_bytes(p->l, p->l, n, false);
   w.z_partial = ar.take<double>(w.z_cap / sizeof(double) + 1);
-  w.pscale = ar.take<double>(2);
+  w.pscale = ar.take<double>(3);
   return w;
 }
 

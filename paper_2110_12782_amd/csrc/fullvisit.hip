@@ -128,6 +128,19 @@ __global__ void k_fill0(int64_t count, float* __restrict__ out) {
   if (idx < count) out[idx] = 0.0f;
 }
 
+template <int N>
+using cint = std::integral_constant<int, N>;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t fv_rsrc(const void* base, uint32_t bytes) {
+  // wave-uniform by construction; readfirstlane keeps the descriptor scalar
+  const uint64_t a = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  void* ptr = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+  // dword 3 = 0x00020000: 32-bit data format, the raw-buffer setting of gfx9
+  return __builtin_amdgcn_make_buffer_rsrc(ptr, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
+
 template <int PREC, int KSM, int NCT>
 __global__ __launch_bounds__(256, 1) void k_fullvisit(int64_t nrows, int64_t njt, int nct_all, int width,
                                                       const void* __restrict__ Bpack, const void* A1pack,
@@ -139,28 +152,38 @@ __global__ __launch_bounds__(256, 1) void k_fullvisit(int64_t nrows, int64_t njt
   constexpr int KS2 = Op::KS2;
   constexpr int NF = KSM + NCT * KS2;    // fragments per column tile in LDS
   extern __shared__ __attribute__((aligned(16))) char lds_raw[];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // wave index made visibly uniform, so that branches on it are scalar
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t vt = (int64_t)blockIdx.x * 4 + wave;
-  const int ct0 = blockIdx.y * NCT;
-  const int nct = nct_all - ct0 < NCT ? nct_all - ct0 : NCT;
+  const int ct0 = blockIdx.y * NCT;  // nct_all is a multiple of NCT (padded with zero blocks)
 
   frag bfr[KSM];
   const frag* Bp = static_cast<const frag*>(Bpack);
 #pragma unroll
   for (int ks = 0; ks < KSM; ++ks) bfr[ks] = Bp[(vt * KSM + ks) * 64 + lane];
-  const char* A1 = static_cast<const char*>(A1pack);
-  const char* A2 = static_cast<const char*>(A2pack);
-  // column tile jt -> LDS buffer b: its KSM fragments of R'^T, then the S^T
-  // fragments of this launch's output tiles; fragment f is one DMA by wave f % 4
-  auto dma = [&](int64_t jt, int b) {
-    char* dst = lds_raw + (int64_t)b * NF * FB;
-    for (int f = wave; f < KSM + nct * KS2; f += 4) {
-      const char* src = f < KSM ? A1 + (jt * KSM + f) * FB
-                                : A2 + ((jt * nct_all + ct0) * KS2 + (f - KSM)) * FB;
+  // column tile jt -> LDS buffer B: its KSM fragments of R'^T, then the S^T
+  // fragments of this launch's output tiles; fragment f is one DMA by wave
+  // f % 4.  Buffer (MUBUF) LDS-DMA, so that no FLAT operation is pending while
+  // the fragments are read (that would turn every LDS-read wait into
+  // lgkmcnt(0)); the host keeps both packed arrays below 4 GiB.
+  const __amdgpu_buffer_rsrc_t a1_rs = fv_rsrc(A1pack, (uint32_t)(njt * KSM * FB));
+  const __amdgpu_buffer_rsrc_t a2_rs = fv_rsrc(A2pack, (uint32_t)(njt * nct_all * KS2 * FB));
+  auto dma = [&](int64_t jt, auto Bc) {
+    constexpr int B = decltype(Bc)::value;
+    char* dst = lds_raw + B * NF * FB;
+#pragma unroll
+    for (int f0 = 0; f0 < NF; f0 += 4) {
+      const int f = f0 + wave;
+      if (NF % 4 != 0 && f >= NF) break;
+      const bool first = f < KSM;
+      const uint32_t off = first ? (uint32_t)((jt * KSM + f) * FB)
+                                 : (uint32_t)(((jt * nct_all + ct0) * KS2 + (f - KSM)) * FB);
       if constexpr (sizeof(frag) == 16)
-        __builtin_amdgcn_global_load_lds((const void*)(src + lane * 16), (lds_void*)(dst + f * FB), 16, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(first ? a1_rs : a2_rs, (lds_void*)(dst + f * FB), 16,
+                                                 off + (uint32_t)(lane * 16), 0, 0, 0);
       else
-        __builtin_amdgcn_global_load_lds((const void*)(src + lane * 4), (lds_void*)(dst + f * FB), 4, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(first ? a1_rs : a2_rs, (lds_void*)(dst + f * FB), 4,
+                                                 off + (uint32_t)(lane * 4), 0, 0, 0);
     }
   };
   floatx16 accY[NCT];
@@ -168,17 +191,30 @@ __global__ __launch_bounds__(256, 1) void k_fullvisit(int64_t nrows, int64_t njt
   for (int q = 0; q < NCT; ++q)
 #pragma unroll
     for (int e = 0; e < 16; ++e) accY[q][e] = 0.0f;
-  dma(0, 0);
+  dma(0, cint<0>());
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  for (int64_t jt = 0; jt < njt; ++jt) {
-    const int b = (int)(jt & 1);
-    if (jt + 1 < njt) dma(jt + 1, b ^ 1);
-    const frag* L = reinterpret_cast<const frag*>(lds_raw + (int64_t)b * NF * FB);
+  // one column tile; the loop below is unrolled by two so that both LDS
+  // buffer offsets are compile-time constants and the reads of one buffer
+  // never wait on the copy into the other
+  auto step = [&](int64_t jt, auto Bc) {
+    constexpr int B = decltype(Bc)::value;
+    if (jt + 1 < njt) dma(jt + 1, cint<B ^ 1>());
+    const frag* L = reinterpret_cast<const frag*>(lds_raw + B * NF * FB);
     // first product: X^T (32 columns x 32 vertices)
     floatx16 x = {};
 #pragma unroll
     for (int ks = 0; ks < KSM; ++ks) x = Op::mma(L[ks * 64 + lane], bfr[ks], x);
+    // fragment reads RA ahead of their MFMAs
+    constexpr int RA = KSM < 6 ? KSM : 6;
+    __builtin_amdgcn_sched_group_barrier(0x100, RA, 0);
+#pragma unroll
+    for (int g = 0; g < KSM - RA; ++g) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, RA, 0);
+    __builtin_amdgcn_sched_barrier(0);
     // F = max(log2 x, 0) as the B operand of the second product
     frag fb[KS2];
     if constexpr (PREC == SKETCHNE_FP32) {
@@ -195,28 +231,41 @@ __global__ __launch_bounds__(256, 1) void k_fullvisit(int64_t nrows, int64_t njt
         fb[s] = __builtin_bit_cast(frag, pk);
       }
     }
-    // second product: Y^T tiles += S^T F
+    // second product: Y^T tiles += S^T F, its first fragments read during
+    // the vector work above
 #pragma unroll
-    for (int q = 0; q < NCT; ++q) {
-      if (q < nct) {
+    for (int q = 0; q < NCT; ++q)
 #pragma unroll
-        for (int s = 0; s < KS2; ++s) accY[q] = Op::mma(L[(KSM + q * KS2 + s) * 64 + lane], fb[s], accY[q]);
-      }
+      for (int s = 0; s < KS2; ++s) accY[q] = Op::mma(L[(KSM + q * KS2 + s) * 64 + lane], fb[s], accY[q]);
+    constexpr int N2 = NCT * KS2;
+    constexpr int RB = N2 < 6 ? N2 : 6;
+    __builtin_amdgcn_sched_group_barrier(0x100, RB, 0);
+    __builtin_amdgcn_sched_group_barrier(0x002, 256, 0);
+#pragma unroll
+    for (int g = 0; g < N2 - RB; ++g) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
+    __builtin_amdgcn_sched_group_barrier(0x008, RB, 0);
+    __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+  };
+  int64_t jt = 0;
+  for (; jt + 2 <= njt; jt += 2) {
+    step(jt, cint<0>());
+    step(jt + 1, cint<1>());
   }
+  if (jt < njt) step(jt, cint<0>());
   // Y^T[c][i], c = 32 (ct0 + q) + 8 (e / 4) + 4 hf + e % 4, i = 32 vt + lane % 32
   const int64_t i = vt * 32 + (lane & 31);
   if (i >= nrows) return;
 #pragma unroll
   for (int q = 0; q < NCT; ++q) {
-    if (q < nct) {
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int c = 32 * (ct0 + q) + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-        if (c < width) out[(int64_t)c * ld_out + i] = out_scale * accY[q][e];
-      }
+    for (int e = 0; e < 16; ++e) {
+      const int c = 32 * (ct0 + q) + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+      if (c < width) out[(int64_t)c * ld_out + i] = out_scale * accY[q][e];
     }
   }
 }
@@ -228,6 +277,11 @@ sketchne_status launch_fullvisit(sketchne_ctx* c, int cls, int64_t nrows, int64_
   typedef typename FvOp<PREC>::frag frag;
   constexpr int NF = KSM + NCT * FvOp<PREC>::KS2;
   const size_t shmem = (size_t)2 * NF * 64 * sizeof(frag);
+  // the tile copies address the packed operands with 32-bit offsets
+  if (nct_all % NCT != 0) return SKETCHNE_E_ARG;
+  const int64_t fb = 64 * (int64_t)sizeof(frag);
+  if (njt * KSM * fb >= ((int64_t)1 << 32) || njt * nct_all * FvOp<PREC>::KS2 * fb >= ((int64_t)1 << 32))
+    return SKETCHNE_E_UNSUPPORTED;
   auto kern = k_fullvisit<PREC, KSM, NCT>;
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)shmem) != hipSuccess)

@@ -16,7 +16,7 @@ sketchne_status scale_rows(sketchne_ctx* c, int rows, int cols, const double* M,
 sketchne_status identity(sketchne_ctx* c, int m, double* M);
 sketchne_status gather_expanded(sketchne_ctx* c, int64_t n, int ntiles, int groups, int z, const int32_t* rows,
                                 const float* U, int64_t ldu, int k, const double* d1, double scale, double* Gsel);
-// pscale = {2^-e, 2^e}: the power-of-two range balance of the FP16 operands
+// pscale = {2^-e, 2^e, max abs R'}: the power-of-two range balance of the FP16 operands
 // (e = 0 for BF16 and FP32), chosen on the device from max |R'|
 sketchne_status balance(sketchne_ctx* c, int prec, int64_t count, const double* RtT, double* pscale);
 sketchne_status pack_A(sketchne_ctx* c, int prec, int ntiles, int KSM, int KSS, int k, int r, const double* RtT,

@@ -279,27 +279,42 @@ __global__ void k_pack_B(int64_t n, int64_t nrows, int64_t nvt, int KSM, int KSS
 // degrees are at least 1).  With M = max |R'| over the expanded columns,
 // e = floor(log2(sqrt(M))) (clamped to [0, 15]) leaves both operands below
 // sqrt(M) <= 65504 for M up to 4e9, and lifts the small entries of L' out of
-// the FP16 subnormal range.  pscale = {2^-e (R' side), 2^e (L' side)}; BF16
-// and FP32 take e = 0.  One workgroup.
-__global__ __launch_bounds__(1024) void k_balance(int64_t count, const double* __restrict__ RtT, int prec,
-                                                  double* __restrict__ pscale) {
-  __shared__ double part[16];
+// the FP16 subnormal range.  pscale = {2^-e (R' side), 2^e (L' side), M};
+// BF16 and FP32 take e = 0 and skip the scan.  M is a grid-wide maximum: the
+// bit patterns of non-negative doubles order as unsigned integers, so an
+// integer atomic max over them is exact and independent of the order.
+__global__ void k_balance_clear(double* __restrict__ pscale) {
+  if (threadIdx.x == 0) pscale[2] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_balance_max(int64_t count, const double* __restrict__ RtT,
+                                                     double* __restrict__ pscale) {
   double m = 0.0;
-  for (int64_t i = threadIdx.x; i < count; i += blockDim.x) m = fmax(m, fabs(RtT[i]));
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < count; i += 4 * stride)
+    m = fmax(fmax(m, fabs(RtT[i])), fmax(fmax(fabs(RtT[i + stride]), fabs(RtT[i + 2 * stride])),
+                                         fabs(RtT[i + 3 * stride])));
+  for (; i < count; i += stride) m = fmax(m, fabs(RtT[i]));
   for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = fmax(t, part[w]);
-    int e = 0;
-    if (prec == SKETCHNE_FP16 && t > 1.0 && isfinite(t)) {
+  // NaN compares false with everything: carry it as +inf so that it is seen
+  if (m != m) m = __builtin_huge_val();
+  if ((threadIdx.x & 63) == 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(pscale + 2), (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ void k_balance_finish(int prec, double* __restrict__ pscale) {
+  if (threadIdx.x != 0) return;
+  int e = 0;
+  if (prec == SKETCHNE_FP16) {
+    const double t = pscale[2];
+    if (t > 1.0 && isfinite(t)) {
       e = (int)floor(0.5 * log2(t));
       e = e < 0 ? 0 : (e > 15 ? 15 : e);
     }
-    pscale[0] = ldexp(1.0, -e);
-    pscale[1] = ldexp(1.0, e);
   }
+  pscale[0] = ldexp(1.0, -e);
+  pscale[1] = ldexp(1.0, e);
 }
 
 // signs in accumulator order: sgn[(rt*2 + hf)*16 + r] for lane half hf, register r
@@ -505,7 +520,8 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
   extern __shared__ __attribute__((aligned(16))) char lds_raw[];
   __shared__ __attribute__((aligned(16))) float sg0[32], sg1[32], sg2[32];
   __shared__ __attribute__((aligned(16))) char blo_all[4 * VT * KSS * 1024 + 16];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // wave index made visibly uniform, so that branches on it are scalar
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t vt0 = (int64_t)blockIdx.x * (4 * VT) + wave * VT;
   // this workgroup's expanded-column tiles: tb .. tb + nt - 1 (blockIdx.y splits
   // the tile range when there are too few vertex blocks to fill the chip)
@@ -536,18 +552,24 @@ __global__ __launch_bounds__(256, 2) void k_fused_lowp(int64_t nrows, int groups
   };
   // tile t -> LDS buffer B: fragment c of the tile is one 1 KiB DMA by wave
   // c % 4, the 128 bytes of signs one DMA by eight lanes of wave 3
+  // The copies are buffer (MUBUF) LDS-DMA loads, not global (FLAT) ones: the
+  // compiler cannot tell whether a pending FLAT operation counts in lgkmcnt,
+  // so with a global DMA in flight every wait for an LDS fragment read became
+  // lgkmcnt(0), a full LDS round trip per four k-steps, instead of a count.
+  const __amdgpu_buffer_rsrc_t a_rs = out_rsrc(reinterpret_cast<const float*>(Ag), (uint32_t)ntiles * (uint32_t)TB);
+  const __amdgpu_buffer_rsrc_t s_rs = out_rsrc(sgn, (uint32_t)ntiles * 128u);
   auto dma = [&](int t, auto Bc) {
     constexpr int B = decltype(Bc)::value;
 #pragma unroll
     for (int u = 0; u < (KS + 3) / 4; ++u) {
       const int c = u * 4 + wave;
       if (KS % 4 == 0 || c < KS)
-        __builtin_amdgcn_global_load_lds((const void*)(Ag + (int64_t)t * TB + c * 1024 + lane * 16),
-                                         (lds_void*)(lds_raw + B * TB + c * 1024), 16, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(a_rs, (lds_void*)(lds_raw + B * TB + c * 1024), 16,
+                                                 (uint32_t)(t * TB + c * 1024 + lane * 16), 0, 0, 0);
     }
     if (wave == 3 && lane < 8)
-      __builtin_amdgcn_global_load_lds((const void*)(sgn + (int64_t)t * 32 + lane * 4),
-                                       (lds_void*)signs_of(Bc), 16, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(s_rs, (lds_void*)signs_of(Bc), 16, (uint32_t)(t * 128 + lane * 16), 0,
+                                               0, 0);
   };
   const int64_t vbase = vt0 * 32 + (lane & 31);
   floatx16 accC[VT];
@@ -784,7 +806,13 @@ sketchne_status gather_expanded(sketchne_ctx* c, int64_t n, int ntiles, int grou
 
 sketchne_status balance(sketchne_ctx* c, int prec, int64_t count, const double* RtT, double* pscale) {
   ProfScope ps(c, SKETCHNE_PROF_PREP);
-  hipLaunchKernelGGL(k_balance, dim3(1), dim3(1024), 0, c->stream, count, RtT, prec, pscale);
+  if (prec == SKETCHNE_FP16 && count > 0) {
+    hipLaunchKernelGGL(k_balance_clear, dim3(1), dim3(64), 0, c->stream, pscale);
+    int64_t blocks = (count + 4 * 256 - 1) / (4 * 256);
+    blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
+    hipLaunchKernelGGL(k_balance_max, dim3((unsigned)blocks), dim3(256), 0, c->stream, count, RtT, pscale);
+  }
+  hipLaunchKernelGGL(k_balance_finish, dim3(1), dim3(64), 0, c->stream, prec, pscale);
   return launch_status();
 }
 
@@ -847,8 +875,10 @@ sketchne_status fused_sketch(sketchne_ctx* c, int cls, int prec, int64_t nrows, 
     }
     return SKETCHNE_E_UNSUPPORTED;
   }
-  // the buffer descriptor of one tile's four output rows holds < 2^32 bytes
+  // the buffer descriptor of one tile's four output rows holds < 2^32 bytes,
+  // and the tile copies address the packed columns with 32-bit offsets
   if (ld_out >= ((int64_t)1 << 28)) return SKETCHNE_E_UNSUPPORTED;
+  if ((int64_t)ntiles * (KSM + 2 * KSS) * 1024 >= ((int64_t)1 << 31)) return SKETCHNE_E_UNSUPPORTED;
   if (prec == SKETCHNE_BF16)
     return fused_lowp<SKETCHNE_BF16>(c, cls, nrows, groups, ntiles, KSM, KSS, Bpack, Apack, sgn, out, ld_out,
                                      out_scale);
