@@ -436,13 +436,10 @@ def sin_theta(A, B) -> float:
 
 
 def source_digest() -> str:
-    """SHA-256 over the HIP sources of the fused sketch kernel."""
+    """SHA-256 of the HIP source that holds the fused sketch kernel."""
     import hashlib
-    h = hashlib.sha256()
-    for f in ("sketch.hip", "sketch.h"):
-        with open(os.path.join(ROOT, "paper_2110_12782_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    with open(os.path.join(ROOT, "paper_2110_12782_amd", "csrc", "sketch.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
 
 
 def pmc_traffic(prec, scale, launches):

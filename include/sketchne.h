@@ -164,10 +164,12 @@ sketchne_status sketchne_embed(sketchne_ctx* ctx, const sketchne_params* p, int6
  * Each tile of f(L'R') is formed on the matrix cores and multiplied by the
  * matching rows of S (or O) on the matrix cores, never leaving registers.
  * L', R' as in sketchne_sketch (Eq. 11); precision FP32 or BF16 (FP16 is
- * SKETCHNE_E_UNSUPPORTED); S->width = h, O->width = l, both z = p->z <= h.
+ * SKETCHNE_E_UNSUPPORTED); S->width = h, O->width = l <= 8192 (else
+ * SKETCHNE_E_UNSUPPORTED), both z = p->z <= h.  Z = O^T T is summed in 64-bit
+ * fixed point, so repeated calls give identical bits.
  * sketchne_embed_fullvisit is sketchne_embed (Alg. 4 lines 5, 8-10) with that
- * O.  Workspace: sketchne_fullvisit_workspace_size (it holds f(L'R') O, l x n,
- * and O as a dense l-column matrix). */
+ * O.  Workspace: sketchne_fullvisit_workspace_size (the sketch's holds
+ * f(L'R') O, l x n; the embed's holds O as a dense l-column matrix). */
 typedef struct {
   int32_t width;   /* columns of the test matrix                               */
   int32_t z;       /* nonzeros per row                                          */

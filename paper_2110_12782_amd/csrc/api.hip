@@ -93,8 +93,9 @@ OrthWs carve_orth(Arena& ar, int64_t n, int m, bool transposed) {
 // dst = src R^-1 (R^-1 upper triangular, given as RinvT = R^-T row-major):
 // the tall FP64 apply when it takes the shape, the general GEMM otherwise.
 sketchne_status apply_rinv(sketchne_ctx* c, int64_t n, int m, const float* src, int64_t ld, bool transposed,
-                           const double* RinvT, float* dst, const OrthWs& w, const int* run_if) {
+                           const double* RinvT, float* dst, const OrthWs& w, const int* run_if, bool f32 = false) {
   ApplyDesc d;
+  d.f32 = f32;
   d.n = n; d.K = m; d.N = m;
   d.A = src; d.lda = ld; d.acol = transposed;
   // R^-1(k, j) = RinvT[j][k]: column-major reads of B (measured faster here
@@ -110,13 +111,17 @@ sketchne_status apply_rinv(sketchne_ctx* c, int64_t n, int m, const float* src, 
 
 // One Cholesky-QR pass src -> dst.  need_more: set by the Cholesky when a
 // second pass is needed; run_if: the pass runs only when it points to 1.
+// f32: Gram and apply on the FP32 matrix cores (the Cholesky stays FP64), for
+// a power-iteration basis: its factor only has to keep the basis well
+// conditioned, since any invertible factor keeps its span.
 sketchne_status orth_pass(sketchne_ctx* c, int64_t n, int m, const float* src, float* dst, int64_t ld,
                           bool transposed, const OrthWs& w, int* need_more, const int* run_if,
-                          double repeat_kappa = kCholQRRepeat) {
-  if (!transposed) SK_TRY(gram_tall(c, n, m, src, ld, 1, nullptr, 0, 0, nullptr, w.G, w.partial, w.partial_cap, run_if));
+                          double repeat_kappa = kCholQRRepeat, bool f32 = false) {
+  if (!transposed)
+    SK_TRY(gram_tall(c, n, m, src, ld, 1, nullptr, 0, 0, nullptr, w.G, w.partial, w.partial_cap, run_if, f32));
   else SK_TRY(gram_tall(c, n, m, src, 1, ld, nullptr, 0, 0, nullptr, w.G, w.partial, w.partial_cap, run_if));
   SK_TRY(chol_inv(c, m, w.G, w.RinvT, w.cwork, need_more, run_if, repeat_kappa));
-  return apply_rinv(c, n, m, src, ld, transposed, w.RinvT, dst, w, run_if);
+  return apply_rinv(c, n, m, src, ld, transposed, w.RinvT, dst, w, run_if, f32);
 }
 
 // Cholesky-QR with FP64 Gram and Cholesky: src -> dst, and a second pass
@@ -126,7 +131,10 @@ sketchne_status orth_pass(sketchne_ctx* c, int64_t n, int m, const float* src, f
 // for a power-iteration basis).
 sketchne_status orth2(sketchne_ctx* c, int64_t n, int m, const float* src, float* tmp, float* dst, int64_t ld,
                       bool transposed, const OrthWs& w, double repeat_kappa = kCholQRRepeat) {
-  SK_TRY(orth_pass(c, n, m, src, dst, ld, transposed, w, w.need2, nullptr, repeat_kappa));
+  // a power-iteration basis takes its first pass on the FP32 matrix cores;
+  // the second pass (after a shifted Cholesky) is FP64
+  const bool inner = repeat_kappa == kCholQRRepeatInner;
+  SK_TRY(orth_pass(c, n, m, src, dst, ld, transposed, w, w.need2, nullptr, repeat_kappa, inner));
   SK_TRY(orth_pass(c, n, m, dst, tmp, ld, transposed, w, nullptr, w.need2));
   int64_t count = transposed ? (int64_t)m * ld : n * ld;
   return copy_if(c, count, tmp, dst, w.need2);
@@ -510,8 +518,11 @@ static sketchne_status eig_impl(sketchne_ctx* c, const sketchne_graph* A, const 
   SK_TRY(gram_tall(c, n, K, w.Q, K, 1, w.P1, K, 1, nullptr, w.H, w.rr_partial, w.rr_cap, nullptr));
   // line 10: eigendecomposition, sorted by |lambda|
   SK_TRY(symeig(c, K, w.H, w.Vh, w.wv, w.symws));
-  // line 11: U = Q U^(:, 1:k)
+  // line 11: U = Q U^(:, 1:k), on the FP32 matrix cores: Q and the columns of
+  // U^ are orthonormal, so the sums have no cancellation to amplify the FP32
+  // rounding (U is stored in FP32 either way)
   ApplyDesc ad;
+  ad.f32 = true;
   ad.n = n; ad.K = K; ad.N = p->k;
   ad.A = w.Q; ad.lda = K;
   ad.B = w.Vh; ad.ldb = K;
@@ -995,6 +1006,8 @@ sketchne_status sketchne_embed_general(sketchne_ctx* c, const sketchne_params* p
 
 namespace {
 
+constexpr int kFullVisitMaxL = 8192;
+
 struct FvGeo {
   int prec, KSM, KSS;
   int64_t npad, njt, nvt_pad;
@@ -1036,9 +1049,7 @@ struct FvWs {
   void* Bp;
   void* A2;
   float* T;
-  float* Od;
-  double* z_partial;
-  size_t z_cap;
+  unsigned* tmax;
   double* pscale;
 };
 
@@ -1062,9 +1073,7 @@ FvWs carve_fv(Arena& ar, const sketchne_params* p, int64_t n) {
   const int nct = g.nct_h > g.nct_l ? g.nct_h : g.nct_l;
   w.A2 = ar.take<char>((size_t)g.njt * nct * g.ks2 * 64 * g.fb);
   w.T = ar.take<float>((size_t)p->l * n);
-  w.Od = ar.take<float>((size_t)n * p->l);
-  w.z_cap = gemm64_partial_bytes(p->l, p->l, n, false);
-  w.z_partial = ar.take<double>(w.z_cap / sizeof(double) + 1);
+  w.tmax = ar.take<unsigned>(1);
   w.pscale = ar.take<double>(3);
   return w;
 }
@@ -1101,6 +1110,7 @@ sketchne_status sketchne_sketch_fullvisit(sketchne_ctx* c, const sketchne_graph*
   SK_TRY(check_params(p, A->n));
   if (!row_sign_ok(S, p->h, p->z) || !row_sign_ok(O, p->l, p->z) || p->z > p->h) return SKETCHNE_E_ARG;
   if (p->precision == SKETCHNE_FP16 || p->k % 4) return SKETCHNE_E_UNSUPPORTED;
+  if (p->l > kFullVisitMaxL) return SKETCHNE_E_UNSUPPORTED;  // the Z pass keeps l 64-bit sums in LDS
   const int64_t n = A->n;
   FvGeo g = fv_geo(p, n);
   if (g.KSM == 0) return SKETCHNE_E_UNSUPPORTED;
@@ -1141,13 +1151,7 @@ sketchne_status sketchne_sketch_fullvisit(sketchne_ctx* c, const sketchne_graph*
   SK_TRY(pack_s_full(c, g.prec, n, g.njt, g.nct_l, p->z, O->cols, O->signs, p->l, w.A2));
   SK_TRY(fullvisit(c, SKETCHNE_PROF_SKETCH_Z, g.prec, g.KSM, n, g.njt, g.nct_l, p->l, w.Bp, w.A1, w.A2, w.T, n,
                    out_scale));
-  SK_TRY(dense_rows(c, n, p->l, p->z, O->cols, O->signs, inv_sqrt_z, w.Od));
-  GemmDesc gd;  // Z = O^T T: O(k, i) = Od[k l + i], T(k, j) = Tt[j n + k]
-  gd.M = p->l; gd.N = p->l; gd.K = n;
-  gd.A = w.Od; gd.ta = Ty::F32; gd.sai = 1; gd.sak = p->l;
-  gd.B = w.T; gd.tb = Ty::F32; gd.sbk = 1; gd.sbj = n;
-  gd.C = Z; gd.tc = Ty::F32; gd.sci = p->l; gd.scj = 1;
-  return gemm64(c, gd, w.z_partial, w.z_cap);
+  return fv_z(c, n, p->l, p->z, O->cols, O->signs, w.T, n, w.tmax, 1.0 / sqrt((double)p->z), Z);
 }
 
 sketchne_status sketchne_embed_fullvisit(sketchne_ctx* c, const sketchne_params* p, int64_t n, const float* Yt,

@@ -13,6 +13,11 @@
 // halves the work of the Cholesky-QR apply; entries below the diagonal are
 // masked on load, whatever the buffer holds there.
 //
+// F32 selects the FP32 matrix cores (v_mfma_f32_16x16x4f32, FP32 operands in
+// LDS, B rounded to FP32): twice the FP64 rate and half the LDS bytes, for the
+// applies whose result only has to span the right space (the power-iteration
+// bases of Alg. 5), not to be accurate to FP64 working precision.
+//
 // 8 wavefronts: wave w owns rows 32 (w & 3) .. +32 (two 16-row MFMA blocks)
 // and the column blocks (16 columns each) of parity w >> 2, i.e. 2 x NBH
 // v_mfma_f64_16x16x4f64 accumulators; interleaving the blocks keeps the two
@@ -23,6 +28,30 @@ namespace skne {
 namespace {
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// operand and accumulator types of the two forms
+template <bool F32>
+struct ApplyTy {
+  typedef double T;
+  typedef doublex4 Acc;
+  static constexpr int PAD = 2;  // LDS row padding (elements)
+  static __device__ __forceinline__ Acc mma(T a, T b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // output element (lane, r) -> row within the 16-row block
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct ApplyTy<true> {
+  typedef float T;
+  typedef floatx4 Acc;
+  static constexpr int PAD = 16;  // rows 16 banks apart: the 4 k-rows of a fragment read hit distinct banks
+  static __device__ __forceinline__ Acc mma(T a, T b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
 
 constexpr int AR = 128;   // rows per workgroup
 constexpr int ABK = 16;   // summation chunk
@@ -37,19 +66,21 @@ struct ApplyArgs {
 
 // One chunk's products for the wave's column blocks 2t + ch, t = T0 .. NBH-1,
 // k-steps in order, as straight-line code.
-template <int T0, int NBH>
-__device__ __forceinline__ void chunk_mfma(const double (*As)[AR + 2], const double (*Bs)[32 * NBH + 2], int rg,
-                                           int ch, int lane, doublex4 (&acc)[2][NBH]) {
+template <int T0, int NBH, bool F32>
+__device__ __forceinline__ void chunk_mfma(const typename ApplyTy<F32>::T (*As)[AR + ApplyTy<F32>::PAD],
+                                           const typename ApplyTy<F32>::T (*Bs)[32 * NBH + ApplyTy<F32>::PAD], int rg,
+                                           int ch, int lane, typename ApplyTy<F32>::Acc (&acc)[2][NBH]) {
+  typedef ApplyTy<F32> Ty;
 #pragma unroll
   for (int kk = 0; kk < ABK / 4; ++kk) {
     const int kr = kk * 4 + (lane >> 4);
-    const double a0 = As[kr][32 * rg + (lane & 15)];
-    const double a1 = As[kr][32 * rg + 16 + (lane & 15)];
+    const typename Ty::T a0 = As[kr][32 * rg + (lane & 15)];
+    const typename Ty::T a1 = As[kr][32 * rg + 16 + (lane & 15)];
 #pragma unroll
     for (int t = T0; t < NBH; ++t) {
-      const double b = Bs[kr][16 * (2 * t + ch) + (lane & 15)];
-      acc[0][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][t], 0, 0, 0);
-      acc[1][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][t], 0, 0, 0);
+      const typename Ty::T b = Bs[kr][16 * (2 * t + ch) + (lane & 15)];
+      acc[0][t] = Ty::mma(a0, b, acc[0][t]);
+      acc[1][t] = Ty::mma(a1, b, acc[1][t]);
     }
   }
 }
@@ -65,15 +96,17 @@ __device__ __forceinline__ void static_for(F&& f) {
 // ACOL: A(i,k) = A[k*lda + i] (else A[i*lda + k]); BCOL: B(k,j) = B[j*ldb + k]
 // (else B[k*ldb + j]); CCOL: C(i,j) = C[j*ldc + i] (else C[i*ldc + j]);
 // TRI: B(k,j) = 0 for k > j.
-template <int NBH, bool ACOL, bool BCOL, bool CCOL, bool TRI>
+template <int NBH, bool ACOL, bool BCOL, bool CCOL, bool TRI, bool F32 = false>
 __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
+  typedef ApplyTy<F32> Ty;
+  typedef typename Ty::T T;
   constexpr int NC = 32 * NBH;                        // columns held by the workgroup
   constexpr int AVEC = AR * ABK / 4;                  // float4 per A chunk
   constexpr int APER = AVEC / 512;
   constexpr int BVEC = ABK * NC / 2;                  // double2 per B chunk
   constexpr int BPER = (BVEC + 511) / 512;
-  __shared__ double As[2][ABK][AR + 2];
-  __shared__ double Bs[2][ABK][NC + 2];
+  __shared__ T As[2][ABK][AR + Ty::PAD];
+  __shared__ T Bs[2][ABK][NC + Ty::PAD];
   if (g.run_if && *g.run_if == 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rg = wave & 3, ch = __builtin_amdgcn_readfirstlane(wave >> 2);
@@ -156,22 +189,22 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
       if (e < BVEC) {
         if (BCOL) {
           const int j = e / (ABK / 2), kk = (e % (ABK / 2)) * 2;
-          Bs[buf][kk][j] = rb[p].x;
-          Bs[buf][kk + 1][j] = rb[p].y;
+          Bs[buf][kk][j] = (T)rb[p].x;
+          Bs[buf][kk + 1][j] = (T)rb[p].y;
         } else {
           const int kk = e / (NC / 2), j = (e % (NC / 2)) * 2;
-          Bs[buf][kk][j] = rb[p].x;
-          Bs[buf][kk][j + 1] = rb[p].y;
+          Bs[buf][kk][j] = (T)rb[p].x;
+          Bs[buf][kk][j + 1] = (T)rb[p].y;
         }
       }
     }
   };
 
-  doublex4 acc[2][NBH];
+  typename Ty::Acc acc[2][NBH];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int t = 0; t < NBH; ++t) acc[m][t] = doublex4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < NBH; ++t) acc[m][t] = typename Ty::Acc{0, 0, 0, 0};
 
   // two LDS buffers; the registers run two chunks ahead
   const int nchunk = (kend + ABK - 1) / ABK;
@@ -201,18 +234,18 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
     static_for<0, 2 * NBH>([&](auto cc) {
       constexpr int c = decltype(cc)::value;
       if (c < nchunk) {
-        chunk_mfma<c / 2, NBH>(As[c & 1], Bs[c & 1], rg, ch, lane, acc);
+        chunk_mfma<c / 2, NBH, F32>(As[c & 1], Bs[c & 1], rg, ch, lane, acc);
         advance(c);
       }
     });
   } else {
     for (int c = 0; c < nchunk; ++c) {
-      chunk_mfma<0, NBH>(As[c & 1], Bs[c & 1], rg, ch, lane, acc);
+      chunk_mfma<0, NBH, F32>(As[c & 1], Bs[c & 1], rg, ch, lane, acc);
       advance(c);
     }
   }
 
-  // v_mfma_f64_16x16x4f64 output: lane l, register r -> row (l / 16) + 4 r, column l % 16
+  // output: lane l, register r -> row Ty::row(l, r) of the 16-row block, column l % 16
 #pragma unroll
   for (int t = 0; t < NBH; ++t) {
     const int j = 16 * (2 * t + ch) + (lane & 15);
@@ -221,7 +254,7 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
     for (int m = 0; m < 2; ++m)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = i0 + 32 * rg + 16 * m + (lane >> 4) + 4 * r;
+        const int64_t i = i0 + 32 * rg + 16 * m + Ty::row(lane, r);
         if (i >= g.n) continue;
         const float v = (float)acc[m][t][r];
         if (CCOL) g.C[(int64_t)j * g.ldc + i] = v;
@@ -248,6 +281,20 @@ sketchne_status apply_tall(sketchne_ctx* c, const ApplyDesc& d) {
   ApplyArgs g{d.n, d.K, d.N, d.A, d.lda, d.B, d.ldb, d.C, d.ldc, d.run_if};
   dim3 grid((unsigned)((d.n + AR - 1) / AR)), blk(512);
   const int nbh = d.N <= 128 ? 4 : (d.N <= 256 ? 8 : 9);
+  // the FP32 form is built for two shapes of a row-major block: the
+  // Cholesky-QR apply (B = R^-1 read by columns) and a plain B read by rows
+  if (d.f32 && !d.acol && !d.ccol && d.upper == d.bcol) {
+    if (d.upper) {
+      if (nbh == 4) hipLaunchKernelGGL((k_apply_tall<4, false, true, false, true, true>), grid, blk, 0, c->stream, g);
+      else if (nbh == 8) hipLaunchKernelGGL((k_apply_tall<8, false, true, false, true, true>), grid, blk, 0, c->stream, g);
+      else hipLaunchKernelGGL((k_apply_tall<9, false, true, false, true, true>), grid, blk, 0, c->stream, g);
+    } else {
+      if (nbh == 4) hipLaunchKernelGGL((k_apply_tall<4, false, false, false, false, true>), grid, blk, 0, c->stream, g);
+      else if (nbh == 8) hipLaunchKernelGGL((k_apply_tall<8, false, false, false, false, true>), grid, blk, 0, c->stream, g);
+      else hipLaunchKernelGGL((k_apply_tall<9, false, false, false, false, true>), grid, blk, 0, c->stream, g);
+    }
+    return launch_status();
+  }
 #define SKNE_APPLY(NBH)                                                                                       \
   do {                                                                                                        \
     if (d.upper && d.bcol) {                                                                                  \

@@ -123,6 +123,64 @@ __global__ void k_dense_rows(int64_t n, int width, int z, const int32_t* __restr
   if (col >= 0 && col < width) out[i * width + col] = inv_sqrt_z * (float)signs[idx];
 }
 
+// Z = O^T T for the row-sparse O (z signed entries per row, value s / sqrt z)
+// and T = f(L'R') O held transposed (Tt, l x n: row c is column c of T).
+// Workgroup c forms column c of Z, Z[c'][c] = (1 / sqrt z) sum over rows j and
+// their entries (c', s) of s T[j][c], streaming row c of Tt once (coalesced)
+// with the entries of O (read by every workgroup, so served from L2).  The
+// terms are added as 64-bit integers at a power-of-two scale 2^e chosen from
+// max |T| so that no sum can leave the range (|sum| <= n max |T| <= 2^62):
+// integer addition is associative, so the LDS atomics that scatter the terms
+// give the same bits in any order, and the only rounding is each term's, at
+// 2^-e (2^-46 of max |T| at n = 2^16).
+__global__ void k_fv_tmax_clear(unsigned* __restrict__ tmax) {
+  if (threadIdx.x == 0) *tmax = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_fv_tmax(int64_t count, const float* __restrict__ T, unsigned* __restrict__ tmax) {
+  float m = 0.0f;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const float a = fabsf(T[i]);
+    m = (a == a) ? fmaxf(m, a) : __builtin_inff();  // a NaN is carried as +inf
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  // non-negative floats order as their bit patterns
+  if ((threadIdx.x & 63) == 0) atomicMax(tmax, __float_as_uint(m));
+}
+
+__global__ __launch_bounds__(256) void k_fv_z(int64_t n, int l, int z, const int32_t* __restrict__ cols,
+                                              const int8_t* __restrict__ signs, const float* __restrict__ Tt,
+                                              int64_t ldt, const unsigned* __restrict__ tmax_bits, double inv_sqrt_z,
+                                              float* __restrict__ Z, uint32_t* __restrict__ flags) {
+  extern __shared__ long long zacc[];  // l
+  const int c = blockIdx.x;
+  for (int i = threadIdx.x; i < l; i += blockDim.x) zacc[i] = 0;
+  const float tmax = __uint_as_float(*tmax_bits);
+  __syncthreads();
+  if (!(tmax <= 3.4e38f)) {  // T holds a non-finite value
+    for (int i = threadIdx.x; i < l; i += blockDim.x) Z[(int64_t)i * l + c] = __builtin_nanf("");
+    if (threadIdx.x == 0) atomicOr(flags, (uint32_t)SKETCHNE_FLAG_NONFINITE);
+    return;
+  }
+  const int e = tmax > 0.0f ? 62 - (int)ceil(log2((double)n * (double)tmax)) : 0;
+  const double scale = ldexp(1.0, e);
+  const float* trow = Tt + (int64_t)c * ldt;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    const double v = (double)trow[j] * scale;
+    for (int t = 0; t < z; ++t) {
+      const int col = cols[j * z + t];
+      if (col >= 0 && col < l) {
+        const long long q = llrint(signs[j * z + t] > 0 ? v : -v);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&zacc[col]), (unsigned long long)q);
+      }
+    }
+  }
+  __syncthreads();
+  const double back = ldexp(inv_sqrt_z, -e);
+  for (int i = threadIdx.x; i < l; i += blockDim.x) Z[(int64_t)i * l + c] = (float)((double)zacc[i] * back);
+}
+
 __global__ void k_fill0(int64_t count, float* __restrict__ out) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < count) out[idx] = 0.0f;
@@ -317,6 +375,20 @@ sketchne_status pack_s_full(sketchne_ctx* c, int prec, int64_t n, int64_t njt, i
   else
     hipLaunchKernelGGL(k_pack_s_full<SKETCHNE_BF16>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, n,
                        njt, nct, z, cols, signs, out, c->d_flags, width);
+  return launch_status();
+}
+
+sketchne_status fv_z(sketchne_ctx* c, int64_t n, int l, int z, const int32_t* cols, const int8_t* signs,
+                     const float* Tt, int64_t ldt, unsigned* tmax, double inv_sqrt_z, float* Z) {
+  if ((size_t)l * sizeof(long long) > 65536) return SKETCHNE_E_UNSUPPORTED;
+  ProfScope ps(c, SKETCHNE_PROF_SKETCH_Z);
+  hipLaunchKernelGGL(k_fv_tmax_clear, dim3(1), dim3(64), 0, c->stream, tmax);
+  const int64_t cnt = (int64_t)l * ldt;
+  int64_t blocks = (cnt + 4 * 256 - 1) / (4 * 256);
+  blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
+  hipLaunchKernelGGL(k_fv_tmax, dim3((unsigned)blocks), dim3(256), 0, c->stream, cnt, Tt, tmax);
+  hipLaunchKernelGGL(k_fv_z, dim3((unsigned)l), dim3(256), (size_t)l * sizeof(long long), c->stream, n, l, z, cols,
+                     signs, Tt, ldt, tmax, inv_sqrt_z, Z, c->d_flags);
   return launch_status();
 }
 

@@ -11,13 +11,20 @@
 // super-tiles.  The super-tiles are split into two groups handled by two
 // workgroups on the same XCD, so the rows are read from memory once and from
 // the XCD's L2 the second time.  Per-workgroup partial sums are added in a
-// fixed order by a second kernel.
+// fixed order by a second kernel.  The F32 form runs the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32: twice the FP64 rate, no conversion of the rows) and
+// keeps FP32 partial sums per workgroup; it serves the Cholesky-QR of
+// power-iteration bases, whose factor only has to keep the basis well
+// conditioned (any invertible factor keeps its span).
+#include <type_traits>
+
 #include "internal.h"
 
 namespace skne {
 namespace {
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int GR_CHUNK = 32;      // rows per LDS chunk
 constexpr int GR_MAXB = 18;       // m <= 16 * GR_MAXB
@@ -54,8 +61,9 @@ __device__ __forceinline__ void blk_coords(int b, int nbk, int& I, int& J) {
 // (xc == 1); else columns are (xr == 1).
 constexpr int GS_SLOTS = 3;
 
-template <bool TWO, bool ROWMAJ>
+template <bool TWO, bool ROWMAJ, bool F32 = false>
 __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
+  typedef std::conditional_t<F32, floatx4, doublex4> Acc;
   if (g.run_if && *g.run_if == 0) return;
   const int L = blockIdx.x;
   const int q = L >> 3;
@@ -87,11 +95,11 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
     if (st >= st1) st = st0;
     blk_coords(st, npair, pI[t], pJ[t]);
   }
-  doublex4 acc[GS_SLOTS][4];
+  Acc acc[GS_SLOTS][4];
 #pragma unroll
   for (int t = 0; t < GS_SLOTS; ++t)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc[t][u] = doublex4{0.0, 0.0, 0.0, 0.0};
+    for (int u = 0; u < 4; ++u) acc[t][u] = Acc{0, 0, 0, 0};
 
   const int cols4 = (g.m + 3) / 4;
   constexpr int MAXV = (GR_CHUNK * GR_MAXB * 16 / 4 + GR_THREADS - 1) / GR_THREADS;
@@ -194,14 +202,26 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
       const float* yr = ys + rr * S + (lane & 15);
 #pragma unroll
       for (int t = 0; t < GS_SLOTS; ++t) {
-        const double a0 = (double)xr[32 * pI[t]] * wr;
-        const double a1 = (double)xr[32 * pI[t] + 16] * wr;
-        const double b0 = (double)yr[32 * pJ[t]];
-        const double b1 = (double)yr[32 * pJ[t] + 16];
-        acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[t][0], 0, 0, 0);
-        acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[t][1], 0, 0, 0);
-        acc[t][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[t][2], 0, 0, 0);
-        acc[t][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[t][3], 0, 0, 0);
+        if constexpr (F32) {
+          const float fw = (float)wr;
+          const float a0 = g.w ? xr[32 * pI[t]] * fw : xr[32 * pI[t]];
+          const float a1 = g.w ? xr[32 * pI[t] + 16] * fw : xr[32 * pI[t] + 16];
+          const float b0 = yr[32 * pJ[t]];
+          const float b1 = yr[32 * pJ[t] + 16];
+          acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[t][0], 0, 0, 0);
+          acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[t][1], 0, 0, 0);
+          acc[t][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[t][2], 0, 0, 0);
+          acc[t][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[t][3], 0, 0, 0);
+        } else {
+          const double a0 = (double)xr[32 * pI[t]] * wr;
+          const double a1 = (double)xr[32 * pI[t] + 16] * wr;
+          const double b0 = (double)yr[32 * pJ[t]];
+          const double b1 = (double)yr[32 * pJ[t] + 16];
+          acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[t][0], 0, 0, 0);
+          acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[t][1], 0, 0, 0);
+          acc[t][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[t][2], 0, 0, 0);
+          acc[t][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[t][3], 0, 0, 0);
+        }
       }
     }
     if (more) stash(buf ^ 1);
@@ -218,11 +238,20 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
       const int I = 2 * pI[t] + (u >> 1), J = 2 * pJ[t] + (u & 1);
       if (I > J || J >= g.nbk) continue;
       const int b = I * g.nbk - I * (I - 1) / 2 + (J - I);  // index of (I, J) in the upper enumeration
-      double* pb = part + (int64_t)b * 256 + lane * 4;
-      pb[0] = acc[t][u][0];
-      pb[1] = acc[t][u][1];
-      pb[2] = acc[t][u][2];
-      pb[3] = acc[t][u][3];
+      if constexpr (F32) {
+        // v_mfma_f32_16x16x4f32 holds row 4 (l / 16) + r, column l % 16 in
+        // lane l, register r; the partial keeps the FP64 form's order
+        // (row l' / 16 + 4 r', column l' % 16 at element 4 l' + r')
+        double* pb = part + (int64_t)b * 256;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pb[4 * ((lane & 15) + 16 * r) + (lane >> 4)] = (double)acc[t][u][r];
+      } else {
+        double* pb = part + (int64_t)b * 256 + lane * 4;
+        pb[0] = acc[t][u][0];
+        pb[1] = acc[t][u][1];
+        pb[2] = acc[t][u][2];
+        pb[3] = acc[t][u][3];
+      }
     }
   }
 }
@@ -272,7 +301,7 @@ size_t gram_ws_bytes(int64_t n, int m) {
 // or xr == 1 (columns contiguous).  Y may equal X (then pass Y = nullptr).
 sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int64_t xr, int64_t xc, const float* Y,
                           int64_t yr, int64_t yc, const double* w, double* G, double* partial, size_t partial_cap,
-                          const int* run_if) {
+                          const int* run_if, bool f32) {
   if (m < 1 || m > 16 * GR_MAXB) return SKETCHNE_E_UNSUPPORTED;
   const bool rowmaj = (xc == 1);
   if (!rowmaj && xr != 1) return SKETCHNE_E_ARG;
@@ -306,14 +335,15 @@ sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int
   const size_t shmem = sizeof(float) * (size_t)2 * (two ? 2 : 1) * GR_CHUNK * g.stride;
   const unsigned blocks = (unsigned)((nr + 7) / 8 * 8 * GR_GROUPS);
   ProfScope ps(c, SKETCHNE_PROF_GEMM64);
-#define SKNE_GRAM(T, R)                                                                                    \
+#define SKNE_GRAM(T, R, F)                                                                                 \
   do {                                                                                                     \
-    hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_st<T, R>),                                    \
+    hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_st<T, R, F>),                                 \
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);                           \
-    hipLaunchKernelGGL((k_gram_st<T, R>), dim3(blocks), dim3(GR_THREADS), shmem, c->stream, g);            \
+    hipLaunchKernelGGL((k_gram_st<T, R, F>), dim3(blocks), dim3(GR_THREADS), shmem, c->stream, g);         \
   } while (0)
-  if (two) { if (rowmaj) SKNE_GRAM(true, true); else SKNE_GRAM(true, false); }
-  else { if (rowmaj) SKNE_GRAM(false, true); else SKNE_GRAM(false, false); }
+  if (f32 && !two && rowmaj) SKNE_GRAM(false, true, true);
+  else if (two) { if (rowmaj) SKNE_GRAM(true, true, false); else SKNE_GRAM(true, false, false); }
+  else { if (rowmaj) SKNE_GRAM(false, true, false); else SKNE_GRAM(false, false, false); }
 #undef SKNE_GRAM
   hipLaunchKernelGGL(k_gram_reduce, dim3((g.nblk * 256 + 255) / 256), dim3(256), 0, c->stream, m, g.nbk, g.nblk, nr,
                      partial, G, run_if);

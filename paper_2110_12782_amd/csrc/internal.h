@@ -126,6 +126,7 @@ struct ApplyDesc {
   bool upper = false;
   float* C = nullptr; int64_t ldc = 0; bool ccol = false;
   const int* run_if = nullptr;
+  bool f32 = false;  // FP32 matrix cores (B rounded to FP32); only where a span is all that matters
 };
 bool apply_tall_supported(const ApplyDesc& d);
 sketchne_status apply_tall(sketchne_ctx* c, const ApplyDesc& d);
@@ -135,7 +136,7 @@ int gram_nwg(int64_t n);
 size_t gram_ws_bytes(int64_t n, int m);
 sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int64_t xr, int64_t xc, const float* Y,
                           int64_t yr, int64_t yc, const double* w, double* G, double* partial, size_t partial_cap,
-                          const int* run_if);
+                          const int* run_if, bool f32 = false);
 
 // dense_small.hip
 // Cholesky G = R^T R of an SPD m x m FP64 matrix (row-major, ld = m) and the

@@ -39,6 +39,10 @@ sketchne_status gather_rows(sketchne_ctx* c, int64_t n, int64_t npad, int k, con
                             const double* d1, double scale, double* out);
 sketchne_status pack_s_full(sketchne_ctx* c, int prec, int64_t n, int64_t njt, int nct, int z, const int32_t* cols,
                             const int8_t* signs, int width, void* out);
+// Z = O^T T for a row-sparse O, T held transposed (l x n, row stride ldt);
+// tmax: one device word of workspace
+sketchne_status fv_z(sketchne_ctx* c, int64_t n, int l, int z, const int32_t* cols, const int8_t* signs,
+                     const float* Tt, int64_t ldt, unsigned* tmax, double inv_sqrt_z, float* Z);
 sketchne_status dense_rows(sketchne_ctx* c, int64_t n, int width, int z, const int32_t* cols, const int8_t* signs,
                            float inv_sqrt_z, float* out);
 sketchne_status fullvisit(sketchne_ctx* c, int cls, int prec, int KSM, int64_t nrows, int64_t njt, int nct_all,
