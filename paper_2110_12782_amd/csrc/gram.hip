@@ -74,8 +74,11 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int S = g.stride;
   const int CH = GR_CHUNK * S;
-  float* bufX[2] = {lds, lds + (TWO ? 2 : 1) * CH};
-  float* bufY[2] = {TWO ? lds + CH : lds, TWO ? lds + 3 * CH : lds + CH};
+  // the two chunk buffers as offsets from the LDS array itself (an array of
+  // pointers indexed at run time would lose the LDS address space, and every
+  // fragment read would become a FLAT load waiting on the row prefetch)
+  auto offX = [&](int b) { return b ? (TWO ? 2 : 1) * CH : 0; };
+  auto offY = [&](int b) { return TWO ? (b ? 3 * CH : CH) : offX(b); };
   __shared__ double wsh[2][GR_CHUNK];
 
   const int64_t r0 = (int64_t)range * g.rows_per_wg;
@@ -149,8 +152,8 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
     if (g.w && tid < GR_CHUNK) pw = (c0 + tid < r1) ? g.w[c0 + tid] : 0.0;
   };
   auto stash = [&](int buf) {
-    float* dx = bufX[buf];
-    float* dy = bufY[buf];
+    float* dx = lds + offX(buf);
+    float* dy = lds + offY(buf);
 #pragma unroll
     for (int u = 0; u < MAXV; ++u) {
       int v = tid + GR_THREADS * u;
@@ -192,8 +195,8 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
   for (int64_t c0 = r0; c0 < r1; c0 += GR_CHUNK) {
     const bool more = c0 + GR_CHUNK < r1;
     if (more) fetch(c0 + GR_CHUNK);
-    const float* xs = bufX[buf];
-    const float* ys = bufY[buf];
+    const float* xs = lds + offX(buf);
+    const float* ys = lds + offY(buf);
 #pragma unroll 2
     for (int st = 0; st < GR_CHUNK / 4; ++st) {
       const int rr = 4 * st + (lane >> 4);
