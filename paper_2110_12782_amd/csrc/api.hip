@@ -296,6 +296,7 @@ struct EmbedWs {
   double* s_partial;
   size_t s_cap;
   void* symws;
+  int* needB;       // set by the Cholesky of B^T B when B = O^T Q needs a second pass
 };
 
 EmbedWs carve_embed(Arena& ar, const sketchne_params* p, int64_t n, bool dense_o = false) {
@@ -322,6 +323,7 @@ EmbedWs carve_embed(Arena& ar, const sketchne_params* p, int64_t n, bool dense_o
   w.ww = ar.take<double>(h);
   w.Map = ar.take<double>((size_t)h * d);
   w.Map2 = ar.take<double>((size_t)h * d);
+  w.needB = ar.take<int>(1);
   // the largest split-K partial of the small products and of E = Y Map2
   w.s_cap = max_bytes({gemm64_partial_bytes(h, h, l, true), gemm64_partial_bytes(l, h, h, false),
                        gemm64_partial_bytes(h, h, h, false), gemm64_partial_bytes(h, l, l, false),
@@ -672,15 +674,24 @@ static sketchne_status embed_impl(sketchne_ctx* c, const sketchne_params* p, int
     SK_TRY(ot_q(c, l, p->z, h, O->rows, O->signs, Yt, n, 1.0 / sqrt((double)p->z), w.OY));
   }
   SK_TRY(small(l, h, h, w.OY, Ty::F64, h, 1, w.Rci, Ty::F64, h, 1, w.Bm, false, nullptr));
-  // QR of B by Cholesky-QR twice in FP64: B = Bq R, R^-1 = R1^-1 R2^-1
+  // QR of B by Cholesky-QR in FP64: B = Bq R.  B = O^T Q is an l x h
+  // sparse-sign projection of orthonormal columns (l > h), so it is well
+  // conditioned and one pass leaves Bq orthonormal to FP64 rounding; the
+  // second pass (R^-1 = R1^-1 R2^-1) runs only when the first factor's
+  // condition number exceeds the orthonormal-basis bound or its Cholesky
+  // needed a shift (a device flag, no host round trip).
   SK_TRY(small(h, h, l, w.Bm, Ty::F64, 1, h, w.Bm, Ty::F64, h, 1, w.Gb, true, nullptr));
-  SK_TRY(chol_inv(c, h, w.Gb, w.Rb1, w.cwork));
-  SK_TRY(small(l, h, h, w.Bm, Ty::F64, h, 1, w.Rb1, Ty::F64, 1, h, w.Bq1, false, nullptr));
-  SK_TRY(small(h, h, l, w.Bq1, Ty::F64, 1, h, w.Bq1, Ty::F64, h, 1, w.Gb, true, nullptr));
-  SK_TRY(chol_inv(c, h, w.Gb, w.Rb2, w.cwork));
-  SK_TRY(small(l, h, h, w.Bq1, Ty::F64, h, 1, w.Rb2, Ty::F64, 1, h, w.Bq, false, nullptr));
-  // Rinv = R1^-1 R2^-1, with R^-1(i, j) = RinvT[j][i]
-  SK_TRY(small(h, h, h, w.Rb1, Ty::F64, 1, h, w.Rb2, Ty::F64, 1, h, w.Rinv, false, nullptr));
+  SK_TRY(chol_inv(c, h, w.Gb, w.Rb1, w.cwork, w.needB, nullptr));
+  SK_TRY(small(l, h, h, w.Bm, Ty::F64, h, 1, w.Rb1, Ty::F64, 1, h, w.Bq, false, nullptr));
+  // Rinv = R1^-1 (R^-1(i, j) = RinvT[j][i]), replaced by R1^-1 R2^-1 after a second pass
+  hipLaunchKernelGGL(k_transpose, dim3((h * h + 255) / 256), dim3(256), 0, c->stream, h, w.Rb1, w.Rinv);
+  SK_TRY(launch_status());
+  SK_TRY(small(h, h, l, w.Bq, Ty::F64, 1, h, w.Bq, Ty::F64, h, 1, w.Gb, true, w.needB));
+  SK_TRY(chol_inv(c, h, w.Gb, w.Rb2, w.cwork, nullptr, w.needB));
+  SK_TRY(small(l, h, h, w.Bq, Ty::F64, h, 1, w.Rb2, Ty::F64, 1, h, w.Bq1, false, w.needB));
+  SK_TRY(copy_if(c, 2 * (int64_t)l * h, reinterpret_cast<const float*>(w.Bq1), reinterpret_cast<float*>(w.Bq),
+                 w.needB));
+  SK_TRY(small(h, h, h, w.Rb1, Ty::F64, 1, h, w.Rb2, Ty::F64, 1, h, w.Rinv, false, w.needB));
   // W = Rinv (Bq^T Z Bq) Rinv^T  (Alg. 4 line 8, two least-squares solves)
   SK_TRY(small(h, l, l, w.Bq, Ty::F64, 1, h, Z, Ty::F32, l, 1, w.M1, false, nullptr));
   SK_TRY(small(h, h, l, w.M1, Ty::F64, l, 1, w.Bq, Ty::F64, h, 1, w.M2, false, nullptr));
