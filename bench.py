@@ -85,12 +85,16 @@ def main():
     prec_code = {"bf16": BF16, "fp16": FP16, "fp32": FP32}
 
     def params(prec):
+        # FP16 carries 3 more mantissa bits than BF16 and runs without the split
+        # (its range balance keeps R' in range)
+        split = 0 if prec == "fp32" or (prec == "fp16" and prec != args.precision) else args.split_r
         return SketchParams(alpha=0.5, T=10, b=1.0, k=256, s_eig=32, q=2, d=128, h=272, l=1128, z=8, seed=7,
-                            precision=prec_code[prec], split_r=0 if prec == "fp32" else args.split_r)
+                            precision=prec_code[prec], split_r=split)
 
     p_main = params(args.precision)
     nb = lib.workspace_size(p_main, g.n, g.nnz, OP_EIG | OP_SKETCH | OP_EMBED)
     nb = max(nb, lib.workspace_size(params("fp32"), g.n, g.nnz, OP_EIG | OP_SKETCH | OP_EMBED))
+    nb = max(nb, lib.workspace_size(params("fp16"), g.n, g.nnz, OP_EIG | OP_SKETCH | OP_EMBED))
     ws = lib.workspace(nb)
     log(f"workspace {nb / 2**30:.2f} GiB")
 
@@ -102,6 +106,7 @@ def main():
 
     def run_form(prec, steps, warmup):
         p = params(prec)
+        log(f"{prec} form: split_r = {p.split_r}")
         for i in range(warmup):
             out = step(p)
             flags = lib.sync()
@@ -157,6 +162,15 @@ def main():
                          "sketch_z_ms": prof32["sketch_z"][0] / s32,
                          "per_class_ms": {kk: vv[0] / s32 for kk, vv in prof32.items()}}
         ref_form = out32
+    other_forms = {}
+    if not args.no_compare and args.precision == "bf16":
+        # the other 16-bit matrix-core form, without the split, for comparison
+        dt16, prof16, out16 = run_form("fp16", max(1, steps - 1), 1)
+        s16 = max(1, steps - 1)
+        forms["fp16"] = {"ms_per_step": dt16 * 1e3, "split_r": 0, "sketch_y_ms": prof16["sketch_y"][0] / s16,
+                         "sketch_z_ms": prof16["sketch_z"][0] / s16,
+                         "per_class_ms": {kk: vv[0] / s16 for kk, vv in prof16.items()}}
+        other_forms["fp16"] = out16
 
     if ref_form is not None:
         # the two forms draw the same Omega, S and O (same seed); their embeddings
@@ -175,7 +189,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args, n, rowptr, colidx, out, ref_form, forms)
+        cpu = cpu_baseline(args, n, rowptr, colidx, out, ref_form, forms, other_forms)
     traffic = pmc_traffic(args.precision, args.scale, y_launches)
 
     line = {
@@ -463,7 +477,7 @@ def pmc_traffic(prec, scale, launches):
         return None
 
 
-def cpu_baseline(args, n, rowptr, colidx, out, ref_form, forms):
+def cpu_baseline(args, n, rowptr, colidx, out, ref_form, forms, other_forms=None):
     """The FP64 oracle timed on the host: Eq. 4 for Y on random row chunks
     (rows of Y are independent) until the time budget is spent, plus all of Z
     (Alg. 4 line 7), on the same U, lambda, S and O as the GPU step.  The same
@@ -511,6 +525,15 @@ def cpu_baseline(args, n, rowptr, colidx, out, ref_form, forms):
         sub = rows[: min(len(rows), 16384)]
         Yo2 = sk.sketch_y_sampled(Lp2, Rp2, rS, sS, row_subset=np.sort(sub))
         errs["fp32"] = {"Y_rows": metrics.rel_fro(ref_form[2].cpu().numpy()[:, np.sort(sub)].T, Yo2)}
+    for name, o in (other_forms or {}).items():
+        # same S and O (same seed); U from the form's own eig
+        U3 = o[0].cpu().numpy().astype(np.float64)
+        Lp3, Rp3, _ = netmf.eq11_factors(U3, o[1].cpu().numpy(), deg, vol, 0.5, 10, 1.0)
+        sub = np.sort(rows[: min(len(rows), 16384)])
+        Yo3 = sk.sketch_y_sampled(Lp3, Rp3, rS, sS, row_subset=sub)
+        Zo3 = sk.sketch_z_sampled(Lp3, Rp3, rO, sO)
+        errs[name] = {"Y_rows": metrics.rel_fro(o[2].cpu().numpy()[:, sub].T, Yo3),
+                      "Z": metrics.rel_fro(o[3].cpu().numpy(), Zo3)}
     for kk, e in errs.items():
         forms[kk]["rel_err_vs_fp64"] = e
     log(f"cpu baseline: Y {ty:.1f}s for {len(rows)} rows, Z {tz:.1f}s; errors {errs}")
