@@ -217,6 +217,9 @@ def main():
         "roofline": {"bound": "mfma", "kernel": ("k_fused_sketch" if args.precision == "fp32" else "k_fused_lowp")
                      + " (Y pass)", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                     "traffic_source": "rocprofv3 FETCH_SIZE + WRITE_SIZE per Y launch, copy-calibrated, from the "
+                                       "committed summary profiles/fused_sketch_y_chunglu_n2p20_bf16_hbm_bytes.txt; "
+                                       "null unless that summary's SHA-256 of sketch.hip matches the source",
                      "launch_ms": y_ms, "algorithmic_flops": y_flops, "executed_flops": executed,
                      "launches_per_step": y_launches},
         "roofline_spmm": {"bound": "hbm", "kernel": "k_spmm", "achieved": sp_gbs, "peak": HBM_PEAK,
