@@ -40,6 +40,7 @@ struct GramArgs {
   const double* w;
   int64_t rows_per_wg;
   int nranges;                  // row ranges
+  int crows;                    // !ROWMAJ: rows of a chunk buffer (one per matrix column i, padded)
   int gsize;                    // blocks per group
   double* partial;              // nranges x nblk x 256
   const int* run_if;            // when non-null and zero: do nothing
@@ -72,8 +73,12 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
   if (range >= g.nranges) return;
   extern __shared__ __attribute__((aligned(16))) float lds[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // chunk buffers: ROWMAJ [data row][column i] (row stride S); otherwise
+  // [column i][data row] (stride S = GR_CHUNK + 2), so that a column-major
+  // input is stored as it is read, without a transposing scatter
   const int S = g.stride;
-  const int CH = GR_CHUNK * S;
+  const int CH = ROWMAJ ? GR_CHUNK * S : g.crows * S;
+  const int rstep = ROWMAJ ? S : 1, cstep = ROWMAJ ? 1 : S;
   // the two chunk buffers as offsets from the LDS array itself (an array of
   // pointers indexed at run time would lose the LDS address space, and every
   // fragment read would become a FLAT load waiting on the row prefetch)
@@ -166,15 +171,12 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
       } else {
         int i = v / (GR_CHUNK / 4), qq = v - i * (GR_CHUNK / 4);
         if (i < g.m) {
-          dx[(4 * qq) * S + i] = px[u].x;
-          dx[(4 * qq + 1) * S + i] = px[u].y;
-          dx[(4 * qq + 2) * S + i] = px[u].z;
-          dx[(4 * qq + 3) * S + i] = px[u].w;
+          // S is even: 8-byte stores
+          *reinterpret_cast<float2*>(dx + i * S + 4 * qq) = make_float2(px[u].x, px[u].y);
+          *reinterpret_cast<float2*>(dx + i * S + 4 * qq + 2) = make_float2(px[u].z, px[u].w);
           if (TWO) {
-            dy[(4 * qq) * S + i] = py[u].x;
-            dy[(4 * qq + 1) * S + i] = py[u].y;
-            dy[(4 * qq + 2) * S + i] = py[u].z;
-            dy[(4 * qq + 3) * S + i] = py[u].w;
+            *reinterpret_cast<float2*>(dy + i * S + 4 * qq) = make_float2(py[u].x, py[u].y);
+            *reinterpret_cast<float2*>(dy + i * S + 4 * qq + 2) = make_float2(py[u].z, py[u].w);
           }
         }
       }
@@ -182,8 +184,9 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
     if (tid < GR_CHUNK) wsh[buf][tid] = pw;
   };
 
+  // columns i >= m are never stored: zero them once
   for (int idx = tid; idx < 2 * (TWO ? 2 : 1) * CH; idx += GR_THREADS) {
-    int col = (idx % CH) % S;
+    const int col = ROWMAJ ? (idx % CH) % S : (idx % CH) / S;
     if (col >= g.m) lds[idx] = 0.f;
   }
   int buf = 0;
@@ -201,25 +204,25 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
     for (int st = 0; st < GR_CHUNK / 4; ++st) {
       const int rr = 4 * st + (lane >> 4);
       const double wr = g.w ? wsh[buf][rr] : 1.0;
-      const float* xr = xs + rr * S + (lane & 15);
-      const float* yr = ys + rr * S + (lane & 15);
+      const float* xr = xs + rr * rstep + (lane & 15) * cstep;
+      const float* yr = ys + rr * rstep + (lane & 15) * cstep;
 #pragma unroll
       for (int t = 0; t < GS_SLOTS; ++t) {
         if constexpr (F32) {
           const float fw = (float)wr;
-          const float a0 = g.w ? xr[32 * pI[t]] * fw : xr[32 * pI[t]];
-          const float a1 = g.w ? xr[32 * pI[t] + 16] * fw : xr[32 * pI[t] + 16];
-          const float b0 = yr[32 * pJ[t]];
-          const float b1 = yr[32 * pJ[t] + 16];
+          const float a0 = g.w ? xr[32 * pI[t] * cstep] * fw : xr[32 * pI[t] * cstep];
+          const float a1 = g.w ? xr[(32 * pI[t] + 16) * cstep] * fw : xr[(32 * pI[t] + 16) * cstep];
+          const float b0 = yr[32 * pJ[t] * cstep];
+          const float b1 = yr[(32 * pJ[t] + 16) * cstep];
           acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[t][0], 0, 0, 0);
           acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[t][1], 0, 0, 0);
           acc[t][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[t][2], 0, 0, 0);
           acc[t][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[t][3], 0, 0, 0);
         } else {
-          const double a0 = (double)xr[32 * pI[t]] * wr;
-          const double a1 = (double)xr[32 * pI[t] + 16] * wr;
-          const double b0 = (double)yr[32 * pJ[t]];
-          const double b1 = (double)yr[32 * pJ[t] + 16];
+          const double a0 = (double)xr[32 * pI[t] * cstep] * wr;
+          const double a1 = (double)xr[(32 * pI[t] + 16) * cstep] * wr;
+          const double b0 = (double)yr[32 * pJ[t] * cstep];
+          const double b1 = (double)yr[(32 * pJ[t] + 16) * cstep];
           acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[t][0], 0, 0, 0);
           acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[t][1], 0, 0, 0);
           acc[t][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[t][2], 0, 0, 0);
@@ -321,6 +324,10 @@ sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int
   // distinct banks
   g.stride = (m + 31) / 32 * 32;
   if (g.stride % 64 == 0 || g.stride % 64 == 32) g.stride += 16;
+  // column-major input: [column][row] buffers of GR_CHUNK + 2 floats per
+  // column (the 16 columns x 2 rows a half-wave reads fall in distinct banks)
+  g.crows = 32 * ((g.nbk + 1) / 2);
+  if (!rowmaj) g.stride = GR_CHUNK + 2;
   g.X = X; g.xr = xr; g.xc = xc;
   g.Y = Y ? Y : X; g.yr = Y ? yr : xr; g.yc = Y ? yc : xc;
   g.w = w;
@@ -335,7 +342,7 @@ sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int
   g.partial = partial;
   g.run_if = run_if;
   const bool two = Y != nullptr;
-  const size_t shmem = sizeof(float) * (size_t)2 * (two ? 2 : 1) * GR_CHUNK * g.stride;
+  const size_t shmem = sizeof(float) * (size_t)2 * (two ? 2 : 1) * (rowmaj ? GR_CHUNK : g.crows) * g.stride;
   const unsigned blocks = (unsigned)((nr + 7) / 8 * 8 * GR_GROUPS);
   ProfScope ps(c, SKETCHNE_PROF_GEMM64);
 #define SKNE_GRAM(T, R, F)                                                                                 \
