@@ -50,7 +50,7 @@ __device__ __forceinline__ double wave_max(double v) {
 // identity, and the row operations of the factorization turn the pair into
 // [R_JJ | R_JJ^-T].  Row t is passed between lanes through LDS (xrow; LDS
 // operations of one wavefront complete in order).  On return the left lanes
-// have written R_JJ to W (and added the column sums of |R_JJ| to colsum when
+// have written R_JJ to W (unless W is null) (and added the column sums of |R_JJ| to colsum when
 // it is non-null), and D holds R_JJ^-T, padded with the identity.  Sets
 // *fail when a pivot is not positive.
 __device__ void chol_diag_wave(double* D, double* xrow, double* W, int64_t m2, int j0, int jb, int lane,
@@ -86,7 +86,7 @@ __device__ void chol_diag_wave(double* D, double* xrow, double* W, int64_t m2, i
 #pragma unroll
       for (int a = 0; a < NB; ++a)
         if (a <= b) {
-          W[(int64_t)(j0 + a) * m2 + j0 + b] = c[a];
+          if (W) W[(int64_t)(j0 + a) * m2 + j0 + b] = c[a];
           cs += fabs(c[a]);
         }
       if (colsum) colsum[j0 + b] += cs;
@@ -428,11 +428,22 @@ __global__ __launch_bounds__(1024) void k_oj_norm(int m, const double* __restric
     return;
   }
   __shared__ double part[16];
+  // ||A||_F^2 from the upper triangle (off-diagonal entries twice), eight
+  // loads in flight per thread
+  constexpr int BATCH = 8;
+  const int mm = m * m, nt = blockDim.x;
   double s = 0.0;
-  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-    int r = idx / m, c = idx - r * m;
-    double a = r <= c ? A[r * m + c] : A[c * m + r];
-    s += a * a;
+  for (int base = threadIdx.x; base < mm; base += nt * BATCH) {
+    double a[BATCH], wt[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int idx = base + nt * u;
+      const int r = idx / m, c = idx - r * m;
+      a[u] = (idx < mm && c >= r) ? A[idx] : 0.0;
+      wt[u] = c > r ? 2.0 : 1.0;
+    }
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) s = fma(a[u] * wt[u], a[u], s);
   }
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
@@ -472,8 +483,11 @@ __global__ void k_oj_init(int m, int mp, const double* __restrict__ A, int gener
 // cos(2 theta) = |d| / h and sin(2 theta) = sgn(d) 2 g / h, so
 // c^2 = (1 + |d| / h) / 2 and s = sgn(d) g / (h c) (tan(theta) =
 // sgn(d) 2g / (|d| + h)); two reciprocal square roots and no division keep
-// the dependent chain short.
-__device__ __forceinline__ bool oj_angle(double a, double b, double g, double& c, double& sn, bool& big) {
+// the dependent chain short.  t = tan(theta) = s / c is returned for the
+// norm update: the rotated pair x' = c x - s y, y' = s x + c y has
+// x'.x' = a - t g and y'.y' = b + t g (its Gram matrix keeps its trace and
+// loses the off-diagonal g).
+__device__ __forceinline__ bool oj_angle(double a, double b, double g, double& c, double& sn, double& t, bool& big) {
   const double tol = 1e-14;
   const double g2 = g * g, ab = a * b;
   big = false;
@@ -482,9 +496,10 @@ __device__ __forceinline__ bool oj_angle(double a, double b, double g, double& c
   const double d = b - a;
   const double rh = rsqrt(fma(d, d, 4.0 * g2));  // 1 / h
   const double c2 = fma(fabs(d), 0.5 * rh, 0.5);  // c^2
-  const double rc = rsqrt(c2);
+  const double rc = rsqrt(c2);                    // 1 / c
   c = c2 * rc;
   sn = (d >= 0.0 ? g : -g) * rh * rc;
+  t = sn * rc;
   return true;
 }
 
@@ -493,31 +508,48 @@ __device__ __forceinline__ bool oj_angle(double a, double b, double g, double& c
 // group cover 256 contiguous bytes.
 __device__ __forceinline__ int oj_row(int sub, int i) { return 2 * sub + 2 * OJ_GL * i; }
 
+// this lane's share of x.y, in three interleaved partial sums so that the
+// FMAs do not form one dependent chain
+__device__ __forceinline__ double oj_dot(const double* x, const double* y) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < OJ_MAXR; i += 3) {
+    s0 = fma(x[i], y[i], s0);
+    s1 = fma(x[i + 1], y[i + 1], s1);
+    s2 = fma(x[i + 2], y[i + 2], s2);
+  }
+  return (s0 + s1) + s2;
+}
+
+__device__ __forceinline__ void oj_load_col(const double* __restrict__ col, int sub, double* x) {
+#pragma unroll
+  for (int i = 0; i < OJ_MAXR / 2; ++i) {
+    const double2 u = *reinterpret_cast<const double2*>(col + oj_row(sub, i));
+    x[2 * i] = u.x;
+    x[2 * i + 1] = u.y;
+  }
+}
+
+// The squared column norms are computed once per round and then carried
+// through the rotations (a - t g, b + t g) instead of being recomputed, so a
+// rotation step computes one inner product.  With the shift c >= 1.5 ||A||_F
+// every column norm stays above (c - ||A||_2)^2 > 0, so the update never
+// cancels.
+
 // orthogonalise columns p and q of sG (LDS, column-major, OJ_ROWS rows) by
-// the lanes of one column group; returns whether a rotation was applied
-__device__ __forceinline__ bool oj_rotate_lds(double* __restrict__ sG, int p, int q, int sub, bool& big) {
+// the lanes of one column group, nrm holding their squared norms; returns
+// whether a rotation was applied
+__device__ __forceinline__ bool oj_rotate_lds(double* __restrict__ sG, double* __restrict__ nrm, int p, int q, int sub,
+                                              bool& big) {
   double* gp = sG + p * OJ_ROWS;
   double* gq = sG + q * OJ_ROWS;
   double x[OJ_MAXR], y[OJ_MAXR];
-  double a = 0.0, b = 0.0, g = 0.0;
-#pragma unroll
-  for (int i = 0; i < OJ_MAXR / 2; ++i) {
-    const double2 u = *reinterpret_cast<const double2*>(gp + oj_row(sub, i));
-    const double2 v = *reinterpret_cast<const double2*>(gq + oj_row(sub, i));
-    x[2 * i] = u.x; x[2 * i + 1] = u.y;
-    y[2 * i] = v.x; y[2 * i + 1] = v.y;
-  }
-#pragma unroll
-  for (int i = 0; i < OJ_MAXR; ++i) {
-    a = fma(x[i], x[i], a);
-    b = fma(y[i], y[i], b);
-    g = fma(x[i], y[i], g);
-  }
-  a = group_sum(a);
-  b = group_sum(b);
-  g = group_sum(g);
-  double c, sn;
-  if (!oj_angle(a, b, g, c, sn, big)) return false;
+  oj_load_col(gp, sub, x);
+  oj_load_col(gq, sub, y);
+  const double a = nrm[p], b = nrm[q];
+  const double g = group_sum(oj_dot(x, y));
+  double c, sn, t;
+  if (!oj_angle(a, b, g, c, sn, t, big)) return false;
 #pragma unroll
   for (int i = 0; i < OJ_MAXR / 2; ++i) {
     *reinterpret_cast<double2*>(gp + oj_row(sub, i)) =
@@ -525,13 +557,17 @@ __device__ __forceinline__ bool oj_rotate_lds(double* __restrict__ sG, int p, in
     *reinterpret_cast<double2*>(gq + oj_row(sub, i)) =
         make_double2(sn * x[2 * i] + c * y[2 * i], sn * x[2 * i + 1] + c * y[2 * i + 1]);
   }
+  if (sub == 0) {
+    nrm[p] = a - t * g;
+    nrm[q] = b + t * g;
+  }
   return true;
 }
 
 // load / store contiguous columns of OJ_ROWS doubles with double2,
 // `batch` transfers in flight per thread
 __device__ __forceinline__ void oj_block_load(const double* __restrict__ src, double* __restrict__ dst, int count) {
-  constexpr int BATCH = 6;
+  constexpr int BATCH = NBJ * OJ_ROWS / (2 * OJ_THREADS);  // one block in a single batch
   for (int base = 2 * threadIdx.x; base < count; base += 2 * blockDim.x * BATCH) {
     double2 v[BATCH];
 #pragma unroll
@@ -549,7 +585,7 @@ __device__ __forceinline__ void oj_block_load(const double* __restrict__ src, do
 
 // workgroup w orthogonalises the pairs inside blocks 2w and 2w+1 (both in LDS)
 __device__ __forceinline__ void oj_intra_round(int w, int sweep, double* __restrict__ G, int* __restrict__ counters,
-                                               double* __restrict__ sG, int* s_cnt) {
+                                               double* __restrict__ sG, double* __restrict__ nrm, int* s_cnt) {
   const int tid = threadIdx.x;
   if (tid == 0) s_cnt[0] = s_cnt[1] = 0;
   const int blk = NBJ * OJ_ROWS;
@@ -557,13 +593,22 @@ __device__ __forceinline__ void oj_intra_round(int w, int sweep, double* __restr
   oj_block_load(g0, sG, 2 * blk);
   __syncthreads();
   const int grp = tid / OJ_GL, sub = tid % OJ_GL;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    double x[OJ_MAXR];
+    const int col = grp + NBJ * h;
+    oj_load_col(sG + col * OJ_ROWS, sub, x);
+    const double a = group_sum(oj_dot(x, x));
+    if (sub == 0) nrm[col] = a;
+  }
+  __syncthreads();
   int my_rot = 0, my_big = 0;
   for (int rnd = 0; rnd < NBJ - 1; ++rnd) {
     const int half = grp >> 3;  // 8 groups per block
     int p, q;
     pair_of(rnd, grp & 7, NBJ, p, q);
     bool big;
-    if (oj_rotate_lds(sG, p + half * NBJ, q + half * NBJ, sub, big) && sub == 0) {
+    if (oj_rotate_lds(sG, nrm, p + half * NBJ, q + half * NBJ, sub, big) && sub == 0) {
       ++my_rot;
       my_big += big;
     }
@@ -579,8 +624,10 @@ __device__ __forceinline__ void oj_intra_round(int w, int sweep, double* __restr
 
 // workgroup w takes the block pair w of round s: column g of block P stays
 // in the registers of lane group g, the 16 columns of block Q rotate past it
+// (their squared norms travel with them in nrm)
 __device__ __forceinline__ void oj_cross_round(int w, int nb, int s, int sweep, double* __restrict__ G,
-                                               int* __restrict__ counters, double* __restrict__ sQ, int* s_cnt) {
+                                               int* __restrict__ counters, double* __restrict__ sQ,
+                                               double* __restrict__ nrm, int* s_cnt) {
   int P, Q;
   pair_of(s, w, nb, P, Q);
   const int tid = threadIdx.x, grp = tid / OJ_GL, sub = tid % OJ_GL;
@@ -589,37 +636,28 @@ __device__ __forceinline__ void oj_cross_round(int w, int nb, int s, int sweep, 
   double* gpcol = G + (int64_t)P * blk + (int64_t)grp * OJ_ROWS;
   double* gQ = G + (int64_t)Q * blk;
   double x[OJ_MAXR];
-#pragma unroll
-  for (int i = 0; i < OJ_MAXR / 2; ++i) {
-    const double2 u = *reinterpret_cast<const double2*>(gpcol + oj_row(sub, i));
-    x[2 * i] = u.x;
-    x[2 * i + 1] = u.y;
-  }
+  oj_load_col(gpcol, sub, x);
   oj_block_load(gQ, sQ, blk);
+  double a = group_sum(oj_dot(x, x));
+  __syncthreads();
+  {
+    double y[OJ_MAXR];
+    oj_load_col(sQ + grp * OJ_ROWS, sub, y);
+    const double b = group_sum(oj_dot(y, y));
+    if (sub == 0) nrm[grp] = b;
+  }
   __syncthreads();
   int my_rot = 0, my_big = 0;
   for (int rnd = 0; rnd < NBJ; ++rnd) {
-    double* gq = sQ + ((grp + rnd) & (NBJ - 1)) * OJ_ROWS;
+    const int qc = (grp + rnd) & (NBJ - 1);
+    double* gq = sQ + qc * OJ_ROWS;
     double y[OJ_MAXR];
-    double a = 0.0, b = 0.0, g = 0.0;
-#pragma unroll
-    for (int i = 0; i < OJ_MAXR / 2; ++i) {
-      const double2 v = *reinterpret_cast<const double2*>(gq + oj_row(sub, i));
-      y[2 * i] = v.x;
-      y[2 * i + 1] = v.y;
-    }
-#pragma unroll
-    for (int i = 0; i < OJ_MAXR; ++i) {
-      a = fma(x[i], x[i], a);
-      b = fma(y[i], y[i], b);
-      g = fma(x[i], y[i], g);
-    }
-    a = group_sum(a);
-    b = group_sum(b);
-    g = group_sum(g);
-    double c, sn;
+    oj_load_col(gq, sub, y);
+    const double b = nrm[qc];
+    const double g = group_sum(oj_dot(x, y));
+    double c, sn, t;
     bool big;
-    if (oj_angle(a, b, g, c, sn, big)) {
+    if (oj_angle(a, b, g, c, sn, t, big)) {
 #pragma unroll
       for (int i = 0; i < OJ_MAXR / 2; ++i) {
         const double x0 = x[2 * i], x1 = x[2 * i + 1];
@@ -628,7 +666,9 @@ __device__ __forceinline__ void oj_cross_round(int w, int nb, int s, int sweep, 
         *reinterpret_cast<double2*>(gq + oj_row(sub, i)) =
             make_double2(sn * x0 + c * y[2 * i], sn * x1 + c * y[2 * i + 1]);
       }
+      a -= t * g;
       if (sub == 0) {
+        nrm[qc] = b + t * g;
         ++my_rot;
         my_big += big;
       }
@@ -655,15 +695,16 @@ __device__ __forceinline__ void oj_cross_round(int w, int nb, int s, int sweep, 
 // depend on the launch shape.
 __global__ __launch_bounds__(OJ_THREADS) void k_oj_sweeps(int nb, double* __restrict__ G, int* __restrict__ counters) {
   extern __shared__ __attribute__((aligned(16))) double lds[];
+  __shared__ double s_nrm[2 * NBJ];  // squared column norms of the blocks in LDS
   __shared__ int s_cnt[2];
   __shared__ int s_stop;
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   const int w = blockIdx.x;
   for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-    oj_intra_round(w, sweep, G, counters, lds, s_cnt);
+    oj_intra_round(w, sweep, G, counters, lds, s_nrm, s_cnt);
     grid.sync();
     for (int s = 0; s < nb - 1; ++s) {
-      oj_cross_round(w, nb, s, sweep, G, counters, lds, s_cnt);
+      oj_cross_round(w, nb, s, sweep, G, counters, lds, s_nrm, s_cnt);
       grid.sync();
     }
     if (threadIdx.x == 0)
@@ -674,17 +715,17 @@ __global__ __launch_bounds__(OJ_THREADS) void k_oj_sweeps(int nb, double* __rest
   }
 }
 
-// lambda_j = ||g_j|| - c and v_j = g_j / ||g_j|| (one wavefront per column);
-// sort by |lambda| desc (ties: lambda desc, then index); write w and the
-// eigenvectors as the columns of the row-major Vout.
+// lambda_j = ||g_j|| - c and v_j = g_j / ||g_j||; sort by |lambda| desc
+// (ties: lambda desc, then index); write w and the eigenvectors as the
+// columns of the row-major Vout.
 __global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restrict__ G,
                                                     const double* __restrict__ shift, const int* __restrict__ counters,
                                                     int sweeps_run, double* __restrict__ Vout,
                                                     double* __restrict__ wout, uint32_t* __restrict__ flags) {
   __shared__ double w[1024];
   __shared__ double inv[1024];
-  __shared__ int rank[1024];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ int perm[1024];  // perm[p] = column of G that goes to position p
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwv = blockDim.x >> 6;
   if (tid == 0) {
     bool conv = false;
     for (int s = 0; s < sweeps_run; ++s)
@@ -692,22 +733,31 @@ __global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restr
     if (!conv) atomicOr(flags, SKETCHNE_FLAG_EIG_NOCONV);
   }
   const double cs = *shift;
-  for (int j = wave; j < m; j += 16) {
-    double d = 0.0;
+  // column norms: a wavefront takes three columns at a time, all their loads
+  // in flight
+  constexpr int RPL = (OJ_ROWS + 63) / 64;  // rows per lane
+  for (int j0 = 3 * wave; j0 < m; j0 += 3 * nwv) {
+    double v[3][RPL];
 #pragma unroll
-    for (int i = 0; i < (OJ_GL * OJ_MAXR + 63) / 64; ++i) {
-      const int r = lane + 64 * i;
-      if (r < m) {
-        const double v = G[(int64_t)j * OJ_ROWS + r];
-        d = fma(v, v, d);
+    for (int u = 0; u < 3; ++u)
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int j = j0 + u, r = lane + 64 * i;
+        v[u][i] = (j < m && r < m) ? G[(int64_t)j * OJ_ROWS + r] : 0.0;
       }
-    }
-    d = wave_sum(d);
-    if (lane == 0) {
-      const double nrm = sqrt(d);
-      w[j] = nrm - cs;
-      inv[j] = nrm > 0.0 ? 1.0 / nrm : 0.0;
-      if (!isfinite(w[j])) atomicOr(flags, SKETCHNE_FLAG_NONFINITE);
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      double d = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) d = fma(v[u][i], v[u][i], d);
+      d = wave_sum(d);
+      const int j = j0 + u;
+      if (lane == 0 && j < m) {
+        const double nrm = sqrt(d);
+        w[j] = nrm - cs;
+        inv[j] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        if (!isfinite(w[j])) atomicOr(flags, SKETCHNE_FLAG_NONFINITE);
+      }
     }
   }
   __syncthreads();
@@ -719,18 +769,33 @@ __global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restr
       bool before = (aj > ai) || (aj == ai && (w[j] > w[i] || (w[j] == w[i] && j < i)));
       rk += before ? 1 : 0;
     }
-    rank[i] = rk;
+    perm[rk] = i;
+    wout[rk] = w[i];
   }
   __syncthreads();
-  for (int i = tid; i < m; i += blockDim.x) wout[rank[i]] = w[i];
-  // one wavefront per column of G, its rows over the lanes
-  for (int j = wave; j < m; j += 16) {
-    const double s = inv[j];
-    const int rj = rank[j];
-    for (int r = lane; r < m; r += 64) {
-      // a zero matrix (c = 0) has G = 0: its eigenvectors are the unit vectors
-      const double v = s > 0.0 ? G[(int64_t)j * OJ_ROWS + r] * s : (r == j ? 1.0 : 0.0);
-      Vout[(int64_t)r * m + rj] = v;
+  // Vout[r][p] = G[perm[p]][r] / ||g||: consecutive threads write consecutive
+  // entries of a row; eight entries in flight per thread
+  constexpr int BATCH = 8;
+  const int mm = m * m, nt = blockDim.x;
+  for (int base = tid; base < mm; base += nt * BATCH) {
+    double v[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int idx = base + nt * u;
+      const int r = idx / m, p = idx - r * m;
+      double x = 0.0;
+      if (idx < mm) {
+        const int j = perm[p];
+        const double s = inv[j];
+        // a zero matrix (c = 0) has G = 0: its eigenvectors are the unit vectors
+        x = s > 0.0 ? G[(int64_t)j * OJ_ROWS + r] * s : (r == j ? 1.0 : 0.0);
+      }
+      v[u] = x;
+    }
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int idx = base + nt * u;
+      if (idx < mm) Vout[idx] = v[u];
     }
   }
 }
@@ -760,9 +825,265 @@ constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 void* g_scratch_ptr[kMaxDevices] = {};
 
+// The same factorization spread over a few workgroups of one cooperative
+// launch, for orders where the trailing updates of a single workgroup (one
+// CU's FP64 matrix cores) dominate.  Every workgroup factors the diagonal
+// block and forms the whole row panel itself (both are small), so that only
+// the trailing update is divided: its live tiles are dealt to all wavefronts
+// of the grid, and one grid barrier per block step publishes the updated rows.
+// Entries of the left half are never read once their block row is done, so
+// R itself is not stored: the row panel lives in LDS (its column sums feed the
+// condition estimate), and its right-half part, the block row of R^-T, is
+// written to W at the start of the next step, after the barrier, when no
+// workgroup reads those entries any more.  Decisions (a failed pivot, the
+// shifted retry) depend only on data every workgroup reads identically, so all
+// workgroups take the same path and meet the same barriers.
+__global__ __launch_bounds__(512) void k_chol_inv_coop(int m, const double* __restrict__ G, double* __restrict__ W,
+                                                       double* __restrict__ rpart, double* __restrict__ RinvT,
+                                                       uint32_t* __restrict__ flags, int* __restrict__ need_more,
+                                                       const int* __restrict__ run_if, double repeat_kappa) {
+  if (run_if && *run_if == 0) return;
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  extern __shared__ double smem[];
+  double* D = smem;                  // NB x (NB+1)
+  double* P = smem + NB * (NB + 1);  // NB x m panel
+  __shared__ double rsc[CH_MAXM];
+  __shared__ double colsum[CH_MAXM];
+  __shared__ double xrow[64];
+  __shared__ double s_red[2][8];
+  __shared__ int s_fail;
+  __shared__ int s_shifted;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), nw = nt >> 6;
+  const int wg = blockIdx.x, nwg = gridDim.x;
+  const int gw = wg * nw + wv, gnw = nwg * nw;  // wavefront index in the grid
+  const int64_t m2 = 2 * (int64_t)m;
+
+  double trp = 0.0;
+  for (int i = tid; i < m; i += nt) {
+    const double g = G[(int64_t)i * m + i];
+    const double r = (g > 0.0 && isfinite(g)) ? 1.0 / sqrt(g) : 1.0;
+    rsc[i] = r;
+    trp += fabs(g) * r * r;
+  }
+  trp = wave_sum(trp);
+  if (lane == 0) s_red[0][wv] = trp;
+  if (tid == 0) s_shifted = 0;
+  __syncthreads();
+  double tr = 0.0;
+  for (int w = 0; w < nw; ++w) tr += s_red[0][w];
+  const double retry_shift = 11.0 * ((double)m * m + m) * 1.1102230246251565e-16 * (tr > 0 ? tr : 1.0);
+
+  // block row (pj0, pjb) of R^-T from the panel in LDS to W
+  auto store_right = [&](int pj0, int pjb) {
+    const int pleft = m - pj0 - pjb, wr = pj0 + pjb;
+    for (int idx = wg * nt + tid; idx < pjb * wr; idx += nwg * nt) {
+      const int i = idx / wr, j = idx - i * wr;
+      W[(int64_t)(pj0 + i) * m2 + m + j] = P[i * m + pleft + j];
+    }
+  };
+
+  int pj0 = 0, pjb = 0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const double shift = attempt == 0 ? 0.0 : retry_shift;
+    for (int r0 = 4 * gw; r0 < m; r0 += 4 * gnw) {
+      double v[4][CH_CHUNKS];
+#pragma unroll
+      for (int h = 0; h < 4; ++h)
+#pragma unroll
+        for (int cc = 0; cc < CH_CHUNKS; ++cc) {
+          const int r = r0 + h, c = lane + 64 * cc;
+          v[h][cc] = (r < m && c < m && c >= r) ? G[(int64_t)r * m + c] : 0.0;
+        }
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int r = r0 + h;
+        if (r >= m) break;
+        double* row = W + (int64_t)r * m2;
+        const int rend = min(m, (r / NB + 1) * NB);
+        const double rr = rsc[r];
+#pragma unroll
+        for (int cc = 0; cc < CH_CHUNKS; ++cc) {
+          const int c = lane + 64 * cc;
+          if (c < m && c >= r) row[c] = v[h][cc] * rr * rsc[c] + (c == r ? shift : 0.0);
+          if (c < rend) row[m + c] = c == r ? 1.0 : 0.0;
+        }
+      }
+    }
+    for (int j = tid; j < m; j += nt) colsum[j] = 0.0;
+    if (tid == 0) s_fail = 0;
+    pjb = 0;
+    grid.sync();
+
+    for (int j0 = 0; j0 < m; j0 += NB) {
+      const int jb = min(NB, m - j0);
+      if (pjb) store_right(pj0, pjb);
+      for (int idx = tid; idx < NB * NB; idx += nt) {
+        const int a = idx / NB, b = idx % NB;
+        D[a * (NB + 1) + b] = (b < jb && a <= b) ? W[(int64_t)(j0 + a) * m2 + j0 + b] : 0.0;
+      }
+      __syncthreads();
+      if (tid < 64) chol_diag_wave(D, xrow, nullptr, m2, j0, jb, tid, need_more ? colsum : nullptr, &s_fail);
+      __syncthreads();
+      if (s_fail) break;
+      // row panel of the whole block row (every workgroup), into LDS only
+      const int nleft = m - j0 - jb;
+      for (int ct = wv; ct < (m + 15) / 16; ct += nw) {
+        const int pc = 16 * ct + (lane & 15);
+        const bool okc = pc < m;
+        const int64_t col = pc < nleft ? (int64_t)(j0 + jb + pc) : (int64_t)m + (pc - nleft);
+        double bv[NB / 4];
+#pragma unroll
+        for (int kk = 0; kk < NB / 4; ++kk) {
+          const int k = 4 * kk + (lane >> 4);
+          bv[kk] = (okc && k < jb) ? W[(int64_t)(j0 + k) * m2 + col] : 0.0;
+        }
+        doublex4 x0 = {0.0, 0.0, 0.0, 0.0}, x1 = x0;
+#pragma unroll
+        for (int kk = 0; kk < NB / 4; ++kk) {
+          const int k = 4 * kk + (lane >> 4);
+          x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(D[(lane & 15) * (NB + 1) + k], bv[kk], x0, 0, 0, 0);
+          x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(D[(16 + (lane & 15)) * (NB + 1) + k], bv[kk], x1, 0, 0, 0);
+        }
+        double cs = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i0 = (lane >> 4) + 4 * q, i1 = i0 + 16;
+          if (okc) {
+            P[i0 * m + pc] = x0[q];
+            P[i1 * m + pc] = x1[q];
+          }
+          cs += fabs(x0[q]) + fabs(x1[q]);
+        }
+        if (need_more) {
+          cs += __shfl_xor(cs, 16, 64);
+          cs += __shfl_xor(cs, 32, 64);
+          if (lane < 16 && pc < nleft) colsum[col] += cs;
+        }
+      }
+      __syncthreads();
+      // trailing update: the live tiles over every wavefront of the grid
+      {
+        const int nrows = nleft;
+        const int tr_n = (nrows + 15) / 16, tc_n = (m + 15) / 16;
+        const int FL = nleft / 16;
+        int nlive = 0;
+        for (int tr = 0; tr < tr_n; ++tr) nlive += tc_n - min(tr, FL);
+        constexpr int UT = 4;
+        for (int base = UT * gw; base < nlive; base += UT * gnw) {
+          doublex4 acc[UT];
+          int64_t gofs[UT][4];
+          bool ok[UT][4];
+          bool live[UT];
+          int pras[UT], pcs[UT];
+#pragma unroll
+          for (int u = 0; u < UT; ++u) {
+            int li = base + u;
+            live[u] = li < nlive;
+            if (!live[u]) li = 0;
+            int tr = 0, len = tc_n;
+            while (li >= len) { li -= len; ++tr; len = tc_n - min(tr, FL); }
+            const int tc = min(tr, FL) + li;
+            pras[u] = 16 * tr + (lane & 15);
+            const int pc = 16 * tc + (lane & 15);
+            pcs[u] = pc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int pr = 16 * tr + (lane >> 4) + 4 * q;
+              ok[u][q] = live[u] && pr < nrows && pc < m && (pc >= nleft || pc >= pr);
+              const int64_t col = pc < nleft ? (int64_t)(j0 + jb + pc) : (int64_t)m + (pc - nleft);
+              gofs[u][q] = (int64_t)(j0 + jb + pr) * m2 + col;
+              acc[u][q] = ok[u][q] ? W[gofs[u][q]] : 0.0;
+            }
+          }
+#pragma unroll
+          for (int k0 = 0; k0 < NB; k0 += 4) {
+            const int t = k0 + (lane >> 4);
+#pragma unroll
+            for (int u = 0; u < UT; ++u) {
+              const double av = (live[u] && pras[u] < nrows) ? -P[t * m + pras[u]] : 0.0;
+              const double bv = (live[u] && pcs[u] < m) ? P[t * m + pcs[u]] : 0.0;
+              acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < UT; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (ok[u][q]) W[gofs[u][q]] = acc[u][q];
+        }
+      }
+      pj0 = j0;
+      pjb = jb;
+      grid.sync();
+    }
+    if (!s_fail) break;
+    // every workgroup saw the same failed pivot: retry once with the shift
+    if (wg == 0 && tid == 0) atomicOr(flags, attempt == 0 ? SKETCHNE_FLAG_CHOL_SHIFT : SKETCHNE_FLAG_CHOL_FAIL);
+    if (tid == 0) s_shifted = 1;
+    grid.sync();  // no workgroup still reads W before it is initialised again
+  }
+  if (!s_fail && pjb) store_right(pj0, pjb);
+  grid.sync();
+  // R^-T = Rs^-T S^-1 from the lower triangle of the right half, rows over
+  // the wavefronts of the grid; the largest row sum of |Rs^-T| per workgroup
+  double rmax = 0.0;
+  for (int r0 = 4 * gw; r0 < m; r0 += 4 * gnw) {
+    double x[4][CH_CHUNKS];
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int cc = 0; cc < CH_CHUNKS; ++cc) {
+        const int r = r0 + h, c = lane + 64 * cc;
+        x[h][cc] = (r < m && c <= r) ? W[(int64_t)r * m2 + m + c] : 0.0;
+      }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int r = r0 + h;
+      if (r >= m) break;
+      double rs = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < CH_CHUNKS; ++cc) {
+        const int c = lane + 64 * cc;
+        if (c < m) RinvT[(int64_t)r * m + c] = x[h][cc] * rsc[c];
+        rs += fabs(x[h][cc]);
+      }
+      rmax = fmax(rmax, wave_sum(rs));
+    }
+  }
+  if (need_more) {
+    if (lane == 0) s_red[1][wv] = rmax;
+    __syncthreads();
+    if (tid == 0) {
+      double b = 0.0;
+      for (int w = 0; w < nw; ++w) b = fmax(b, s_red[1][w]);
+      rpart[wg] = b;
+    }
+    grid.sync();
+    if (wg == 0) {
+      // kappa_1(Rs) = ||Rs||_1 ||Rs^-1||_1 (column sums of Rs gathered in
+      // every workgroup's LDS, row sums of Rs^-T from all workgroups)
+      double cmax = 0.0;
+      for (int j = tid; j < m; j += nt) cmax = fmax(cmax, colsum[j]);
+      cmax = wave_max(cmax);
+      if (lane == 0) s_red[0][wv] = cmax;
+      __syncthreads();
+      if (tid == 0) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < nw; ++w) a = fmax(a, s_red[0][w]);
+        for (int w = 0; w < nwg; ++w) b = fmax(b, rpart[w]);
+        const double kappa = a * b;
+        *need_more = (s_shifted || !(kappa <= repeat_kappa)) ? 1 : 0;
+      }
+    }
+  }
+}
+
 }  // namespace
 
-size_t chol_ws_bytes(int m) { return align_up(sizeof(double) * (size_t)m * 2 * m); }
+// W (m x 2m), then one slot per workgroup of the cooperative form
+constexpr int CHC_MAXWG = 8;
+size_t chol_ws_bytes(int m) { return align_up(sizeof(double) * ((size_t)m * 2 * m + CHC_MAXWG)); }
 
 sketchne_status copy_if(sketchne_ctx* c, int64_t count, const float* src, float* dst, const int* run_if) {
   if (count == 0) return SKETCHNE_OK;
@@ -780,10 +1101,31 @@ sketchne_status chol_inv(sketchne_ctx* c, int m, const double* G, double* RinvT,
   if (m > CH_MAXM) return SKETCHNE_E_UNSUPPORTED;
   ProfScope ps(c, SKETCHNE_PROF_SMALL);
   size_t shmem = sizeof(double) * (NB * (NB + 1) + (size_t)NB * m);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_inv), hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)shmem);
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(512), shmem, c->stream, m, G, work, RinvT, c->d_flags, need_more,
-                     run_if, repeat_kappa);
+  if (m <= 2 * NB) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_inv), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)shmem);
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(512), shmem, c->stream, m, G, work, RinvT, c->d_flags, need_more,
+                       run_if, repeat_kappa);
+    return launch_status();
+  }
+  // workgroups: the first (largest) trailing update in passes of four tiles
+  // per wavefront, eight wavefronts per workgroup
+  const int nleft0 = m - NB, tr_n = (nleft0 + 15) / 16, tc_n = (m + 15) / 16, FL = nleft0 / 16;
+  int nlive0 = 0;
+  for (int tr = 0; tr < tr_n; ++tr) nlive0 += tc_n - (tr < FL ? tr : FL);
+  int nwg = (nlive0 + 31) / 32;
+  nwg = nwg < 2 ? 2 : (nwg > CHC_MAXWG ? CHC_MAXWG : nwg);
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_inv_coop), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)shmem) != hipSuccess)
+    return SKETCHNE_E_DEVICE;
+  double* W = work;
+  double* rpart = work + (size_t)m * 2 * m;
+  uint32_t* flags = c->d_flags;
+  int m_arg = m;
+  void* args[] = {&m_arg, &G, &W, &rpart, &RinvT, &flags, &need_more, &run_if, &repeat_kappa};
+  if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_chol_inv_coop), dim3(nwg), dim3(512), args,
+                                 (unsigned)shmem, c->stream) != hipSuccess)
+    return SKETCHNE_E_DEVICE;
   return launch_status();
 }
 
