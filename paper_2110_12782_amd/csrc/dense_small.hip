@@ -53,7 +53,7 @@ __device__ __forceinline__ double wave_max(double v) {
 // have written R_JJ to W (unless W is null) (and added the column sums of |R_JJ| to colsum when
 // it is non-null), and D holds R_JJ^-T, padded with the identity.  Sets
 // *fail when a pivot is not positive.
-__device__ void chol_diag_wave(double* D, double* xrow, double* W, int64_t m2, int j0, int jb, int lane,
+__device__ __forceinline__ void chol_diag_wave(double* D, double* xrow, double* W, int64_t m2, int j0, int jb, int lane,
                                double* colsum, int* fail) {
   const int b = lane & (NB - 1);
   const bool right = lane >= NB;
@@ -77,8 +77,19 @@ __device__ void chol_diag_wave(double* D, double* xrow, double* W, int64_t m2, i
     // take the same unconditional operations as the rest)
     c[t] = (!right && b == t) ? d : c[t] * rd;
     xrow[lane] = c[t];  // row t of [R_JJ | R_JJ^-T]
+    // read back the part of the row this step needs, every 16-byte read
+    // issued before the first use (one LDS round trip per step)
+    double xr[NB];
 #pragma unroll
-    for (int a = t + 1; a < NB; ++a) c[a] = fma(-xrow[a], c[t], c[a]);  // xrow[a] = R(t, a)
+    for (int a = (t + 1) & ~1; a < NB; a += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(xrow + a);
+      xr[a] = v.x;
+      xr[a + 1] = v.y;
+    }
+    __builtin_amdgcn_sched_group_barrier(0x100, NB / 2, 0);  // the DS reads first (at most NB / 2)
+    __builtin_amdgcn_sched_group_barrier(0x002, NB, 0);      // then the FMAs
+#pragma unroll
+    for (int a = t + 1; a < NB; ++a) c[a] = fma(-xr[a], c[t], c[a]);  // xr[a] = R(t, a)
   }
   if (!right) {
     if (b < jb) {
@@ -115,7 +126,7 @@ __global__ __launch_bounds__(512) void k_chol_inv(int m, const double* __restric
   double* P = smem + NB * (NB + 1);  // NB x m panel
   __shared__ double rsc[CH_MAXM];     // 1 / sqrt(G_ii) (1 for a zero or invalid diagonal)
   __shared__ double colsum[CH_MAXM];  // column sums of |Rs|, added as block rows of Rs are finished
-  __shared__ double xrow[64];         // row exchange of the diagonal-block factorization
+  __shared__ __attribute__((aligned(16))) double xrow[64];         // row exchange of the diagonal-block factorization
   __shared__ double s_red[2][8];
   __shared__ int s_fail;
   __shared__ int s_shifted;
@@ -717,22 +728,38 @@ __global__ __launch_bounds__(OJ_THREADS) void k_oj_sweeps(int nb, double* __rest
 
 // lambda_j = ||g_j|| - c and v_j = g_j / ||g_j||; sort by |lambda| desc
 // (ties: lambda desc, then index); write w and the eigenvectors as the
-// columns of the row-major Vout.
+// columns of the row-major Vout.  Workgroup b writes rows 32 b .. 32 b + 31
+// of Vout: every workgroup computes all norms and the order itself (a few
+// microseconds), then moves the 32-row segments of every column (256-byte
+// reads) through LDS and writes whole output rows.
+constexpr int OJF_ROWS = 32;  // output rows per workgroup
 __global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restrict__ G,
                                                     const double* __restrict__ shift, const int* __restrict__ counters,
                                                     int sweeps_run, double* __restrict__ Vout,
                                                     double* __restrict__ wout, uint32_t* __restrict__ flags) {
-  __shared__ double w[1024];
-  __shared__ double inv[1024];
-  __shared__ int perm[1024];  // perm[p] = column of G that goes to position p
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwv = blockDim.x >> 6;
-  if (tid == 0) {
+  extern __shared__ __attribute__((aligned(16))) double tile[];  // m x OJF_ROWS, row stride OJF_ROWS + 1
+  __shared__ double w[OJ_ROWS];
+  __shared__ double inv[OJ_ROWS];
+  __shared__ int perm[OJ_ROWS];  // perm[p] = column of G that goes to position p
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwv = blockDim.x >> 6, nt = blockDim.x;
+  const bool lead = blockIdx.x == 0;
+  const int r0 = OJF_ROWS * blockIdx.x;
+  if (lead && tid == 0) {
     bool conv = false;
     for (int s = 0; s < sweeps_run; ++s)
       if (counters[kMaxSweeps + s] == 0) { conv = true; break; }
     if (!conv) atomicOr(flags, SKETCHNE_FLAG_EIG_NOCONV);
   }
   const double cs = *shift;
+  // this workgroup's row segments: issued first, stored to LDS after the norms
+  constexpr int TB = (OJ_ROWS * OJF_ROWS + 1023) / 1024;
+  double seg[TB];
+#pragma unroll
+  for (int u = 0; u < TB; ++u) {
+    const int idx = tid + nt * u;
+    const int j = idx / OJF_ROWS, rr = idx - j * OJF_ROWS;
+    seg[u] = (j < m && r0 + rr < m) ? G[(int64_t)j * OJ_ROWS + r0 + rr] : 0.0;
+  }
   // column norms: a wavefront takes three columns at a time, all their loads
   // in flight
   constexpr int RPL = (OJ_ROWS + 63) / 64;  // rows per lane
@@ -756,12 +783,18 @@ __global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restr
         const double nrm = sqrt(d);
         w[j] = nrm - cs;
         inv[j] = nrm > 0.0 ? 1.0 / nrm : 0.0;
-        if (!isfinite(w[j])) atomicOr(flags, SKETCHNE_FLAG_NONFINITE);
+        if (lead && !isfinite(w[j])) atomicOr(flags, SKETCHNE_FLAG_NONFINITE);
       }
     }
   }
+#pragma unroll
+  for (int u = 0; u < TB; ++u) {
+    const int idx = tid + nt * u;
+    const int j = idx / OJF_ROWS, rr = idx - j * OJF_ROWS;
+    if (j < m) tile[j * (OJF_ROWS + 1) + rr] = seg[u];
+  }
   __syncthreads();
-  for (int i = tid; i < m; i += blockDim.x) {
+  for (int i = tid; i < m; i += nt) {
     double ai = fabs(w[i]);
     int rk = 0;
     for (int j = 0; j < m; ++j) {
@@ -770,33 +803,17 @@ __global__ __launch_bounds__(1024) void k_oj_finish(int m, const double* __restr
       rk += before ? 1 : 0;
     }
     perm[rk] = i;
-    wout[rk] = w[i];
+    if (lead) wout[rk] = w[i];
   }
   __syncthreads();
-  // Vout[r][p] = G[perm[p]][r] / ||g||: consecutive threads write consecutive
-  // entries of a row; eight entries in flight per thread
-  constexpr int BATCH = 8;
-  const int mm = m * m, nt = blockDim.x;
-  for (int base = tid; base < mm; base += nt * BATCH) {
-    double v[BATCH];
-#pragma unroll
-    for (int u = 0; u < BATCH; ++u) {
-      const int idx = base + nt * u;
-      const int r = idx / m, p = idx - r * m;
-      double x = 0.0;
-      if (idx < mm) {
-        const int j = perm[p];
-        const double s = inv[j];
-        // a zero matrix (c = 0) has G = 0: its eigenvectors are the unit vectors
-        x = s > 0.0 ? G[(int64_t)j * OJ_ROWS + r] * s : (r == j ? 1.0 : 0.0);
-      }
-      v[u] = x;
-    }
-#pragma unroll
-    for (int u = 0; u < BATCH; ++u) {
-      const int idx = base + nt * u;
-      if (idx < mm) Vout[idx] = v[u];
-    }
+  // Vout[r][p] = G[perm[p]][r] / ||g||, consecutive threads along a row
+  for (int idx = tid; idx < OJF_ROWS * m; idx += nt) {
+    const int rr = idx / m, p = idx - rr * m, r = r0 + rr;
+    if (r >= m) break;
+    const int j = perm[p];
+    const double s = inv[j];
+    // a zero matrix (c = 0) has G = 0: its eigenvectors are the unit vectors
+    Vout[(int64_t)r * m + p] = s > 0.0 ? tile[j * (OJF_ROWS + 1) + rr] * s : (r == j ? 1.0 : 0.0);
   }
 }
 
@@ -849,7 +866,7 @@ __global__ __launch_bounds__(512) void k_chol_inv_coop(int m, const double* __re
   double* P = smem + NB * (NB + 1);  // NB x m panel
   __shared__ double rsc[CH_MAXM];
   __shared__ double colsum[CH_MAXM];
-  __shared__ double xrow[64];
+  __shared__ __attribute__((aligned(16))) double xrow[64];
   __shared__ double s_red[2][8];
   __shared__ int s_fail;
   __shared__ int s_shifted;
@@ -1211,8 +1228,12 @@ sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* Vout, do
   // every sweep slot not reached keeps its zero count, so the finish kernel's
   // convergence test may scan them all
   const int run = kMaxSweeps;
-  hipLaunchKernelGGL(k_oj_finish, dim3(1), dim3(1024), 0, c->stream, m, G, shift, counters, run, Vout, wout,
-                     c->d_flags);
+  const size_t sh_fin = sizeof(double) * (size_t)m * (OJF_ROWS + 1);
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_oj_finish), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)sh_fin) != hipSuccess)
+    return SKETCHNE_E_DEVICE;
+  hipLaunchKernelGGL(k_oj_finish, dim3((unsigned)((m + OJF_ROWS - 1) / OJF_ROWS)), dim3(1024), sh_fin, c->stream, m,
+                     G, shift, counters, run, Vout, wout, c->d_flags);
   return launch_status();
 }
 
