@@ -7,10 +7,10 @@
 // U^T D U).  Each workgroup owns a contiguous range of rows: it (512 threads)
 // streams them through LDS in chunks of 32 rows (double buffered, next chunk
 // prefetched through registers) and keeps the accumulators of its share of
-// the upper blocks of the m x m result in registers, grouped in 2 x 2
-// super-tiles.  The super-tiles are split into two groups handled by two
-// workgroups on the same XCD, so the rows are read from memory once and from
-// the XCD's L2 the second time.  Per-workgroup partial sums are added in a
+// the upper 16 x 16 blocks of the m x m result in registers.  The blocks are
+// dealt one by one to the sixteen wavefronts of two workgroups on the same
+// XCD (so the rows are read from memory once and from the XCD's L2 the
+// second time): m = 288 has 171 upper blocks, 11 per wavefront at most.  Per-workgroup partial sums are added in a
 // fixed order by a second kernel.  The F32 form runs the FP32 matrix cores
 // (v_mfma_f32_16x16x4f32: twice the FP64 rate, no conversion of the rows) and
 // keeps FP32 partial sums per workgroup; it serves the Cholesky-QR of
@@ -31,6 +31,13 @@ constexpr int GR_MAXB = 18;       // m <= 16 * GR_MAXB
 constexpr int GR_GROUPS = 2;      // block groups (workgroups per row range)
 constexpr int GR_THREADS = 512;
 constexpr int GR_WAVES = GR_THREADS / 64;
+// LDS row stride of a row-major chunk: room for 288 columns, 48 floats past
+// a multiple of 64 so the 4 rows read by one MFMA fragment fall in distinct
+// banks; a compile-time stride turns every row step into an immediate offset
+constexpr int GR_RSTRIDE = 304;
+// column-major chunks are stored [column][row]: GR_CHUNK + 2 floats per
+// column, so the 16 columns x 2 rows a half-wave reads fall in distinct banks
+constexpr int GR_CSTRIDE = 34;
 
 struct GramArgs {
   int64_t n;
@@ -41,7 +48,6 @@ struct GramArgs {
   int64_t rows_per_wg;
   int nranges;                  // row ranges
   int crows;                    // !ROWMAJ: rows of a chunk buffer (one per matrix column i, padded)
-  int gsize;                    // blocks per group
   double* partial;              // nranges x nblk x 256
   const int* run_if;            // when non-null and zero: do nothing
 };
@@ -53,16 +59,15 @@ __device__ __forceinline__ void blk_coords(int b, int nbk, int& I, int& J) {
   J = r + b;
 }
 
-// The upper triangle of 16 x 16 blocks is covered by 2 x 2 "super-tiles"
-// (blocks 2pi, 2pi+1 x 2pj, 2pj+1 with pi <= pj; the one lower block of a
-// diagonal super-tile is computed and dropped).  A wavefront takes up to
-// GS_SLOTS super-tiles of its group, so one row step reads two A and two B
-// fragments for four MFMAs (register blocking; eight fragments for four
-// unrelated blocks took 35% longer).  ROWMAJ: X and Y rows are contiguous
-// (xc == 1); else columns are (xr == 1).
-constexpr int GS_SLOTS = 3;
+// Wavefront g (0..15 over the two workgroups of a row range) takes the upper
+// blocks g, g + 16, g + 32, ... of the row-by-row enumeration; a slot past
+// the last block repeats the wavefront's first block and is not stored.
+// (2 x 2 super-tiles of blocks, which share fragment reads, cost 12% more
+// MFMA work at m = 288 from the lower block of each diagonal super-tile and
+// from uneven shares, 17% at m = 272 and 33% at m = 256.)
+constexpr int GR_WG = GR_GROUPS * GR_WAVES;  // wavefronts per row range
 
-template <bool TWO, bool ROWMAJ, bool F32 = false>
+template <bool TWO, bool ROWMAJ, bool F32, int NSL>
 __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
   typedef std::conditional_t<F32, floatx4, doublex4> Acc;
   if (g.run_if && *g.run_if == 0) return;
@@ -76,9 +81,9 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
   // chunk buffers: ROWMAJ [data row][column i] (row stride S); otherwise
   // [column i][data row] (stride S = GR_CHUNK + 2), so that a column-major
   // input is stored as it is read, without a transposing scatter
-  const int S = g.stride;
+  constexpr int S = ROWMAJ ? GR_RSTRIDE : GR_CSTRIDE;
   const int CH = ROWMAJ ? GR_CHUNK * S : g.crows * S;
-  const int rstep = ROWMAJ ? S : 1, cstep = ROWMAJ ? 1 : S;
+  constexpr int rstep = ROWMAJ ? S : 1, cstep = ROWMAJ ? 1 : S;
   // the two chunk buffers as offsets from the LDS array itself (an array of
   // pointers indexed at run time would lose the LDS address space, and every
   // fragment read would become a FLAT load waiting on the row prefetch)
@@ -89,25 +94,19 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
   const int64_t r0 = (int64_t)range * g.rows_per_wg;
   const int64_t r1 = min(g.n, r0 + g.rows_per_wg);
 
-  // super-tiles of this wavefront: st0 + wave + GR_WAVES t (past the group:
-  // a copy of its first super-tile, not stored)
-  const int npair = (g.nbk + 1) / 2;
-  const int nst = npair * (npair + 1) / 2;
+  // blocks of this wavefront
   const int uw = __builtin_amdgcn_readfirstlane(wave);
-  const int st0 = grp * g.gsize;
-  const int st1 = min(nst, st0 + g.gsize);
-  int pI[GS_SLOTS], pJ[GS_SLOTS];
+  const int gw = grp * GR_WAVES + uw;
+  int pI[NSL], pJ[NSL];
 #pragma unroll
-  for (int t = 0; t < GS_SLOTS; ++t) {
-    int st = st0 + uw + GR_WAVES * t;
-    if (st >= st1) st = st0;
-    blk_coords(st, npair, pI[t], pJ[t]);
+  for (int t = 0; t < NSL; ++t) {
+    int b = gw + GR_WG * t;
+    if (b >= g.nblk) b = gw < g.nblk ? gw : 0;
+    blk_coords(b, g.nbk, pI[t], pJ[t]);
   }
-  Acc acc[GS_SLOTS][4];
+  Acc acc[NSL];
 #pragma unroll
-  for (int t = 0; t < GS_SLOTS; ++t)
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc[t][u] = Acc{0, 0, 0, 0};
+  for (int t = 0; t < NSL; ++t) acc[t] = Acc{0, 0, 0, 0};
 
   const int cols4 = (g.m + 3) / 4;
   constexpr int MAXV = (GR_CHUNK * GR_MAXB * 16 / 4 + GR_THREADS - 1) / GR_THREADS;
@@ -198,35 +197,29 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
   for (int64_t c0 = r0; c0 < r1; c0 += GR_CHUNK) {
     const bool more = c0 + GR_CHUNK < r1;
     if (more) fetch(c0 + GR_CHUNK);
-    const float* xs = lds + offX(buf);
-    const float* ys = lds + offY(buf);
-#pragma unroll 2
-    for (int st = 0; st < GR_CHUNK / 4; ++st) {
-      const int rr = 4 * st + (lane >> 4);
-      const double wr = g.w ? wsh[buf][rr] : 1.0;
-      const float* xr = xs + rr * rstep + (lane & 15) * cstep;
-      const float* yr = ys + rr * rstep + (lane & 15) * cstep;
+    // this lane's fragment address in each slot's blocks; the row steps of
+    // the chunk are compile-time offsets from it
+    const float* xa[NSL];
+    const float* ya[NSL];
 #pragma unroll
-      for (int t = 0; t < GS_SLOTS; ++t) {
+    for (int t = 0; t < NSL; ++t) {
+      xa[t] = lds + offX(buf) + (lane >> 4) * rstep + ((lane & 15) + 16 * pI[t]) * cstep;
+      ya[t] = lds + offY(buf) + (lane >> 4) * rstep + ((lane & 15) + 16 * pJ[t]) * cstep;
+    }
+#pragma unroll
+    for (int st = 0; st < GR_CHUNK / 4; ++st) {
+      const double wr = g.w ? wsh[buf][4 * st + (lane >> 4)] : 1.0;
+#pragma unroll
+      for (int t = 0; t < NSL; ++t) {
         if constexpr (F32) {
-          const float fw = (float)wr;
-          const float a0 = g.w ? xr[32 * pI[t] * cstep] * fw : xr[32 * pI[t] * cstep];
-          const float a1 = g.w ? xr[(32 * pI[t] + 16) * cstep] * fw : xr[(32 * pI[t] + 16) * cstep];
-          const float b0 = yr[32 * pJ[t] * cstep];
-          const float b1 = yr[(32 * pJ[t] + 16) * cstep];
-          acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[t][0], 0, 0, 0);
-          acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[t][1], 0, 0, 0);
-          acc[t][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[t][2], 0, 0, 0);
-          acc[t][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[t][3], 0, 0, 0);
+          const float a0 = xa[t][4 * st * rstep];
+          const float a = g.w ? a0 * (float)wr : a0;
+          const float b = ya[t][4 * st * rstep];
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
         } else {
-          const double a0 = (double)xr[32 * pI[t] * cstep] * wr;
-          const double a1 = (double)xr[(32 * pI[t] + 16) * cstep] * wr;
-          const double b0 = (double)yr[32 * pJ[t] * cstep];
-          const double b1 = (double)yr[(32 * pJ[t] + 16) * cstep];
-          acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[t][0], 0, 0, 0);
-          acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[t][1], 0, 0, 0);
-          acc[t][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[t][2], 0, 0, 0);
-          acc[t][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[t][3], 0, 0, 0);
+          const double a = (double)xa[t][4 * st * rstep] * wr;
+          const double b = (double)ya[t][4 * st * rstep];
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
         }
       }
     }
@@ -236,28 +229,22 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
   }
   double* part = g.partial + (int64_t)range * g.nblk * 256;
 #pragma unroll
-  for (int t = 0; t < GS_SLOTS; ++t) {
-    const int st = st0 + uw + GR_WAVES * t;
-    if (st >= st1) continue;
+  for (int t = 0; t < NSL; ++t) {
+    const int b = gw + GR_WG * t;
+    if (b >= g.nblk) continue;
+    if constexpr (F32) {
+      // v_mfma_f32_16x16x4f32 holds row 4 (l / 16) + r, column l % 16 in
+      // lane l, register r; the partial keeps the FP64 form's order
+      // (row l' / 16 + 4 r', column l' % 16 at element 4 l' + r')
+      double* pb = part + (int64_t)b * 256;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int I = 2 * pI[t] + (u >> 1), J = 2 * pJ[t] + (u & 1);
-      if (I > J || J >= g.nbk) continue;
-      const int b = I * g.nbk - I * (I - 1) / 2 + (J - I);  // index of (I, J) in the upper enumeration
-      if constexpr (F32) {
-        // v_mfma_f32_16x16x4f32 holds row 4 (l / 16) + r, column l % 16 in
-        // lane l, register r; the partial keeps the FP64 form's order
-        // (row l' / 16 + 4 r', column l' % 16 at element 4 l' + r')
-        double* pb = part + (int64_t)b * 256;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) pb[4 * ((lane & 15) + 16 * r) + (lane >> 4)] = (double)acc[t][u][r];
-      } else {
-        double* pb = part + (int64_t)b * 256 + lane * 4;
-        pb[0] = acc[t][u][0];
-        pb[1] = acc[t][u][1];
-        pb[2] = acc[t][u][2];
-        pb[3] = acc[t][u][3];
-      }
+      for (int r = 0; r < 4; ++r) pb[4 * ((lane & 15) + 16 * r) + (lane >> 4)] = (double)acc[t][r];
+    } else {
+      double* pb = part + (int64_t)b * 256 + lane * 4;
+      pb[0] = acc[t][0];
+      pb[1] = acc[t][1];
+      pb[2] = acc[t][2];
+      pb[3] = acc[t][3];
     }
   }
 }
@@ -319,15 +306,8 @@ sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int
   g.m = m;
   g.nbk = (m + 15) / 16;
   g.nblk = g.nbk * (g.nbk + 1) / 2;
-  // LDS row length: room for whole super-tiles (32 columns each), moved off
-  // multiples of 32 floats so the 4 rows read by one MFMA fragment fall in
-  // distinct banks
-  g.stride = (m + 31) / 32 * 32;
-  if (g.stride % 64 == 0 || g.stride % 64 == 32) g.stride += 16;
-  // column-major input: [column][row] buffers of GR_CHUNK + 2 floats per
-  // column (the 16 columns x 2 rows a half-wave reads fall in distinct banks)
-  g.crows = 32 * ((g.nbk + 1) / 2);
-  if (!rowmaj) g.stride = GR_CHUNK + 2;
+  g.stride = rowmaj ? GR_RSTRIDE : GR_CSTRIDE;
+  g.crows = 16 * g.nbk;  // column-major buffers: one LDS row per matrix column
   g.X = X; g.xr = xr; g.xc = xc;
   g.Y = Y ? Y : X; g.yr = Y ? yr : xr; g.yc = Y ? yc : xc;
   g.w = w;
@@ -335,25 +315,36 @@ sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int
   int64_t rpw = (n + nr - 1) / nr;
   g.rows_per_wg = (rpw + GR_CHUNK - 1) / GR_CHUNK * GR_CHUNK;
   g.nranges = nr;
-  const int npair = (g.nbk + 1) / 2;
-  const int nst = npair * (npair + 1) / 2;
-  g.gsize = (nst + GR_GROUPS - 1) / GR_GROUPS;  // super-tiles per group
-  if (g.gsize > GR_WAVES * GS_SLOTS) return SKETCHNE_E_UNSUPPORTED;
+  // blocks per wavefront (instantiated for 3, 6, 9, 10 and 11)
+  const int need = (g.nblk + GR_WG - 1) / GR_WG;
+  const int nsl = need <= 3 ? 3 : need <= 6 ? 6 : need <= 9 ? 9 : need <= 10 ? 10 : 11;
+  if (need > 11) return SKETCHNE_E_UNSUPPORTED;
   g.partial = partial;
   g.run_if = run_if;
   const bool two = Y != nullptr;
   const size_t shmem = sizeof(float) * (size_t)2 * (two ? 2 : 1) * (rowmaj ? GR_CHUNK : g.crows) * g.stride;
   const unsigned blocks = (unsigned)((nr + 7) / 8 * 8 * GR_GROUPS);
   ProfScope ps(c, SKETCHNE_PROF_GEMM64);
+#define SKNE_GRAM_N(T, R, F, N)                                                                            \
+  do {                                                                                                     \
+    hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_st<T, R, F, N>),                              \
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);                           \
+    hipLaunchKernelGGL((k_gram_st<T, R, F, N>), dim3(blocks), dim3(GR_THREADS), shmem, c->stream, g);      \
+  } while (0)
 #define SKNE_GRAM(T, R, F)                                                                                 \
   do {                                                                                                     \
-    hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_st<T, R, F>),                                 \
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);                           \
-    hipLaunchKernelGGL((k_gram_st<T, R, F>), dim3(blocks), dim3(GR_THREADS), shmem, c->stream, g);         \
+    switch (nsl) {                                                                                         \
+      case 3: SKNE_GRAM_N(T, R, F, 3); break;                                                              \
+      case 6: SKNE_GRAM_N(T, R, F, 6); break;                                                              \
+      case 9: SKNE_GRAM_N(T, R, F, 9); break;                                                              \
+      case 10: SKNE_GRAM_N(T, R, F, 10); break;                                                            \
+      default: SKNE_GRAM_N(T, R, F, 11); break;                                                            \
+    }                                                                                                      \
   } while (0)
   if (f32 && !two && rowmaj) SKNE_GRAM(false, true, true);
   else if (two) { if (rowmaj) SKNE_GRAM(true, true, false); else SKNE_GRAM(true, false, false); }
   else { if (rowmaj) SKNE_GRAM(false, true, false); else SKNE_GRAM(false, false, false); }
+#undef SKNE_GRAM_N
 #undef SKNE_GRAM
   hipLaunchKernelGGL(k_gram_reduce, dim3((g.nblk * 256 + 255) / 256), dim3(256), 0, c->stream, m, g.nbk, g.nblk, nr,
                      partial, G, run_if);
