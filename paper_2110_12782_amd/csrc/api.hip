@@ -50,6 +50,7 @@ struct OrthWs {
   double* RinvT;
   double* cwork;
   int* need2;
+  float* B32;  // FP32 copy of an m x m apply operand (the FP32 applies)
 };
 
 GemmDesc apply_desc(int64_t n, int m, const float* X, int64_t ld, bool transposed, const double* RinvT, float* out) {
@@ -87,6 +88,7 @@ OrthWs carve_orth(Arena& ar, int64_t n, int m, bool transposed) {
   w.RinvT = ar.take<double>((size_t)m * m);
   w.cwork = ar.take<double>(chol_ws_bytes(m) / sizeof(double) + 1);
   w.need2 = ar.take<int>(1);
+  w.B32 = ar.take<float>((size_t)m * m);
   return w;
 }
 
@@ -96,6 +98,7 @@ sketchne_status apply_rinv(sketchne_ctx* c, int64_t n, int m, const float* src, 
                            const double* RinvT, float* dst, const OrthWs& w, const int* run_if, bool f32 = false) {
   ApplyDesc d;
   d.f32 = f32;
+  d.b32 = w.B32;
   d.n = n; d.K = m; d.N = m;
   d.A = src; d.lda = ld; d.acol = transposed;
   // R^-1(k, j) = RinvT[j][k]: column-major reads of B (measured faster here
@@ -525,6 +528,7 @@ static sketchne_status eig_impl(sketchne_ctx* c, const sketchne_graph* A, const 
   // rounding (U is stored in FP32 either way)
   ApplyDesc ad;
   ad.f32 = true;
+  ad.b32 = w.ow.B32;  // K x K floats, free once the last basis is formed
   ad.n = n; ad.K = K; ad.N = p->k;
   ad.A = w.Q; ad.lda = K;
   ad.B = w.Vh; ad.ldb = K;

@@ -16,12 +16,17 @@
 // F32 selects the FP32 matrix cores (v_mfma_f32_16x16x4f32, FP32 operands in
 // LDS, B rounded to FP32): twice the FP64 rate and half the LDS bytes, for the
 // applies whose result only has to span the right space (the power-iteration
-// bases of Alg. 5), not to be accurate to FP64 working precision.
+// bases of Alg. 5), not to be accurate to FP64 working precision.  This form
+// reads B from an FP32 copy made just before the launch, so the chunk held in
+// registers takes half the VGPRs and four wavefronts fit per SIMD (two
+// workgroups per CU) instead of two.
 //
 // 8 wavefronts: wave w owns rows 32 (w & 3) .. +32 (two 16-row MFMA blocks)
 // and the column blocks (16 columns each) of parity w >> 2, i.e. 2 x NBH
 // v_mfma_f64_16x16x4f64 accumulators; interleaving the blocks keeps the two
 // halves equally loaded when a triangular B skips blocks.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace skne {
@@ -62,7 +67,14 @@ struct ApplyArgs {
   const double* B; int64_t ldb;
   float* C; int64_t ldc;
   const int* run_if;
+  const float* B32;  // the FP32 form's copy of B (same layout)
 };
+
+// FP32 copy of a B given by `rows` strided rows of ldb doubles
+__global__ void k_b_to_f32(int64_t count, const double* __restrict__ B, float* __restrict__ B32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) B32[i] = (float)B[i];
+}
 
 // One chunk's products for the wave's column blocks 2t + ch, t = T0 .. NBH-1,
 // k-steps in order, as straight-line code.
@@ -97,7 +109,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 // (else B[k*ldb + j]); CCOL: C(i,j) = C[j*ldc + i] (else C[i*ldc + j]);
 // TRI: B(k,j) = 0 for k > j.
 template <int NBH, bool ACOL, bool BCOL, bool CCOL, bool TRI, bool F32 = false>
-__global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(F32 ? 4 : 1))) void k_apply_tall(ApplyArgs g) {
   typedef ApplyTy<F32> Ty;
   typedef typename Ty::T T;
   constexpr int NC = 32 * NBH;                        // columns held by the workgroup
@@ -113,8 +125,9 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
   const int64_t i0 = (int64_t)blockIdx.x * AR;
   const int kend = TRI ? min(g.K, g.N) : g.K;
 
+  typedef std::conditional_t<F32, float2, double2> BPair;
   float4 ra[APER];
-  double2 rb[BPER];
+  BPair rb[BPER];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int p = 0; p < APER; ++p) {
@@ -145,20 +158,23 @@ __global__ __launch_bounds__(512) void k_apply_tall(ApplyArgs g) {
 #pragma unroll
     for (int p = 0; p < BPER; ++p) {
       const int e = tid + 512 * p;
-      double2 v = make_double2(0.0, 0.0);
+      BPair v;
+      v.x = 0;
+      v.y = 0;
       if (e < BVEC) {
         int j, k;
-        // BCOL: eight consecutive lanes read one column's 16 indices (128 B)
+        // BCOL: eight consecutive lanes read one column's 16 indices
         if (BCOL) { j = e / (ABK / 2); k = k0 + (e % (ABK / 2)) * 2; }
         else { k = k0 + e / (NC / 2); j = (e % (NC / 2)) * 2; }
         // with a triangular B, whole columns j < k0 are zero in this chunk
         if (j < g.N && k < kend && !(TRI && j < k0)) {
-          v = BCOL ? *reinterpret_cast<const double2*>(g.B + (int64_t)j * g.ldb + k)
-                   : *reinterpret_cast<const double2*>(g.B + (int64_t)k * g.ldb + j);
+          const int64_t at = BCOL ? (int64_t)j * g.ldb + k : (int64_t)k * g.ldb + j;
+          if constexpr (F32) v = *reinterpret_cast<const float2*>(g.B32 + at);
+          else v = *reinterpret_cast<const double2*>(g.B + at);
           if (TRI) {
             // BCOL: (k, j) and (k+1, j); else (k, j) and (k, j+1)
-            if (BCOL) { if (k > j) v.x = 0.0; if (k + 1 > j) v.y = 0.0; }
-            else { if (k > j) v.x = 0.0; if (k > j + 1) v.y = 0.0; }
+            if (BCOL) { if (k > j) v.x = 0; if (k + 1 > j) v.y = 0; }
+            else { if (k > j) v.x = 0; if (k > j + 1) v.y = 0; }
           }
         }
       }
@@ -278,12 +294,16 @@ sketchne_status apply_tall(sketchne_ctx* c, const ApplyDesc& d) {
   if (d.n == 0) return SKETCHNE_OK;
   if (!apply_tall_supported(d)) return SKETCHNE_E_UNSUPPORTED;
   ProfScope ps(c, SKETCHNE_PROF_GEMM64);
-  ApplyArgs g{d.n, d.K, d.N, d.A, d.lda, d.B, d.ldb, d.C, d.ldc, d.run_if};
+  ApplyArgs g{d.n, d.K, d.N, d.A, d.lda, d.B, d.ldb, d.C, d.ldc, d.run_if, d.b32};
   dim3 grid((unsigned)((d.n + AR - 1) / AR)), blk(512);
   const int nbh = d.N <= 128 ? 4 : (d.N <= 256 ? 8 : 9);
   // the FP32 form is built for two shapes of a row-major block: the
-  // Cholesky-QR apply (B = R^-1 read by columns) and a plain B read by rows
-  if (d.f32 && !d.acol && !d.ccol && d.upper == d.bcol) {
+  // Cholesky-QR apply (B = R^-1 read by columns) and a plain B read by rows;
+  // it needs the scratch for B's FP32 copy
+  if (d.f32 && d.b32 && !d.acol && !d.ccol && d.upper == d.bcol) {
+    // B spans (N columns or K rows) of ldb doubles; the last one only to K or N
+    const int64_t count = (int64_t)((d.bcol ? d.N : d.K) - 1) * d.ldb + (d.bcol ? d.K : d.N);
+    hipLaunchKernelGGL(k_b_to_f32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, c->stream, count, d.B, d.b32);
     if (d.upper) {
       if (nbh == 4) hipLaunchKernelGGL((k_apply_tall<4, false, true, false, true, true>), grid, blk, 0, c->stream, g);
       else if (nbh == 8) hipLaunchKernelGGL((k_apply_tall<8, false, true, false, true, true>), grid, blk, 0, c->stream, g);

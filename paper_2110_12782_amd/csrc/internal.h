@@ -127,6 +127,7 @@ struct ApplyDesc {
   float* C = nullptr; int64_t ldc = 0; bool ccol = false;
   const int* run_if = nullptr;
   bool f32 = false;  // FP32 matrix cores (B rounded to FP32); only where a span is all that matters
+  float* b32 = nullptr;  // f32: scratch for B's FP32 copy (as many floats as B spans); without it, FP64
 };
 bool apply_tall_supported(const ApplyDesc& d);
 sketchne_status apply_tall(sketchne_ctx* c, const ApplyDesc& d);

@@ -136,6 +136,21 @@ def test_orth(lib, torch):
         assert s.max() < 1e-5
 
 
+def test_orth_deterministic(lib, torch):
+    # the Cholesky of orders above 64 runs over several workgroups of one
+    # cooperative launch that exchange block rows through global memory
+    # between grid barriers; every workgroup factors the diagonal blocks
+    # itself, so a stale read would show as a bitwise difference
+    for n, K in [(30000, 288), (9000, 96), (5000, 272)]:
+        say(f"orth twice, bitwise n={n} K={K}")
+        rng = np.random.default_rng(K + 1)
+        B = (rng.standard_normal((n, K)) @ np.diag(np.logspace(0, 2, K))).astype(np.float32)
+        Q1 = lib.orth(torch.from_numpy(B.copy()).cuda()).cpu().numpy()
+        Q2 = lib.orth(torch.from_numpy(B.copy()).cuda()).cpu().numpy()
+        assert lib.sync() & ~1 == 0
+        assert np.array_equal(Q1.view(np.uint32), Q2.view(np.uint32))
+
+
 @pytest.mark.parametrize("kappa", [1e6, 1e12])
 def test_orth_ill_conditioned(lib, torch, kappa):
     # correlated columns, so the condition number survives the scaling of the
