@@ -151,14 +151,15 @@ def test_orth_deterministic(lib, torch):
         assert np.array_equal(Q1.view(np.uint32), Q2.view(np.uint32))
 
 
-@pytest.mark.parametrize("kappa", [1e6, 1e12])
-def test_orth_ill_conditioned(lib, torch, kappa):
+@pytest.mark.parametrize("kappa,K", [(1e6, 96), (1e12, 96), (1e12, 288)])
+def test_orth_ill_conditioned(lib, torch, kappa, K):
     # correlated columns, so the condition number survives the scaling of the
     # Gram to unit diagonal: 1e6 takes the second Cholesky-QR pass; at 1e12
     # the FP32 rounding of B leaves an effective condition number near the
     # limit of the FP64 Gram, so the first Cholesky may take the shifted
-    # retry (flag 1) before the second pass
-    n, K = 20000, 96
+    # retry (flag 1) before the second pass.  K = 96 runs the Cholesky on two
+    # workgroups, K = 288 on six (every one of them takes the retry).
+    n = 20000
     say(f"orth ill-conditioned n={n} K={K} kappa={kappa:g}")
     rng = np.random.default_rng(int(np.log10(kappa)))
     Ua, _ = np.linalg.qr(rng.standard_normal((n, K)))
