@@ -67,16 +67,23 @@ __device__ __forceinline__ void blk_coords(int b, int nbk, int& I, int& J) {
 // from uneven shares, 17% at m = 272 and 33% at m = 256.)
 constexpr int GR_WG = GR_GROUPS * GR_WAVES;  // wavefronts per row range
 
-template <bool TWO, bool ROWMAJ, bool F32, int NSL>
+// WGT: G = X^T diag(w) X (w given).  The one-operand row-major FP64 form
+// stages its chunks in LDS already converted to FP64 (S64): each value is
+// converted once instead of once per block that reads it, and a fragment
+// read is one 8-byte LDS read with no conversion after it.
+template <bool TWO, bool ROWMAJ, bool F32, int NSL, bool WGT>
 __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
   typedef std::conditional_t<F32, floatx4, doublex4> Acc;
+  constexpr bool S64 = !TWO && ROWMAJ && !F32;
+  typedef std::conditional_t<S64, double, float> LT;  // LDS element
   if (g.run_if && *g.run_if == 0) return;
   const int L = blockIdx.x;
   const int q = L >> 3;
   const int grp = q % GR_GROUPS;
   const int range = (q / GR_GROUPS) * 8 + (L & 7);
   if (range >= g.nranges) return;
-  extern __shared__ __attribute__((aligned(16))) float lds[];
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  LT* lds = reinterpret_cast<LT*>(lds_raw);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // chunk buffers: ROWMAJ [data row][column i] (row stride S); otherwise
   // [column i][data row] (stride S = GR_CHUNK + 2), so that a column-major
@@ -153,21 +160,26 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
       px[u] = a;
       py[u] = b;
     }
-    if (g.w && tid < GR_CHUNK) pw = (c0 + tid < r1) ? g.w[c0 + tid] : 0.0;
+    if (WGT && tid < GR_CHUNK) pw = (c0 + tid < r1) ? g.w[c0 + tid] : 0.0;
   };
   auto stash = [&](int buf) {
-    float* dx = lds + offX(buf);
-    float* dy = lds + offY(buf);
+    LT* dx = lds + offX(buf);
+    LT* dy = lds + offY(buf);
 #pragma unroll
     for (int u = 0; u < MAXV; ++u) {
       int v = tid + GR_THREADS * u;
       if (ROWMAJ) {
         int rr = v / cols4, c4 = v - rr * cols4;
         if (rr < GR_CHUNK) {
-          *reinterpret_cast<float4*>(dx + rr * S + 4 * c4) = px[u];
-          if (TWO) *reinterpret_cast<float4*>(dy + rr * S + 4 * c4) = py[u];
+          if constexpr (S64) {
+            *reinterpret_cast<double2*>(dx + rr * S + 4 * c4) = make_double2(px[u].x, px[u].y);
+            *reinterpret_cast<double2*>(dx + rr * S + 4 * c4 + 2) = make_double2(px[u].z, px[u].w);
+          } else {
+            *reinterpret_cast<float4*>(dx + rr * S + 4 * c4) = px[u];
+            if (TWO) *reinterpret_cast<float4*>(dy + rr * S + 4 * c4) = py[u];
+          }
         }
-      } else {
+      } else if constexpr (!S64) {
         int i = v / (GR_CHUNK / 4), qq = v - i * (GR_CHUNK / 4);
         if (i < g.m) {
           // S is even: 8-byte stores
@@ -186,7 +198,7 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
   // columns i >= m are never stored: zero them once
   for (int idx = tid; idx < 2 * (TWO ? 2 : 1) * CH; idx += GR_THREADS) {
     const int col = ROWMAJ ? (idx % CH) % S : (idx % CH) / S;
-    if (col >= g.m) lds[idx] = 0.f;
+    if (col >= g.m) lds[idx] = LT(0);
   }
   int buf = 0;
   if (r0 < r1) {
@@ -199,8 +211,8 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
     if (more) fetch(c0 + GR_CHUNK);
     // this lane's fragment address in each slot's blocks; the row steps of
     // the chunk are compile-time offsets from it
-    const float* xa[NSL];
-    const float* ya[NSL];
+    const LT* xa[NSL];
+    const LT* ya[NSL];
 #pragma unroll
     for (int t = 0; t < NSL; ++t) {
       xa[t] = lds + offX(buf) + (lane >> 4) * rstep + ((lane & 15) + 16 * pI[t]) * cstep;
@@ -208,16 +220,17 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
     }
 #pragma unroll
     for (int st = 0; st < GR_CHUNK / 4; ++st) {
-      const double wr = g.w ? wsh[buf][4 * st + (lane >> 4)] : 1.0;
+      const double wr = WGT ? wsh[buf][4 * st + (lane >> 4)] : 1.0;
 #pragma unroll
       for (int t = 0; t < NSL; ++t) {
         if constexpr (F32) {
           const float a0 = xa[t][4 * st * rstep];
-          const float a = g.w ? a0 * (float)wr : a0;
+          const float a = WGT ? a0 * (float)wr : a0;
           const float b = ya[t][4 * st * rstep];
           acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
         } else {
-          const double a = (double)xa[t][4 * st * rstep] * wr;
+          const double a0 = (double)xa[t][4 * st * rstep];
+          const double a = WGT ? a0 * wr : a0;
           const double b = (double)ya[t][4 * st * rstep];
           acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
         }
@@ -291,7 +304,8 @@ size_t gram_ws_bytes(int64_t n, int m) {
 }
 
 // X, Y: element (r, i) at X[r*xr + i*xc]; either xc == 1 (rows contiguous)
-// or xr == 1 (columns contiguous).  Y may equal X (then pass Y = nullptr).
+// or xr == 1 (columns contiguous).  Y may equal X (then pass Y = nullptr);
+// two operands and weights take row-major blocks.
 sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int64_t xr, int64_t xc, const float* Y,
                           int64_t yr, int64_t yc, const double* w, double* G, double* partial, size_t partial_cap,
                           const int* run_if, bool f32) {
@@ -322,28 +336,33 @@ sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int
   g.partial = partial;
   g.run_if = run_if;
   const bool two = Y != nullptr;
-  const size_t shmem = sizeof(float) * (size_t)2 * (two ? 2 : 1) * (rowmaj ? GR_CHUNK : g.crows) * g.stride;
+  const bool s64 = !two && rowmaj && !(f32 && !w);  // the FP64 one-operand row-major form stages FP64
+  const size_t shmem = (s64 ? sizeof(double) : sizeof(float)) * (size_t)2 * (two ? 2 : 1) *
+                       (rowmaj ? GR_CHUNK : g.crows) * g.stride;
+  // weights: the one-operand row-major form; two operands: row-major
+  if ((w && (two || !rowmaj)) || (two && !rowmaj)) return SKETCHNE_E_UNSUPPORTED;
   const unsigned blocks = (unsigned)((nr + 7) / 8 * 8 * GR_GROUPS);
   ProfScope ps(c, SKETCHNE_PROF_GEMM64);
-#define SKNE_GRAM_N(T, R, F, N)                                                                            \
+#define SKNE_GRAM_N(T, R, F, N, W)                                                                         \
   do {                                                                                                     \
-    hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_st<T, R, F, N>),                              \
+    hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_st<T, R, F, N, W>),                           \
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);                           \
-    hipLaunchKernelGGL((k_gram_st<T, R, F, N>), dim3(blocks), dim3(GR_THREADS), shmem, c->stream, g);      \
+    hipLaunchKernelGGL((k_gram_st<T, R, F, N, W>), dim3(blocks), dim3(GR_THREADS), shmem, c->stream, g);   \
   } while (0)
-#define SKNE_GRAM(T, R, F)                                                                                 \
+#define SKNE_GRAM(T, R, F, W)                                                                              \
   do {                                                                                                     \
     switch (nsl) {                                                                                         \
-      case 3: SKNE_GRAM_N(T, R, F, 3); break;                                                              \
-      case 6: SKNE_GRAM_N(T, R, F, 6); break;                                                              \
-      case 9: SKNE_GRAM_N(T, R, F, 9); break;                                                              \
-      case 10: SKNE_GRAM_N(T, R, F, 10); break;                                                            \
-      default: SKNE_GRAM_N(T, R, F, 11); break;                                                            \
+      case 3: SKNE_GRAM_N(T, R, F, 3, W); break;                                                           \
+      case 6: SKNE_GRAM_N(T, R, F, 6, W); break;                                                           \
+      case 9: SKNE_GRAM_N(T, R, F, 9, W); break;                                                           \
+      case 10: SKNE_GRAM_N(T, R, F, 10, W); break;                                                         \
+      default: SKNE_GRAM_N(T, R, F, 11, W); break;                                                         \
     }                                                                                                      \
   } while (0)
-  if (f32 && !two && rowmaj) SKNE_GRAM(false, true, true);
-  else if (two) { if (rowmaj) SKNE_GRAM(true, true, false); else SKNE_GRAM(true, false, false); }
-  else { if (rowmaj) SKNE_GRAM(false, true, false); else SKNE_GRAM(false, false, false); }
+  if (w) SKNE_GRAM(false, true, false, true);
+  else if (f32 && !two && rowmaj) SKNE_GRAM(false, true, true, false);
+  else if (two) SKNE_GRAM(true, true, false, false);
+  else { if (rowmaj) SKNE_GRAM(false, true, false, false); else SKNE_GRAM(false, false, false, false); }
 #undef SKNE_GRAM_N
 #undef SKNE_GRAM
   hipLaunchKernelGGL(k_gram_reduce, dim3((g.nblk * 256 + 255) / 256), dim3(256), 0, c->stream, m, g.nbk, g.nblk, nr,
