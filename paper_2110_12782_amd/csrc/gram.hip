@@ -67,14 +67,14 @@ __device__ __forceinline__ void blk_coords(int b, int nbk, int& I, int& J) {
 // from uneven shares, 17% at m = 272 and 33% at m = 256.)
 constexpr int GR_WG = GR_GROUPS * GR_WAVES;  // wavefronts per row range
 
-// WGT: G = X^T diag(w) X (w given).  The one-operand row-major FP64 form
-// stages its chunks in LDS already converted to FP64 (S64): each value is
-// converted once instead of once per block that reads it, and a fragment
-// read is one 8-byte LDS read with no conversion after it.
+// WGT: G = X^T diag(w) X (w given).  The one-operand FP64 forms stage their
+// chunks in LDS already converted to FP64 (S64): each value is converted
+// once instead of once per block that reads it, and a fragment read is one
+// 8-byte LDS read with no conversion after it.
 template <bool TWO, bool ROWMAJ, bool F32, int NSL, bool WGT>
 __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
   typedef std::conditional_t<F32, floatx4, doublex4> Acc;
-  constexpr bool S64 = !TWO && ROWMAJ && !F32;
+  constexpr bool S64 = !TWO && !F32;
   typedef std::conditional_t<S64, double, float> LT;  // LDS element
   if (g.run_if && *g.run_if == 0) return;
   const int L = blockIdx.x;
@@ -179,15 +179,20 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
             if (TWO) *reinterpret_cast<float4*>(dy + rr * S + 4 * c4) = py[u];
           }
         }
-      } else if constexpr (!S64) {
+      } else {
         int i = v / (GR_CHUNK / 4), qq = v - i * (GR_CHUNK / 4);
         if (i < g.m) {
-          // S is even: 8-byte stores
-          *reinterpret_cast<float2*>(dx + i * S + 4 * qq) = make_float2(px[u].x, px[u].y);
-          *reinterpret_cast<float2*>(dx + i * S + 4 * qq + 2) = make_float2(px[u].z, px[u].w);
-          if (TWO) {
-            *reinterpret_cast<float2*>(dy + i * S + 4 * qq) = make_float2(py[u].x, py[u].y);
-            *reinterpret_cast<float2*>(dy + i * S + 4 * qq + 2) = make_float2(py[u].z, py[u].w);
+          if constexpr (S64) {
+            *reinterpret_cast<double2*>(dx + i * S + 4 * qq) = make_double2(px[u].x, px[u].y);
+            *reinterpret_cast<double2*>(dx + i * S + 4 * qq + 2) = make_double2(px[u].z, px[u].w);
+          } else {
+            // S is even: 8-byte stores
+            *reinterpret_cast<float2*>(dx + i * S + 4 * qq) = make_float2(px[u].x, px[u].y);
+            *reinterpret_cast<float2*>(dx + i * S + 4 * qq + 2) = make_float2(px[u].z, px[u].w);
+            if (TWO) {
+              *reinterpret_cast<float2*>(dy + i * S + 4 * qq) = make_float2(py[u].x, py[u].y);
+              *reinterpret_cast<float2*>(dy + i * S + 4 * qq + 2) = make_float2(py[u].z, py[u].w);
+            }
           }
         }
       }
@@ -336,7 +341,7 @@ sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int
   g.partial = partial;
   g.run_if = run_if;
   const bool two = Y != nullptr;
-  const bool s64 = !two && rowmaj && !(f32 && !w);  // the FP64 one-operand row-major form stages FP64
+  const bool s64 = !two && !(f32 && !w && rowmaj);  // the FP64 one-operand forms stage FP64
   const size_t shmem = (s64 ? sizeof(double) : sizeof(float)) * (size_t)2 * (two ? 2 : 1) *
                        (rowmaj ? GR_CHUNK : g.crows) * g.stride;
   // weights: the one-operand row-major form; two operands: row-major
