@@ -74,7 +74,10 @@ constexpr int GR_WG = GR_GROUPS * GR_WAVES;  // wavefronts per row range
 template <bool TWO, bool ROWMAJ, bool F32, int NSL, bool WGT>
 __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
   typedef std::conditional_t<F32, floatx4, doublex4> Acc;
-  constexpr bool S64 = !TWO && !F32;
+  constexpr bool S64 = !F32;
+  // rows per chunk: the two-operand FP64 form takes 16 so that its four
+  // FP64 chunk buffers fit the LDS
+  constexpr int CHK = (TWO && S64) ? 16 : GR_CHUNK;
   typedef std::conditional_t<S64, double, float> LT;  // LDS element
   if (g.run_if && *g.run_if == 0) return;
   const int L = blockIdx.x;
@@ -89,7 +92,7 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
   // [column i][data row] (stride S = GR_CHUNK + 2), so that a column-major
   // input is stored as it is read, without a transposing scatter
   constexpr int S = ROWMAJ ? GR_RSTRIDE : GR_CSTRIDE;
-  const int CH = ROWMAJ ? GR_CHUNK * S : g.crows * S;
+  const int CH = ROWMAJ ? CHK * S : g.crows * S;
   constexpr int rstep = ROWMAJ ? S : 1, cstep = ROWMAJ ? 1 : S;
   // the two chunk buffers as offsets from the LDS array itself (an array of
   // pointers indexed at run time would lose the LDS address space, and every
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
   for (int t = 0; t < NSL; ++t) acc[t] = Acc{0, 0, 0, 0};
 
   const int cols4 = (g.m + 3) / 4;
-  constexpr int MAXV = (GR_CHUNK * GR_MAXB * 16 / 4 + GR_THREADS - 1) / GR_THREADS;
+  constexpr int MAXV = (CHK * GR_MAXB * 16 / 4 + GR_THREADS - 1) / GR_THREADS;
   float4 px[MAXV], py[MAXV];
   double pw = 1.0;
   auto fetch = [&](int64_t c0) {
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
       if (ROWMAJ) {
         int rr = v / cols4, c4 = v - rr * cols4;
         int64_t r = c0 + rr;
-        if (rr < GR_CHUNK && r < r1) {
+        if (rr < CHK && r < r1) {
           a = *reinterpret_cast<const float4*>(g.X + r * g.xr + 4 * c4);
           if (TWO) b = *reinterpret_cast<const float4*>(g.Y + r * g.yr + 4 * c4);
         }
@@ -160,7 +163,7 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
       px[u] = a;
       py[u] = b;
     }
-    if (WGT && tid < GR_CHUNK) pw = (c0 + tid < r1) ? g.w[c0 + tid] : 0.0;
+    if (WGT && tid < CHK) pw = (c0 + tid < r1) ? g.w[c0 + tid] : 0.0;
   };
   auto stash = [&](int buf) {
     LT* dx = lds + offX(buf);
@@ -170,10 +173,14 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
       int v = tid + GR_THREADS * u;
       if (ROWMAJ) {
         int rr = v / cols4, c4 = v - rr * cols4;
-        if (rr < GR_CHUNK) {
+        if (rr < CHK) {
           if constexpr (S64) {
             *reinterpret_cast<double2*>(dx + rr * S + 4 * c4) = make_double2(px[u].x, px[u].y);
             *reinterpret_cast<double2*>(dx + rr * S + 4 * c4 + 2) = make_double2(px[u].z, px[u].w);
+            if (TWO) {
+              *reinterpret_cast<double2*>(dy + rr * S + 4 * c4) = make_double2(py[u].x, py[u].y);
+              *reinterpret_cast<double2*>(dy + rr * S + 4 * c4 + 2) = make_double2(py[u].z, py[u].w);
+            }
           } else {
             *reinterpret_cast<float4*>(dx + rr * S + 4 * c4) = px[u];
             if (TWO) *reinterpret_cast<float4*>(dy + rr * S + 4 * c4) = py[u];
@@ -197,7 +204,7 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
         }
       }
     }
-    if (tid < GR_CHUNK) wsh[buf][tid] = pw;
+    if (tid < CHK) wsh[buf][tid] = pw;
   };
 
   // columns i >= m are never stored: zero them once
@@ -211,9 +218,9 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
     stash(0);
   }
   __syncthreads();
-  for (int64_t c0 = r0; c0 < r1; c0 += GR_CHUNK) {
-    const bool more = c0 + GR_CHUNK < r1;
-    if (more) fetch(c0 + GR_CHUNK);
+  for (int64_t c0 = r0; c0 < r1; c0 += CHK) {
+    const bool more = c0 + CHK < r1;
+    if (more) fetch(c0 + CHK);
     // this lane's fragment address in each slot's blocks; the row steps of
     // the chunk are compile-time offsets from it
     const LT* xa[NSL];
@@ -224,7 +231,7 @@ __global__ __launch_bounds__(GR_THREADS) void k_gram_st(GramArgs g) {
       ya[t] = lds + offY(buf) + (lane >> 4) * rstep + ((lane & 15) + 16 * pJ[t]) * cstep;
     }
 #pragma unroll
-    for (int st = 0; st < GR_CHUNK / 4; ++st) {
+    for (int st = 0; st < CHK / 4; ++st) {
       const double wr = WGT ? wsh[buf][4 * st + (lane >> 4)] : 1.0;
 #pragma unroll
       for (int t = 0; t < NSL; ++t) {
@@ -341,9 +348,10 @@ sketchne_status gram_tall(sketchne_ctx* c, int64_t n, int m, const float* X, int
   g.partial = partial;
   g.run_if = run_if;
   const bool two = Y != nullptr;
-  const bool s64 = !two && !(f32 && !w && rowmaj);  // the FP64 one-operand forms stage FP64
+  const bool s64 = !(f32 && !w && !two && rowmaj);  // the FP64 forms stage FP64
+  const int chk = (two && s64) ? 16 : GR_CHUNK;
   const size_t shmem = (s64 ? sizeof(double) : sizeof(float)) * (size_t)2 * (two ? 2 : 1) *
-                       (rowmaj ? GR_CHUNK : g.crows) * g.stride;
+                       (rowmaj ? chk : g.crows) * g.stride;
   // weights: the one-operand row-major form; two operands: row-major
   if ((w && (two || !rowmaj)) || (two && !rowmaj)) return SKETCHNE_E_UNSUPPORTED;
   const unsigned blocks = (unsigned)((nr + 7) / 8 * 8 * GR_GROUPS);
