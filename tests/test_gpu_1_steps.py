@@ -122,6 +122,35 @@ def test_spmm_hubs_and_isolated(lib, torch, cols):
     assert err < 1e-6 and rowerr < 1e-5
 
 
+@pytest.mark.parametrize("cols", [288, 8])
+def test_spmm_slice_boundaries(lib, torch, cols):
+    # The SpMM cuts the stored entries into slices of 256; a row that a cut
+    # falls inside is finished from partial sums.  Rows of 250-260, 511-513
+    # and 1000 entries (one to four cuts each), runs of isolated vertices
+    # after them and a short last row put the cuts at row starts, inside
+    # short rows and inside long ones.
+    say(f"spmm slice boundaries, cols={cols}")
+    rng = np.random.default_rng(77)
+    n = 6000
+    hubs = rng.choice(np.arange(10, n - 10), size=40, replace=False)
+    degs = rng.choice([250, 255, 256, 257, 260, 300, 511, 512, 513, 1000], size=len(hubs))
+    u, v = [], []
+    for h, d in zip(hubs, degs):
+        nb = rng.choice(np.setdiff1d(np.arange(n), [h]), size=d, replace=False)
+        u.append(np.full(d, h)); v.append(nb)
+    ring = np.arange(n - 1)
+    u.append(ring); v.append(ring + 1)
+    u = np.concatenate(u); v = np.concatenate(v)
+    # isolate a few runs of vertices (drop their edges) right after some hubs
+    iso = np.concatenate([np.arange(h + 1, h + 4) for h in hubs[:10]])
+    keep = ~(np.isin(u, iso) | np.isin(v, iso))
+    rowptr, colidx = synth.csr_from_edges(n, u[keep], v[keep])
+    deg = np.diff(rowptr)
+    assert (deg > 256).sum() > 10 and (deg == 0).sum() >= 10
+    err, rowerr = _spmm_case(lib, torch, rowptr, colidx, cols, 0.5, 3)
+    assert err < 1e-6 and rowerr < 1e-5
+
+
 def test_orth(lib, torch):
     # K = 100 and 20: an odd number of 16-index apply chunks, the last one
     # partial; n = 777 and 4100 leave a ragged last row block
