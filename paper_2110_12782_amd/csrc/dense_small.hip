@@ -862,8 +862,10 @@ __global__ __launch_bounds__(512) void k_chol_inv_coop(int m, const double* __re
   if (run_if && *run_if == 0) return;
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   extern __shared__ double smem[];
-  double* D = smem;                  // NB x (NB+1)
-  double* P = smem + NB * (NB + 1);  // NB x m panel
+  // two NB x (NB+1) diagonal-block buffers (this step's, the next one's),
+  // then the NB x m panel; buffers are offsets from the LDS array
+  constexpr int DSZ = NB * (NB + 1);
+  double* P = smem + 2 * DSZ;
   __shared__ double rsc[CH_MAXM];
   __shared__ double colsum[CH_MAXM];
   __shared__ __attribute__((aligned(16))) double xrow[64];
@@ -932,16 +934,21 @@ __global__ __launch_bounds__(512) void k_chol_inv_coop(int m, const double* __re
     pjb = 0;
     grid.sync();
 
+    int dcur = 0;         // buffer of this step's diagonal block
+    bool have_d = false;  // already factored during the previous step
     for (int j0 = 0; j0 < m; j0 += NB) {
       const int jb = min(NB, m - j0);
       if (pjb) store_right(pj0, pjb);
-      for (int idx = tid; idx < NB * NB; idx += nt) {
-        const int a = idx / NB, b = idx % NB;
-        D[a * (NB + 1) + b] = (b < jb && a <= b) ? W[(int64_t)(j0 + a) * m2 + j0 + b] : 0.0;
+      double* D = smem + dcur * DSZ;
+      if (!have_d) {
+        for (int idx = tid; idx < NB * NB; idx += nt) {
+          const int a = idx / NB, b = idx % NB;
+          D[a * (NB + 1) + b] = (b < jb && a <= b) ? W[(int64_t)(j0 + a) * m2 + j0 + b] : 0.0;
+        }
+        __syncthreads();
+        if (tid < 64) chol_diag_wave(D, xrow, nullptr, m2, j0, jb, tid, need_more ? colsum : nullptr, &s_fail);
+        __syncthreads();
       }
-      __syncthreads();
-      if (tid < 64) chol_diag_wave(D, xrow, nullptr, m2, j0, jb, tid, need_more ? colsum : nullptr, &s_fail);
-      __syncthreads();
       if (s_fail) break;
       // row panel of the whole block row (every workgroup), into LDS only
       const int nleft = m - j0 - jb;
@@ -979,7 +986,41 @@ __global__ __launch_bounds__(512) void k_chol_inv_coop(int m, const double* __re
         }
       }
       __syncthreads();
-      // trailing update: the live tiles over every wavefront of the grid
+      // Look-ahead: wavefront 0 of every workgroup forms the next diagonal
+      // block from the panel (its entries before this step's update minus
+      // P^T P; nobody writes them back, since no later step reads them) and
+      // factors it, while the other wavefronts run the trailing update.
+      const int jbn = min(NB, nleft);
+      const bool ahead = nleft > 0;
+      if (ahead && wv == 0) {
+        double* Dn = smem + (dcur ^ 1) * DSZ;
+        for (int ti = 0; ti < 2; ++ti)
+          for (int tj = ti; tj < 2; ++tj) {
+            doublex4 acc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int a = 16 * ti + (lane >> 4) + 4 * q, b = 16 * tj + (lane & 15);
+              acc[q] = (a < jbn && b < jbn && a <= b) ? W[(int64_t)(j0 + jb + a) * m2 + j0 + jb + b] : 0.0;
+            }
+#pragma unroll
+            for (int k0 = 0; k0 < NB; k0 += 4) {
+              const int t = k0 + (lane >> 4);
+              const int pa = 16 * ti + (lane & 15), pb = 16 * tj + (lane & 15);
+              const double av = (t < jb && pa < jbn) ? -P[t * m + pa] : 0.0;
+              const double bv = (t < jb && pb < jbn) ? P[t * m + pb] : 0.0;
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int a = 16 * ti + (lane >> 4) + 4 * q, b = 16 * tj + (lane & 15);
+              Dn[a * (NB + 1) + b] = (a < jbn && b < jbn && a <= b) ? acc[q] : 0.0;
+            }
+          }
+        // (one wavefront: its LDS writes complete before its reads below)
+        chol_diag_wave(Dn, xrow, nullptr, m2, j0 + jb, jbn, lane, need_more ? colsum : nullptr, &s_fail);
+      }
+      // trailing update: the live tiles over the other wavefronts of the
+      // grid, without the next diagonal block's tiles
       {
         const int nrows = nleft;
         const int tr_n = (nrows + 15) / 16, tc_n = (m + 15) / 16;
@@ -987,7 +1028,9 @@ __global__ __launch_bounds__(512) void k_chol_inv_coop(int m, const double* __re
         int nlive = 0;
         for (int tr = 0; tr < tr_n; ++tr) nlive += tc_n - min(tr, FL);
         constexpr int UT = 4;
-        for (int base = UT * gw; base < nlive; base += UT * gnw) {
+        const int tw = ahead ? wg * (nw - 1) + (wv - 1) : gw;  // wavefront 0 is busy when ahead
+        const int tnw = ahead ? nwg * (nw - 1) : gnw;
+        for (int base = UT * tw; (!ahead || wv > 0) && base < nlive; base += UT * tnw) {
           doublex4 acc[UT];
           int64_t gofs[UT][4];
           bool ok[UT][4];
@@ -1007,7 +1050,10 @@ __global__ __launch_bounds__(512) void k_chol_inv_coop(int m, const double* __re
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const int pr = 16 * tr + (lane >> 4) + 4 * q;
-              ok[u][q] = live[u] && pr < nrows && pc < m && (pc >= nleft || pc >= pr);
+              // the next diagonal block (rows and columns < jbn of the left
+              // part) is formed by the look-ahead and not stored
+              const bool dblk = ahead && pr < jbn && pc < jbn;
+              ok[u][q] = live[u] && !dblk && pr < nrows && pc < m && (pc >= nleft || pc >= pr);
               const int64_t col = pc < nleft ? (int64_t)(j0 + jb + pc) : (int64_t)m + (pc - nleft);
               gofs[u][q] = (int64_t)(j0 + jb + pr) * m2 + col;
               acc[u][q] = ok[u][q] ? W[gofs[u][q]] : 0.0;
@@ -1032,6 +1078,8 @@ __global__ __launch_bounds__(512) void k_chol_inv_coop(int m, const double* __re
       }
       pj0 = j0;
       pjb = jb;
+      if (ahead) dcur ^= 1;
+      have_d = ahead;
       grid.sync();
     }
     if (!s_fail) break;
@@ -1132,6 +1180,7 @@ sketchne_status chol_inv(sketchne_ctx* c, int m, const double* G, double* RinvT,
   for (int tr = 0; tr < tr_n; ++tr) nlive0 += tc_n - (tr < FL ? tr : FL);
   int nwg = (nlive0 + 31) / 32;
   nwg = nwg < 2 ? 2 : (nwg > CHC_MAXWG ? CHC_MAXWG : nwg);
+  shmem += sizeof(double) * NB * (NB + 1);  // the look-ahead's second diagonal-block buffer
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_inv_coop), hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)shmem) != hipSuccess)
     return SKETCHNE_E_DEVICE;
