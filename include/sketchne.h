@@ -56,6 +56,9 @@ typedef enum { SKETCHNE_FP32 = 0, SKETCHNE_BF16 = 1, SKETCHNE_FP16 = 2 } sketchn
 #define SKETCHNE_FLAG_EIG_NOCONV   0x4u  /* Jacobi reached its sweep limit            */
 #define SKETCHNE_FLAG_NONFINITE    0x8u  /* non-finite eigenvalue / singular value    */
 #define SKETCHNE_FLAG_BAD_INDEX    0x10u /* a test-matrix row outside [0, n) was read  */
+#define SKETCHNE_FLAG_BARRIER      0x20u /* a grid barrier of the Cholesky or Jacobi
+                                          * kernel waited over a second (workgroups not
+                                          * all resident): the results are invalid   */
 
 /* Workspace query operations (bitmask: the size covers every op named). */
 #define SKETCHNE_OP_EIG    0x1
@@ -281,13 +284,14 @@ sketchne_status sketchne_propagate(sketchne_ctx* ctx, const sketchne_graph* A, i
 /* For callers that cannot allocate device memory (code under stream capture,
  * tight serving loops, harnesses that forbid allocation): sketchne_symeig
  * without a workspace argument.  Its scratch (the padded column block,
- * rotation counts and shift of the eigensolver, 664,064 bytes, enough for
- * m <= 288) is a device array inside the library, one per device, held until
- * the process ends; its address is looked up once per device by
- * sketchne_create.  m > 288 returns SKETCHNE_E_UNSUPPORTED; SKETCHNE_E_DEVICE
- * if the scratch could not be located.  The call allocates nothing (the
- * eigensolver is one ordinary and one cooperative launch plus two small
- * ones).  Every call on a device shares that device's scratch, which keeps
+ * rotation counts, grid barrier count and shift of the eigensolver, 664,064
+ * bytes, enough for m <= 288) is a device array inside the library, one per
+ * device, held until the process ends; its address is looked up once per
+ * device by sketchne_create.  m > 288 returns SKETCHNE_E_UNSUPPORTED;
+ * SKETCHNE_E_DEVICE if the scratch could not be located.  The call
+ * allocates nothing (the eigensolver is four launches, the sweeps among
+ * them one launch of at most nine workgroups that must all be resident at
+ * once).  Every call on a device shares that device's scratch, which keeps
  * the last call's contents (each call initialises what it reads): calls that
  * overlap on one device -- from two streams or two contexts -- race and must
  * be serialised by the caller.  Results equal sketchne_symeig's. */
@@ -407,10 +411,15 @@ sketchne_status sketchne_eig_learned(sketchne_ctx* ctx, const sketchne_graph* A,
                                      size_t ws_bytes);
 
 /* ---- Per-kernel-class timing (measurement support) --------------------- */
-/* When enabled, every launch of a kernel class is bracketed by HIP events on
- * the context's stream.  sketchne_profile_read() synchronizes and returns,
- * per class, the summed milliseconds and the launch count since the last
- * reset (host arrays of length SKETCHNE_PROF_CLASSES). */
+/* When enabled, every launch of a timed kernel class is bracketed by HIP
+ * events on the context's stream.  on = 0 stops timing (and resets the
+ * sums), on = 1 times every class, and on = SKETCHNE_PROF_SELECT | (1 <<
+ * class) | ... times only the named classes: the others then run without
+ * events, which cost about 10 us of idle stream time per bracketed launch
+ * group.  Any other value is SKETCHNE_E_ARG.  sketchne_profile_read()
+ * synchronizes and returns, per class, the summed milliseconds and the
+ * launch count since the last reset (host arrays of length
+ * SKETCHNE_PROF_CLASSES). */
 #define SKETCHNE_PROF_SPMM      0
 #define SKETCHNE_PROF_SKETCH_Y  1
 #define SKETCHNE_PROF_SKETCH_Z  2
@@ -419,6 +428,7 @@ sketchne_status sketchne_eig_learned(sketchne_ctx* ctx, const sketchne_graph* A,
 #define SKETCHNE_PROF_PREP      5
 #define SKETCHNE_PROF_PROPAGATE 6
 #define SKETCHNE_PROF_CLASSES   7
+#define SKETCHNE_PROF_SELECT    0x40000000
 sketchne_status sketchne_profile_enable(sketchne_ctx* ctx, int on);
 sketchne_status sketchne_profile_read(sketchne_ctx* ctx, double* ms, int64_t* launches);
 

@@ -19,6 +19,7 @@ OK, E_ARG, E_WORKSPACE, E_DEVICE, E_NUMERIC, E_UNSUPPORTED = range(6)
 FP32, BF16, FP16 = 0, 1, 2
 OP_EIG, OP_SKETCH, OP_EMBED, OP_SPMM = 1, 2, 4, 8
 PROF_NAMES = ["spmm", "sketch_y", "sketch_z", "gemm64", "small", "prep", "propagate"]
+PROF_SELECT = 0x40000000  # with class bits: time only those classes
 
 EXPORTED = [
     "sketchne_status_str", "sketchne_create", "sketchne_destroy", "sketchne_set_stream",
@@ -585,8 +586,15 @@ class Library:
             return U, lam, bool(fb.value), worst.value
         return U, lam, bool(fb.value)
 
-    def profile_enable(self, on: bool):
-        self.check(self.lib.sketchne_profile_enable(self.ctx(), int(on)), "profile_enable")
+    def profile_enable(self, on: bool, classes=None):
+        """Time every kernel class (or, with `classes`, only those named in
+        PROF_NAMES; the rest then run without events)."""
+        v = int(on)
+        if on and classes is not None:
+            v = PROF_SELECT
+            for name in classes:
+                v |= 1 << PROF_NAMES.index(name)
+        self.check(self.lib.sketchne_profile_enable(self.ctx(), v), "profile_enable")
 
     def profile_read(self) -> dict:
         ms = (C.c_double * len(PROF_NAMES))()

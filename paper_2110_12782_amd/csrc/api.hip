@@ -432,6 +432,10 @@ sketchne_status sketchne_create(sketchne_ctx** out, int device, void* stream) {
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
   if (hipSetDevice(device) != hipSuccess) { delete c; return SKETCHNE_E_DEVICE; }
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+    delete c;
+    return SKETCHNE_E_DEVICE;
+  }
   if (hipMalloc(&c->d_flags, sizeof(uint32_t)) != hipSuccess) { delete c; return SKETCHNE_E_DEVICE; }
   if (hipHostMalloc(&c->h_flags, sizeof(uint32_t) + sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
     hipFree(c->d_flags);
@@ -1496,7 +1500,11 @@ sketchne_status sketchne_eig_learned(sketchne_ctx* c, const sketchne_graph* A, c
 
 sketchne_status sketchne_profile_enable(sketchne_ctx* c, int on) {
   if (!c) return SKETCHNE_E_ARG;
+  const uint32_t all = (1u << SKETCHNE_PROF_CLASSES) - 1;
+  if (on != 0 && on != 1 && ((on & SKETCHNE_PROF_SELECT) == 0 || ((uint32_t)on & ~(SKETCHNE_PROF_SELECT | all))))
+    return SKETCHNE_E_ARG;
   c->profiling = on != 0;
+  c->prof_mask = on == 1 ? all : (uint32_t)on & all;
   c->n_ev = 0;
   for (int i = 0; i < SKETCHNE_PROF_CLASSES; ++i) { c->prof_ms[i] = 0; c->prof_n[i] = 0; }
   return SKETCHNE_OK;

@@ -11,8 +11,6 @@
 // failure raises CHOL_FAIL.
 //
 // Eigensolver: one-sided block Jacobi (see the comment above oj_cross_round).
-#include <hip/hip_cooperative_groups.h>
-
 #include <mutex>
 
 #include "internal.h"
@@ -31,6 +29,45 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
   return __hiloint2double(hi, lo);
 }
+
+// Grid barrier for the few-workgroup kernels below (at most 9 workgroups of
+// one CU each, launched on the stream after the previous kernel has ended, so
+// all of them are resident together).  *bar is zero at launch; barrier b
+// (1, 2, ...) is passed once all workgroups have added their arrival, i.e.
+// when *bar reaches b times the grid size.  The workgroup barrier before the
+// arrival and thread 0's agent-scope release publish the workgroup's stores;
+// thread 0's acquire fence once the count is seen (the polling itself is
+// relaxed, so the caches are invalidated once) and the closing workgroup
+// barrier make the other workgroups' stores visible to every thread.  A wait
+// longer than kBarSpinLimit polls (over a second) raises
+// SKETCHNE_FLAG_BARRIER and returns false, and the caller then leaves the
+// kernel, so a grid that were not all resident ends with an error instead of
+// hanging.
+constexpr uint32_t kBarSpinLimit = 1u << 22;
+
+__device__ __forceinline__ bool grid_barrier(uint32_t* bar, uint32_t& target, uint32_t* flags, int* s_abort) {
+  __syncthreads();
+  target += gridDim.x;
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int abort = 0;
+    uint32_t spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++spins > kBarSpinLimit) {
+        atomicOr(flags, SKETCHNE_FLAG_BARRIER);
+        abort = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *s_abort = abort;
+  }
+  __syncthreads();
+  return *s_abort == 0;
+}
+
+__global__ void k_zero_u32(uint32_t* __restrict__ p) { *p = 0u; }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -130,6 +167,8 @@ __global__ __launch_bounds__(512) void k_chol_inv(int m, const double* __restric
   __shared__ double s_red[2][8];
   __shared__ int s_fail;
   __shared__ int s_shifted;
+  __shared__ int s_abort;
+  uint32_t target = 0;  // grid barrier count
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), nw = nt >> 6;
   const int64_t m2 = 2 * (int64_t)m;
@@ -697,26 +736,30 @@ __device__ __forceinline__ void oj_cross_round(int w, int nb, int s, int sweep, 
   if (tid == 0 && s_cnt[1]) atomicAdd(&counters[kMaxSweeps + sweep], s_cnt[1]);
 }
 
-// All sweeps in one cooperative launch of nb / 2 workgroups (one per block
-// pair of a round): a grid barrier separates the rounds, and after the last
+// All sweeps in one launch of nb / 2 workgroups (one per block pair of a
+// round): a grid barrier separates the rounds, and after the last
 // round of a sweep every workgroup reads that sweep's count of large
 // rotations (final once the barrier has passed) and leaves the loop when it is
 // zero, so the stopping rule needs no host round trip.  The rounds and their
 // arithmetic are those of a sweep-per-launch schedule, so the results do not
 // depend on the launch shape.
-__global__ __launch_bounds__(OJ_THREADS) void k_oj_sweeps(int nb, double* __restrict__ G, int* __restrict__ counters) {
+// counters[2 * kMaxSweeps] is the grid barrier's arrival count.
+__global__ __launch_bounds__(OJ_THREADS) void k_oj_sweeps(int nb, double* __restrict__ G, int* __restrict__ counters,
+                                                          uint32_t* __restrict__ flags) {
   extern __shared__ __attribute__((aligned(16))) double lds[];
   __shared__ double s_nrm[2 * NBJ];  // squared column norms of the blocks in LDS
   __shared__ int s_cnt[2];
   __shared__ int s_stop;
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  __shared__ int s_abort;
+  uint32_t* bar = reinterpret_cast<uint32_t*>(counters + 2 * kMaxSweeps);
+  uint32_t target = 0;
   const int w = blockIdx.x;
   for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
     oj_intra_round(w, sweep, G, counters, lds, s_nrm, s_cnt);
-    grid.sync();
+    if (!grid_barrier(bar, target, flags, &s_abort)) return;
     for (int s = 0; s < nb - 1; ++s) {
       oj_cross_round(w, nb, s, sweep, G, counters, lds, s_nrm, s_cnt);
-      grid.sync();
+      if (!grid_barrier(bar, target, flags, &s_abort)) return;
     }
     if (threadIdx.x == 0)
       s_stop = __hip_atomic_load(&counters[kMaxSweeps + sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
@@ -824,10 +867,10 @@ constexpr int oj_nblocks(int m) {
 constexpr size_t oj_align(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // workspace of the eigensolver of order m: the padded column block, the
-// per-sweep rotation counts and the shift
+// per-sweep rotation counts and the grid barrier's count, and the shift
 constexpr size_t oj_ws_bytes(int m) {
-  return oj_align(sizeof(double) * (size_t)(oj_nblocks(m) * NBJ) * OJ_ROWS) + oj_align(sizeof(int) * 2 * kMaxSweeps) +
-         oj_align(sizeof(double));
+  return oj_align(sizeof(double) * (size_t)(oj_nblocks(m) * NBJ) * OJ_ROWS) +
+         oj_align(sizeof(int) * (2 * kMaxSweeps + 1)) + oj_align(sizeof(double));
 }
 
 // The no-allocation variant's scratch: the workspace of the largest order, in
@@ -842,8 +885,8 @@ constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 void* g_scratch_ptr[kMaxDevices] = {};
 
-// The same factorization spread over a few workgroups of one cooperative
-// launch, for orders where the trailing updates of a single workgroup (one
+// The same factorization spread over a few workgroups of one launch, for
+// orders where the trailing updates of a single workgroup (one
 // CU's FP64 matrix cores) dominate.  Every workgroup factors the diagonal
 // block and forms the whole row panel itself (both are small), so that only
 // the trailing update is divided: its live tiles are dealt to all wavefronts
@@ -858,9 +901,9 @@ void* g_scratch_ptr[kMaxDevices] = {};
 __global__ __launch_bounds__(512) void k_chol_inv_coop(int m, const double* __restrict__ G, double* __restrict__ W,
                                                        double* __restrict__ rpart, double* __restrict__ RinvT,
                                                        uint32_t* __restrict__ flags, int* __restrict__ need_more,
-                                                       const int* __restrict__ run_if, double repeat_kappa) {
+                                                       const int* __restrict__ run_if, double repeat_kappa,
+                                                       uint32_t* __restrict__ bar) {
   if (run_if && *run_if == 0) return;
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   extern __shared__ double smem[];
   // two NB x (NB+1) diagonal-block buffers (this step's, the next one's),
   // then the NB x m panel; buffers are offsets from the LDS array
@@ -872,6 +915,8 @@ __global__ __launch_bounds__(512) void k_chol_inv_coop(int m, const double* __re
   __shared__ double s_red[2][8];
   __shared__ int s_fail;
   __shared__ int s_shifted;
+  __shared__ int s_abort;
+  uint32_t target = 0;  // grid barrier count
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), nw = nt >> 6;
   const int wg = blockIdx.x, nwg = gridDim.x;
@@ -932,7 +977,7 @@ __global__ __launch_bounds__(512) void k_chol_inv_coop(int m, const double* __re
     for (int j = tid; j < m; j += nt) colsum[j] = 0.0;
     if (tid == 0) s_fail = 0;
     pjb = 0;
-    grid.sync();
+    if (!grid_barrier(bar, target, flags, &s_abort)) return;
 
     int dcur = 0;         // buffer of this step's diagonal block
     bool have_d = false;  // already factored during the previous step
@@ -1080,16 +1125,16 @@ __global__ __launch_bounds__(512) void k_chol_inv_coop(int m, const double* __re
       pjb = jb;
       if (ahead) dcur ^= 1;
       have_d = ahead;
-      grid.sync();
+      if (!grid_barrier(bar, target, flags, &s_abort)) return;
     }
     if (!s_fail) break;
     // every workgroup saw the same failed pivot: retry once with the shift
     if (wg == 0 && tid == 0) atomicOr(flags, attempt == 0 ? SKETCHNE_FLAG_CHOL_SHIFT : SKETCHNE_FLAG_CHOL_FAIL);
     if (tid == 0) s_shifted = 1;
-    grid.sync();  // no workgroup still reads W before it is initialised again
+    if (!grid_barrier(bar, target, flags, &s_abort)) return;  // no workgroup still reads W before it is initialised again
   }
   if (!s_fail && pjb) store_right(pj0, pjb);
-  grid.sync();
+  if (!grid_barrier(bar, target, flags, &s_abort)) return;
   // R^-T = Rs^-T S^-1 from the lower triangle of the right half, rows over
   // the wavefronts of the grid; the largest row sum of |Rs^-T| per workgroup
   double rmax = 0.0;
@@ -1124,7 +1169,7 @@ __global__ __launch_bounds__(512) void k_chol_inv_coop(int m, const double* __re
       for (int w = 0; w < nw; ++w) b = fmax(b, s_red[1][w]);
       rpart[wg] = b;
     }
-    grid.sync();
+    if (!grid_barrier(bar, target, flags, &s_abort)) return;
     if (wg == 0) {
       // kappa_1(Rs) = ||Rs||_1 ||Rs^-1||_1 (column sums of Rs gathered in
       // every workgroup's LDS, row sums of Rs^-T from all workgroups)
@@ -1146,9 +1191,21 @@ __global__ __launch_bounds__(512) void k_chol_inv_coop(int m, const double* __re
 
 }  // namespace
 
-// W (m x 2m), then one slot per workgroup of the cooperative form
-constexpr int CHC_MAXWG = 8;
-size_t chol_ws_bytes(int m) { return align_up(sizeof(double) * ((size_t)m * 2 * m + CHC_MAXWG)); }
+constexpr int CHC_MAXWG = 8;  // workgroups of the multi-workgroup form
+// W (m x 2m), the per-workgroup row-sum maxima, the grid barrier's count
+size_t chol_ws_bytes(int m) { return align_up(sizeof(double) * ((size_t)m * 2 * m + CHC_MAXWG + 1)); }
+
+namespace {
+
+// The grid barrier needs all `blocks` workgroups resident at once.
+sketchne_status check_resident(sketchne_ctx* c, const void* kernel, int blocks, int threads, size_t shmem) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, shmem) != hipSuccess)
+    return SKETCHNE_E_DEVICE;
+  return (int64_t)per_cu * c->n_cu >= blocks ? SKETCHNE_OK : SKETCHNE_E_UNSUPPORTED;
+}
+
+}  // namespace
 
 sketchne_status copy_if(sketchne_ctx* c, int64_t count, const float* src, float* dst, const int* run_if) {
   if (count == 0) return SKETCHNE_OK;
@@ -1184,14 +1241,13 @@ sketchne_status chol_inv(sketchne_ctx* c, int m, const double* G, double* RinvT,
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_inv_coop), hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)shmem) != hipSuccess)
     return SKETCHNE_E_DEVICE;
+  SK_TRY(check_resident(c, reinterpret_cast<const void*>(k_chol_inv_coop), nwg, 512, shmem));
   double* W = work;
   double* rpart = work + (size_t)m * 2 * m;
-  uint32_t* flags = c->d_flags;
-  int m_arg = m;
-  void* args[] = {&m_arg, &G, &W, &rpart, &RinvT, &flags, &need_more, &run_if, &repeat_kappa};
-  if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_chol_inv_coop), dim3(nwg), dim3(512), args,
-                                 (unsigned)shmem, c->stream) != hipSuccess)
-    return SKETCHNE_E_DEVICE;
+  uint32_t* bar = reinterpret_cast<uint32_t*>(rpart + CHC_MAXWG);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, bar);
+  hipLaunchKernelGGL(k_chol_inv_coop, dim3(nwg), dim3(512), shmem, c->stream, m, G, W, rpart, RinvT, c->d_flags,
+                     need_more, run_if, repeat_kappa, bar);
   return launch_status();
 }
 
@@ -1258,22 +1314,20 @@ sketchne_status symeig(sketchne_ctx* c, int m, const double* A, double* Vout, do
   const int nb = oj_nblocks(m), mp = nb * NBJ;
   Arena ar(ws, symeig_ws_bytes(m));
   double* G = ar.take<double>((size_t)mp * OJ_ROWS);
-  int* counters = ar.take<int>(2 * kMaxSweeps);  // rotations, then large rotations, per sweep
+  // rotations, then large rotations, per sweep; then the grid barrier's count
+  int* counters = ar.take<int>(2 * kMaxSweeps + 1);
   double* shift = ar.take<double>(1);
   ProfScope ps(c, SKETCHNE_PROF_SMALL);
   hipLaunchKernelGGL(k_oj_norm, dim3(1), dim3(1024), 0, c->stream, m, A, (int)general, shift);
   int tot = mp * OJ_ROWS;
   hipLaunchKernelGGL(k_oj_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, c->stream, m, mp, A, (int)general,
-                     shift, G, counters, 2 * kMaxSweeps);
+                     shift, G, counters, 2 * kMaxSweeps + 1);
   const size_t sh_intra = sizeof(double) * (size_t)(2 * NBJ) * OJ_ROWS;  // the larger of the two rounds
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_oj_sweeps), hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)sh_intra) != hipSuccess)
     return SKETCHNE_E_DEVICE;
-  int nb_arg = nb;
-  void* args[] = {&nb_arg, &G, &counters};
-  if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_oj_sweeps), dim3(nb / 2), dim3(OJ_THREADS), args,
-                                 (unsigned)sh_intra, c->stream) != hipSuccess)
-    return SKETCHNE_E_DEVICE;
+  SK_TRY(check_resident(c, reinterpret_cast<const void*>(k_oj_sweeps), nb / 2, OJ_THREADS, sh_intra));
+  hipLaunchKernelGGL(k_oj_sweeps, dim3(nb / 2), dim3(OJ_THREADS), sh_intra, c->stream, nb, G, counters, c->d_flags);
   // every sweep slot not reached keeps its zero count, so the finish kernel's
   // convergence test may scan them all
   const int run = kMaxSweeps;

@@ -9,11 +9,13 @@
 
 struct sketchne_ctx {
   int device = 0;
+  int n_cu = 0;                     // compute units of the device
   hipStream_t stream = nullptr;
   uint32_t* d_flags = nullptr;      // numeric flag word (device)
   uint32_t* h_flags = nullptr;      // pinned host copy
   int* h_counter = nullptr;         // pinned host scratch for convergence checks
   bool profiling = false;
+  uint32_t prof_mask = 0;           // classes timed while profiling (bit = class)
   // per-class event pairs (recorded on the stream when profiling)
   static constexpr int kMaxEvents = 4096;
   hipEvent_t ev[kMaxEvents];
@@ -60,7 +62,7 @@ struct ProfScope {
   int cls;
   int slot = -1;
   ProfScope(sketchne_ctx* ctx, int klass) : c(ctx), cls(klass) {
-    if (c && c->profiling && c->n_ev + 2 <= sketchne_ctx::kMaxEvents) {
+    if (c && c->profiling && ((c->prof_mask >> cls) & 1u) && c->n_ev + 2 <= sketchne_ctx::kMaxEvents) {
       slot = c->n_ev;
       c->n_ev += 2;
       c->ev_class[slot / 2] = cls;

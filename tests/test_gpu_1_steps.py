@@ -151,6 +151,32 @@ def test_spmm_slice_boundaries(lib, torch, cols):
     assert err < 1e-6 and rowerr < 1e-5
 
 
+def test_profile_select(lib, torch):
+    # timing restricted to named classes: only those launches are bracketed
+    # and counted; other values of the switch are argument errors
+    from paper_2110_12782_amd.binding import DeviceGraph, PROF_SELECT, SketchneError
+    rowptr, colidx = c1_graph()
+    g = DeviceGraph(rowptr, colidx)
+    B = torch.randn(g.n, 8, device="cuda")
+    lib.profile_enable(True, classes=("sketch_y",))
+    lib.spmm(g, 0.5, B)
+    prof = lib.profile_read()
+    assert prof["spmm"][1] == 0 and all(v[1] == 0 for v in prof.values())
+    lib.profile_enable(True, classes=("spmm", "sketch_z"))
+    lib.spmm(g, 0.5, B)
+    lib.spmm(g, 0.5, B)
+    prof = lib.profile_read()
+    assert prof["spmm"][1] == 2 and prof["spmm"][0] > 0
+    assert sum(v[1] for v in prof.values()) == 2
+    lib.profile_enable(True)
+    lib.spmm(g, 0.5, B)
+    assert lib.profile_read()["spmm"][1] == 1
+    lib.profile_enable(False)
+    for bad in (2, PROF_SELECT | (1 << 7), 1 << 7):
+        with pytest.raises(SketchneError):
+            lib.check(lib.lib.sketchne_profile_enable(lib.ctx(), bad), "profile_enable")
+
+
 def test_orth(lib, torch):
     # K = 100 and 20: an odd number of 16-index apply chunks, the last one
     # partial; n = 777 and 4100 leave a ragged last row block
@@ -167,7 +193,7 @@ def test_orth(lib, torch):
 
 def test_orth_deterministic(lib, torch):
     # the Cholesky of orders above 64 runs over several workgroups of one
-    # cooperative launch that exchange block rows through global memory
+    # launch that exchange block rows through global memory
     # between grid barriers; every workgroup factors the diagonal blocks
     # itself, so a stale read would show as a bitwise difference
     for n, K in [(30000, 288), (9000, 96), (5000, 272)]:
@@ -233,7 +259,7 @@ def test_symeig_random(lib, torch, m):
 
 
 def test_symeig_deterministic(lib, torch):
-    # the sweeps run as one cooperative launch whose rounds exchange columns
+    # the sweeps run as one launch of several workgroups whose rounds exchange columns
     # through global memory between grid barriers: two calls on the same input
     # must agree bit for bit (a stale read would change the rotation path)
     say("symeig m=288 twice, bitwise")
