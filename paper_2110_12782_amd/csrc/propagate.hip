@@ -173,13 +173,13 @@ __global__ __launch_bounds__(256) void k_cheb_fixup(int64_t nnz, const int64_t* 
   }
 }
 
-// isolated vertices: M has a zero row there
+// isolated vertices: M has a zero row there.  One thread per vertex; the
+// rare isolated ones write all their column quads.
 __global__ void k_cheb_isolated(int64_t n, const int64_t* __restrict__ rowptr, int nq, ChebStep st) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t r = idx / nq;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   if (rowptr[r + 1] != rowptr[r]) return;
-  cheb_row(st, r, (int)(idx - r * nq), 0, make_float4(0.f, 0.f, 0.f, 0.f));
+  for (int q = 0; q < nq; ++q) cheb_row(st, r, q, 0, make_float4(0.f, 0.f, 0.f, 0.f));
 }
 
 // out = c0 E (a degree-0 polynomial)
@@ -249,7 +249,8 @@ sketchne_status propagate(sketchne_ctx* c, int64_t n, int64_t nnz, const int64_t
         hipLaunchKernelGGL(k_cheb_fixup, dim3((unsigned)((nwaves - 1 + 3) / 4)), dim3(256), 0, c->stream, nnz, rowptr,
                            nq, st, partial, brow, nwaves);
     }
-    hipLaunchKernelGGL(k_cheb_isolated, dim3(eblocks), dim3(256), 0, c->stream, n, rowptr, nq, st);
+    hipLaunchKernelGGL(k_cheb_isolated, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, rowptr, nq,
+                       st);
     SK_TRY(launch_status());
     prev = cur; ldprev = ldcur;
     cur = dst; ldcur = d;
