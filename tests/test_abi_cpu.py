@@ -118,3 +118,22 @@ def test_warm_start_null_arguments_rejected(lib):
     fb = C.c_int32(0)
     assert L.sketchne_eig_learned(None, C.byref(g), C.byref(p), C.byref(net), 1, 1.0, None, None, C.byref(fb),
                                   None, None, 0) == B.E_ARG
+
+
+def test_profile_constants_match_header():
+    # the binding's class names and selection bit are the header's macros
+    text = open(HEADER).read()
+    macros = dict(re.findall(r"#define\s+SKETCHNE_PROF_(\w+)\s+(0x[0-9a-fA-F]+|\d+)", text))
+    assert int(macros["SELECT"], 0) == B.PROF_SELECT
+    assert int(macros["CLASSES"], 0) == len(B.PROF_NAMES)
+    for i, name in enumerate(B.PROF_NAMES):
+        assert int(macros[name.upper()], 0) == i, name
+    assert B.PROF_SELECT >> int(macros["CLASSES"]) != 0  # the selection bit lies above every class bit
+
+
+def test_profile_calls_without_context_rejected(lib):
+    ms = (C.c_double * len(B.PROF_NAMES))()
+    n = (C.c_int64 * len(B.PROF_NAMES))()
+    assert lib.lib.sketchne_profile_enable(None, 1) == B.E_ARG
+    assert lib.lib.sketchne_profile_enable(None, B.PROF_SELECT | 1) == B.E_ARG
+    assert lib.lib.sketchne_profile_read(None, ms, n) == B.E_ARG
