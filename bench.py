@@ -207,6 +207,8 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, n, rowptr, colidx, out, ref_form, forms, other_forms)
     traffic = pmc_traffic(args.precision, args.scale, y_launches)
+    traffic_spmm = pmc_traffic(args.precision, args.scale, 6, summary=f"spmm_chunglu_n2p{args.scale}_hbm_bytes.txt",
+                               source="spmm.hip")
 
     line = {
         "metric": "sketched NetMF entries/s + embed time at n=1M; BF16-MFMA vs FP32 at equal error",
@@ -239,8 +241,11 @@ def main():
                      "launch_ms": y_ms, "algorithmic_flops": y_flops, "executed_flops": executed,
                      "launches_per_step": y_launches},
         "roofline_spmm": {"bound": "hbm", "kernel": "k_spmm", "achieved": sp_gbs, "peak": HBM_PEAK,
-                          "unit": "GB/s", "frac": sp_gbs / HBM_PEAK, "traffic": None, "launch_ms": sp_ms,
-                          "algorithmic_bytes": sp_bytes},
+                          "unit": "GB/s", "frac": sp_gbs / HBM_PEAK, "traffic": traffic_spmm,
+                          "traffic_source": "rocprofv3 FETCH_SIZE + WRITE_SIZE per k_spmm launch, copy-calibrated, from "
+                                            f"the committed summary profiles/spmm_chunglu_n2p{args.scale}_hbm_bytes.txt;"
+                                            " null unless that summary's SHA-256 of spmm.hip matches the source",
+                          "launch_ms": sp_ms, "algorithmic_bytes": sp_bytes},
         "forms": forms,
         "beyond_the_step": extras,
         "cpu_baseline": cpu,
@@ -468,18 +473,20 @@ def sin_theta(A, B) -> float:
     return float(torch.sqrt((s * s).sum() / s.numel()))
 
 
-def source_digest() -> str:
-    """SHA-256 of the HIP source that holds the fused sketch kernel."""
+def source_digest(source: str = "sketch.hip") -> str:
+    """SHA-256 of the HIP source that holds a kernel (default: the fused sketch)."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2110_12782_amd", "csrc", "sketch.hip"), "rb") as fh:
+    with open(os.path.join(ROOT, "paper_2110_12782_amd", "csrc", source), "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def pmc_traffic(prec, scale, launches):
-    """HBM bytes per launch of the fused Y kernel, from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, or None when that summary was taken on
-    another workload or on kernel sources that have changed since."""
-    path = os.path.join(ROOT, "profiles", f"fused_sketch_y_chunglu_n2p{scale}_{prec}_hbm_bytes.txt")
+def pmc_traffic(prec, scale, launches, summary=None, source="sketch.hip"):
+    """HBM bytes per launch of a kernel (default: the fused Y kernel) from its
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when that
+    summary was taken on another workload or on kernel sources that have
+    changed since."""
+    name = summary or f"fused_sketch_y_chunglu_n2p{scale}_{prec}_hbm_bytes.txt"
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -487,7 +494,7 @@ def pmc_traffic(prec, scale, launches):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("source_sha256") != source_digest():
+    if vals.get("source_sha256") != source_digest(source):
         log("pmc summary is stale (kernel sources changed); traffic = null")
         return None
     try:
